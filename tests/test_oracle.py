@@ -1,0 +1,357 @@
+"""Pins for the CPU oracle: every solver and step oracle is checked against
+something other than itself -- closed forms, exhaustive enumeration, library
+routines, invariants of the definitions (paper, Section 2 and 2.1)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+import gen
+import oracle
+
+SOLVERS = [("brute", oracle.brute), ("sw", oracle.stoer_wagner), ("noi", oracle.noi)]
+
+
+def check_side(g, lam, side):
+    assert side.shape == (g.n,)
+    assert side[0] == 0
+    assert 0 < int(side.sum()) < g.n
+    assert oracle.cut_value(g, side) == lam
+
+
+# ------------------------------------------------------------ closed forms
+@pytest.mark.parametrize("name,fn", SOLVERS)
+@pytest.mark.parametrize("n", [2, 3, 4, 7, 11])
+def test_complete_graph(name, fn, n):
+    lam, side = fn(gen.complete(n, weight=3))
+    assert lam == 3 * (n - 1)
+    check_side(gen.complete(n, weight=3), lam, side)
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+@pytest.mark.parametrize("seed", range(8))
+def test_weighted_cycle(name, fn, seed):
+    r = gen.SplitMix64(seed)
+    n = 3 + seed % 10
+    wts = [1 + r.below(50) for _ in range(n)]
+    g = gen.cycle(wts)
+    lam, side = fn(g)
+    assert lam == sum(sorted(wts)[:2])
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+@pytest.mark.parametrize("seed", range(8))
+def test_tree(name, fn, seed):
+    g = gen.random_tree(2 + 2 * seed, seed, 1, 100)
+    lam, side = fn(g)
+    assert lam == int(g.w.min())
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+@pytest.mark.parametrize("a,b,k", [(3, 4, 1), (5, 5, 2), (6, 8, 4), (9, 7, 6)])
+def test_two_cliques(name, fn, a, b, k):
+    g = gen.two_cliques(a, b, k)
+    lam, side = fn(g)
+    assert lam == k
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+@pytest.mark.parametrize("n", [4, 5, 9, 13])
+def test_wheel(name, fn, n):
+    g = gen.wheel(n)
+    lam, side = fn(g)
+    assert lam == 2 * n - 2
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+def test_two_vertices(name, fn):
+    g = gen.from_edges(2, [0], [1], [17])
+    assert fn(g)[0] == 17
+
+
+@pytest.mark.parametrize("name,fn", SOLVERS)
+def test_disconnected(name, fn):
+    g = gen.disjoint_union(gen.complete(4), gen.cycle([2, 3, 4]))
+    lam, side = fn(g)
+    assert lam == 0
+    check_side(g, lam, side)
+
+
+# ----------------------------------------------------- exhaustive agreement
+@pytest.mark.parametrize("seed", range(400))
+def test_solvers_agree_small(seed):
+    n = 2 + seed % 15
+    g = gen.random_small(n, [0.2, 0.5, 0.9][seed % 3], seed, 0, 9)
+    lam, side = oracle.brute(g)
+    check_side(g, lam, side)
+    for name, fn in SOLVERS[1:]:
+        l2, s2 = fn(g)
+        assert l2 == lam, name
+        check_side(g, l2, s2)
+
+
+def test_brute_matches_explicit_enumeration():
+    # the Gray-code update against a direct sum over every set S
+    for seed in range(20):
+        g = gen.random_small(9, 0.6, 100 + seed, 0, 20)
+        best = None
+        for mask in range(1, 1 << (g.n - 1)):
+            side = np.array([0] + [(mask >> (x - 1)) & 1 for x in range(1, g.n)], np.uint8)
+            c = oracle.cut_value(g, side)
+            best = c if best is None else min(best, c)
+        assert oracle.brute(g)[0] == best
+
+
+# -------------------------------------------------------------- metamorphic
+@pytest.mark.parametrize("seed", range(20))
+def test_scale_and_permutation(seed):
+    g = gen.random_small(10 + seed % 5, 0.5, 7000 + seed, 1, 30)
+    lam = oracle.brute(g)[0]
+    for name, fn in SOLVERS:
+        assert fn(gen.scale(g, 7))[0] == 7 * lam
+        gp, _ = gen.permute(g, seed)
+        assert fn(gp)[0] == lam
+
+
+def test_raising_a_weight_never_lowers_lambda():
+    for seed in range(20):
+        g = gen.random_small(11, 0.5, 900 + seed, 1, 9)
+        lam = oracle.brute(g)[0]
+        h = gen.Graph(g.n, g.row_ptr.copy(), g.col.copy(), g.w.copy())
+        j = seed % h.nnz
+        u = int(np.searchsorted(h.row_ptr, j, side="right") - 1)
+        v = int(h.col[j])
+        h.w[j] += 5
+        k = h.row_ptr[v] + int(np.where(h.col[h.row_ptr[v]:h.row_ptr[v + 1]] == u)[0][0])
+        h.w[k] += 5
+        assert oracle.noi(h)[0] >= lam
+        assert oracle.stoer_wagner(h)[0] >= lam
+
+
+def test_raw_input_folding():
+    # loops are ignored and parallel edges add up
+    g = gen.raw_csr(4, [0, 0, 1, 2, 2, 3, 1], [1, 1, 2, 3, 2, 0, 1], [2, 3, 4, 5, 100, 6, 50])
+    simple = gen.from_edges(4, [0, 1, 2, 3], [1, 2, 3, 0], [5, 4, 5, 6])
+    for name, fn in SOLVERS:
+        assert fn(g)[0] == oracle.brute(simple)[0] == 9
+
+
+# ------------------------------------------------- larger closed forms
+@pytest.mark.parametrize("name,fn", SOLVERS[1:])
+def test_larger_closed_forms(name, fn):
+    assert fn(gen.complete(40))[0] == 39
+    wts = [5 + (i * 37) % 91 for i in range(700)]
+    assert fn(gen.cycle(wts))[0] == sum(sorted(wts)[:2])
+    t = gen.random_tree(1500, 3, 2, 500)
+    assert fn(t)[0] == int(t.w.min())
+    assert fn(gen.two_cliques(25, 30, 7))[0] == 7
+    assert fn(gen.wheel(120))[0] == 238
+
+
+def test_planted_two_blocks():
+    g = gen.config_planted_2x1000()
+    assert g.n == 2000 and g.m == 12005
+    lam_sw, side_sw = oracle.stoer_wagner(g)
+    lam_noi, side_noi = oracle.noi(g)
+    assert lam_sw == lam_noi == 5
+    check_side(g, 5, side_sw)
+    check_side(g, 5, side_noi)
+
+
+# ------------------------------------------------------------ step oracles
+def test_degrees():
+    g = gen.raw_csr(5, [0, 1, 1, 2, 3], [1, 2, 2, 2, 4], [3, 4, 5, 9, 1])
+    assert list(oracle.degrees(g)) == [3, 12, 9, 1, 1]
+
+
+def _check_contraction(g, lab, n2):
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert rp[0] == 0 and rp.size == n2 + 1
+    loops = sum(int(g.w[j]) for v in range(g.n) for j in range(g.row_ptr[v], g.row_ptr[v + 1])
+                if lab[v] == lab[g.col[j]])
+    assert int(w.sum()) == int(g.w.sum()) - loops
+    for x in range(n2):
+        row = col[rp[x]:rp[x + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert np.all(row != x)
+        # the collapsed degree is the capacity of the group's cut
+        side = (lab == x).astype(np.uint8)
+        assert int(w[rp[x]:rp[x + 1]].sum()) == oracle.cut_value(g, side)
+    # entry (x,y) is the total weight between the two groups
+    for x in range(n2):
+        for j in range(rp[x], rp[x + 1]):
+            y = col[j]
+            mask = (lab[:, None] == x) & (lab[None, :] == y)
+            dense = np.zeros((g.n, g.n), np.int64)
+            for v in range(g.n):
+                for k in range(g.row_ptr[v], g.row_ptr[v + 1]):
+                    dense[v, g.col[k]] += g.w[k]
+            assert int(dense[mask].sum()) == int(w[j])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_contraction_invariants(seed):
+    g = gen.random_small(12, 0.5, 300 + seed, 1, 9)
+    r = gen.SplitMix64(seed)
+    n2 = 1 + r.below(g.n)
+    lab = np.array([r.below(n2) for _ in range(g.n)], np.int32)
+    lab[:n2] = np.arange(n2)  # every label used
+    _check_contraction(g, lab, n2)
+
+
+def test_identity_contraction_is_canonical_folding():
+    r = gen.SplitMix64(5)
+    u = [r.below(30) for _ in range(400)]
+    v = [r.below(30) for _ in range(400)]
+    w = [r.below(7) for _ in range(400)]
+    raw = gen.raw_csr(30, u, v, w)
+    rp, col, ww = oracle.contract(raw, np.arange(30, dtype=np.int32), 30)
+    ref = gen.from_edges(30, u, v, w)
+    keep = ref.w != 0
+    src = np.repeat(np.arange(30), np.diff(ref.row_ptr))[keep]
+    assert np.array_equal(np.repeat(np.arange(30), np.diff(rp)), src)
+    assert np.array_equal(col, ref.col[keep])
+    assert np.array_equal(ww, ref.w[keep])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_components_match_scipy(seed):
+    r = gen.SplitMix64(seed)
+    n = 50 + seed
+    k = r.below(60)
+    a = np.array([r.below(n) for _ in range(k)], np.int32)
+    b = np.array([r.below(n) for _ in range(k)], np.int32)
+    lab, nc = oracle.components(n, a, b)
+    m = sp.coo_matrix((np.ones(k), (a, b)), shape=(n, n))
+    nc_ref, lab_ref = connected_components(m, directed=False)
+    assert nc == nc_ref
+    # same partition
+    assert len(set(zip(lab.tolist(), lab_ref.tolist()))) == nc
+    # canonical numbering: first occurrences appear as 0, 1, 2, ...
+    first = [lab[v] for v in range(n) if lab[v] not in lab[:v]]
+    assert first == list(range(nc))
+
+
+def test_pr12_definitions():
+    g = gen.from_edges(5, [0, 0, 1, 2, 3], [1, 2, 2, 3, 4], [6, 1, 2, 7, 7])
+    flag, ptr = oracle.pr12(g, 7)
+    heavy = [(u, int(c)) for u in range(5) for c, ww in
+             zip(g.col[g.row_ptr[u]:g.row_ptr[u + 1]], g.w[g.row_ptr[u]:g.row_ptr[u + 1]]) if ww >= 7]
+    got = [(u, int(g.col[j])) for u in range(5) for j in range(g.row_ptr[u], g.row_ptr[u + 1]) if flag[j]]
+    assert got == heavy
+    # degrees 7, 8, 10, 14, 7; heaviest neighbours 1 (6), 0 (6), 3 (7),
+    # 2 and 4 tied at 7 (smaller id wins), 3 (7); all pass 2c >= deg
+    assert list(ptr) == [1, 0, 3, 2, 3]
+    flag, ptr = oracle.pr12(gen.from_edges(4, [0, 1, 1], [1, 2, 3], [3, 4, 2]), 100)
+    # degrees 3, 9, 4, 2: vertex 1's heaviest edge (4) is less than half of 9
+    assert list(ptr) == [1, -1, 1, 1] and not flag.any()
+
+
+def _contract_marks(g, pairs):
+    a = np.array([p[0] for p in pairs], np.int32)
+    b = np.array([p[1] for p in pairs], np.int32)
+    lab, nc = oracle.components(g.n, a, b)
+    rp, col, w = oracle.contract(g, lab, nc)
+    return gen.Graph(nc, rp, col, w), nc
+
+
+def test_pr2_counterexample_single_pointer():
+    # two 5-cliques of weight 10 and a vertex joined to one vertex of each by
+    # weight 3: both edges pass the exchange test, only one may be applied
+    X = list(range(5))
+    Y = list(range(5, 10))
+    a = 10
+    u, v, w = [], [], []
+    for S in (X, Y):
+        for i in S:
+            for j in S:
+                if i < j:
+                    u.append(i); v.append(j); w.append(10)
+    u += [a, a]; v += [0, 5]; w += [3, 3]
+    g = gen.from_edges(11, u, v, w)
+    lam = oracle.brute(g)[0]
+    assert lam == 3
+    lam_hat = int(oracle.degrees(g).min())
+    assert lam_hat == 6
+    flag, ptr = oracle.pr12(g, lam_hat)
+    assert ptr[a] == 0
+    pairs = [(x, int(g.col[j])) for x in range(g.n) for j in range(g.row_ptr[x], g.row_ptr[x + 1]) if flag[j]]
+    pairs += [(x, int(ptr[x])) for x in range(g.n) if ptr[x] >= 0]
+    h, nc = _contract_marks(g, pairs)
+    assert nc == 2 and oracle.brute(h)[0] == 3
+    # applying both exchange edges at once would lose the cut
+    h2, nc2 = _contract_marks(g, pairs + [(a, 5)])
+    assert nc2 == 1
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_pr12_safe_contraction(seed):
+    # contracting every test-1 edge and every test-2 pointer keeps lambda
+    # whenever the bound is above it
+    g = gen.random_small(6 + seed % 8, 0.6, 5000 + seed, 1, 12)
+    lam = oracle.brute(g)[0]
+    lam_hat = int(oracle.degrees(g).min())
+    if lam_hat <= lam:
+        return
+    flag, ptr = oracle.pr12(g, lam_hat)
+    pairs = [(x, int(g.col[j])) for x in range(g.n) for j in range(g.row_ptr[x], g.row_ptr[x + 1]) if flag[j]]
+    pairs += [(x, int(ptr[x])) for x in range(g.n) if ptr[x] >= 0]
+    h, nc = _contract_marks(g, pairs)
+    assert nc >= 2
+    assert oracle.brute(h)[0] == lam
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_lp_round_rule(seed):
+    g = gen.random_small(25, 0.3, 800 + seed, 1, 5)
+    r = gen.SplitMix64(seed)
+    lab = np.array([r.below(6) for _ in range(g.n)], np.int32)
+    out = oracle.lp_round(g, lab)
+    for v in range(g.n):
+        tot = {}
+        for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            tot[int(lab[g.col[j]])] = tot.get(int(lab[g.col[j]]), 0) + int(g.w[j])
+        own = tot.get(int(lab[v]), 0)
+        chosen = int(out[v])
+        if chosen == lab[v]:
+            assert all(t <= own for l, t in tot.items() if l != lab[v])
+        else:
+            assert tot[chosen] > own
+            assert tot[chosen] == max(tot.values())
+            assert chosen == min(l for l, t in tot.items() if t == tot[chosen] and l != lab[v])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_capforest_marks_are_safe(seed):
+    # every pair joined by marks has connectivity >= the final bound, and the
+    # recorded alpha is the capacity of the recorded prefix
+    g = gen.random_small(5 + seed % 8, 0.6, 6000 + seed, 1, 9)
+    if connected_components(sp.csr_matrix((g.w, g.col, g.row_ptr), shape=(g.n, g.n)))[0] > 1:
+        return
+    lam0 = int(oracle.degrees(g).min())
+    res = oracle.capforest_pass(g, lam0, seed % g.n)
+    assert res["order"].size == g.n
+    lab = res["labels"]
+    for x in range(g.n):
+        for y in range(x + 1, g.n):
+            if lab[x] == lab[y]:
+                assert oracle.brute_st(g, x, y) >= res["lam"]
+    if res["best_len"] > 0:
+        side = np.zeros(g.n, np.uint8)
+        side[res["order"][:res["best_len"]]] = 1
+        assert oracle.cut_value(g, side) == res["best_alpha"]
+        assert res["lam"] == min(lam0, res["best_alpha"])
+    if res["lam"] == lam0:
+        assert res["marks"] >= 1  # a full pass with a fixed bound marks an edge
+
+
+def test_capforest_truncated_pass():
+    g = gen.complete(8, weight=2)
+    res = oracle.capforest_pass(g, 14, 3, max_scan=3)
+    assert list(res["order"]) == [3, 0, 1]
+    # after two scans every vertex has r = 4; at the third scan r = 6, below 14
+    assert res["marks"] == 0
