@@ -1,0 +1,127 @@
+/*
+ * mincut.h -- exact global minimum cut on one AMD MI355X (gfx950).
+ *
+ * Problem (paper, Section 2 "Basic Concepts"): G = (V, E, c) undirected with
+ * non-negative integer edge weights. A cut (A, V\A) has two non-empty sides;
+ * its capacity is the total weight of the edges between them. The solver
+ * returns lambda, the smallest capacity, and one side A of a cut attaining
+ * it. The method is the exact algorithm summarised in Section 2.1 and
+ * Algorithm 2 (bound from a label-propagation heuristic, reduction tests
+ * that depend on the bound, parallel CAPFOREST of Algorithm 1, parallel
+ * contraction, collapsed degrees as bounds), run as hand-written HIP
+ * kernels. All arithmetic is 64-bit integer; results are exact.
+ *
+ * Conventions shared by every call:
+ *  - A graph is a symmetric CSR: row_ptr[n+1] (int32, row_ptr[0] = 0,
+ *    non-decreasing, row_ptr[n] = nnz), col[nnz] (int32, 0 <= col < n) and
+ *    w[nnz] (int64, w >= 0). Every undirected edge {u,v} with u != v is
+ *    listed in row u and in row v with the same weight. Loops (col[j] = row)
+ *    are allowed and ignored; parallel entries are allowed and summed.
+ *    Rows need not be sorted.
+ *  - `location` says where the three arrays live: MC_HOST (pageable or
+ *    pinned host memory) or MC_DEVICE (device memory of the context's GPU).
+ *  - The caller owns every buffer it passes. The library keeps no caller
+ *    pointer after a call returns (the server copies what it is given).
+ *  - Every call returns an mc_status; on error the outputs are left
+ *    untouched and mc_last_error() describes the failure (thread-local).
+ *  - The sum of all weights over all nnz entries must be below 2^62 so that
+ *    every degree, cut and doubled sum fits in int64 (MC_E_OVERFLOW).
+ */
+#ifndef MINCUT_H
+#define MINCUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC_OK = 0,
+    MC_E_INVALID_ARG = -1, /* null pointer, n < 2, bad option value, small workspace */
+    MC_E_BAD_GRAPH = -2,   /* row_ptr not monotone, col out of range, negative w,
+                              or (with validate) an asymmetric edge list */
+    MC_E_OVERFLOW = -3,    /* total weight >= 2^62, or nnz >= 2^31 */
+    MC_E_OOM = -4,         /* host allocation failed, or a server request does
+                              not fit its HBM budget */
+    MC_E_DEVICE = -5,      /* a HIP call failed */
+    MC_E_NOT_READY = -6,   /* server ticket still running */
+    MC_E_CANCELLED = -7,   /* server ticket was cancelled */
+    MC_E_TIMEOUT = -8
+} mc_status;
+
+enum { MC_HOST = 0, MC_DEVICE = 1 };
+
+typedef struct {
+    int32_t n;             /* vertices, >= 2 */
+    int32_t nnz;           /* entries = row_ptr[n] */
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const int64_t* w;
+    int32_t location;      /* MC_HOST or MC_DEVICE */
+} mc_csr;
+
+typedef struct {
+    uint64_t seed;            /* start vertices of CAPFOREST passes */
+    int32_t heuristic_min_n;  /* run the label-propagation bound only when
+                                 n >= this (Section 4, session 2 item 2;
+                                 default 10000; <= 0 disables it) */
+    int32_t lp_iters;         /* label-propagation rounds per coarsening level
+                                 (default 2) */
+    int32_t pr_tri_deg_cap;   /* reserved (triangle tests); 0 = off */
+    int32_t capforest_passes; /* concurrent CAPFOREST passes per round (0 =
+                                 automatic, 4 per compute unit) */
+    int32_t pass_len_cap;     /* scans per pass (0 = until its queue empties) */
+    int32_t deterministic;    /* 1: passes do not share the visited array,
+                                 so results do not depend on timing */
+    int32_t validate;         /* 1: check symmetry of host inputs */
+} mc_options;
+
+typedef struct {
+    int32_t rounds;              /* exact-phase rounds */
+    int32_t heuristic_levels;    /* coarsening levels of the bound heuristic */
+    int64_t lambda_min_degree;   /* bound from the minimum degree */
+    int64_t lambda_heuristic;    /* bound after the heuristic (-1: not run) */
+    int64_t marks_pr;            /* edges unioned by the reduction tests */
+    int64_t marks_capforest;     /* edges unioned by CAPFOREST */
+    int32_t fallback_passes;     /* sequential CAPFOREST runs (Algorithm 2) */
+    int32_t n_input;             /* vertices after normalisation */
+    int64_t m_input;             /* undirected edges after normalisation */
+    double ms_total;             /* wall time of the call */
+} mc_stats;
+
+typedef struct mc_ctx mc_ctx;
+
+/* Default options (seed 1, heuristic at n >= 10000, 2 LP rounds, automatic
+ * pass count, no length cap, shared visited array, no validation). */
+void mc_default_options(mc_options* opt);
+
+/* Create a context on HIP device `device` issuing all work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). `opt` may be NULL. The
+ * context holds pinned host scratch of a few KB; device memory always comes
+ * from the caller's workspace. */
+mc_status mc_ctx_create(int device, void* hip_stream, const mc_options* opt, mc_ctx** out);
+mc_status mc_ctx_destroy(mc_ctx* ctx);
+mc_status mc_ctx_set_options(mc_ctx* ctx, const mc_options* opt);
+
+/* Device workspace bytes that mc_mincut needs for a graph with n vertices
+ * and nnz entries. */
+mc_status mc_workspace_size(const mc_ctx* ctx, int32_t n, int32_t nnz, size_t* bytes);
+
+/* Solve one graph (Algorithm 2). `dev_workspace` is device memory of at
+ * least mc_workspace_size bytes, 256-byte aligned. On success *lambda is the
+ * minimum cut and, if side != NULL, side[v] in {0,1} (host memory, n bytes)
+ * marks one side of a minimum cut, with side[0] = 0; when lambda = 0 (the
+ * graph is disconnected) side[v] = 1 exactly for the vertices outside the
+ * component of vertex 0. `st` may be NULL. Synchronises the stream. */
+mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws_bytes,
+                    int64_t* lambda, uint8_t* side, mc_stats* st);
+
+/* Thread-local description of the last error (never NULL). */
+const char* mc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MINCUT_H */

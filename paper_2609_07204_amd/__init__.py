@@ -1,0 +1,296 @@
+"""Python binding of the MI355X exact minimum-cut library (libmincut.so).
+
+Argument marshalling only: graphs are handed to the C ABI of
+include/mincut.h and include/mincut_steps.h as raw pointers; PyTorch supplies
+device memory (workspaces, device copies of inputs) and the HIP stream. Every
+step of the computation runs in the library's HIP kernels. If the library is
+missing, importing the binding's entry points raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmincut.so")
+
+MC_HOST, MC_DEVICE = 0, 1
+STATUS = {0: "MC_OK", -1: "MC_E_INVALID_ARG", -2: "MC_E_BAD_GRAPH", -3: "MC_E_OVERFLOW", -4: "MC_E_OOM",
+          -5: "MC_E_DEVICE", -6: "MC_E_NOT_READY", -7: "MC_E_CANCELLED", -8: "MC_E_TIMEOUT"}
+INT64_MAX = (1 << 63) - 1
+
+
+class MincutError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("location", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("heuristic_min_n", ctypes.c_int32), ("lp_iters", ctypes.c_int32),
+                ("pr_tri_deg_cap", ctypes.c_int32), ("capforest_passes", ctypes.c_int32),
+                ("pass_len_cap", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("heuristic_levels", ctypes.c_int32),
+                ("lambda_min_degree", ctypes.c_int64), ("lambda_heuristic", ctypes.c_int64),
+                ("marks_pr", ctypes.c_int64), ("marks_capforest", ctypes.c_int64),
+                ("fallback_passes", ctypes.c_int32), ("n_input", ctypes.c_int32), ("m_input", ctypes.c_int64),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DGraphC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("cap", ctypes.c_int64), ("off", ctypes.c_void_p), ("len", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("deg", ctypes.c_void_p)]
+
+
+# name -> (restype, argtypes) for every symbol the headers declare
+P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = {
+    "mc_default_options": (None, [P]),
+    "mc_ctx_create": (ctypes.c_int, [ctypes.c_int, P, P, P]),
+    "mc_ctx_destroy": (ctypes.c_int, [P]),
+    "mc_ctx_set_options": (ctypes.c_int, [P, P]),
+    "mc_workspace_size": (ctypes.c_int, [P, I32, I32, P]),
+    "mc_mincut": (ctypes.c_int, [P, P, P, SZ, P, P, P]),
+    "mc_last_error": (ctypes.c_char_p, []),
+    "mc_step_ws_size": (ctypes.c_int, [I32, I64, I32, P]),
+    "mc_step_contract": (ctypes.c_int, [P, P, P, I32, P, P, SZ, P, P]),
+    "mc_step_components": (ctypes.c_int, [P, I32, I64, P, P, P, P, P, SZ]),
+    "mc_step_pr12": (ctypes.c_int, [P, P, I64, P, P, P, P, P, SZ]),
+    "mc_step_capforest": (ctypes.c_int, [P, P, I64, I32, I32, I32, I32, I32, P, P, P, P, P, P, P, P, SZ]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmincut.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmincut.so is not built: run __graft_entry__.build() "
+                              "or python paper_2609_07204_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MincutError(rc, lib().mc_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def default_options(**kw):
+    o = Options()
+    lib().mc_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A library context bound to one GPU and the current torch stream."""
+
+    def __init__(self, device=0, stream=None, **options):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.options = default_options(**options)
+        h = ctypes.c_void_p()
+        _check(lib().mc_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self.options),
+                                   ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.options, k, v)
+        _check(lib().mc_ctx_set_options(self.h, ctypes.byref(self.options)))
+
+    # ------------------------------------------------------------ solve
+    def workspace_bytes(self, n, nnz):
+        b = ctypes.c_size_t()
+        _check(lib().mc_workspace_size(self.h, n, nnz, ctypes.byref(b)))
+        return b.value
+
+    def upload(self, g):
+        """Device copies (row_ptr, col, w) of a host graph."""
+        torch = _torch()
+        return (torch.as_tensor(np.ascontiguousarray(g.row_ptr, np.int32)).to(self.device),
+                torch.as_tensor(np.ascontiguousarray(g.col, np.int32)).to(self.device),
+                torch.as_tensor(np.ascontiguousarray(g.w, np.int64)).to(self.device))
+
+    def mincut(self, g=None, dev=None, n=None, workspace=None, want_side=True, return_stats=False):
+        """Minimum cut of a graph given either as a host graph `g` (fields
+        n, row_ptr, col, w as numpy arrays) or as device tensors
+        dev = (row_ptr, col, w) with n vertices. Returns (lambda, side) and,
+        with return_stats, the mc_stats record as a dict."""
+        torch = _torch()
+        if dev is not None:
+            rp, col, w = dev
+            n = int(rp.numel() - 1)
+            nnz = int(col.numel())
+            csr = CSR(n, nnz, rp.data_ptr(), col.data_ptr() if nnz else 0, w.data_ptr() if nnz else 0, MC_DEVICE)
+            keep = (rp, col, w)
+        else:
+            rp = np.ascontiguousarray(g.row_ptr, np.int32)
+            col = np.ascontiguousarray(g.col, np.int32)
+            w = np.ascontiguousarray(g.w, np.int64)
+            n, nnz = int(g.n), int(rp[-1])
+            csr = CSR(n, nnz, rp.ctypes.data, col.ctypes.data if nnz else 0, w.ctypes.data if nnz else 0, MC_HOST)
+            keep = (rp, col, w)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(n, nnz), dtype=torch.uint8, device=self.device)
+        lam = ctypes.c_int64()
+        side = np.zeros(n, np.uint8) if want_side else None
+        st = Stats()
+        _check(lib().mc_mincut(self.h, ctypes.byref(csr), ctypes.c_void_p(workspace.data_ptr()),
+                               workspace.numel(), ctypes.byref(lam),
+                               side.ctypes.data if want_side else None, ctypes.byref(st)))
+        del keep
+        if return_stats:
+            return lam.value, side, st.as_dict()
+        return lam.value, side
+
+    # ------------------------------------------------------------ steps
+    def step_workspace(self, n, cap, passes=1):
+        b = ctypes.c_size_t()
+        _check(lib().mc_step_ws_size(n, cap, passes, ctypes.byref(b)))
+        return _torch().empty(b.value, dtype=_torch().uint8, device=self.device)
+
+    def dgraph(self, g):
+        """Padded-CSR device graph of a host CSR (off = row_ptr, len = row
+        lengths); degrees are filled by step_contract."""
+        torch = _torch()
+        rp = np.ascontiguousarray(g.row_ptr, np.int64)
+        d = DeviceGraph(int(g.n), max(int(rp[-1]), 1), self.device)
+        d.off.copy_(torch.as_tensor(rp[:-1].astype(np.int32)))
+        d.len.copy_(torch.as_tensor(np.diff(rp).astype(np.int32)))
+        if rp[-1] > 0:
+            d.col[:rp[-1]].copy_(torch.as_tensor(np.ascontiguousarray(g.col, np.int32)))
+            d.w[:rp[-1]].copy_(torch.as_tensor(np.ascontiguousarray(g.w, np.int64)))
+        return d
+
+    def step_contract(self, src, labels=None, n2=None):
+        n2 = src.n if labels is None else int(n2)
+        dst = DeviceGraph(n2, src.cap, self.device)
+        ws = self.step_workspace(src.n, src.cap)
+        dmin, darg = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().mc_step_contract(self.h, ctypes.byref(src.c()), _ptr(labels), n2, ctypes.byref(dst.c()),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(dmin),
+                                      ctypes.byref(darg)))
+        return dst, dmin.value, darg.value
+
+    def step_components(self, n, a, b):
+        torch = _torch()
+        a = torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(self.device)
+        b = torch.as_tensor(np.ascontiguousarray(b, np.int32)).to(self.device)
+        lab = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        n2 = ctypes.c_int32()
+        ws = self.step_workspace(n, 1)
+        _check(lib().mc_step_components(self.h, n, a.numel(), _ptr(a), _ptr(b), _ptr(lab), ctypes.byref(n2),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return lab[:n].cpu().numpy(), n2.value
+
+    def step_pr12(self, g, lam):
+        torch = _torch()
+        flag = torch.zeros(g.cap, dtype=torch.uint8, device=self.device)
+        ptr = torch.empty(g.n, dtype=torch.int32, device=self.device)
+        lab = torch.empty(g.n, dtype=torch.int32, device=self.device)
+        n2 = ctypes.c_int32()
+        ws = self.step_workspace(g.n, g.cap)
+        _check(lib().mc_step_pr12(self.h, ctypes.byref(g.c()), lam, _ptr(flag), _ptr(ptr), _ptr(lab),
+                                  ctypes.byref(n2), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return flag, ptr.cpu().numpy(), lab.cpu().numpy(), n2.value
+
+    def step_capforest(self, g, lam, start=0, complete=True, passes=1, shared=False, len_cap=0):
+        torch = _torch()
+        lab = torch.empty(g.n, dtype=torch.int32, device=self.device)
+        order = torch.full((max(g.n, 4096),), -1, dtype=torch.int32, device=self.device)
+        n2, ns, bl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ba, lo = ctypes.c_int64(), ctypes.c_int64()
+        ws = self.step_workspace(g.n, g.cap, passes)
+        _check(lib().mc_step_capforest(self.h, ctypes.byref(g.c()), lam, start, int(complete), passes, int(shared),
+                                       len_cap, _ptr(lab), ctypes.byref(n2), _ptr(order), ctypes.byref(ns),
+                                       ctypes.byref(ba), ctypes.byref(bl), ctypes.byref(lo),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return {"labels": lab.cpu().numpy(), "n2": n2.value, "order": order[:ns.value].cpu().numpy(),
+                "best_alpha": ba.value, "best_len": bl.value, "lam": lo.value}
+
+
+class DeviceGraph:
+    """Padded CSR in device memory (see mc_dgraph in include/mincut_steps.h)."""
+
+    def __init__(self, n, cap, device):
+        torch = _torch()
+        self.n, self.cap = int(n), int(cap)
+        self.off = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.len = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.deg = torch.zeros(max(self.n, 1), dtype=torch.int64, device=device)
+        self.col = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=device)
+        self.w = torch.zeros(max(self.cap, 1), dtype=torch.int64, device=device)
+
+    def c(self):
+        return DGraphC(self.n, self.cap, self.off.data_ptr(), self.len.data_ptr(), self.col.data_ptr(),
+                       self.w.data_ptr(), self.deg.data_ptr())
+
+    def to_canonical(self):
+        """Host (row_ptr, col, w, deg) with every row sorted by target."""
+        off = self.off[:self.n].cpu().numpy().astype(np.int64)
+        ln = self.len[:self.n].cpu().numpy().astype(np.int64)
+        col = self.col.cpu().numpy()
+        w = self.w.cpu().numpy()
+        rp = np.zeros(self.n + 1, np.int64)
+        rp[1:] = np.cumsum(ln)
+        rows = np.repeat(np.arange(self.n, dtype=np.int64), ln)
+        pos = np.repeat(off - rp[:-1], ln) + np.arange(int(rp[-1]), dtype=np.int64)
+        c, ww = col[pos], w[pos]
+        o = np.lexsort((c, rows))
+        oc, ow = c[o].astype(np.int32), ww[o].astype(np.int64)
+        return rp.astype(np.int32), oc, ow, self.deg[:self.n].cpu().numpy()
+
+
+_default_ctx = None
+
+
+def mincut(g, **kw):
+    """lambda and one side of a minimum cut of host graph g, on cuda:0."""
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return _default_ctx.mincut(g, **kw)

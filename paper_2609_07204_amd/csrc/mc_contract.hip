@@ -1,0 +1,369 @@
+// Graph contraction (paper, Section 2 "Basic Concepts" and Section 2.1
+// "Parallel CAPFOREST and contraction"; Algorithm 2, contraction step).
+//
+// Given labels L: V -> [0, n2), vertex g of the result stands for the group
+// {v : L[v] = g}; every entry v->x becomes g->L[x], loops (L[v] = L[x]) and
+// zero weights vanish, entries between the same pair of groups add up. The
+// degree of a collapsed vertex (the sum of its new row) is written at the
+// same time; it is the capacity of the cut around the group.
+//
+// The merge is organised by contracted vertex, as the paper's accepted
+// change 3 of the parallel session suggests, but in a GPU form:
+//  1. counting sort of the vertices by label (atomics + scan): the members
+//     of group g are perm[vstart[g] .. vstart[g+1]);
+//  2. a scan of the member row lengths gives every group a private output
+//     window [gstart[g], gstart[g+1]) as large as all rows it absorbs, so
+//     new rows are written in place without a global offset pass (the
+//     result is a padded CSR with off/len per row);
+//  3. small groups (<= 512 entries) are packed into chunks of <= 1023
+//     entries; one workgroup merges a chunk in an LDS hash table keyed by
+//     (group, target) with 64-bit LDS atomics, then writes the rows;
+//  4. large groups (hubs, big clusters) get a global hash table of about
+//     2x their entries; one wavefront per member row inserts with global
+//     CAS/atomic add, and 256-slot tiles are extracted in parallel.
+// Streaming traffic per entry: 12 B read (col, w) + 4 B label gather +
+// 12 B written per surviving entry.
+#include "mc_internal.h"
+
+namespace {
+
+constexpr int CHUNK = 512;          // chunk span in (entry offset + group index)
+constexpr int SMALL_MAX = 512;      // larger groups take the global-table path
+constexpr int HSLOTS = 2048;        // LDS hash slots per chunk (load <= 1/2)
+constexpr int TILE_SLOTS = 256;     // global-table allocation and extraction unit
+constexpr uint64_t EMPTY_KEY = ~0ULL;
+
+__global__ void k_group_count(const int32_t* __restrict__ L, int32_t n, int32_t* __restrict__ gcnt) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&gcnt[L[u]], 1);
+}
+
+__global__ void k_group_scatter(const int32_t* __restrict__ L, int32_t n, const int32_t* __restrict__ vstart,
+                                int32_t* __restrict__ gcur, int32_t* __restrict__ perm) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        int32_t g = L[u];
+        perm[vstart[g] + atomicAdd(&gcur[g], 1)] = (int32_t)u;
+    }
+}
+
+__global__ void k_member_len(const int32_t* __restrict__ len, const int32_t* __restrict__ perm, int32_t n,
+                             int32_t* __restrict__ mlen) {
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x)
+        mlen[m] = len[perm ? perm[m] : m];
+}
+
+__global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t* __restrict__ mstart, int32_t n2,
+                              int32_t* __restrict__ gstart) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= n2; g += (int64_t)gridDim.x * blockDim.x)
+        gstart[g] = mstart[vstart[g]];
+}
+
+// Split groups into the chunk path and the global-table path; every group
+// gets its output window start.
+__global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
+                           int32_t* __restrict__ tsize, int32_t* __restrict__ bigm, int32_t* __restrict__ bcur,
+                           DGraph dst) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = gstart[g + 1] - gstart[g];
+        dst.off[g] = gstart[g];
+        if (s > SMALL_MAX) {
+            int64_t t = ((2 * (int64_t)s + TILE_SLOTS - 1) / TILE_SLOTS) * TILE_SLOTS;
+            tsize[g] = (int32_t)t;
+            bigm[g] = vstart ? vstart[g + 1] - vstart[g] : 1;
+            bcur[g] = 0;
+            dst.len[g] = 0;
+            dst.deg[g] = 0;
+        } else {
+            tsize[g] = 0;
+            bigm[g] = 0;
+        }
+    }
+}
+
+// last index g in [0, n) with a[g] <= key (a non-decreasing, a[0] <= key)
+__device__ __forceinline__ int32_t last_le(const int32_t* __restrict__ a, int32_t n, int64_t key) {
+    int32_t lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)a[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// first g in [0, n2] with gstart[g] + g >= key
+__device__ __forceinline__ int32_t first_key_ge(const int32_t* __restrict__ gstart, int32_t n2, int64_t key) {
+    int32_t lo = 0, hi = n2 + 1;
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)gstart[mid] + mid >= key) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+constexpr int MERGE_THREADS = 256;
+constexpr int SUB = 16;                              // lanes per group
+constexpr int NSUB = MERGE_THREADS / SUB;
+
+__global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const int32_t* __restrict__ L,
+                                                              const int32_t* __restrict__ perm,
+                                                              const int32_t* __restrict__ vstart,
+                                                              const int32_t* __restrict__ gstart, int32_t n2,
+                                                              DGraph dst) {
+    __shared__ unsigned long long hkey[HSLOTS];
+    __shared__ long long hval[HSLOTS];
+    __shared__ int32_t gst[CHUNK + 1];
+    __shared__ int32_t gvs[CHUNK + 1];
+    __shared__ int32_t gcur[CHUNK];
+    __shared__ long long gdeg[CHUNK];
+    __shared__ int32_t range[2];
+
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int64_t k0 = (int64_t)blockIdx.x * CHUNK;
+        range[0] = first_key_ge(gstart, n2, k0);
+        range[1] = first_key_ge(gstart, n2, k0 + CHUNK);
+        if (range[1] > n2) range[1] = n2;
+    }
+    __syncthreads();
+    const int32_t g_lo = range[0], g_hi = range[1];
+    if (g_lo >= n2 || g_lo >= g_hi) return;
+    const int32_t ng = g_hi - g_lo;
+    for (int i = tid; i < HSLOTS; i += MERGE_THREADS) { hkey[i] = EMPTY_KEY; hval[i] = 0; }
+    for (int i = tid; i <= ng; i += MERGE_THREADS) {
+        gst[i] = gstart[g_lo + i];
+        gvs[i] = vstart ? vstart[g_lo + i] : g_lo + i;
+    }
+    for (int i = tid; i < ng; i += MERGE_THREADS) { gcur[i] = 0; gdeg[i] = 0; }
+    __syncthreads();
+
+    const int sg = tid / SUB, sl = tid % SUB;
+    for (int gl = sg; gl < ng; gl += NSUB) {
+        if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
+        const int32_t g = g_lo + gl;
+        for (int32_t m = gvs[gl]; m < gvs[gl + 1]; m++) {
+            const int32_t u = perm ? perm[m] : m;
+            const int32_t o = src.off[u], l = src.len[u];
+            for (int32_t j = sl; j < l; j += SUB) {
+                const int32_t x = src.col[o + j];
+                const int64_t c = src.w[o + j];
+                if (c <= 0) continue;
+                const int32_t t = L ? L[x] : x;
+                if (t == g) continue;
+                const unsigned long long key = ((unsigned long long)gl << 32) | (uint32_t)t;
+                uint32_t h = hash32((uint32_t)t ^ ((uint32_t)gl * 0x9E3779B1u)) & (HSLOTS - 1);
+                for (;;) {
+                    unsigned long long k = hkey[h];
+                    if (k == key) break;
+                    if (k == EMPTY_KEY) {
+                        unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
+                        if (old == EMPTY_KEY || old == key) break;
+                    }
+                    h = (h + 1) & (HSLOTS - 1);
+                }
+                atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < HSLOTS; i += MERGE_THREADS) {
+        unsigned long long k = hkey[i];
+        if (k == EMPTY_KEY) continue;
+        const int gl = (int)(k >> 32);
+        const int32_t t = (int32_t)(k & 0xFFFFFFFFu);
+        const int64_t s = hval[i];
+        const int32_t pos = atomicAdd(&gcur[gl], 1);
+        dst.col[gst[gl] + pos] = t;
+        dst.w[gst[gl] + pos] = s;
+        atomicAdd((unsigned long long*)&gdeg[gl], (unsigned long long)s);
+    }
+    __syncthreads();
+    for (int gl = tid; gl < ng; gl += MERGE_THREADS) {
+        if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
+        dst.len[g_lo + gl] = gcur[gl];
+        dst.deg[g_lo + gl] = gdeg[gl];
+    }
+}
+
+__global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __restrict__ tkey,
+                            int64_t* __restrict__ tval) {
+    const int64_t total = *total_p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        tkey[i] = -1;
+        tval[i] = 0;
+    }
+}
+
+// One wavefront per member row of a large group.
+__global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* __restrict__ L,
+                                                   const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ vstart,
+                                                   const int32_t* __restrict__ bmbase,
+                                                   const int32_t* __restrict__ tbase, int32_t n2,
+                                                   int32_t* __restrict__ tkey, int64_t* __restrict__ tval,
+                                                   DGraph dst) {
+    const int64_t total = bmbase[n2];
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / MC_WAVE);
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE; i < total; i += nwaves) {
+        const int32_t g = last_le(bmbase, n2, i);
+        const int32_t m = (vstart ? vstart[g] : g) + (int32_t)(i - bmbase[g]);
+        const int32_t u = perm ? perm[m] : m;
+        const int32_t o = src.off[u], l = src.len[u];
+        const int32_t tb = tbase[g];
+        const uint32_t ts = (uint32_t)(tbase[g + 1] - tb);
+        for (int32_t j = lane; j < l; j += MC_WAVE) {
+            const int32_t x = src.col[o + j];
+            const int64_t c = src.w[o + j];
+            if (c <= 0) continue;
+            const int32_t t = L ? L[x] : x;
+            if (t == g) continue;
+            uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)t) * ts) >> 32);
+            for (;;) {
+                int32_t k = ld_acq(&tkey[tb + h]);
+                if (k == t) break;
+                if (k == -1) {
+                    int32_t old = atomicCAS(&tkey[tb + h], -1, t);
+                    if (old == -1) { atomicAdd(&dst.len[g], 1); break; }
+                    if (old == t) break;
+                }
+                if (++h == ts) h = 0;
+            }
+            atomic_add_i64(&tval[tb + h], c);
+        }
+    }
+}
+
+__global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __restrict__ tbase,
+                                                            const int32_t* __restrict__ gstart, int32_t n2,
+                                                            const int32_t* __restrict__ tkey,
+                                                            const int64_t* __restrict__ tval,
+                                                            int32_t* __restrict__ bcur, DGraph dst) {
+    const int64_t ntiles = tbase[n2] / TILE_SLOTS;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * TILE_SLOTS;
+        const int32_t g = last_le(tbase, n2, base);
+        const int64_t k = base + threadIdx.x;
+        const int32_t key = tkey[k];
+        if (key < 0) continue;
+        const int64_t s = tval[k];
+        const int32_t pos = atomicAdd(&bcur[g], 1);
+        dst.col[gstart[g] + pos] = key;
+        dst.w[gstart[g] + pos] = s;
+        atomic_add_i64(&dst.deg[g], s);
+    }
+}
+
+// minimum degree, ties to the smallest vertex: per-block partials, then one
+// block folds them
+__global__ __launch_bounds__(256) void k_min_deg_blocks(const int64_t* __restrict__ deg, int32_t n,
+                                                       int64_t* __restrict__ rv, int32_t* __restrict__ ri) {
+    __shared__ int64_t sv[4];
+    __shared__ int32_t si[4];
+    int64_t best = 0;
+    int32_t bid = -1;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = deg[v];
+        if (bid < 0 || d < best) { best = d; bid = (int32_t)v; }
+    }
+    wave_argmin(best, bid);
+    if (lane_id() == 0) { sv[threadIdx.x / MC_WAVE] = best; si[threadIdx.x / MC_WAVE] = bid; }
+    __syncthreads();
+    if (threadIdx.x < MC_WAVE) {
+        int64_t b = threadIdx.x < 4 ? sv[threadIdx.x] : 0;
+        int32_t i = threadIdx.x < 4 ? si[threadIdx.x] : -1;
+        wave_argmin(b, i);
+        if (threadIdx.x == 0) { rv[blockIdx.x] = b; ri[blockIdx.x] = i; }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_min_deg_final(const int64_t* __restrict__ rv, const int32_t* __restrict__ ri,
+                                                     int nblocks, DevScalars* sc) {
+    int64_t best = 0;
+    int32_t bid = -1;
+    for (int i = threadIdx.x; i < nblocks; i += MC_WAVE) {
+        int32_t id = ri[i];
+        if (id >= 0 && (bid < 0 || rv[i] < best || (rv[i] == best && id < bid))) { best = rv[i]; bid = id; }
+    }
+    wave_argmin(best, bid);
+    if (threadIdx.x == 0) { sc->dmin = best; sc->dmin_arg = bid; }
+}
+
+inline int grid_for(int64_t count, int threads, int cap = 8192) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace
+
+void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
+    ws.gcnt = a.take<int32_t>((size_t)n + 2);
+    ws.vstart = ws.gcnt;
+    ws.gcur = a.take<int32_t>((size_t)n + 1);
+    ws.perm = a.take<int32_t>((size_t)n + 1);
+    ws.mstart = a.take<int32_t>((size_t)n + 2);
+    ws.gstart = a.take<int32_t>((size_t)n + 2);
+    ws.tsize = a.take<int32_t>((size_t)n + 2);
+    ws.bigm = a.take<int32_t>((size_t)n + 2);
+    ws.bcur = a.take<int32_t>((size_t)n + 1);
+    // large-group tables: sum over groups of round_up(2 s, 256) with s > 512
+    // is at most 2 cap + 256 cap / 513 < 2.5 cap
+    size_t slots = (size_t)(cap * 5 / 2) + 4 * TILE_SLOTS;
+    ws.tkey = a.take<int32_t>(slots);
+    ws.tval = a.take<int64_t>(slots);
+    ws.scan_tmp = a.take<int32_t>(scan_tmp_elems((int64_t)n + 2) + 16);
+    ws.red_val = a.take<int64_t>(1024);
+    ws.red_id = a.take<int32_t>(1024);
+}
+
+bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) {
+    int nb = grid_for(g.n, 256, 1024);
+    k_min_deg_blocks<<<nb, 256, 0, s>>>(g.deg, g.n, ws.red_val, ws.red_id);
+    MC_LAUNCHED("k_min_deg_blocks");
+    k_min_deg_final<<<1, 64, 0, s>>>(ws.red_val, ws.red_id, nb, sc);
+    MC_LAUNCHED("k_min_deg_final");
+    return true;
+}
+
+bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws, DevScalars* sc,
+              hipStream_t s) {
+    const int32_t n = src.n;
+    dst.n = n2;
+    const int32_t* perm = nullptr;
+    const int32_t* vstart = nullptr;
+    if (L) {
+        if (!fill_i32(ws.gcnt, 0, (int64_t)n2 + 1, s)) return false;
+        if (!fill_i32(ws.gcur, 0, n2, s)) return false;
+        k_group_count<<<grid_for(n, 256), 256, 0, s>>>(L, n, ws.gcnt);
+        MC_LAUNCHED("k_group_count");
+        if (!scan_i32(ws.gcnt, ws.vstart, n2, ws.scan_tmp, s)) return false;
+        k_group_scatter<<<grid_for(n, 256), 256, 0, s>>>(L, n, ws.vstart, ws.gcur, ws.perm);
+        MC_LAUNCHED("k_group_scatter");
+        perm = ws.perm;
+        vstart = ws.vstart;
+    }
+    k_member_len<<<grid_for(n, 256), 256, 0, s>>>(src.len, perm, n, ws.mstart);
+    MC_LAUNCHED("k_member_len");
+    if (!scan_i32(ws.mstart, ws.mstart, n, ws.scan_tmp, s)) return false;
+    const int32_t* gstart = ws.mstart;
+    if (L) {
+        k_group_start<<<grid_for((int64_t)n2 + 1, 256), 256, 0, s>>>(vstart, ws.mstart, n2, ws.gstart);
+        MC_LAUNCHED("k_group_start");
+        gstart = ws.gstart;
+    }
+    k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, ws.tsize, ws.bigm, ws.bcur, dst);
+    MC_LAUNCHED("k_classify");
+    if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
+    if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bmbase
+    const int64_t chunks = (src.cap + n2) / CHUNK + 2;
+    k_merge_small<<<(unsigned)chunks, MERGE_THREADS, 0, s>>>(src, L, perm, vstart, gstart, n2, dst);
+    MC_LAUNCHED("k_merge_small");
+    k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);
+    MC_LAUNCHED("k_big_clear");
+    k_big_insert<<<2048, 256, 0, s>>>(src, L, perm, vstart, ws.bigm, ws.tsize, n2, ws.tkey, ws.tval, dst);
+    MC_LAUNCHED("k_big_insert");
+    k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.tkey, ws.tval, ws.bcur, dst);
+    MC_LAUNCHED("k_big_extract");
+    return min_degree(dst, ws, sc, s);
+}

@@ -1,0 +1,247 @@
+// Union-find over contractible edges, canonical relabelling, the
+// Padberg-Rinaldi tests 1 and 2, side tracking and input checks.
+//
+// Contractible edges found in one round (reduction tests and CAPFOREST,
+// Algorithm 1's U.union) all land in one concurrent union-find; the round's
+// contraction uses its components. Roots are always the smallest vertex of
+// their component (see uf_union), so numbering roots in increasing order
+// gives labels that do not depend on the order of the unions.
+#include "mc_internal.h"
+
+namespace {
+
+inline int grid_for(int64_t count, int threads, int cap = 8192) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+constexpr int SUB = 16;  // lanes per row for row-wise kernels
+
+__global__ void k_uf_init(int32_t* par, int32_t n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        par[v] = (int32_t)v;
+}
+
+__global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        const int32_t o = g.off[v], l = g.len[v];
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = g.col[o + j];
+            if (x > v && g.w[o + j] > 0) uf_union(par, (int32_t)v, x);
+        }
+    }
+}
+
+// After all unions: point every vertex at its root. Each thread writes only
+// its own entry, so concurrent finds still see valid ancestors.
+__global__ void k_uf_compress(int32_t* par, int32_t n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t x = (int32_t)v, p = ld_acq(&par[x]);
+        while (p != x) { x = p; p = ld_acq(&par[x]); }
+        st_rel(&par[v], x);
+    }
+}
+
+__global__ void k_root_flag(const int32_t* par, int32_t n, int32_t* flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = par[v] == v;
+}
+
+__global__ void k_label(const int32_t* par, const int32_t* newid, int32_t n, int32_t* L, DevScalars* sc) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        L[v] = newid[par[v]];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->n2 = newid[n];
+}
+
+// Padberg-Rinaldi tests on the current graph with bound lam:
+//  test 1: an edge of weight >= lam joins two vertices whose connectivity is
+//          at least lam, so no cut below lam separates them;
+//  test 2: if 2 c(v,p) >= c(v) for v's heaviest neighbour p (smallest id on
+//          ties), moving v to p's side of any cut does not increase it; one
+//          such pointer per vertex may be contracted together with all
+//          connectivity-based marks of the round.
+__global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int32_t* par,
+                                             unsigned long long* marks, uint8_t* flag1, int32_t* ptr2) {
+    const int64_t lam = *lamp;
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    unsigned long long joined = 0;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        const int32_t o = g.off[v], l = g.len[v];
+        int64_t bw = -1;
+        int32_t bx = -1;
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = g.col[o + j];
+            const int64_t c = g.w[o + j];
+            const bool heavy = c >= lam;
+            if (flag1) flag1[o + j] = heavy;
+            if (heavy && x > v && uf_union(par, (int32_t)v, x)) joined++;
+            if (c > bw || (c == bw && x < bx)) { bw = c; bx = x; }
+        }
+        for (int k = SUB / 2; k > 0; k >>= 1) {
+            int64_t w2 = __shfl_xor(bw, k, SUB);
+            int32_t x2 = __shfl_xor(bx, k, SUB);
+            if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
+        }
+        const bool take = bx >= 0 && 2 * bw >= g.deg[v];
+        if (sl == 0) {
+            if (ptr2) ptr2[v] = take ? bx : -1;
+            if (take && uf_union(par, (int32_t)v, bx)) joined++;
+        }
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) atomicAdd(marks, joined);
+}
+
+__global__ void k_map_update(int32_t* map0, const int32_t* L, int32_t n0) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
+        map0[v] = L[map0[v]];
+}
+
+__global__ void k_side_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int32_t* target) {
+    const int32_t t = *target;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
+        side[v] = map0[v] == t;
+}
+
+__global__ void k_mark_prefix(uint8_t* flag, const int32_t* order, const int32_t* lenp) {
+    const int32_t len = *lenp;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += (int64_t)gridDim.x * blockDim.x)
+        flag[order[k]] = 1;
+}
+
+__global__ void k_side_flag(uint8_t* side, const int32_t* map0, int32_t n0, const uint8_t* flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
+        side[v] = flag[map0[v]];
+}
+
+__global__ void k_side_comp(uint8_t* side, const int32_t* par, int32_t n0) {
+    const int32_t r0 = par[0];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
+        side[v] = par[v] != r0;
+}
+
+__global__ void k_csr_to_padded(const int32_t* rp, int32_t n, int32_t* off, int32_t* len) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        off[v] = rp[v];
+        len[v] = rp[v + 1] - rp[v];
+    }
+}
+
+constexpr unsigned long long WCAP = 1ULL << 62;
+
+__device__ void set_err(DevScalars* sc, int32_t code) { atomicCAS(&sc->err, 0, code); }
+
+__global__ __launch_bounds__(256) void k_validate(const int32_t* rp, const int32_t* col, const int64_t* w, int32_t n,
+                                                 int32_t nnz, DevScalars* sc, unsigned long long* part) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0 && (rp[0] != 0 || rp[n] != nnz)) set_err(sc, MC_E_BAD_GRAPH);
+    for (int64_t v = tid; v < n; v += nth)
+        if (rp[v + 1] < rp[v]) set_err(sc, MC_E_BAD_GRAPH);
+    unsigned long long s = 0;
+    for (int64_t j = tid; j < nnz; j += nth) {
+        const int32_t x = col[j];
+        const int64_t c = w[j];
+        if (x < 0 || x >= n || c < 0) set_err(sc, MC_E_BAD_GRAPH);
+        if (c > 0) {
+            s += (unsigned long long)c;
+            if (s >= WCAP || (unsigned long long)c >= WCAP) s = WCAP;
+        }
+    }
+    __shared__ unsigned long long bs[256];
+    bs[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 256; k++) { t += bs[k]; if (t >= WCAP) t = WCAP; }
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_validate_sum(const unsigned long long* part, int nb, DevScalars* sc) {
+    unsigned long long t = 0;
+    for (int k = 0; k < nb; k++) { t += part[k]; if (t >= WCAP) t = WCAP; }
+    if (t >= WCAP) set_err(sc, MC_E_OVERFLOW);
+}
+
+}  // namespace
+
+bool uf_init(int32_t* parent, int32_t n, hipStream_t s) {
+    k_uf_init<<<grid_for(n, 256), 256, 0, s>>>(parent, n);
+    MC_LAUNCHED("k_uf_init");
+    return true;
+}
+
+bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
+    k_uf_all_edges<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent);
+    MC_LAUNCHED("k_uf_all_edges");
+    return true;
+}
+
+bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp, DevScalars* sc,
+               hipStream_t s) {
+    k_uf_compress<<<grid_for(n, 256), 256, 0, s>>>(parent, n);
+    MC_LAUNCHED("k_uf_compress");
+    k_root_flag<<<grid_for(n, 256), 256, 0, s>>>(parent, n, flag_tmp);
+    MC_LAUNCHED("k_root_flag");
+    if (!scan_i32(flag_tmp, flag_tmp, n, scan_tmp, s)) return false;
+    k_label<<<grid_for(n, 256), 256, 0, s>>>(parent, flag_tmp, n, L, sc);
+    MC_LAUNCHED("k_label");
+    return true;
+}
+
+bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
+          int32_t* ptr2, hipStream_t s) {
+    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, marks, flag1, ptr2);
+    MC_LAUNCHED("k_pr12");
+    return true;
+}
+
+bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s) {
+    k_map_update<<<grid_for(n0, 256), 256, 0, s>>>(map0, L, n0);
+    MC_LAUNCHED("k_map_update");
+    return true;
+}
+
+bool side_from_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int32_t* target_dev, hipStream_t s) {
+    k_side_vertex<<<grid_for(n0, 256), 256, 0, s>>>(side, map0, n0, target_dev);
+    MC_LAUNCHED("k_side_vertex");
+    return true;
+}
+
+bool side_from_prefix(uint8_t* side, const int32_t* map0, int32_t n0, uint8_t* flag, int32_t n,
+                      const int32_t* order, const int32_t* len_dev, hipStream_t s) {
+    if (!fill_u8(flag, 0, n, s)) return false;
+    k_mark_prefix<<<grid_for(n, 256), 256, 0, s>>>(flag, order, len_dev);
+    MC_LAUNCHED("k_mark_prefix");
+    k_side_flag<<<grid_for(n0, 256), 256, 0, s>>>(side, map0, n0, flag);
+    MC_LAUNCHED("k_side_flag");
+    return true;
+}
+
+bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipStream_t s) {
+    k_side_comp<<<grid_for(n0, 256), 256, 0, s>>>(side, parent, n0);
+    MC_LAUNCHED("k_side_comp");
+    return true;
+}
+
+bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len, hipStream_t s) {
+    k_csr_to_padded<<<grid_for(n, 256), 256, 0, s>>>(row_ptr, n, off, len);
+    MC_LAUNCHED("k_csr_to_padded");
+    return true;
+}
+
+bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
+                  DevScalars* sc, unsigned long long* part, hipStream_t s) {
+    const int nb = grid_for(nnz > n ? nnz : n, 256, 1024);
+    k_validate<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, sc, part);
+    MC_LAUNCHED("k_validate");
+    k_validate_sum<<<1, 1, 0, s>>>(part, nb, sc);
+    MC_LAUNCHED("k_validate_sum");
+    return true;
+}

@@ -1,0 +1,154 @@
+// Host-side declarations shared by the translation units of the library:
+// workspace carving, kernel launchers and the per-call state.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "mc_device.h"
+#include "mincut.h"
+
+// Records the first HIP failure of a call; launchers return false on error.
+bool mc_hip_ok(hipError_t e, const char* what);
+#define MC_HIP(call) do { if (!mc_hip_ok((call), #call)) return false; } while (0)
+#define MC_LAUNCHED(what) do { if (!mc_hip_ok(hipGetLastError(), what)) return false; } while (0)
+
+// Bump allocator over the caller's device workspace. With base == nullptr
+// it only measures, so mc_workspace_size and the solver carve identically.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~(size_t)255;
+        used = off + count * sizeof(T);
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+};
+
+// --------------------------------------------------------------- scan
+// Exclusive prefix sum of in[0..count) into out[0..count]; out[count] is
+// the total. in and out may alias. tmp must hold scan_tmp_elems(count).
+size_t scan_tmp_elems(int64_t count);
+bool scan_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* tmp, hipStream_t s);
+
+// ------------------------------------------------------- fill / misc
+bool fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+bool fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s);
+bool fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
+bool iota_i32(int32_t* p, int64_t count, hipStream_t s);
+
+// ------------------------------------------------------- contraction
+// Scratch of the contraction (sized for at most n input vertices and cap
+// entries).
+struct ContractWS {
+    int32_t* gcnt;    // [n+1]  members per group -> vstart
+    int32_t* vstart;  // [n+1]
+    int32_t* gcur;    // [n]
+    int32_t* perm;    // [n]    vertices grouped by label
+    int32_t* mstart;  // [n+1]  entry offset of each member (perm order)
+    int32_t* gstart;  // [n+1]  entry offset of each group
+    int32_t* tsize;   // [n+1]  hash-table slots of each large group -> tbase
+    int32_t* bigm;    // [n+1]  members of each large group -> bmbase
+    int32_t* bcur;    // [n]
+    int32_t* tkey;    // [4*cap+1024]
+    int64_t* tval;    // [4*cap+1024]
+    int32_t* scan_tmp;
+    int64_t* red_val; // [1024] per-block minima
+    int32_t* red_id;  // [1024]
+};
+void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
+
+// Contract `src` by labels L (L == nullptr: identity, which only folds
+// loops, parallel and zero-weight entries) into `dst` with n2 vertices.
+// dst.cap must be >= the sum of src.len. Writes dst.off/len/col/w/deg and
+// the minimum degree (and its vertex) into sc->dmin / sc->dmin_arg.
+bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws,
+              DevScalars* sc, hipStream_t s);
+
+// Minimum degree of g (ties: smallest vertex) into sc->dmin / dmin_arg.
+bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s);
+
+// --------------------------------------------------------- union-find
+bool uf_init(int32_t* parent, int32_t n, hipStream_t s);
+// Union the endpoints of every entry with positive weight.
+bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s);
+// Compress parent[] and write canonical labels (components numbered by
+// their smallest vertex) to L; the count goes to sc->n2.
+bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp,
+               DevScalars* sc, hipStream_t s);
+
+// ----------------------------------------------------- reduction tests
+// Padberg-Rinaldi test 1 (entry weight >= lam) and test 2 (one pointer per
+// vertex to its heaviest neighbour when 2 c(v,p) >= c(v)), unioned into
+// parent. Optional outputs for parity checks: flag1[entry], ptr2[vertex].
+bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
+          uint8_t* flag1, int32_t* ptr2, hipStream_t s);
+
+// ----------------------------------------------------------- CAPFOREST
+struct CapforestArgs {
+    DGraph g;
+    const int64_t* lam;     // bound at launch
+    int32_t* parent;        // union-find of contractible edges
+    int32_t* claim;         // [n] shared visited array (round-tagged)
+    int32_t tag;            // round tag for claim[]
+    int32_t shared;         // 1: passes share the visited array
+    int32_t passes;
+    int32_t len_cap;        // scans per pass, 0 = unlimited
+    uint64_t seed;
+    int32_t start;          // >= 0: every pass starts here (parity runs)
+    int32_t* order;         // [passes * CF_HC] scanned vertices per pass
+    int32_t* nscan;         // [passes]
+    int64_t* alpha;         // [passes] smallest alpha of the pass (INT64_MAX: none)
+    int32_t* alpha_len;     // [passes] prefix length of that alpha
+    int64_t* lam_out;       // [passes] bound at the end of the pass
+    unsigned long long* marks;
+};
+constexpr int CF_HC = 2048;     // per-pass LDS hash capacity (vertices touched)
+bool capforest_passes(const CapforestArgs& a, hipStream_t s);
+// Reduce per-pass results: smallest alpha (ties: smallest pass) and its
+// prefix length into sc->best_alpha / best_pass / best_len.
+bool capforest_reduce(const CapforestArgs& a, DevScalars* sc, hipStream_t s);
+
+// One complete sequential pass (Algorithm 2's fallback): no capacity limit.
+struct CompleteArgs {
+    DGraph g;
+    const int64_t* lam;
+    int32_t* parent;
+    int32_t start;
+    int32_t tag;
+    int32_t* st;            // [n] per-vertex state, tagged
+    int64_t* r;             // [n]
+    int64_t* l1;            // [n/64 + 1] block maxima of queued r
+    int32_t* order;         // [n]
+    int32_t* nscan;         // [1]
+    int64_t* alpha;         // [1]
+    int32_t* alpha_len;     // [1]
+    int64_t* lam_out;       // [1]
+    unsigned long long* marks;
+};
+bool capforest_complete(const CompleteArgs& a, hipStream_t s);
+
+// -------------------------------------------------------- side tracking
+bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s);
+// side[v0] = (map0[v0] == target)
+bool side_from_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int32_t* target_dev,
+                      hipStream_t s);
+// flag[v] = 1 for v in order[0..len) (len read from device), else 0 (flag
+// has n entries); then side[v0] = flag[map0[v0]]
+bool side_from_prefix(uint8_t* side, const int32_t* map0, int32_t n0, uint8_t* flag, int32_t n,
+                      const int32_t* order, const int32_t* len_dev, hipStream_t s);
+// side[v0] = (root(map0[v0]) != root(0)) over a compressed parent array
+bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipStream_t s);
+
+// ------------------------------------------------------- input handling
+// Turn a user CSR (row_ptr) into padded form (off = row_ptr, len = diff).
+bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len, hipStream_t s);
+// Device-side validation of a user CSR: sets sc->err to an mc_status code.
+bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
+                  DevScalars* sc, unsigned long long* part, hipStream_t s);
+
+std::string& mc_error_slot();

@@ -1,0 +1,672 @@
+// Host driver and C ABI of the minimum-cut library.
+//
+// mc_mincut runs Algorithm 2 of the paper on the device:
+//   normalise the input (contraction by the identity), lambda-hat <- minimum
+//   degree (Section 2 "Basic Concepts"), connectivity check (lambda = 0),
+//   then rounds of { reduction tests 1-2, parallel CAPFOREST passes,
+//   sequential CAPFOREST if nothing was marked, union-find relabel,
+//   contraction, collapsed degrees as bounds } until at most two vertices
+//   remain. The host only launches kernels and reads back a few scalars per
+//   round; every step of the path runs in the kernels of this library.
+//
+// The side of the cut is tracked without keeping old graphs (paper,
+// Section 4, session 1 item 2): map0 sends every input vertex to its
+// current vertex, and whenever lambda-hat strictly drops the side is
+// snapshot from the vertex or scanned prefix that produced the new bound.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mc_internal.h"
+#include "mincut_steps.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+inline int grid_for(int64_t count, int threads, int cap = 8192) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+__global__ void k_set_lam(DevScalars* sc, int64_t lam) { sc->lam = lam; }
+__global__ void k_reset_round(DevScalars* sc) {
+    sc->marks_pr = 0;
+    sc->marks_cf = 0;
+    sc->err = 0;
+}
+__global__ void k_uf_pairs(const int32_t* a, const int32_t* b, int64_t np, int32_t* par) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+        uf_union(par, a[i], b[i]);
+}
+
+mc_status fail(mc_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+}  // namespace
+
+std::string& mc_error_slot() { return g_err; }
+
+bool mc_hip_ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+struct mc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mc_options opt{};
+    int cus = 256;
+    DevScalars* hsc = nullptr;   // pinned readback slot
+    int32_t tag = 0;             // round tag for visited arrays (never reset)
+};
+
+extern "C" void mc_default_options(mc_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->seed = 1;
+    o->heuristic_min_n = 10000;
+    o->lp_iters = 2;
+    o->pr_tri_deg_cap = 0;
+    o->capforest_passes = 0;
+    o->pass_len_cap = 0;
+    o->deterministic = 0;
+    o->validate = 0;
+}
+
+extern "C" const char* mc_last_error(void) { return g_err.c_str(); }
+
+extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_options* opt, mc_ctx** out) {
+    if (!out) return fail(MC_E_INVALID_ARG, "mc_ctx_create: out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(MC_E_DEVICE, "mc_ctx_create: no such HIP device");
+    mc_ctx* c = new (std::nothrow) mc_ctx();
+    if (!c) return fail(MC_E_OOM, "mc_ctx_create: out of host memory");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (opt) c->opt = *opt; else mc_default_options(&c->opt);
+    if (hipSetDevice(device) != hipSuccess) { delete c; return fail(MC_E_DEVICE, "hipSetDevice failed"); }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cus = prop.multiProcessorCount;
+    if (hipHostMalloc((void**)&c->hsc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(MC_E_DEVICE, "hipHostMalloc failed");
+    }
+    *out = c;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_ctx_destroy(mc_ctx* c) {
+    if (!c) return MC_OK;
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    delete c;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_ctx_set_options(mc_ctx* c, const mc_options* opt) {
+    if (!c || !opt) return fail(MC_E_INVALID_ARG, "mc_ctx_set_options: NULL argument");
+    c->opt = *opt;
+    return MC_OK;
+}
+
+namespace {
+
+// All device buffers of one solve, carved from the caller's workspace.
+struct SolveWS {
+    int32_t* in_rp = nullptr;
+    int32_t* in_col = nullptr;
+    int64_t* in_w = nullptr;
+    DGraph g[3];
+    int32_t* L = nullptr;
+    int32_t* parent = nullptr;
+    int32_t* flag = nullptr;
+    uint8_t* flag8 = nullptr;
+    int32_t* claim = nullptr;
+    int32_t* map0 = nullptr;
+    uint8_t* side = nullptr;
+    ContractWS cw;
+    int32_t passes = 0;
+    int32_t* order = nullptr;
+    int32_t* nscan = nullptr;
+    int64_t* alpha = nullptr;
+    int32_t* alen = nullptr;
+    int64_t* lamout = nullptr;
+    int32_t* cst = nullptr;
+    int64_t* cr = nullptr;
+    int64_t* cl1 = nullptr;
+    int32_t* corder = nullptr;
+    int32_t* cnscan = nullptr;
+    int64_t* calpha = nullptr;
+    int32_t* calen = nullptr;
+    int64_t* clamout = nullptr;
+    DevScalars* sc = nullptr;
+    unsigned long long* vpart = nullptr;
+};
+
+void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
+    g.n = n;
+    g.cap = cap;
+    g.off = a.take<int32_t>((size_t)n + 1);
+    g.len = a.take<int32_t>((size_t)n + 1);
+    g.deg = a.take<int64_t>((size_t)n + 1);
+    g.col = a.take<int32_t>((size_t)cap + 1);
+    g.w = a.take<int64_t>((size_t)cap + 1);
+}
+
+void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, bool host_input, int ngraphs, SolveWS& w) {
+    w.sc = a.take<DevScalars>(1);
+    if (host_input) {
+        w.in_rp = a.take<int32_t>((size_t)n + 1);
+        w.in_col = a.take<int32_t>((size_t)cap + 1);
+        w.in_w = a.take<int64_t>((size_t)cap + 1);
+    }
+    for (int k = 0; k < ngraphs; k++) carve_graph(a, n, cap, w.g[k]);
+    w.L = a.take<int32_t>((size_t)n + 1);
+    w.parent = a.take<int32_t>((size_t)n + 1);
+    w.flag = a.take<int32_t>((size_t)n + 2);
+    w.flag8 = a.take<uint8_t>((size_t)n + 1);
+    w.claim = a.take<int32_t>((size_t)n + 1);
+    w.map0 = a.take<int32_t>((size_t)n + 1);
+    w.side = a.take<uint8_t>((size_t)n + 1);
+    contract_ws_carve(a, n, cap, w.cw);
+    w.passes = passes;
+    w.order = a.take<int32_t>((size_t)passes * CF_HC);
+    w.nscan = a.take<int32_t>((size_t)passes);
+    w.alpha = a.take<int64_t>((size_t)passes);
+    w.alen = a.take<int32_t>((size_t)passes);
+    w.lamout = a.take<int64_t>((size_t)passes);
+    w.cst = a.take<int32_t>((size_t)n + 1);
+    w.cr = a.take<int64_t>((size_t)n + 1);
+    w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
+    w.corder = a.take<int32_t>((size_t)n + 1);
+    w.cnscan = a.take<int32_t>(1);
+    w.calpha = a.take<int64_t>(1);
+    w.calen = a.take<int32_t>(1);
+    w.clamout = a.take<int64_t>(1);
+    w.vpart = a.take<unsigned long long>(1024);
+}
+
+int32_t pass_count(const mc_ctx* c) {
+    int32_t p = c->opt.capforest_passes;
+    if (p <= 0) p = 4 * c->cus;
+    return p;
+}
+
+// Host-side checks of a host CSR (exact, including symmetry when asked).
+mc_status check_host_csr(const mc_csr* g, bool symmetric) {
+    const int32_t n = g->n, nnz = g->nnz;
+    if (g->row_ptr[0] != 0 || g->row_ptr[n] != nnz) return fail(MC_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    for (int32_t v = 0; v < n; v++)
+        if (g->row_ptr[v + 1] < g->row_ptr[v]) return fail(MC_E_BAD_GRAPH, "row_ptr is not non-decreasing");
+    const unsigned long long cap = 1ULL << 62;
+    unsigned long long s = 0;
+    for (int32_t j = 0; j < nnz; j++) {
+        if (g->col[j] < 0 || g->col[j] >= n) return fail(MC_E_BAD_GRAPH, "col out of range");
+        if (g->w[j] < 0) return fail(MC_E_BAD_GRAPH, "negative weight");
+        s += (unsigned long long)g->w[j];
+        if (s >= cap || (unsigned long long)g->w[j] >= cap) return fail(MC_E_OVERFLOW, "total weight must be below 2^62");
+    }
+    if (symmetric) {
+        // fold each row, then every (u,v,s) must have a matching (v,u,s)
+        std::vector<std::pair<int64_t, int64_t>> e;  // key u*n+v -> weight
+        e.reserve((size_t)nnz);
+        for (int32_t u = 0; u < n; u++)
+            for (int32_t j = g->row_ptr[u]; j < g->row_ptr[u + 1]; j++)
+                if (g->col[j] != u) e.push_back({(int64_t)u * n + g->col[j], g->w[j]});
+        std::sort(e.begin(), e.end());
+        std::vector<std::pair<int64_t, int64_t>> f;
+        for (size_t i = 0; i < e.size();) {
+            size_t k = i;
+            int64_t t = 0;
+            while (k < e.size() && e[k].first == e[i].first) t += e[k++].second;
+            f.push_back({e[i].first, t});
+            i = k;
+        }
+        for (auto& p : f) {
+            int64_t u = p.first / n, v = p.first % n;
+            auto it = std::lower_bound(f.begin(), f.end(), std::make_pair(v * n + u, (int64_t)INT64_MIN));
+            if (it == f.end() || it->first != v * n + u || it->second != p.second)
+                return fail(MC_E_BAD_GRAPH, "edge list is not symmetric");
+        }
+    }
+    return MC_OK;
+}
+
+struct Solver {
+    mc_ctx* c;
+    hipStream_t s;
+    SolveWS w;
+    int32_t n0 = 0;
+    int64_t lam = 0;
+    mc_stats stats{};
+
+    bool readback() {
+        MC_HIP(hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        return true;
+    }
+    bool set_lam(int64_t v) {
+        lam = v;
+        k_set_lam<<<1, 1, 0, s>>>(w.sc, v);
+        MC_LAUNCHED("k_set_lam");
+        return true;
+    }
+};
+
+}  // namespace
+
+extern "C" mc_status mc_workspace_size(const mc_ctx* c, int32_t n, int32_t nnz, size_t* bytes) {
+    if (!c || !bytes) return fail(MC_E_INVALID_ARG, "mc_workspace_size: NULL argument");
+    if (n < 2 || nnz < 0) return fail(MC_E_INVALID_ARG, "mc_workspace_size: need n >= 2 and nnz >= 0");
+    Arena a;
+    SolveWS w;
+    carve(a, n, nnz, pass_count(c), true, 3, w);
+    *bytes = a.used + 256;
+    return MC_OK;
+}
+
+// Exact rounds of Algorithm 2 on w.g[src] until at most two vertices remain.
+static mc_status exact_rounds(Solver& S, int src) {
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    DGraph* cur = &w.g[src];
+    int nxt_idx = src == 1 ? 2 : 1;
+    int32_t round = 0;
+    while (cur->n > 2) {
+        DGraph* nxt = &w.g[nxt_idx];
+        const int32_t n = cur->n;
+        k_reset_round<<<1, 1, 0, s>>>(w.sc);
+        if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
+        if (!pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, s)) return MC_E_DEVICE;
+        CapforestArgs ca{};
+        ca.g = *cur;
+        ca.lam = &w.sc->lam;
+        ca.parent = w.parent;
+        ca.claim = w.claim;
+        ca.tag = ++S.c->tag;
+        ca.shared = S.c->opt.deterministic ? 0 : 1;
+        ca.passes = w.passes;
+        ca.len_cap = S.c->opt.pass_len_cap;
+        ca.seed = S.c->opt.seed;
+        ca.start = -1;
+        ca.order = w.order;
+        ca.nscan = w.nscan;
+        ca.alpha = w.alpha;
+        ca.alpha_len = w.alen;
+        ca.lam_out = w.lamout;
+        ca.marks = &w.sc->marks_cf;
+        if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+        if (!S.readback()) return MC_E_DEVICE;
+        DevScalars h = *S.c->hsc;
+        if (h.best_pass >= 0 && h.best_alpha < S.lam) {
+            if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, w.order + (int64_t)h.best_pass * CF_HC,
+                                  &w.sc->best_len, s))
+                return MC_E_DEVICE;
+            if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
+        }
+        S.stats.marks_pr += (int64_t)h.marks_pr;
+        S.stats.marks_capforest += (int64_t)h.marks_cf;
+        if (h.marks_pr + h.marks_cf == 0) {
+            // Algorithm 2: no contractible edge found, run CAPFOREST
+            // sequentially over the whole graph.
+            const int64_t lam_before = S.lam;
+            CompleteArgs cp{};
+            cp.g = *cur;
+            cp.lam = &w.sc->lam;
+            cp.parent = w.parent;
+            cp.start = (int32_t)(((S.c->opt.seed * 0x9E3779B97F4A7C15ULL + (uint64_t)round) >> 33) % (uint64_t)n);
+            cp.tag = ++S.c->tag;
+            cp.st = w.cst;
+            cp.r = w.cr;
+            cp.l1 = w.cl1;
+            cp.order = w.corder;
+            cp.nscan = w.cnscan;
+            cp.alpha = w.calpha;
+            cp.alpha_len = w.calen;
+            cp.lam_out = w.clamout;
+            cp.marks = &w.sc->marks_cf;
+            if (!capforest_complete(cp, s)) return MC_E_DEVICE;
+            int64_t calpha = 0;
+            int32_t cns = 0;
+            if (hipMemcpyAsync(&cns, w.cnscan, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+                return fail(MC_E_DEVICE, "readback after sequential CAPFOREST failed");
+            if (hipMemcpyAsync(&calpha, w.calpha, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                !S.readback())
+                return fail(MC_E_DEVICE, "readback after sequential CAPFOREST failed");
+            h = *S.c->hsc;
+            if (cns < 0) return fail(MC_E_DEVICE, "sequential CAPFOREST: inconsistent queue index");
+            S.stats.fallback_passes++;
+            S.stats.marks_capforest += (int64_t)h.marks_cf;
+            if (calpha < S.lam) {
+                if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, w.corder, w.calen, s)) return MC_E_DEVICE;
+                if (!S.set_lam(calpha)) return MC_E_DEVICE;
+            }
+            if (h.marks_cf == 0) {
+                if (S.lam < lam_before) { round++; continue; }
+                return fail(MC_E_DEVICE, "sequential CAPFOREST marked no edge at a fixed bound");
+            }
+        }
+        if (!uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+        if (!S.readback()) return MC_E_DEVICE;
+        const int32_t n2 = S.c->hsc->n2;
+        if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s)) return MC_E_DEVICE;
+        if (!map_update(w.map0, w.L, S.n0, s)) return MC_E_DEVICE;
+        if (!S.readback()) return MC_E_DEVICE;
+        h = *S.c->hsc;
+        if (n2 >= 2 && h.dmin < S.lam) {
+            if (!side_from_vertex(w.side, w.map0, S.n0, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
+            if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
+        }
+        nxt_idx = (nxt_idx == 1) ? 2 : 1;
+        cur = nxt;
+        round++;
+    }
+    S.stats.rounds += round;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t ws_bytes, int64_t* lambda,
+                               uint8_t* side_out, mc_stats* st) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c || !g || !lambda) return fail(MC_E_INVALID_ARG, "mc_mincut: NULL argument");
+    if (g->n < 2) return fail(MC_E_INVALID_ARG, "mc_mincut: need n >= 2");
+    if (g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
+        return fail(MC_E_INVALID_ARG, "mc_mincut: bad CSR pointers");
+    if (g->location != MC_HOST && g->location != MC_DEVICE) return fail(MC_E_INVALID_ARG, "mc_mincut: bad location");
+    if (!dev_ws) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace is NULL");
+    const bool host_input = g->location == MC_HOST;
+    if (host_input) {
+        mc_status v = check_host_csr(g, c->opt.validate != 0);
+        if (v != MC_OK) return v;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
+
+    Solver S;
+    S.c = c;
+    S.s = c->stream;
+    const int32_t n = g->n;
+    const int64_t nnz = g->nnz;
+    Arena a;
+    a.base = (char*)dev_ws;
+    a.size = ws_bytes;
+    carve(a, n, nnz, pass_count(c), host_input, 3, S.w);
+    if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    S.n0 = n;
+    S.stats.lambda_heuristic = -1;
+
+    const int32_t* rp = g->row_ptr;
+    const int32_t* col = g->col;
+    const int64_t* wt = g->w;
+    if (host_input) {
+        if (hipMemcpyAsync(w.in_rp, g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+            (nnz > 0 && hipMemcpyAsync(w.in_col, g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s) != hipSuccess) ||
+            (nnz > 0 && hipMemcpyAsync(w.in_w, g->w, sizeof(int64_t) * (size_t)nnz, hipMemcpyHostToDevice, s) != hipSuccess))
+            return fail(MC_E_DEVICE, "copy of the input graph failed");
+        rp = w.in_rp;
+        col = w.in_col;
+        wt = w.in_w;
+    }
+    k_reset_round<<<1, 1, 0, s>>>(w.sc);
+    if (!host_input) {
+        if (!validate_csr(rp, col, wt, n, (int32_t)nnz, w.sc, w.vpart, s) || !S.readback()) return MC_E_DEVICE;
+        if (c->hsc->err != 0)
+            return fail((mc_status)c->hsc->err, c->hsc->err == MC_E_OVERFLOW ? "total weight must be below 2^62"
+                                                                              : "malformed CSR (row_ptr, col or w)");
+    }
+    // normalise: contraction by the identity folds loops, parallel entries
+    // and zero weights; the padded view of the input reuses g[1]'s arrays
+    DGraph user = w.g[1];
+    user.n = n;
+    user.cap = nnz;
+    user.col = const_cast<int32_t*>(col);
+    user.w = const_cast<int64_t*>(wt);
+    if (!csr_to_padded(rp, n, user.off, user.len, s)) return MC_E_DEVICE;
+    if (!contract(user, nullptr, n, w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
+    if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
+    // connectivity: lambda = 0 iff the positive-weight graph is disconnected
+    if (!uf_init(w.parent, n, s) || !uf_all_edges(w.g[0], w.parent, s) ||
+        !uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
+        return MC_E_DEVICE;
+    DevScalars h = *c->hsc;
+    S.stats.n_input = n;
+    int64_t result = 0;
+    if (h.n2 > 1) {
+        if (!side_from_components(w.side, w.parent, n, s)) return MC_E_DEVICE;
+        result = 0;
+    } else {
+        // minimum degree is the first bound; its vertex is the first side
+        if (!side_from_vertex(w.side, w.map0, n, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
+        if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
+        S.stats.lambda_min_degree = h.dmin;
+        mc_status r = exact_rounds(S, 0);
+        if (r != MC_OK) return r;
+        result = S.lam;
+    }
+    if (side_out) {
+        if (hipMemcpyAsync(side_out, w.side, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(MC_E_DEVICE, "copy of the side failed");
+        if (side_out[0])
+            for (int32_t v = 0; v < n; v++) side_out[v] ^= 1;
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
+        return fail(MC_E_DEVICE, "stream synchronisation failed");
+    }
+    *lambda = result;
+    if (st) {
+        S.stats.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *st = S.stats;
+    }
+    return MC_OK;
+}
+
+// ------------------------------------------------------------ step ABI
+namespace {
+DGraph to_dgraph(const mc_dgraph* g) {
+    DGraph d;
+    d.n = g->n;
+    d.cap = g->cap;
+    d.off = g->off;
+    d.len = g->len;
+    d.col = g->col;
+    d.w = g->w;
+    d.deg = g->deg;
+    return d;
+}
+
+struct StepWS {
+    DevScalars* sc;
+    int32_t* parent;
+    int32_t* flag;
+    int32_t* claim;
+    ContractWS cw;
+    int32_t* order;
+    int32_t* nscan;
+    int64_t* alpha;
+    int32_t* alen;
+    int64_t* lamout;
+    int32_t* cst;
+    int64_t* cr;
+    int64_t* cl1;
+    int64_t* lam;
+};
+
+void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
+    w.sc = a.take<DevScalars>(1);
+    w.lam = a.take<int64_t>(1);
+    w.parent = a.take<int32_t>((size_t)n + 1);
+    w.flag = a.take<int32_t>((size_t)n + 2);
+    w.claim = a.take<int32_t>((size_t)n + 1);
+    contract_ws_carve(a, n, cap, w.cw);
+    if (passes < 1) passes = 1;
+    w.order = a.take<int32_t>((size_t)passes * CF_HC);
+    w.nscan = a.take<int32_t>((size_t)passes);
+    w.alpha = a.take<int64_t>((size_t)passes);
+    w.alen = a.take<int32_t>((size_t)passes);
+    w.lamout = a.take<int64_t>((size_t)passes);
+    w.cst = a.take<int32_t>((size_t)n + 1);
+    w.cr = a.take<int64_t>((size_t)n + 1);
+    w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
+}
+
+mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws, size_t bytes, StepWS& w) {
+    if (!c || !ws) return fail(MC_E_INVALID_ARG, "step: NULL context or workspace");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
+    Arena a;
+    a.base = (char*)ws;
+    a.size = bytes;
+    carve_step(a, n, cap, passes, w);
+    if (a.used > bytes) return fail(MC_E_INVALID_ARG, "step: workspace too small");
+    return MC_OK;
+}
+
+mc_status sync_read(mc_ctx* c, StepWS& w) {
+    if (hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(MC_E_DEVICE, "step: readback failed");
+    return MC_OK;
+}
+}  // namespace
+
+extern "C" mc_status mc_step_ws_size(int32_t n, int64_t cap, int32_t passes, size_t* bytes) {
+    if (!bytes || n < 1 || cap < 0) return fail(MC_E_INVALID_ARG, "mc_step_ws_size: bad arguments");
+    Arena a;
+    StepWS w;
+    carve_step(a, n, cap, passes, w);
+    *bytes = a.used + 256;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_step_contract(mc_ctx* c, const mc_dgraph* src, const int32_t* labels, int32_t n2,
+                                      mc_dgraph* dst, void* ws, size_t bytes, int64_t* dmin, int32_t* dmin_arg) {
+    if (!src || !dst) return fail(MC_E_INVALID_ARG, "mc_step_contract: NULL graph");
+    StepWS w;
+    mc_status r = step_begin(c, src->n, src->cap, 1, ws, bytes, w);
+    if (r != MC_OK) return r;
+    DGraph s = to_dgraph(src), d = to_dgraph(dst);
+    if (!contract(s, labels, labels ? n2 : src->n, d, w.cw, w.sc, c->stream)) return MC_E_DEVICE;
+    if ((r = sync_read(c, w)) != MC_OK) return r;
+    if (dmin) *dmin = c->hsc->dmin;
+    if (dmin_arg) *dmin_arg = c->hsc->dmin_arg;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_step_components(mc_ctx* c, int32_t n, int64_t np, const int32_t* a, const int32_t* b,
+                                        int32_t* labels, int32_t* n2, void* ws, size_t bytes) {
+    StepWS w;
+    mc_status r = step_begin(c, n, 1, 1, ws, bytes, w);
+    if (r != MC_OK) return r;
+    hipStream_t s = c->stream;
+    if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
+    if (np > 0) {
+        k_uf_pairs<<<grid_for(np, 256), 256, 0, s>>>(a, b, np, w.parent);
+        if (!mc_hip_ok(hipGetLastError(), "k_uf_pairs")) return MC_E_DEVICE;
+    }
+    if (!uf_labels(w.parent, n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+    if ((r = sync_read(c, w)) != MC_OK) return r;
+    if (n2) *n2 = c->hsc->n2;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_step_pr12(mc_ctx* c, const mc_dgraph* g, int64_t lam, uint8_t* flag1, int32_t* ptr2,
+                                  int32_t* labels, int32_t* n2, void* ws, size_t bytes) {
+    if (!g) return fail(MC_E_INVALID_ARG, "mc_step_pr12: NULL graph");
+    StepWS w;
+    mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
+    if (r != MC_OK) return r;
+    hipStream_t s = c->stream;
+    k_set_lam<<<1, 1, 0, s>>>(w.sc, lam);
+    k_reset_round<<<1, 1, 0, s>>>(w.sc);
+    if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
+    if (!pr12(to_dgraph(g), &w.sc->lam, w.parent, &w.sc->marks_pr, flag1, ptr2, s)) return MC_E_DEVICE;
+    if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+    if ((r = sync_read(c, w)) != MC_OK) return r;
+    if (n2) *n2 = c->hsc->n2;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t lam, int32_t start, int32_t complete,
+                                       int32_t passes, int32_t shared, int32_t len_cap, int32_t* labels, int32_t* n2,
+                                       int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,
+                                       int64_t* lam_out, void* ws, size_t bytes) {
+    if (!g || !labels || !order) return fail(MC_E_INVALID_ARG, "mc_step_capforest: NULL argument");
+    if ((complete && start < 0) || start >= g->n) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
+    if (!complete && passes < 1) return fail(MC_E_INVALID_ARG, "mc_step_capforest: passes must be >= 1");
+    StepWS w;
+    mc_status r = step_begin(c, g->n, g->cap, complete ? 1 : passes, ws, bytes, w);
+    if (r != MC_OK) return r;
+    hipStream_t s = c->stream;
+    k_set_lam<<<1, 1, 0, s>>>(w.sc, lam);
+    k_reset_round<<<1, 1, 0, s>>>(w.sc);
+    if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
+    int64_t alpha = 0, lo = 0;
+    int32_t alen = 0, ns = 0;
+    if (complete) {
+        CompleteArgs cp{};
+        cp.g = to_dgraph(g);
+        cp.lam = &w.sc->lam;
+        cp.parent = w.parent;
+        cp.start = start;
+        cp.tag = ++c->tag;
+        cp.st = w.cst;
+        cp.r = w.cr;
+        cp.l1 = w.cl1;
+        cp.order = order;
+        cp.nscan = w.nscan;
+        cp.alpha = w.alpha;
+        cp.alpha_len = w.alen;
+        cp.lam_out = w.lamout;
+        cp.marks = &w.sc->marks_cf;
+        if (!capforest_complete(cp, s)) return MC_E_DEVICE;
+    } else {
+        if (!fill_i32(w.claim, 0, g->n, s)) return MC_E_DEVICE;
+        CapforestArgs ca{};
+        ca.g = to_dgraph(g);
+        ca.lam = &w.sc->lam;
+        ca.parent = w.parent;
+        ca.claim = w.claim;
+        ca.tag = ++c->tag;
+        ca.shared = shared;
+        ca.passes = passes;
+        ca.len_cap = len_cap;
+        ca.seed = c->opt.seed;
+        ca.start = start;
+        ca.order = w.order;
+        ca.nscan = w.nscan;
+        ca.alpha = w.alpha;
+        ca.alpha_len = w.alen;
+        ca.lam_out = w.lamout;
+        ca.marks = &w.sc->marks_cf;
+        if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+    }
+    if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+    if (hipMemcpyAsync(&ns, w.nscan, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&lo, w.lamout, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(MC_E_DEVICE, "step: readback failed");
+    if (!complete && hipMemcpyAsync(order, w.order, sizeof(int32_t) * (size_t)CF_HC, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(MC_E_DEVICE, "step: order copy failed");
+    if ((r = sync_read(c, w)) != MC_OK) return r;
+    DevScalars h = *c->hsc;
+    if (complete) {
+        if (hipMemcpy(&alpha, w.alpha, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&alen, w.alen, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(MC_E_DEVICE, "step: readback failed");
+    } else {
+        alpha = h.best_alpha;
+        alen = h.best_len;
+    }
+    if (n2) *n2 = h.n2;
+    if (nscan) *nscan = ns;
+    if (best_alpha) *best_alpha = alpha;
+    if (best_len) *best_len = alen;
+    if (lam_out) *lam_out = lo;
+    return MC_OK;
+}

@@ -1,0 +1,309 @@
+"""GPU parity: every step kernel against the CPU oracle, element by element,
+through the C ABI (include/mincut_steps.h), and the whole solver against
+the oracle's lambda. Integer work, so the bar is bit-exact; where several
+answers are correct (row order, the side of the cut) the unique part is
+compared and the rest checked for validity."""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2609_07204_amd as mc
+    assert torch.cuda.is_available()
+    c = mc.Context(0)
+    yield c
+    c.close()
+
+
+def canon_dev(ctx, g):
+    """Device padded graph of g with degrees filled (identity contraction)."""
+    src = ctx.dgraph(g)
+    dst, dmin, darg = ctx.step_contract(src)
+    return dst, dmin, darg
+
+
+def assert_same_csr(dev_graph, rp, col, w):
+    drp, dcol, dw, ddeg = dev_graph.to_canonical()
+    assert np.array_equal(drp, rp)
+    assert np.array_equal(dcol, col)
+    assert np.array_equal(dw, w)
+    deg = np.add.reduceat(w, rp[:-1]) if w.size else np.zeros(len(rp) - 1, np.int64)
+    deg = np.where(np.diff(rp) > 0, deg, 0)
+    assert np.array_equal(ddeg, deg)
+
+
+# --------------------------------------------------------- contraction
+def raw_graph(n, m, seed, wmax=7):
+    r = gen.SplitMix64(seed)
+    u = [r.below(n) for _ in range(m)]
+    v = [r.below(n) for _ in range(m)]
+    w = [r.below(wmax + 1) for _ in range(m)]
+    return gen.raw_csr(n, u, v, w)
+
+
+@pytest.mark.parametrize("n,m,seed", [(2, 1, 1), (5, 30, 2), (40, 300, 3), (700, 9000, 4), (3000, 60000, 5)])
+def test_normalise_matches_oracle(ctx, n, m, seed):
+    say("normalise", n, m, seed)
+    g = raw_graph(n, m, seed)
+    dst, dmin, darg = canon_dev(ctx, g)
+    rp, col, w = oracle.contract(g, np.arange(n, dtype=np.int32), n)
+    assert_same_csr(dst, rp, col, w)
+    deg = oracle.degrees(g)
+    assert dmin == deg.min() and darg == int(np.argmin(deg))
+
+
+def test_normalise_hub_rows(ctx):
+    # rows far longer than the chunk limit take the global-table path
+    say("normalise hubs")
+    r = gen.SplitMix64(9)
+    u, v, w = [], [], []
+    for hub in (0, 1, 2):
+        for _ in range(5000):
+            u.append(hub)
+            v.append(r.below(400))
+            w.append(1 + r.below(5))
+    g = gen.raw_csr(400, u, v, w)
+    dst, dmin, darg = canon_dev(ctx, g)
+    rp, col, ww = oracle.contract(g, np.arange(400, dtype=np.int32), 400)
+    assert_same_csr(dst, rp, col, ww)
+
+
+@pytest.mark.parametrize("seed,n2frac", [(1, 0.5), (2, 0.05), (3, 0.9), (4, 0.002), (5, 1.0)])
+def test_contract_random_labels(ctx, seed, n2frac):
+    say("contract labels", seed, n2frac)
+    g = gen.erdos_renyi(4000, 12 / 3999, seed, 1, 50, lcc=False)
+    r = gen.SplitMix64(100 + seed)
+    n2 = max(1, int(g.n * n2frac))
+    lab = np.array([r.below(n2) for _ in range(g.n)], np.int32)
+    lab[:n2] = np.arange(n2)
+    import torch
+    src, _, _ = canon_dev(ctx, g)
+    dst, dmin, darg = ctx.step_contract(src, torch.as_tensor(lab).cuda(), n2)
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert_same_csr(dst, rp, col, w)
+    deg = np.diff(rp)
+    odeg = np.array([w[rp[x]:rp[x + 1]].sum() for x in range(n2)])
+    assert dmin == odeg.min() and darg == int(np.argmin(odeg))
+
+
+def test_contract_mixed_group_sizes(ctx):
+    # one giant group, many tiny ones, and medium groups straddling the
+    # small/large threshold
+    say("contract mixed groups")
+    g = gen.chung_lu(20000, 2.5, 16.0, 7, 1, 9, kcore=0, lcc=True)
+    n = g.n
+    lab = np.arange(n, dtype=np.int32) // 37
+    lab[: n // 5] = 0
+    uniq, lab = np.unique(lab, return_inverse=True)
+    lab = lab.astype(np.int32)
+    n2 = int(uniq.size)
+    import torch
+    src, _, _ = canon_dev(ctx, g)
+    dst, dmin, darg = ctx.step_contract(src, torch.as_tensor(lab).cuda(), n2)
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert_same_csr(dst, rp, col, w)
+
+
+# ---------------------------------------------------------- union-find
+@pytest.mark.parametrize("n,k,seed", [(1, 0, 1), (10, 5, 2), (5000, 3000, 3), (200000, 150000, 4)])
+def test_components(ctx, n, k, seed):
+    say("components", n, k)
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, n, k).astype(np.int32)
+    b = rng.integers(0, n, k).astype(np.int32)
+    lab, n2 = ctx.step_components(n, a, b)
+    ref, nref = oracle.components(n, a, b)
+    assert n2 == nref
+    assert np.array_equal(lab, ref)
+
+
+# ------------------------------------------------- reduction tests 1-2
+@pytest.mark.parametrize("seed", range(6))
+def test_pr12(ctx, seed):
+    say("pr12", seed)
+    g = gen.erdos_renyi(3000, 6 / 2999, seed, 1, 40, lcc=True) if seed % 2 else \
+        gen.chung_lu(5000, 2.5, 8.0, seed, 1, 30, lcc=True)
+    lam = int(oracle.degrees(g).min()) + seed * 3
+    dev, _, _ = canon_dev(ctx, g)
+    flag, ptr, lab, n2 = ctx.step_pr12(dev, lam)
+    oflag, optr = oracle.pr12(g, lam)
+    assert np.array_equal(ptr, optr)
+    # flags live at the device entry positions: compare per (row, target)
+    off = dev.off.cpu().numpy()
+    col = dev.col.cpu().numpy()
+    fl = flag.cpu().numpy()
+    got = set()
+    for v in range(g.n):
+        for j in range(off[v], off[v] + int(dev.len[v])):
+            if fl[j]:
+                got.add((v, int(col[j])))
+    ref = {(v, int(g.col[j])) for v in range(g.n) for j in range(g.row_ptr[v], g.row_ptr[v + 1]) if oflag[j]}
+    assert got == ref
+    pa = [p[0] for p in ref] + [v for v in range(g.n) if optr[v] >= 0]
+    pb = [p[1] for p in ref] + [int(optr[v]) for v in range(g.n) if optr[v] >= 0]
+    rl, rn = oracle.components(g.n, np.array(pa, np.int32), np.array(pb, np.int32))
+    assert n2 == rn and np.array_equal(lab, rl)
+
+
+# ------------------------------------------------------------ CAPFOREST
+def cf_oracle(g, lam, start, cap=0):
+    return oracle.capforest_pass(g, lam, start, max_scan=cap)
+
+
+def check_cf_equal(res, ref):
+    assert np.array_equal(res["order"], ref["order"])
+    assert res["n2"] == int(ref["labels"].max()) + 1
+    assert np.array_equal(res["labels"], ref["labels"])
+    assert res["lam"] == ref["lam"]
+    if ref["best_len"] > 0:
+        assert res["best_alpha"] == ref["best_alpha"] and res["best_len"] == ref["best_len"]
+
+
+CF_GRAPHS = [
+    ("planted", lambda: gen.planted(300, 300, 8, 3, 1, 10, 5)),
+    ("er", lambda: gen.erdos_renyi(800, 10 / 799, 3, 1, 100, lcc=True)),
+    ("chung_lu", lambda: gen.chung_lu(1000, 2.5, 10.0, 4, 1, 1, kcore=3, lcc=True)),
+    ("wheel", lambda: gen.wheel(200)),
+    ("cliques", lambda: gen.two_cliques(30, 40, 5)),
+    ("cycle", lambda: gen.cycle([1 + (i * 7919) % 97 for i in range(500)])),
+]
+
+
+@pytest.mark.parametrize("name,mk", CF_GRAPHS)
+def test_capforest_complete_pass_matches_oracle(ctx, name, mk):
+    g = mk()
+    say("capforest complete", name, g.n)
+    dev, dmin, _ = canon_dev(ctx, g)
+    for start in (0, g.n // 2, g.n - 1):
+        for lam in (dmin, max(1, dmin // 2), dmin * 3):
+            res = ctx.step_capforest(dev, lam, start=start, complete=True)
+            check_cf_equal(res, cf_oracle(g, lam, start))
+
+
+@pytest.mark.parametrize("name,mk", CF_GRAPHS)
+def test_capforest_lds_pass_matches_oracle(ctx, name, mk):
+    g = mk()
+    say("capforest lds", name, g.n)
+    dev, dmin, _ = canon_dev(ctx, g)
+    for start in (0, g.n // 3):
+        for cap in (0, 50):
+            # every graph here has n + max degree <= 1536, so the pass never
+            # runs out of hash capacity and must match the oracle exactly
+            assert g.n + int(np.diff(g.row_ptr).max()) <= 1536
+            res = ctx.step_capforest(dev, dmin, start=start, complete=False, passes=1, shared=False, len_cap=cap)
+            check_cf_equal(res, cf_oracle(g, dmin, start, cap))
+
+
+def test_capforest_parallel_marks_are_safe(ctx):
+    for seed in range(12):
+        g = gen.random_small(12 + seed % 5, 0.5, 4000 + seed, 1, 9)
+        lam_min = int(oracle.degrees(g).min())
+        if g.nnz == 0 or lam_min == 0:
+            continue
+        say("capforest parallel safety", seed)
+        dev, dmin, _ = canon_dev(ctx, g)
+        res = ctx.step_capforest(dev, dmin, start=-1, complete=False, passes=64, shared=True)
+        # each pass marks against its own bound, which never drops below
+        # min(dmin, smallest alpha of any pass); connectivity is ultrametric,
+        # so every pair joined through marks clears that threshold
+        thr = min(dmin, res["best_alpha"])
+        lab = res["labels"]
+        for x in range(g.n):
+            for y in range(x + 1, g.n):
+                if lab[x] == lab[y]:
+                    assert oracle.brute_st(g, x, y) >= thr
+
+
+# ---------------------------------------------------------- end to end
+def solve_check(ctx, g, lam_ref, device_input=False):
+    lam, side = ctx.mincut(dev=ctx.upload(g)) if device_input else ctx.mincut(g)
+    assert lam == lam_ref, (g.name, lam, lam_ref)
+    assert side[0] == 0
+    if lam > 0 or g.n > 1:
+        assert 0 < int(side.sum()) < g.n
+    assert oracle.cut_value(g, side) == lam
+    return side
+
+
+def test_closed_forms(ctx):
+    cases = [(gen.complete(2, 5), 5), (gen.complete(9), 8), (gen.complete(60, 3), 177),
+             (gen.cycle([4, 9, 2, 7, 5, 3]), 5), (gen.two_cliques(12, 15, 4), 4), (gen.wheel(50), 98),
+             (gen.wheel(4), 6), (gen.random_tree(300, 5, 3, 90), None),
+             (gen.disjoint_union(gen.complete(5), gen.cycle([3, 3, 3])), 0)]
+    for g, lam in cases:
+        if lam is None:
+            lam = int(g.w.min())
+        say("closed form", g.name)
+        solve_check(ctx, g, lam)
+        solve_check(ctx, g, lam, device_input=True)
+
+
+def test_disconnected_side_is_component_of_zero(ctx):
+    g = gen.disjoint_union(gen.cycle([2, 2, 2, 2]), gen.complete(3))
+    lam, side = ctx.mincut(g)
+    assert lam == 0 and list(side) == [0, 0, 0, 0, 1, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_random_small_vs_brute(ctx, seed):
+    g = gen.random_small(2 + seed % 15, [0.3, 0.6, 0.95][seed % 3], 10000 + seed, 0, 9)
+    lam_ref = oracle.brute(g)[0]
+    solve_check(ctx, g, lam_ref)
+
+
+def test_planted_two_blocks(ctx):
+    g = gen.config_planted_2x1000()
+    say("planted 2x1000")
+    side = solve_check(ctx, g, 5)
+    solve_check(ctx, g, 5, device_input=True)
+
+
+@pytest.mark.parametrize("fam,seed", [(f, s) for f in range(3) for s in range(4)])
+def test_mixed_medium_vs_oracle(ctx, fam, seed):
+    n = [300, 1500, 5000, 12000][seed]
+    g = gen.mixed_graph(n, 8 + 5 * seed, fam, 77 + seed, 1, 100)
+    say("mixed", fam, seed, g.n, g.m)
+    lam_ref = oracle.stoer_wagner(g)[0] if g.n <= 3000 else oracle.noi(g)[0]
+    solve_check(ctx, g, lam_ref)
+
+
+def test_unit_weight_chung_lu_core(ctx):
+    g = gen.config_chung_lu(15)
+    say("chung-lu 2^15 core", g.n, g.m)
+    lam_ref = oracle.noi(g)[0]
+    solve_check(ctx, g, lam_ref)
+
+
+def test_bad_device_input_rejected(ctx):
+    import torch
+    import paper_2609_07204_amd as mc
+    g = gen.complete(5)
+    rp, col, w = ctx.upload(g)
+    w2 = w.clone()
+    w2[3] = -1
+    with pytest.raises(mc.MincutError) as e:
+        ctx.mincut(dev=(rp, col, w2))
+    assert e.value.code == -2
+    col2 = col.clone()
+    col2[0] = 7
+    with pytest.raises(mc.MincutError) as e:
+        ctx.mincut(dev=(rp, col2, w))
+    assert e.value.code == -2
+    w3 = w.clone()
+    w3[:] = 1 << 60
+    with pytest.raises(mc.MincutError) as e:
+        ctx.mincut(dev=(rp, col, w3))
+    assert e.value.code == -3
