@@ -52,6 +52,7 @@ typedef enum {
 } mc_status;
 
 enum { MC_HOST = 0, MC_DEVICE = 1 };
+enum { MC_CF_PRIVATE = 0, MC_CF_SHARED = 1 };
 
 typedef struct {
     int32_t n;             /* vertices, >= 2 */
@@ -70,11 +71,17 @@ typedef struct {
     int32_t lp_iters;         /* label-propagation rounds per coarsening level
                                  (default 2) */
     int32_t pr_tri_deg_cap;   /* reserved (triangle tests); 0 = off */
-    int32_t capforest_passes; /* concurrent CAPFOREST passes per round (0 =
-                                 automatic, 4 per compute unit) */
-    int32_t pass_len_cap;     /* scans per pass (0 = until its queue empties) */
-    int32_t deterministic;    /* 1: passes do not share the visited array,
-                                 so results do not depend on timing */
+    int32_t capforest_passes; /* concurrent CAPFOREST passes per round
+                                 (0 = automatic) */
+    int32_t pass_len_cap;     /* scans per pass (0 = automatic; < 0 = until
+                                 the pass's queue empties) */
+    int32_t capforest_mode;   /* MC_CF_PRIVATE (default): passes with private
+                                 visited state that scan capped vertices in
+                                 batches; MC_CF_SHARED: passes that share one
+                                 visited array (Algorithm 1 as printed) */
+    int32_t deterministic;    /* 1: one sequential pass per round, one vertex
+                                 at a time, smallest id first on ties; the
+                                 whole solve then does not depend on timing */
     int32_t validate;         /* 1: check symmetry of host inputs */
 } mc_options;
 
@@ -94,7 +101,7 @@ typedef struct {
 typedef struct mc_ctx mc_ctx;
 
 /* Default options (seed 1, heuristic at n >= 10000, 2 LP rounds, automatic
- * pass count, no length cap, shared visited array, no validation). */
+ * pass count and length, private passes, no validation). */
 void mc_default_options(mc_options* opt);
 
 /* Create a context on HIP device `device` issuing all work on `hip_stream`

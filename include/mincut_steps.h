@@ -57,15 +57,22 @@ mc_status mc_step_components(mc_ctx* ctx, int32_t n, int64_t npairs, const int32
 mc_status mc_step_pr12(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, uint8_t* flag1, int32_t* ptr2,
                        int32_t* labels, int32_t* n2, void* ws, size_t ws_bytes);
 
-/* CAPFOREST (Algorithm 1). complete = 1: one sequential pass with no
- * capacity limit (Algorithm 2's fallback), from `start`. complete = 0:
- * `passes` concurrent passes in LDS (start >= 0 forces every pass to begin
- * there), sharing the visited array iff shared = 1, each stopping after
- * len_cap scans (0: no cap). Outputs: canonical labels of the marked edges
- * (labels[n], *n2), the scan order of pass 0 (order[n], *nscan), the
- * smallest alpha over the passes with its prefix length (*best_alpha =
- * INT64_MAX if none), and the bound after pass 0 (*lam_out). */
-mc_status mc_step_capforest(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t start, int32_t complete,
+/* CAPFOREST (Algorithm 1), in one of three forms (mode):
+ *  MC_STEP_CF_SHARED (0): `passes` concurrent passes, one wavefront each,
+ *     state in LDS (at most 1536 vertices touched per pass), sharing the
+ *     visited array iff shared = 1; start >= 0 forces every pass to begin
+ *     there;
+ *  MC_STEP_CF_SEQUENTIAL (1): one pass from `start`, one vertex at a time,
+ *     largest key and smallest id first, no capacity limit (Algorithm 2's
+ *     sequential fallback; the deterministic reference form);
+ *  MC_STEP_CF_PRIVATE (2): `passes` passes, one workgroup each, private
+ *     visited state in HBM, capped vertices scanned in batches.
+ * Each pass stops after len_cap scans (0: none). Outputs: canonical labels
+ * of the marked edges (labels[n], *n2), the scan order of pass 0 (order[n],
+ * *nscan), the smallest alpha over the passes with its prefix length
+ * (*best_alpha = INT64_MAX if none), and the bound after pass 0 (*lam_out). */
+enum { MC_STEP_CF_SHARED = 0, MC_STEP_CF_SEQUENTIAL = 1, MC_STEP_CF_PRIVATE = 2 };
+mc_status mc_step_capforest(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t start, int32_t mode,
                             int32_t passes, int32_t shared, int32_t len_cap, int32_t* labels, int32_t* n2,
                             int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,
                             int64_t* lam_out, void* ws, size_t ws_bytes);

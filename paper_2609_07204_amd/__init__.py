@@ -15,6 +15,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmincut.so")
 
 MC_HOST, MC_DEVICE = 0, 1
+MC_CF_PRIVATE, MC_CF_SHARED = 0, 1
+CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE = 0, 1, 2  # step modes
 STATUS = {0: "MC_OK", -1: "MC_E_INVALID_ARG", -2: "MC_E_BAD_GRAPH", -3: "MC_E_OVERFLOW", -4: "MC_E_OOM",
           -5: "MC_E_DEVICE", -6: "MC_E_NOT_READY", -7: "MC_E_CANCELLED", -8: "MC_E_TIMEOUT"}
 INT64_MAX = (1 << 63) - 1
@@ -34,7 +36,8 @@ class CSR(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("heuristic_min_n", ctypes.c_int32), ("lp_iters", ctypes.c_int32),
                 ("pr_tri_deg_cap", ctypes.c_int32), ("capforest_passes", ctypes.c_int32),
-                ("pass_len_cap", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
+                ("pass_len_cap", ctypes.c_int32), ("capforest_mode", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -238,14 +241,16 @@ class Context:
                                   ctypes.byref(n2), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return flag, ptr.cpu().numpy(), lab.cpu().numpy(), n2.value
 
-    def step_capforest(self, g, lam, start=0, complete=True, passes=1, shared=False, len_cap=0):
+    def step_capforest(self, g, lam, start=0, mode=CF_SEQUENTIAL, passes=1, shared=False, len_cap=0):
+        """One CAPFOREST launch in the given mode (CF_SHARED, CF_SEQUENTIAL,
+        CF_PRIVATE); see mc_step_capforest."""
         torch = _torch()
         lab = torch.empty(g.n, dtype=torch.int32, device=self.device)
         order = torch.full((max(g.n, 4096),), -1, dtype=torch.int32, device=self.device)
         n2, ns, bl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ba, lo = ctypes.c_int64(), ctypes.c_int64()
         ws = self.step_workspace(g.n, g.cap, passes)
-        _check(lib().mc_step_capforest(self.h, ctypes.byref(g.c()), lam, start, int(complete), passes, int(shared),
+        _check(lib().mc_step_capforest(self.h, ctypes.byref(g.c()), lam, start, int(mode), passes, int(shared),
                                        len_cap, _ptr(lab), ctypes.byref(n2), _ptr(order), ctypes.byref(ns),
                                        ctypes.byref(ba), ctypes.byref(bl), ctypes.byref(lo),
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel()))

@@ -17,7 +17,8 @@ LIB = os.path.join(PKG, "libmincut.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mc_scan.hip", "mc_contract.hip", "mc_graph_ops.hip", "mc_capforest.hip", "mc_solver.hip"]
+SOURCES = ["mc_scan.hip", "mc_contract.hip", "mc_graph_ops.hip", "mc_capforest.hip",
+           "mc_capforest_private.hip", "mc_solver.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]

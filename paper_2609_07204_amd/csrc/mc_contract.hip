@@ -33,16 +33,54 @@ constexpr int HSLOTS = 2048;        // LDS hash slots per chunk (load <= 1/2)
 constexpr int TILE_SLOTS = 256;     // global-table allocation and extraction unit
 constexpr uint64_t EMPTY_KEY = ~0ULL;
 
+// Counting sort of vertices by label. Contraction often sends most of a
+// wavefront to one label (a giant group), so for a few rounds the lanes that
+// share the label of the first pending lane combine their atomics into one;
+// whatever is left goes alone.
+constexpr int AGG_ROUNDS = 4;
 __global__ void k_group_count(const int32_t* __restrict__ L, int32_t n, int32_t* __restrict__ gcnt) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&gcnt[L[u]], 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t top = ((int64_t)n + MC_WAVE - 1) / MC_WAVE * MC_WAVE;
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < top; u += stride) {
+        bool pending = u < n;
+        const int32_t g = pending ? L[u] : -1;
+        for (int round = 0; round < AGG_ROUNDS; round++) {
+            const unsigned long long act = __ballot(pending);
+            if (act == 0) break;
+            const int lead = __ffsll((long long)act) - 1;
+            const int32_t gl = __shfl(g, lead, MC_WAVE);
+            const unsigned long long same = __ballot(pending && g == gl);
+            if (lane == lead) atomicAdd(&gcnt[gl], __popcll(same));
+            if (g == gl) pending = false;
+        }
+        if (pending) atomicAdd(&gcnt[g], 1);
+    }
 }
 
 __global__ void k_group_scatter(const int32_t* __restrict__ L, int32_t n, const int32_t* __restrict__ vstart,
                                 int32_t* __restrict__ gcur, int32_t* __restrict__ perm) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        int32_t g = L[u];
-        perm[vstart[g] + atomicAdd(&gcur[g], 1)] = (int32_t)u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t top = ((int64_t)n + MC_WAVE - 1) / MC_WAVE * MC_WAVE;
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < top; u += stride) {
+        bool pending = u < n;
+        const int32_t g = pending ? L[u] : -1;
+        for (int round = 0; round < AGG_ROUNDS; round++) {
+            const unsigned long long act = __ballot(pending);
+            if (act == 0) break;
+            const int lead = __ffsll((long long)act) - 1;
+            const int32_t gl = __shfl(g, lead, MC_WAVE);
+            const unsigned long long same = __ballot(pending && g == gl);
+            int32_t base = 0;
+            if (lane == lead) base = atomicAdd(&gcur[gl], __popcll(same));
+            base = __shfl(base, lead, MC_WAVE);
+            if (pending && g == gl) {
+                perm[vstart[gl] + base + __popcll(same & ((1ULL << lane) - 1))] = (int32_t)u;
+                pending = false;
+            }
+        }
+        if (pending) perm[vstart[g] + atomicAdd(&gcur[g], 1)] = (int32_t)u;
     }
 }
 
@@ -58,18 +96,29 @@ __global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t*
         gstart[g] = mstart[vstart[g]];
 }
 
-// Split groups into the chunk path and the global-table path; every group
-// gets its output window start.
+// Split groups into the chunk path and the large-group path; every group
+// gets its output window start. A few giant groups (at least a quarter of
+// n2 entries) accumulate into a dense array over all n2 targets instead of a
+// hash table: no probing, and the extraction is a stream over n2 values.
+constexpr int DENSE_SLOTS = 4;
+
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
                            int32_t* __restrict__ tsize, int32_t* __restrict__ bigm, int32_t* __restrict__ bcur,
-                           DGraph dst) {
+                           int32_t* __restrict__ dslot, int32_t* __restrict__ dinfo, DGraph dst) {
+    const int64_t dense_min = n2 / 4 > 16384 ? n2 / 4 : 16384;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x) {
         int32_t s = gstart[g + 1] - gstart[g];
         dst.off[g] = gstart[g];
+        dslot[g] = -1;
         if (s > SMALL_MAX) {
-            int64_t t = ((2 * (int64_t)s + TILE_SLOTS - 1) / TILE_SLOTS) * TILE_SLOTS;
-            tsize[g] = (int32_t)t;
-            bigm[g] = vstart ? vstart[g + 1] - vstart[g] : 1;
+            int32_t d = -1;
+            if (s >= dense_min) {
+                d = atomicAdd(&dinfo[0], 1);
+                if (d < DENSE_SLOTS) { dslot[g] = d; dinfo[1 + d] = (int32_t)g; } else d = -1;
+            }
+            const int64_t t = ((2 * (int64_t)s + TILE_SLOTS - 1) / TILE_SLOTS) * TILE_SLOTS;
+            tsize[g] = d >= 0 ? 0 : (int32_t)t;
+            bigm[g] = s;
             bcur[g] = 0;
             dst.len[g] = 0;
             dst.deg[g] = 0;
@@ -193,44 +242,140 @@ __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __rest
     }
 }
 
-// One wavefront per member row of a large group.
+// Large groups: their entries form one flattened space (bebase = prefix
+// of the entry counts of large groups). A workgroup takes a tile of
+// BIG_TILE entries, combines equal (group, target) pairs in an LDS hash, and
+// adds each distinct pair once to the group's global table, so a target hit
+// by many members costs one global atomic per tile rather than per entry.
+constexpr int BIG_TILE = 1024;
+constexpr int BIG_HSLOTS = 2048;
+
 __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* __restrict__ L,
                                                    const int32_t* __restrict__ perm,
                                                    const int32_t* __restrict__ vstart,
-                                                   const int32_t* __restrict__ bmbase,
+                                                   const int32_t* __restrict__ mstart,
+                                                   const int32_t* __restrict__ gstart,
+                                                   const int32_t* __restrict__ bebase,
                                                    const int32_t* __restrict__ tbase, int32_t n2,
                                                    int32_t* __restrict__ tkey, int64_t* __restrict__ tval,
+                                                   const int32_t* __restrict__ dslot, int64_t* __restrict__ dense,
                                                    DGraph dst) {
-    const int64_t total = bmbase[n2];
-    const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / MC_WAVE);
-    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE; i < total; i += nwaves) {
-        const int32_t g = last_le(bmbase, n2, i);
-        const int32_t m = (vstart ? vstart[g] : g) + (int32_t)(i - bmbase[g]);
-        const int32_t u = perm ? perm[m] : m;
-        const int32_t o = src.off[u], l = src.len[u];
-        const int32_t tb = tbase[g];
-        const uint32_t ts = (uint32_t)(tbase[g + 1] - tb);
-        for (int32_t j = lane; j < l; j += MC_WAVE) {
-            const int32_t x = src.col[o + j];
-            const int64_t c = src.w[o + j];
-            if (c <= 0) continue;
-            const int32_t t = L ? L[x] : x;
-            if (t == g) continue;
+    __shared__ unsigned long long hkey[BIG_HSLOTS];
+    __shared__ long long hval[BIG_HSLOTS];
+    __shared__ int32_t wm[BIG_TILE + 2];     // member-space start of each member in the window
+    __shared__ int32_t info[4];              // g, first member, member count in window, g's group end
+    const int64_t total = bebase[n2];
+    const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < BIG_HSLOTS; i += blockDim.x) { hkey[i] = EMPTY_KEY; hval[i] = 0; }
+        const int64_t e0 = tile * BIG_TILE;
+        const int64_t e1 = e0 + BIG_TILE < total ? e0 + BIG_TILE : total;
+        // a tile may straddle groups; handle it one group segment at a time
+        int64_t e = e0;
+        while (e < e1) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int32_t g = last_le(bebase, n2, e);
+                const int32_t ge = gstart[g] + (int32_t)(e - bebase[g]);
+                const int32_t m0 = vstart ? vstart[g] : g;
+                const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
+                const int32_t mf = m0 + last_le(mstart + m0, mc, ge);
+                info[0] = g;
+                info[1] = mf;
+                info[2] = (m0 + mc) - mf;            // members from mf to the group's end
+                info[3] = bebase[g + 1];
+            }
+            __syncthreads();
+            const int32_t g = info[0], mf = info[1];
+            const int32_t wc = info[2] < BIG_TILE + 1 ? info[2] : BIG_TILE + 1;
+            const int64_t seg_end = (int64_t)info[3] < e1 ? (int64_t)info[3] : e1;
+            for (int i = threadIdx.x; i <= wc; i += blockDim.x) wm[i] = mstart[mf + i];
+            __syncthreads();
+            const int32_t gbase = gstart[g] - bebase[g];
+            for (int64_t f = e + threadIdx.x; f < seg_end; f += blockDim.x) {
+                const int32_t ge = gbase + (int32_t)f;
+                int32_t k;
+                if (ge < wm[wc]) {
+                    int32_t lo = 0, hi = wc;
+                    while (hi - lo > 1) { int32_t mid = (lo + hi) >> 1; if (wm[mid] <= ge) lo = mid; else hi = mid; }
+                    k = mf + lo;
+                } else {
+                    // rows shorter than one entry cannot occur in a contracted
+                    // graph; search HBM if a window is ever too short
+                    const int32_t m0 = vstart ? vstart[g] : g;
+                    const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
+                    k = m0 + last_le(mstart + m0, mc, ge);
+                }
+                const int32_t u = perm ? perm[k] : k;
+                const int32_t j = ge - mstart[k];
+                const int32_t x = src.col[src.off[u] + j];
+                const int64_t c = src.w[src.off[u] + j];
+                if (c <= 0) continue;
+                const int32_t t = L ? L[x] : x;
+                if (t == g) continue;
+                const unsigned long long key = ((unsigned long long)(uint32_t)g << 32) | (uint32_t)t;
+                uint32_t h = hash32((uint32_t)t ^ hash32((uint32_t)g)) & (BIG_HSLOTS - 1);
+                for (;;) {
+                    unsigned long long kk = hkey[h];
+                    if (kk == key) break;
+                    if (kk == EMPTY_KEY) {
+                        unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
+                        if (old == EMPTY_KEY || old == key) break;
+                    }
+                    h = (h + 1) & (BIG_HSLOTS - 1);
+                }
+                atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c);
+            }
+            e = seg_end;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < BIG_HSLOTS; i += blockDim.x) {
+            const unsigned long long k = hkey[i];
+            if (k == EMPTY_KEY) continue;
+            const int32_t g = (int32_t)(k >> 32);
+            const int32_t t = (int32_t)(k & 0xFFFFFFFFu);
+            const int32_t d = dslot[g];
+            if (d >= 0) {
+                atomic_add_i64(&dense[(int64_t)d * n2 + t], hval[i]);
+                continue;
+            }
+            const int32_t tb = tbase[g];
+            const uint32_t ts = (uint32_t)(tbase[g + 1] - tb);
             uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)t) * ts) >> 32);
             for (;;) {
-                int32_t k = ld_acq(&tkey[tb + h]);
-                if (k == t) break;
-                if (k == -1) {
+                int32_t kk = ld_acq(&tkey[tb + h]);
+                if (kk == t) break;
+                if (kk == -1) {
                     int32_t old = atomicCAS(&tkey[tb + h], -1, t);
-                    if (old == -1) { atomicAdd(&dst.len[g], 1); break; }
-                    if (old == t) break;
+                    if (old == -1 || old == t) break;
                 }
                 if (++h == ts) h = 0;
             }
-            atomic_add_i64(&tval[tb + h], c);
+            atomic_add_i64(&tval[tb + h], hval[i]);
         }
+        __syncthreads();
     }
+}
+
+// Block-level allocation of output slots: one atomic per block for `take`
+// items; returns this thread's slot (valid where take) and the block sum of v.
+__device__ __forceinline__ int32_t block_alloc(int32_t* ctr, bool take, int64_t v, int64_t* deg,
+                                               int32_t* s_cnt, long long* s_sum, int32_t* s_base) {
+    const int lane = lane_id(), wid = threadIdx.x / MC_WAVE;
+    const unsigned long long m = __ballot(take);
+    const int32_t rank = __popcll(m & ((1ULL << lane) - 1));
+    const int64_t ws = wave_sum_i64(take ? v : 0);
+    if (lane == 0) { s_cnt[wid] = __popcll(m); s_sum[wid] = ws; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        long long sum = 0;
+        for (int k = 0; k < (int)(blockDim.x / MC_WAVE); k++) { int32_t c = s_cnt[k]; s_cnt[k] = tot; tot += c; sum += s_sum[k]; }
+        s_base[0] = tot ? atomicAdd(ctr, tot) : 0;
+        if (sum) atomic_add_i64(deg, sum);
+    }
+    __syncthreads();
+    return s_base[0] + s_cnt[wid] + rank;
 }
 
 __global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __restrict__ tbase,
@@ -238,19 +383,58 @@ __global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __res
                                                             const int32_t* __restrict__ tkey,
                                                             const int64_t* __restrict__ tval,
                                                             int32_t* __restrict__ bcur, DGraph dst) {
+    __shared__ int32_t sg, s_cnt[TILE_SLOTS / MC_WAVE], s_base[1];
+    __shared__ long long s_sum[TILE_SLOTS / MC_WAVE];
     const int64_t ntiles = tbase[n2] / TILE_SLOTS;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * TILE_SLOTS;
-        const int32_t g = last_le(tbase, n2, base);
+        __syncthreads();
+        if (threadIdx.x == 0) sg = last_le(tbase, n2, base);
+        __syncthreads();
+        const int32_t g = sg;
         const int64_t k = base + threadIdx.x;
         const int32_t key = tkey[k];
-        if (key < 0) continue;
-        const int64_t s = tval[k];
-        const int32_t pos = atomicAdd(&bcur[g], 1);
-        dst.col[gstart[g] + pos] = key;
-        dst.w[gstart[g] + pos] = s;
-        atomic_add_i64(&dst.deg[g], s);
+        const int64_t v = key >= 0 ? tval[k] : 0;
+        const int32_t pos = block_alloc(&bcur[g], key >= 0, v, &dst.deg[g], s_cnt, s_sum, s_base);
+        if (key >= 0) {
+            dst.col[gstart[g] + pos] = key;
+            dst.w[gstart[g] + pos] = v;
+        }
     }
+}
+
+// dense accumulators of the giant groups: stream over n2 targets, emit the
+// non-zero ones, and leave the array zero for the next contraction
+__global__ __launch_bounds__(256) void k_dense_extract(const int32_t* __restrict__ dinfo,
+                                                       const int32_t* __restrict__ gstart, int32_t n2,
+                                                       int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
+                                                       DGraph dst) {
+    __shared__ int32_t s_cnt[4], s_base[1];
+    __shared__ long long s_sum[4];
+    const int32_t nd = dinfo[0] < DENSE_SLOTS ? dinfo[0] : DENSE_SLOTS;
+    const int64_t per = ((int64_t)n2 + 255) / 256 * 256;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nd * per;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = (int32_t)(i / per);
+        const int32_t t = (int32_t)(i % per);
+        const int32_t g = dinfo[1 + d];
+        int64_t v = 0;
+        if (t < n2) {
+            v = dense[(int64_t)d * n2 + t];
+            if (v) dense[(int64_t)d * n2 + t] = 0;
+        }
+        const int32_t pos = block_alloc(&bcur[g], v != 0, v, &dst.deg[g], s_cnt, s_sum, s_base);
+        if (v != 0) {
+            dst.col[gstart[g] + pos] = t;
+            dst.w[gstart[g] + pos] = v;
+        }
+    }
+}
+
+__global__ void k_big_finalize(const int32_t* __restrict__ bebase, int32_t n2, const int32_t* __restrict__ bcur,
+                               DGraph dst) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x)
+        if (bebase[g + 1] > bebase[g]) dst.len[g] = bcur[g];
 }
 
 // minimum degree, ties to the smallest vertex: per-block partials, then one
@@ -312,6 +496,9 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
     size_t slots = (size_t)(cap * 5 / 2) + 4 * TILE_SLOTS;
     ws.tkey = a.take<int32_t>(slots);
     ws.tval = a.take<int64_t>(slots);
+    ws.dslot = a.take<int32_t>((size_t)n + 1);
+    ws.dinfo = a.take<int32_t>(1 + DENSE_SLOTS);
+    ws.dense = a.take<int64_t>((size_t)DENSE_SLOTS * ((size_t)n + 1));
     ws.scan_tmp = a.take<int32_t>(scan_tmp_elems((int64_t)n + 2) + 16);
     ws.red_val = a.take<int64_t>(1024);
     ws.red_id = a.take<int32_t>(1024);
@@ -352,18 +539,26 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
         MC_LAUNCHED("k_group_start");
         gstart = ws.gstart;
     }
-    k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, ws.tsize, ws.bigm, ws.bcur, dst);
+    if (!fill_i32(ws.dinfo, 0, 1 + DENSE_SLOTS, s) || !fill_i64(ws.dense, 0, (int64_t)DENSE_SLOTS * n2, s)) return false;
+    k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, ws.tsize, ws.bigm, ws.bcur, ws.dslot, ws.dinfo,
+                                                 dst);
     MC_LAUNCHED("k_classify");
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
-    if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bmbase
+    if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
     const int64_t chunks = (src.cap + n2) / CHUNK + 2;
     k_merge_small<<<(unsigned)chunks, MERGE_THREADS, 0, s>>>(src, L, perm, vstart, gstart, n2, dst);
     MC_LAUNCHED("k_merge_small");
     k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);
     MC_LAUNCHED("k_big_clear");
-    k_big_insert<<<2048, 256, 0, s>>>(src, L, perm, vstart, ws.bigm, ws.tsize, n2, ws.tkey, ws.tval, dst);
+    k_big_insert<<<4096, 256, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.bigm, ws.tsize, n2, ws.tkey,
+                                      ws.tval, ws.dslot, ws.dense, dst);
     MC_LAUNCHED("k_big_insert");
     k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.tkey, ws.tval, ws.bcur, dst);
     MC_LAUNCHED("k_big_extract");
+    k_dense_extract<<<grid_for((int64_t)DENSE_SLOTS * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, gstart, n2, ws.dense,
+                                                                                   ws.bcur, dst);
+    MC_LAUNCHED("k_dense_extract");
+    k_big_finalize<<<grid_for(n2, 256), 256, 0, s>>>(ws.bigm, n2, ws.bcur, dst);
+    MC_LAUNCHED("k_big_finalize");
     return min_degree(dst, ws, sc, s);
 }

@@ -6,6 +6,8 @@
 // contraction uses its components. Roots are always the smallest vertex of
 // their component (see uf_union), so numbering roots in increasing order
 // gives labels that do not depend on the order of the unions.
+#include <algorithm>
+
 #include "mc_internal.h"
 
 namespace {
@@ -64,14 +66,24 @@ __global__ void k_label(const int32_t* par, const int32_t* newid, int32_t n, int
 //          ties), moving v to p's side of any cut does not increase it; one
 //          such pointer per vertex may be contracted together with all
 //          connectivity-based marks of the round.
+// Rows longer than PR_LONG are handed to k_pr12_long (many workgroups per
+// row) so one giant collapsed vertex does not serialise the launch.
+constexpr int32_t PR_LONG = 2048;
+constexpr int32_t PR_CHUNK = 4096;
+
 __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int32_t* par,
-                                             unsigned long long* marks, uint8_t* flag1, int32_t* ptr2) {
+                                             unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
+                                             int32_t* long_list, int32_t* long_cnt) {
     const int64_t lam = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
         const int32_t o = g.off[v], l = g.len[v];
+        if (l > PR_LONG) {
+            if (sl == 0) long_list[atomicAdd(long_cnt, 1)] = (int32_t)v;
+            continue;
+        }
         int64_t bw = -1;
         int32_t bx = -1;
         for (int32_t j = sl; j < l; j += SUB) {
@@ -95,6 +107,108 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int
     }
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
     if (lane_id() == 0 && joined) atomicAdd(marks, joined);
+}
+
+// task offsets of the long rows: ceil(len / PR_CHUNK) tasks each
+__global__ __launch_bounds__(1024) void k_pr12_long_scan(const DGraph g, const int32_t* long_list,
+                                                        const int32_t* long_cnt, int32_t* task_off) {
+    __shared__ int32_t part[1024];
+    const int32_t nl = *long_cnt;
+    const int32_t per = (nl + 1023) / 1024;
+    const int32_t b = threadIdx.x * per, e = b + per < nl ? b + per : nl;
+    int32_t s = 0;
+    for (int32_t i = b; i < e; i++) s += (g.len[long_list[i]] + PR_CHUNK - 1) / PR_CHUNK;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < 1024; k++) { int32_t t = part[k]; part[k] = run; run += t; }
+        task_off[nl] = run;
+    }
+    __syncthreads();
+    int32_t run = part[threadIdx.x];
+    for (int32_t i = b; i < e; i++) {
+        task_off[i] = run;
+        run += (g.len[long_list[i]] + PR_CHUNK - 1) / PR_CHUNK;
+    }
+}
+
+__device__ __forceinline__ int32_t last_le_g(const int32_t* a, int32_t n, int64_t key) {
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)a[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// one workgroup per PR_CHUNK-entry piece of a long row: test 1 unions and
+// the piece's heaviest entry
+__global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp, int32_t* par,
+                                                  unsigned long long* marks, uint8_t* flag1,
+                                                  const int32_t* long_list, const int32_t* long_cnt,
+                                                  const int32_t* task_off, int64_t* part_w, int32_t* part_x) {
+    __shared__ int64_t sw[4];
+    __shared__ int32_t sx[4];
+    const int64_t lam = *lamp;
+    const int32_t nl = *long_cnt;
+    const int32_t ntask = task_off[nl];
+    unsigned long long joined = 0;
+    for (int32_t t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const int32_t i = last_le_g(task_off, nl, t);
+        const int32_t v = long_list[i];
+        const int32_t o = g.off[v], l = g.len[v];
+        const int32_t j0 = (t - task_off[i]) * PR_CHUNK;
+        const int32_t j1 = j0 + PR_CHUNK < l ? j0 + PR_CHUNK : l;
+        int64_t bw = -1;
+        int32_t bx = -1;
+        for (int32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+            const int32_t x = g.col[o + j];
+            const int64_t c = g.w[o + j];
+            const bool heavy = c >= lam;
+            if (flag1) flag1[o + j] = heavy;
+            if (heavy && x > v && uf_union(par, v, x)) joined++;
+            if (c > bw || (c == bw && x < bx)) { bw = c; bx = x; }
+        }
+        int32_t aux = 0;
+        wave_argmax(bw, bx, aux);
+        __syncthreads();
+        if (lane_id() == 0) { sw[threadIdx.x / MC_WAVE] = bw; sx[threadIdx.x / MC_WAVE] = bx; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < 4; k++)
+                if (sx[k] >= 0 && (bx < 0 || sw[k] > bw || (sw[k] == bw && sx[k] < bx))) { bw = sw[k]; bx = sx[k]; }
+            part_w[t] = bw;
+            part_x[t] = bx;
+        }
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) atomicAdd(marks, joined);
+}
+
+// one wavefront per long row: fold its pieces, apply test 2
+__global__ __launch_bounds__(64) void k_pr12_long_final(DGraph g, int32_t* par, unsigned long long* marks,
+                                                       int32_t* ptr2, const int32_t* long_list,
+                                                       const int32_t* long_cnt, const int32_t* task_off,
+                                                       const int64_t* part_w, const int32_t* part_x) {
+    const int32_t nl = *long_cnt;
+    for (int32_t i = blockIdx.x; i < nl; i += gridDim.x) {
+        int64_t bw = -1;
+        int32_t bx = -1;
+        for (int32_t t = task_off[i] + threadIdx.x; t < task_off[i + 1]; t += MC_WAVE) {
+            const int64_t w2 = part_w[t];
+            const int32_t x2 = part_x[t];
+            if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
+        }
+        int32_t aux = 0;
+        wave_argmax(bw, bx, aux);
+        if (threadIdx.x == 0) {
+            const int32_t v = long_list[i];
+            const bool take = bx >= 0 && 2 * bw >= g.deg[v];
+            if (ptr2) ptr2[v] = take ? bx : -1;
+            if (take && uf_union(par, v, bx)) atomicAdd(marks, 1ULL);
+        }
+    }
 }
 
 __global__ void k_map_update(int32_t* map0, const int32_t* L, int32_t n0) {
@@ -195,10 +309,31 @@ bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_
     return true;
 }
 
+void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
+    // rows longer than PR_LONG: at most n and at most cap / PR_LONG
+    const size_t nlong = (size_t)std::min<int64_t>(n, cap / PR_LONG + 1) + 64;
+    w.long_list = a.take<int32_t>(nlong);
+    w.counters = a.take<int32_t>(4);
+    w.task_off = a.take<int32_t>(nlong + 1);
+    const size_t tasks = (size_t)(cap / PR_CHUNK) + nlong;
+    w.part_w = a.take<int64_t>(tasks);
+    w.part_x = a.take<int32_t>(tasks);
+}
+
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
-          int32_t* ptr2, hipStream_t s) {
-    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, marks, flag1, ptr2);
+          int32_t* ptr2, Pr12WS& w, hipStream_t s) {
+    if (!fill_i32(w.counters, 0, 4, s)) return false;
+    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, marks, flag1, ptr2, w.long_list,
+                                                            w.counters);
     MC_LAUNCHED("k_pr12");
+    k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);
+    MC_LAUNCHED("k_pr12_long_scan");
+    k_pr12_long<<<2048, 256, 0, s>>>(g, lam, parent, marks, flag1, w.long_list, w.counters, w.task_off, w.part_w,
+                                     w.part_x);
+    MC_LAUNCHED("k_pr12_long");
+    k_pr12_long_final<<<256, 64, 0, s>>>(g, parent, marks, ptr2, w.long_list, w.counters, w.task_off, w.part_w,
+                                         w.part_x);
+    MC_LAUNCHED("k_pr12_long_final");
     return true;
 }
 

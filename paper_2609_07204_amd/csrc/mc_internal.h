@@ -52,10 +52,13 @@ struct ContractWS {
     int32_t* mstart;  // [n+1]  entry offset of each member (perm order)
     int32_t* gstart;  // [n+1]  entry offset of each group
     int32_t* tsize;   // [n+1]  hash-table slots of each large group -> tbase
-    int32_t* bigm;    // [n+1]  members of each large group -> bmbase
+    int32_t* bigm;    // [n+1]  entries of each large group -> bebase
     int32_t* bcur;    // [n]
     int32_t* tkey;    // [4*cap+1024]
     int64_t* tval;    // [4*cap+1024]
+    int32_t* dslot;   // [n+1]  dense accumulator of a giant group, or -1
+    int32_t* dinfo;   // [1+slots] count, then the group of each slot
+    int64_t* dense;   // [slots*(n+1)]
     int32_t* scan_tmp;
     int64_t* red_val; // [1024] per-block minima
     int32_t* red_id;  // [1024]
@@ -85,8 +88,16 @@ bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_
 // Padberg-Rinaldi test 1 (entry weight >= lam) and test 2 (one pointer per
 // vertex to its heaviest neighbour when 2 c(v,p) >= c(v)), unioned into
 // parent. Optional outputs for parity checks: flag1[entry], ptr2[vertex].
+struct Pr12WS {
+    int32_t* long_list;   // rows too long for the per-row pass
+    int32_t* counters;
+    int32_t* task_off;
+    int64_t* part_w;
+    int32_t* part_x;
+};
+void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
-          uint8_t* flag1, int32_t* ptr2, hipStream_t s);
+          uint8_t* flag1, int32_t* ptr2, Pr12WS& w, hipStream_t s);
 
 // ----------------------------------------------------------- CAPFOREST
 struct CapforestArgs {
@@ -131,6 +142,42 @@ struct CompleteArgs {
     unsigned long long* marks;
 };
 bool capforest_complete(const CompleteArgs& a, hipStream_t s);
+
+// Private passes with capped batches: `passes` workgroups, each one pass
+// with its own dense state over the vertices (no shared visited array), so
+// passes never fragment each other's traversal. All queued vertices whose
+// key is capped at lam are scanned together as one batch.
+struct PrivateArgs {
+    DGraph g;
+    const int64_t* lam;
+    int32_t* parent;
+    int32_t passes;
+    int32_t len_cap;        // scans per pass, 0 = unlimited (complete pass)
+    uint64_t seed;
+    int32_t round;
+    int32_t start;          // >= 0: every pass starts here
+    int64_t stride;         // elements per pass in the per-pass arrays (>= n)
+    int32_t* st;            // [passes*stride] 0 new, 1 queued, 2 scanned, 3 in batch; all 0 between calls
+    int64_t* r;             // [passes*stride] all 0 between calls
+    int32_t* fifo;          // [passes*stride] capped vertices in crossing order
+    int32_t* touched;       // [passes*stride]
+    int32_t* order;         // [passes*stride] scanned vertices
+    int64_t stride1;        // elements per pass in l1 / dlist (>= n/64 + 1)
+    int64_t* l1;            // [passes*stride1] per 64-vertex block: max r of queued uncapped vertices
+    int32_t* dlist;         // [passes*stride1] blocks whose l1 may be stale
+    uint32_t* dbits;        // [passes*(stride1/32+1)] dirty flags of the blocks
+    int32_t* nscan;         // [passes]
+    int64_t* alpha;         // [passes]
+    int32_t* alpha_len;     // [passes]
+    int64_t* lam_out;       // [passes]
+    unsigned long long* marks;
+    int32_t* steps;         // [passes] batches + single pops (diagnostics)
+    int64_t* diag;          // [passes*8] optional counters (nullptr: off)
+};
+constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
+bool capforest_private(const PrivateArgs& a, hipStream_t s);
+// clear st/r of a fresh workspace region (once per solve)
+bool capforest_private_reset(const PrivateArgs& a, hipStream_t s);
 
 // -------------------------------------------------------- side tracking
 bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s);

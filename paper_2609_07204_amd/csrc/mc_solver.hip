@@ -15,6 +15,8 @@
 // snapshot from the vertex or scanned prefix that produced the new bound.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,6 +44,13 @@ __global__ void k_reset_round(DevScalars* sc) {
 __global__ void k_uf_pairs(const int32_t* a, const int32_t* b, int64_t np, int32_t* par) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
         uf_union(par, a[i], b[i]);
+}
+
+uint64_t splitmix_host(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
 }
 
 mc_status fail(mc_status code, const std::string& msg) {
@@ -76,6 +85,7 @@ extern "C" void mc_default_options(mc_options* o) {
     o->pr_tri_deg_cap = 0;
     o->capforest_passes = 0;
     o->pass_len_cap = 0;
+    o->capforest_mode = MC_CF_PRIVATE;
     o->deterministic = 0;
     o->validate = 0;
 }
@@ -146,6 +156,9 @@ struct SolveWS {
     int64_t* calpha = nullptr;
     int32_t* calen = nullptr;
     int64_t* clamout = nullptr;
+    Pr12WS prw{};
+    PrivateArgs pv{};             // per-pass arrays of the private passes
+    int32_t* psteps = nullptr;
     DevScalars* sc = nullptr;
     unsigned long long* vpart = nullptr;
 };
@@ -160,7 +173,29 @@ void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
     g.w = a.take<int64_t>((size_t)cap + 1);
 }
 
-void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, bool host_input, int ngraphs, SolveWS& w) {
+void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t*& psteps) {
+    pv.passes = passes;
+    pv.stride = n;
+    const size_t cnt = (size_t)passes * (size_t)n;
+    pv.st = a.take<int32_t>(cnt);
+    pv.r = a.take<int64_t>(cnt);
+    pv.fifo = a.take<int32_t>(cnt);
+    pv.touched = a.take<int32_t>(cnt);
+    pv.order = a.take<int32_t>(cnt);
+    pv.stride1 = (int64_t)n / 64 + 2;
+    pv.l1 = a.take<int64_t>((size_t)passes * (size_t)pv.stride1);
+    pv.dlist = a.take<int32_t>((size_t)passes * (size_t)pv.stride1);
+    pv.dbits = a.take<uint32_t>((size_t)passes * (size_t)(pv.stride1 / 32 + 1));
+    pv.nscan = a.take<int32_t>((size_t)passes);
+    pv.alpha = a.take<int64_t>((size_t)passes);
+    pv.alpha_len = a.take<int32_t>((size_t)passes);
+    pv.lam_out = a.take<int64_t>((size_t)passes);
+    psteps = a.take<int32_t>((size_t)passes);
+    pv.diag = a.take<int64_t>((size_t)passes * 8);
+}
+
+void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, bool host_input, int ngraphs,
+           SolveWS& w) {
     w.sc = a.take<DevScalars>(1);
     if (host_input) {
         w.in_rp = a.take<int32_t>((size_t)n + 1);
@@ -176,6 +211,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, bool host_input, in
     w.map0 = a.take<int32_t>((size_t)n + 1);
     w.side = a.take<uint8_t>((size_t)n + 1);
     contract_ws_carve(a, n, cap, w.cw);
+    pr12_ws_carve(a, n, cap, w.prw);
     w.passes = passes;
     w.order = a.take<int32_t>((size_t)passes * CF_HC);
     w.nscan = a.take<int32_t>((size_t)passes);
@@ -191,12 +227,34 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, bool host_input, in
     w.calen = a.take<int32_t>(1);
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
+    carve_private(a, n, ppasses, w.pv, w.psteps);
 }
 
+// passes of the shared-visited-array form (one wavefront each)
 int32_t pass_count(const mc_ctx* c) {
+    if (c->opt.capforest_mode != MC_CF_SHARED) return 1;
     int32_t p = c->opt.capforest_passes;
     if (p <= 0) p = 4 * c->cus;
     return p;
+}
+
+// passes of the private form (one workgroup each); per-pass state costs
+// PRIV_BYTES_PER_VERTEX * n, kept under 16 GiB by default
+int32_t private_pass_count(const mc_ctx* c, int32_t n) {
+    if (c->opt.capforest_mode == MC_CF_SHARED || c->opt.deterministic) return 1;
+    int32_t p = c->opt.capforest_passes;
+    if (p > 0) return p;
+    const double budget = 16.0 * (1 << 30);
+    int64_t fit = (int64_t)(budget / ((double)PRIV_BYTES_PER_VERTEX * (n > 0 ? n : 1)));
+    p = 128;
+    if (fit < p) p = (int32_t)(fit < 8 ? 8 : fit);
+    return p;
+}
+
+int32_t private_len_cap(const mc_ctx* c) {
+    if (c->opt.pass_len_cap < 0) return 0;
+    if (c->opt.pass_len_cap > 0) return c->opt.pass_len_cap;
+    return 8192;
 }
 
 // Host-side checks of a host CSR (exact, including symmetry when asked).
@@ -245,6 +303,7 @@ struct Solver {
     SolveWS w;
     int32_t n0 = 0;
     int64_t lam = 0;
+    bool debug = false;
     mc_stats stats{};
 
     bool readback() {
@@ -267,9 +326,79 @@ extern "C" mc_status mc_workspace_size(const mc_ctx* c, int32_t n, int32_t nnz, 
     if (n < 2 || nnz < 0) return fail(MC_E_INVALID_ARG, "mc_workspace_size: need n >= 2 and nnz >= 0");
     Arena a;
     SolveWS w;
-    carve(a, n, nnz, pass_count(c), true, 3, w);
+    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), true, 3, w);
     *bytes = a.used + 256;
     return MC_OK;
+}
+
+// MC_DEBUG=1: one line per round on stderr (sizes, marks, pass counters).
+static void debug_round(Solver& S, const DGraph& g, int32_t round, int32_t passes) {
+    DevScalars h = *S.c->hsc;
+    std::vector<int64_t> d((size_t)std::max(passes, 1) * 8, 0);
+    std::vector<int32_t> len((size_t)g.n);
+    if (passes > 0) (void)hipMemcpy(d.data(), S.w.pv.diag, d.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(len.data(), g.len, len.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    int64_t nnz = 0;
+    for (int32_t v : len) nnz += v;
+    int64_t mx[8] = {0}, sum[8] = {0};
+    for (int32_t p = 0; p < passes; p++)
+        for (int k = 0; k < 8; k++) { mx[k] = std::max(mx[k], d[p * 8 + k]); sum[k] += d[p * 8 + k]; }
+    int clk = 100000;
+    (void)hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, S.c->device);
+    fprintf(stderr,
+            "[mc] round %d n=%d nnz=%lld lam=%lld marks_pr=%llu marks_cf=%llu | passes=%d steps max %lld singles max %lld "
+            "touched max %lld entries sum %lld max %lld | pop ms max %.3f batch ms max %.3f | scans max %lld maxbatch %lld\n",
+            round, g.n, (long long)nnz, (long long)S.lam, h.marks_pr, h.marks_cf, passes, (long long)mx[0],
+            (long long)mx[1], (long long)mx[2], (long long)sum[3], (long long)mx[3], mx[4] / (double)clk,
+            mx[5] / (double)clk, (long long)mx[6], (long long)mx[7]);
+}
+
+// One sequential single-pop pass over g (deterministic), results in sc.
+static bool sequential_pass(Solver& S, const DGraph& g, int32_t round) {
+    SolveWS& w = S.w;
+    CompleteArgs cp{};
+    cp.g = g;
+    cp.lam = &w.sc->lam;
+    cp.parent = w.parent;
+    cp.start = (int32_t)(splitmix_host(S.c->opt.seed ^ (uint64_t)round) % (uint64_t)g.n);
+    cp.tag = ++S.c->tag;
+    cp.st = w.cst;
+    cp.r = w.cr;
+    cp.l1 = w.cl1;
+    cp.order = w.corder;
+    cp.nscan = w.cnscan;
+    cp.alpha = w.calpha;
+    cp.alpha_len = w.calen;
+    cp.lam_out = w.clamout;
+    cp.marks = &w.sc->marks_cf;
+    if (!capforest_complete(cp, S.s)) return false;
+    CapforestArgs ra{};
+    ra.alpha = w.calpha;
+    ra.alpha_len = w.calen;
+    ra.passes = 1;
+    return capforest_reduce(ra, w.sc, S.s);
+}
+
+// `passes` private batched passes over g (len_cap 0: complete), results in sc.
+static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t passes, int32_t len_cap) {
+    SolveWS& w = S.w;
+    PrivateArgs pa = w.pv;
+    pa.g = g;
+    pa.lam = &w.sc->lam;
+    pa.parent = w.parent;
+    pa.passes = passes;
+    pa.len_cap = len_cap;
+    pa.seed = S.c->opt.seed;
+    pa.round = round;
+    pa.start = -1;
+    pa.marks = &w.sc->marks_cf;
+    pa.steps = w.psteps;
+    if (!capforest_private(pa, S.s)) return false;
+    CapforestArgs ra{};
+    ra.alpha = pa.alpha;
+    ra.alpha_len = pa.alpha_len;
+    ra.passes = passes;
+    return capforest_reduce(ra, w.sc, S.s);
 }
 
 // Exact rounds of Algorithm 2 on w.g[src] until at most two vertices remain.
@@ -284,69 +413,66 @@ static mc_status exact_rounds(Solver& S, int src) {
         const int32_t n = cur->n;
         k_reset_round<<<1, 1, 0, s>>>(w.sc);
         if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
-        if (!pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, s)) return MC_E_DEVICE;
-        CapforestArgs ca{};
-        ca.g = *cur;
-        ca.lam = &w.sc->lam;
-        ca.parent = w.parent;
-        ca.claim = w.claim;
-        ca.tag = ++S.c->tag;
-        ca.shared = S.c->opt.deterministic ? 0 : 1;
-        ca.passes = w.passes;
-        ca.len_cap = S.c->opt.pass_len_cap;
-        ca.seed = S.c->opt.seed;
-        ca.start = -1;
-        ca.order = w.order;
-        ca.nscan = w.nscan;
-        ca.alpha = w.alpha;
-        ca.alpha_len = w.alen;
-        ca.lam_out = w.lamout;
-        ca.marks = &w.sc->marks_cf;
-        if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+        if (!pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, w.prw, s)) return MC_E_DEVICE;
+        const bool det = S.c->opt.deterministic != 0;
+        const bool shared = S.c->opt.capforest_mode == MC_CF_SHARED && !det;
+        const int32_t* pref_order = nullptr;   // scan order of the pass with the best alpha
+        if (det) {
+            if (!sequential_pass(S, *cur, round)) return MC_E_DEVICE;
+        } else if (shared) {
+            CapforestArgs ca{};
+            ca.g = *cur;
+            ca.lam = &w.sc->lam;
+            ca.parent = w.parent;
+            ca.claim = w.claim;
+            ca.tag = ++S.c->tag;
+            ca.shared = 1;
+            ca.passes = w.passes;
+            ca.len_cap = S.c->opt.pass_len_cap > 0 ? S.c->opt.pass_len_cap : 0;
+            ca.seed = S.c->opt.seed;
+            ca.start = -1;
+            ca.order = w.order;
+            ca.nscan = w.nscan;
+            ca.alpha = w.alpha;
+            ca.alpha_len = w.alen;
+            ca.lam_out = w.lamout;
+            ca.marks = &w.sc->marks_cf;
+            if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+        } else {
+            if (!private_passes(S, *cur, round, w.pv.passes, private_len_cap(S.c))) return MC_E_DEVICE;
+        }
         if (!S.readback()) return MC_E_DEVICE;
         DevScalars h = *S.c->hsc;
+        if (S.debug) debug_round(S, *cur, round, det || shared ? 0 : w.pv.passes);
         if (h.best_pass >= 0 && h.best_alpha < S.lam) {
-            if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, w.order + (int64_t)h.best_pass * CF_HC,
-                                  &w.sc->best_len, s))
+            if (det) pref_order = w.corder;
+            else if (shared) pref_order = w.order + (int64_t)h.best_pass * CF_HC;
+            else pref_order = w.pv.order + (int64_t)h.best_pass * w.pv.stride;
+            if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, pref_order, &w.sc->best_len, s))
                 return MC_E_DEVICE;
             if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
         }
         S.stats.marks_pr += (int64_t)h.marks_pr;
         S.stats.marks_capforest += (int64_t)h.marks_cf;
         if (h.marks_pr + h.marks_cf == 0) {
-            // Algorithm 2: no contractible edge found, run CAPFOREST
-            // sequentially over the whole graph.
+            // Algorithm 2: no contractible edge found, run CAPFOREST over the
+            // whole graph without a length limit; with a fixed bound it marks
+            // at least one edge, otherwise it lowered the bound
             const int64_t lam_before = S.lam;
-            CompleteArgs cp{};
-            cp.g = *cur;
-            cp.lam = &w.sc->lam;
-            cp.parent = w.parent;
-            cp.start = (int32_t)(((S.c->opt.seed * 0x9E3779B97F4A7C15ULL + (uint64_t)round) >> 33) % (uint64_t)n);
-            cp.tag = ++S.c->tag;
-            cp.st = w.cst;
-            cp.r = w.cr;
-            cp.l1 = w.cl1;
-            cp.order = w.corder;
-            cp.nscan = w.cnscan;
-            cp.alpha = w.calpha;
-            cp.alpha_len = w.calen;
-            cp.lam_out = w.clamout;
-            cp.marks = &w.sc->marks_cf;
-            if (!capforest_complete(cp, s)) return MC_E_DEVICE;
-            int64_t calpha = 0;
-            int32_t cns = 0;
-            if (hipMemcpyAsync(&cns, w.cnscan, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
-                return fail(MC_E_DEVICE, "readback after sequential CAPFOREST failed");
-            if (hipMemcpyAsync(&calpha, w.calpha, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                !S.readback())
-                return fail(MC_E_DEVICE, "readback after sequential CAPFOREST failed");
+            if (det) {
+                if (!sequential_pass(S, *cur, round + 7777)) return MC_E_DEVICE;
+            } else {
+                if (!private_passes(S, *cur, round + 7777, 1, 0)) return MC_E_DEVICE;
+            }
+            if (!S.readback()) return MC_E_DEVICE;
             h = *S.c->hsc;
-            if (cns < 0) return fail(MC_E_DEVICE, "sequential CAPFOREST: inconsistent queue index");
             S.stats.fallback_passes++;
             S.stats.marks_capforest += (int64_t)h.marks_cf;
-            if (calpha < S.lam) {
-                if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, w.corder, w.calen, s)) return MC_E_DEVICE;
-                if (!S.set_lam(calpha)) return MC_E_DEVICE;
+            if (h.best_pass >= 0 && h.best_alpha < S.lam) {
+                pref_order = det ? w.corder : w.pv.order;
+                if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, pref_order, &w.sc->best_len, s))
+                    return MC_E_DEVICE;
+                if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
             }
             if (h.marks_cf == 0) {
                 if (S.lam < lam_before) { round++; continue; }
@@ -391,12 +517,13 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     Solver S;
     S.c = c;
     S.s = c->stream;
+    S.debug = getenv("MC_DEBUG") != nullptr;
     const int32_t n = g->n;
     const int64_t nnz = g->nnz;
     Arena a;
     a.base = (char*)dev_ws;
     a.size = ws_bytes;
-    carve(a, n, nnz, pass_count(c), host_input, 3, S.w);
+    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), host_input, 3, S.w);
     if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
     SolveWS& w = S.w;
     hipStream_t s = S.s;
@@ -432,6 +559,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     if (!csr_to_padded(rp, n, user.off, user.len, s)) return MC_E_DEVICE;
     if (!contract(user, nullptr, n, w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
+    if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected
     if (!uf_init(w.parent, n, s) || !uf_all_edges(w.g[0], w.parent, s) ||
         !uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
@@ -497,6 +625,9 @@ struct StepWS {
     int64_t* cr;
     int64_t* cl1;
     int64_t* lam;
+    PrivateArgs pv;
+    int32_t* psteps;
+    Pr12WS prw;
 };
 
 void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
@@ -506,6 +637,7 @@ void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.flag = a.take<int32_t>((size_t)n + 2);
     w.claim = a.take<int32_t>((size_t)n + 1);
     contract_ws_carve(a, n, cap, w.cw);
+    pr12_ws_carve(a, n, cap, w.prw);
     if (passes < 1) passes = 1;
     w.order = a.take<int32_t>((size_t)passes * CF_HC);
     w.nscan = a.take<int32_t>((size_t)passes);
@@ -515,6 +647,7 @@ void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.cst = a.take<int32_t>((size_t)n + 1);
     w.cr = a.take<int64_t>((size_t)n + 1);
     w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
+    carve_private(a, n, passes, w.pv, w.psteps);
 }
 
 mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws, size_t bytes, StepWS& w) {
@@ -586,30 +719,36 @@ extern "C" mc_status mc_step_pr12(mc_ctx* c, const mc_dgraph* g, int64_t lam, ui
     k_set_lam<<<1, 1, 0, s>>>(w.sc, lam);
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
     if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
-    if (!pr12(to_dgraph(g), &w.sc->lam, w.parent, &w.sc->marks_pr, flag1, ptr2, s)) return MC_E_DEVICE;
+    if (!pr12(to_dgraph(g), &w.sc->lam, w.parent, &w.sc->marks_pr, flag1, ptr2, w.prw, s)) return MC_E_DEVICE;
     if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
     if ((r = sync_read(c, w)) != MC_OK) return r;
     if (n2) *n2 = c->hsc->n2;
     return MC_OK;
 }
 
-extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t lam, int32_t start, int32_t complete,
+extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t lam, int32_t start, int32_t mode,
                                        int32_t passes, int32_t shared, int32_t len_cap, int32_t* labels, int32_t* n2,
                                        int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,
                                        int64_t* lam_out, void* ws, size_t bytes) {
     if (!g || !labels || !order) return fail(MC_E_INVALID_ARG, "mc_step_capforest: NULL argument");
-    if ((complete && start < 0) || start >= g->n) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
-    if (!complete && passes < 1) return fail(MC_E_INVALID_ARG, "mc_step_capforest: passes must be >= 1");
+    if (mode < MC_STEP_CF_SHARED || mode > MC_STEP_CF_PRIVATE) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad mode");
+    if ((mode == MC_STEP_CF_SEQUENTIAL && start < 0) || start >= g->n)
+        return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
+    if (mode != MC_STEP_CF_SEQUENTIAL && passes < 1) return fail(MC_E_INVALID_ARG, "mc_step_capforest: passes must be >= 1");
+    if (mode == MC_STEP_CF_SEQUENTIAL) passes = 1;
     StepWS w;
-    mc_status r = step_begin(c, g->n, g->cap, complete ? 1 : passes, ws, bytes, w);
+    mc_status r = step_begin(c, g->n, g->cap, passes, ws, bytes, w);
     if (r != MC_OK) return r;
     hipStream_t s = c->stream;
     k_set_lam<<<1, 1, 0, s>>>(w.sc, lam);
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
     if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
-    int64_t alpha = 0, lo = 0;
-    int32_t alen = 0, ns = 0;
-    if (complete) {
+    const int32_t* nscan_dev = w.nscan;
+    const int64_t* lamout_dev = w.lamout;
+    const int32_t* order_dev = w.order;
+    int64_t order_len = CF_HC;
+    CapforestArgs red{};
+    if (mode == MC_STEP_CF_SEQUENTIAL) {
         CompleteArgs cp{};
         cp.g = to_dgraph(g);
         cp.lam = &w.sc->lam;
@@ -626,7 +765,11 @@ extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t la
         cp.lam_out = w.lamout;
         cp.marks = &w.sc->marks_cf;
         if (!capforest_complete(cp, s)) return MC_E_DEVICE;
-    } else {
+        red.alpha = w.alpha;
+        red.alpha_len = w.alen;
+        red.passes = 1;
+        order_dev = nullptr;
+    } else if (mode == MC_STEP_CF_SHARED) {
         if (!fill_i32(w.claim, 0, g->n, s)) return MC_E_DEVICE;
         CapforestArgs ca{};
         ca.g = to_dgraph(g);
@@ -645,28 +788,45 @@ extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t la
         ca.alpha_len = w.alen;
         ca.lam_out = w.lamout;
         ca.marks = &w.sc->marks_cf;
-        if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+        if (!capforest_passes(ca, s)) return MC_E_DEVICE;
+        red = ca;
+    } else {
+        PrivateArgs pa = w.pv;
+        pa.g = to_dgraph(g);
+        pa.lam = &w.sc->lam;
+        pa.parent = w.parent;
+        pa.passes = passes;
+        pa.len_cap = len_cap;
+        pa.seed = c->opt.seed;
+        pa.round = ++c->tag;
+        pa.start = start;
+        pa.marks = &w.sc->marks_cf;
+        pa.steps = w.psteps;
+        if (!capforest_private_reset(pa, s) || !capforest_private(pa, s)) return MC_E_DEVICE;
+        red.alpha = pa.alpha;
+        red.alpha_len = pa.alpha_len;
+        red.passes = passes;
+        nscan_dev = pa.nscan;
+        lamout_dev = pa.lam_out;
+        order_dev = pa.order;
+        order_len = g->n;
     }
+    if (!capforest_reduce(red, w.sc, s)) return MC_E_DEVICE;
     if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
-    if (hipMemcpyAsync(&ns, w.nscan, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&lo, w.lamout, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    int32_t ns = 0;
+    int64_t lo = 0;
+    if (hipMemcpyAsync(&ns, nscan_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&lo, lamout_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return fail(MC_E_DEVICE, "step: readback failed");
-    if (!complete && hipMemcpyAsync(order, w.order, sizeof(int32_t) * (size_t)CF_HC, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (order_dev &&
+        hipMemcpyAsync(order, order_dev, sizeof(int32_t) * (size_t)order_len, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(MC_E_DEVICE, "step: order copy failed");
     if ((r = sync_read(c, w)) != MC_OK) return r;
     DevScalars h = *c->hsc;
-    if (complete) {
-        if (hipMemcpy(&alpha, w.alpha, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(&alen, w.alen, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-            return fail(MC_E_DEVICE, "step: readback failed");
-    } else {
-        alpha = h.best_alpha;
-        alen = h.best_len;
-    }
     if (n2) *n2 = h.n2;
     if (nscan) *nscan = ns;
-    if (best_alpha) *best_alpha = alpha;
-    if (best_len) *best_len = alen;
+    if (best_alpha) *best_alpha = h.best_alpha;
+    if (best_len) *best_len = h.best_len;
     if (lam_out) *lam_out = lo;
     return MC_OK;
 }

@@ -13,6 +13,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
+CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE = 0, 1, 2
+
 
 def say(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -189,7 +191,7 @@ def test_capforest_complete_pass_matches_oracle(ctx, name, mk):
     dev, dmin, _ = canon_dev(ctx, g)
     for start in (0, g.n // 2, g.n - 1):
         for lam in (dmin, max(1, dmin // 2), dmin * 3):
-            res = ctx.step_capforest(dev, lam, start=start, complete=True)
+            res = ctx.step_capforest(dev, lam, start=start, mode=CF_SEQUENTIAL)
             check_cf_equal(res, cf_oracle(g, lam, start))
 
 
@@ -203,11 +205,12 @@ def test_capforest_lds_pass_matches_oracle(ctx, name, mk):
             # every graph here has n + max degree <= 1536, so the pass never
             # runs out of hash capacity and must match the oracle exactly
             assert g.n + int(np.diff(g.row_ptr).max()) <= 1536
-            res = ctx.step_capforest(dev, dmin, start=start, complete=False, passes=1, shared=False, len_cap=cap)
+            res = ctx.step_capforest(dev, dmin, start=start, mode=CF_SHARED, passes=1, shared=False, len_cap=cap)
             check_cf_equal(res, cf_oracle(g, dmin, start, cap))
 
 
-def test_capforest_parallel_marks_are_safe(ctx):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_capforest_parallel_marks_are_safe(ctx, mode):
     for seed in range(12):
         g = gen.random_small(12 + seed % 5, 0.5, 4000 + seed, 1, 9)
         lam_min = int(oracle.degrees(g).min())
@@ -215,7 +218,7 @@ def test_capforest_parallel_marks_are_safe(ctx):
             continue
         say("capforest parallel safety", seed)
         dev, dmin, _ = canon_dev(ctx, g)
-        res = ctx.step_capforest(dev, dmin, start=-1, complete=False, passes=64, shared=True)
+        res = ctx.step_capforest(dev, dmin, start=-1, mode=mode, passes=64, shared=True)
         # each pass marks against its own bound, which never drops below
         # min(dmin, smallest alpha of any pass); connectivity is ultrametric,
         # so every pair joined through marks clears that threshold
@@ -307,3 +310,57 @@ def test_bad_device_input_rejected(ctx):
     with pytest.raises(mc.MincutError) as e:
         ctx.mincut(dev=(rp, col, w3))
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("name,mk", CF_GRAPHS)
+def test_capforest_private_complete_pass_is_valid(ctx, name, mk):
+    # one private pass without a length cap scans every vertex once; its
+    # recorded alpha is the capacity of its scanned prefix; contracting its
+    # marks keeps lambda whenever the final bound is above lambda
+    g = mk()
+    say("capforest private complete", name, g.n)
+    dev, dmin, _ = canon_dev(ctx, g)
+    lam_true = oracle.stoer_wagner(g)[0]
+    for start in (0, g.n // 2):
+        res = ctx.step_capforest(dev, dmin, start=start, mode=CF_PRIVATE, passes=1)
+        order = res["order"]
+        assert order.size == g.n and np.array_equal(np.sort(order), np.arange(g.n))
+        assert order[0] == start
+        if res["best_len"] > 0:
+            side = np.zeros(g.n, np.uint8)
+            side[order[:res["best_len"]]] = 1
+            assert oracle.cut_value(g, side) == res["best_alpha"]
+            assert res["lam"] == min(dmin, res["best_alpha"])
+        thr = min(dmin, res["best_alpha"])
+        if thr > lam_true:
+            rp, col, w = oracle.contract(g, res["labels"], res["n2"])
+            h = gen.Graph(res["n2"], rp, col, w)
+            assert res["n2"] >= 2 and oracle.stoer_wagner(h)[0] == lam_true
+        else:
+            assert thr == lam_true
+
+
+def test_capforest_private_truncated_passes_valid(ctx):
+    g = gen.config_chung_lu(14)
+    say("capforest private truncated", g.n)
+    dev, dmin, _ = canon_dev(ctx, g)
+    lam_true = oracle.noi(g)[0]
+    res = ctx.step_capforest(dev, dmin, start=-1, mode=CF_PRIVATE, passes=32, len_cap=300)
+    assert res["n2"] < g.n  # the passes mark edges
+    thr = min(dmin, res["best_alpha"])
+    rp, col, w = oracle.contract(g, res["labels"], res["n2"])
+    h = gen.Graph(res["n2"], rp, col, w)
+    if thr > lam_true:
+        assert oracle.noi(h)[0] == lam_true
+
+
+@pytest.mark.parametrize("mode", ["shared", "deterministic"])
+def test_solver_modes(ctx, mode):
+    import paper_2609_07204_amd as mc
+    c = mc.Context(0, capforest_mode=1 if mode == "shared" else 0, deterministic=1 if mode == "deterministic" else 0)
+    for g in [gen.config_planted_2x1000(), gen.mixed_graph(3000, 12, 2, 5, 1, 100), gen.wheel(30)]:
+        say("mode", mode, g.name)
+        lam, side = c.mincut(g)
+        lam_ref = oracle.stoer_wagner(g)[0]
+        assert lam == lam_ref and oracle.cut_value(g, side) == lam
+    c.close()
