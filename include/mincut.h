@@ -79,6 +79,10 @@ typedef struct {
                                  visited state that scan capped vertices in
                                  batches; MC_CF_SHARED: passes that share one
                                  visited array (Algorithm 1 as printed) */
+    int32_t levels_min_n;     /* current graphs with at least this many
+                                 vertices advance all private passes in
+                                 whole-GPU steps; smaller ones run one
+                                 workgroup per pass (0 = default 65536) */
     int32_t deterministic;    /* 1: one sequential pass per round, one vertex
                                  at a time, smallest id first on ties; the
                                  whole solve then does not depend on timing */

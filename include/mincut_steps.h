@@ -66,12 +66,14 @@ mc_status mc_step_pr12(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, uint8_t* fl
  *     largest key and smallest id first, no capacity limit (Algorithm 2's
  *     sequential fallback; the deterministic reference form);
  *  MC_STEP_CF_PRIVATE (2): `passes` passes, one workgroup each, private
- *     visited state in HBM, capped vertices scanned in batches.
+ *     visited state in HBM, capped vertices scanned in batches;
+ *  MC_STEP_CF_LEVELS (3): the same passes advanced in steps, each step's
+ *     edges processed by all compute units.
  * Each pass stops after len_cap scans (0: none). Outputs: canonical labels
  * of the marked edges (labels[n], *n2), the scan order of pass 0 (order[n],
  * *nscan), the smallest alpha over the passes with its prefix length
  * (*best_alpha = INT64_MAX if none), and the bound after pass 0 (*lam_out). */
-enum { MC_STEP_CF_SHARED = 0, MC_STEP_CF_SEQUENTIAL = 1, MC_STEP_CF_PRIVATE = 2 };
+enum { MC_STEP_CF_SHARED = 0, MC_STEP_CF_SEQUENTIAL = 1, MC_STEP_CF_PRIVATE = 2, MC_STEP_CF_LEVELS = 3 };
 mc_status mc_step_capforest(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t start, int32_t mode,
                             int32_t passes, int32_t shared, int32_t len_cap, int32_t* labels, int32_t* n2,
                             int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,

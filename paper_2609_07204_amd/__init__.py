@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libmincut.so")
 
 MC_HOST, MC_DEVICE = 0, 1
 MC_CF_PRIVATE, MC_CF_SHARED = 0, 1
-CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE = 0, 1, 2  # step modes
+CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE, CF_LEVELS = 0, 1, 2, 3  # step modes
 STATUS = {0: "MC_OK", -1: "MC_E_INVALID_ARG", -2: "MC_E_BAD_GRAPH", -3: "MC_E_OVERFLOW", -4: "MC_E_OOM",
           -5: "MC_E_DEVICE", -6: "MC_E_NOT_READY", -7: "MC_E_CANCELLED", -8: "MC_E_TIMEOUT"}
 INT64_MAX = (1 << 63) - 1
@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("heuristic_min_n", ctypes.c_int32), ("lp_iters", ctypes.c_int32),
                 ("pr_tri_deg_cap", ctypes.c_int32), ("capforest_passes", ctypes.c_int32),
                 ("pass_len_cap", ctypes.c_int32), ("capforest_mode", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
+                ("levels_min_n", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -243,7 +243,7 @@ class Context:
 
     def step_capforest(self, g, lam, start=0, mode=CF_SEQUENTIAL, passes=1, shared=False, len_cap=0):
         """One CAPFOREST launch in the given mode (CF_SHARED, CF_SEQUENTIAL,
-        CF_PRIVATE); see mc_step_capforest."""
+        CF_PRIVATE, CF_LEVELS); see mc_step_capforest."""
         torch = _torch()
         lab = torch.empty(g.n, dtype=torch.int32, device=self.device)
         order = torch.full((max(g.n, 4096),), -1, dtype=torch.int32, device=self.device)

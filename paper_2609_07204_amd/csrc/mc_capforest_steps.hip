@@ -1,0 +1,468 @@
+// CAPFOREST with private passes, run level-synchronously over the whole GPU
+// (paper, Section 2.1 and Algorithm 1; same pass semantics as
+// mc_capforest_private.hip, where each pass is one workgroup).
+//
+// Every pass advances in steps. A step scans one batch per pass: all
+// queued vertices with capped keys (cut at the pass's remaining budget), or,
+// when there are none, the single queued vertex with the largest key. The
+// work of a step is split into launches so that all compute units work on
+// the edges of all passes at once:
+//   k_cfs_popscan all workgroups: for passes with no capped vertex queued,
+//                the largest key over the pass's vertex words, in parts;
+//   k_cfs_plan   one workgroup per pass: pick the batch (capped FIFO slice,
+//                or the single vertex the parts agree on), mark it, prefix
+//                of the batch's row lengths, sum of c(x) - 2 r(x);
+//   k_cfs_tiles  one workgroup: cut every pass's entries into 1024-entry
+//                tiles, and count the passes still running;
+//   k_cfs_edges  all workgroups, one tile at a time: one 64-bit atomic add
+//                per entry raises r and reports the target's state; marks,
+//                capped FIFO and touched list follow from it;
+//   k_cfs_finish one workgroup per pass: batch becomes scanned, alpha and
+//                the bound are updated.
+// The host issues steps and reads the running-pass count every few steps.
+#include "mc_internal.h"
+
+namespace {
+
+constexpr int T = 1024;           // threads of the per-pass kernels
+constexpr int TW = T / MC_WAVE;
+constexpr int ETILE = 1024;       // entries per edge tile
+constexpr int ET = 256;           // threads of the edge kernel
+
+// Per-pass vertex word: r in the low 62 bits (every r is below the total
+// weight, < 2^62), the state in the top two: 00 new (r = 0) or queued
+// (r > 0), 11 in the current batch, 10 scanned. One 64-bit atomic add per
+// entry then both raises r and reports the state it found.
+constexpr unsigned long long SCAN_BIT = 1ULL << 63;
+constexpr unsigned long long BATCH_BIT = 1ULL << 62;
+constexpr unsigned long long R_MASK = BATCH_BIT - 1;
+
+__device__ __forceinline__ bool is_queued(unsigned long long wv) { return (wv >> 62) == 0 && (wv & R_MASK) > 0; }
+
+__device__ __forceinline__ int64_t ld64(const int64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ldw(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Red {
+    int64_t v64[TW];
+    int32_t v32[TW];
+    int32_t s32[TW];
+};
+
+__device__ int32_t bscan(int32_t v, int32_t& total, Red& R) {
+    const int lane = lane_id(), wid = threadIdx.x / MC_WAVE;
+    int32_t incl = v;
+    for (int o = 1; o < MC_WAVE; o <<= 1) {
+        int32_t y = __shfl_up(incl, o, MC_WAVE);
+        if (lane >= o) incl += y;
+    }
+    __syncthreads();
+    if (lane == MC_WAVE - 1) R.s32[wid] = incl;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int k = 0; k < TW; k++) { int32_t t = R.s32[k]; if (k < wid) pre += t; tot += t; }
+    total = tot;
+    return pre + incl - v;
+}
+
+__device__ int64_t bsum(int64_t v, Red& R) {
+    v = wave_sum_i64(v);
+    __syncthreads();
+    if (lane_id() == 0) R.v64[threadIdx.x / MC_WAVE] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < TW; k++) t += R.v64[k];
+    return t;
+}
+
+__device__ void bargmax(int64_t& key, int32_t& id, Red& R) {
+    int32_t aux = 0;
+    wave_argmax(key, id, aux);
+    __syncthreads();
+    if (lane_id() == 0) { R.v64[threadIdx.x / MC_WAVE] = key; R.v32[threadIdx.x / MC_WAVE] = id; }
+    __syncthreads();
+    key = -1;
+    id = -1;
+    for (int k = 0; k < TW; k++) {
+        const int32_t i2 = R.v32[k];
+        const int64_t k2 = R.v64[k];
+        if (i2 >= 0 && (id < 0 || k2 > key || (k2 == key && i2 < id))) { key = k2; id = i2; }
+    }
+}
+
+struct PassView {
+    int32_t *fifo, *tl, *order, *bpre, *single;
+    unsigned long long* rw;
+    StepCtl* ctl;
+};
+
+__device__ __forceinline__ PassView view(const StepArgs& a, int p) {
+    const PrivateArgs& v = a.pv;
+    PassView w;
+    w.rw = reinterpret_cast<unsigned long long*>(v.r + (int64_t)p * v.stride);
+    w.fifo = v.fifo + (int64_t)p * v.stride;
+    w.tl = v.touched + (int64_t)p * v.stride;
+    w.order = v.order + (int64_t)p * v.stride;
+    w.bpre = a.bpre + (int64_t)p * (a.bcap + 1);
+    w.single = a.single + p;
+    w.ctl = a.ctl + p;
+    return w;
+}
+
+__global__ __launch_bounds__(T) void k_cfs_init(StepArgs a) {
+    const int p = blockIdx.x;
+    PassView w = view(a, p);
+    const int32_t n = a.pv.g.n;
+    if (threadIdx.x == 0) {
+        int32_t s = a.pv.start;
+        if (s < 0) {
+            uint64_t h = splitmix64(a.pv.seed ^ splitmix64(((uint64_t)(uint32_t)a.pv.round << 32) | (uint32_t)p));
+            s = (int32_t)(((h >> 32) * (uint64_t)n) >> 32);
+        }
+        w.tl[0] = s;
+        StepCtl c{};
+        c.tn = 1;
+        c.lam = *a.pv.lam;
+        c.best_alpha = INT64_MAX;
+        c.single_pending = 1;
+        *w.single = s;
+        *w.ctl = c;
+    }
+}
+
+constexpr int POP_BLOCKS = 512;
+constexpr int POP_T = 256;
+
+__device__ __forceinline__ bool wants_pop(const StepCtl& c, int32_t cap) {
+    return !c.done && !c.single_pending && c.head >= c.tail && !(cap > 0 && c.nscan >= cap);
+}
+
+// largest (r, smallest id) over the queued vertices of every pass that will
+// need a single pop; one partial per workgroup and pass
+__global__ __launch_bounds__(POP_T) void k_cfs_popscan(StepArgs a) {
+    __shared__ int64_t sk[POP_T / MC_WAVE];
+    __shared__ int32_t si[POP_T / MC_WAVE];
+    const int32_t n = a.pv.g.n;
+    for (int32_t p = 0; p < a.pv.passes; p++) {
+        const StepCtl& c = a.ctl[p];
+        if (!wants_pop(c, a.pv.len_cap)) continue;   // uniform per launch
+        const unsigned long long* rw = reinterpret_cast<const unsigned long long*>(a.pv.r + (int64_t)p * a.pv.stride);
+        int64_t bk = -1;
+        int32_t bv = -1;
+        for (int64_t v = (int64_t)blockIdx.x * POP_T + threadIdx.x; v < n; v += (int64_t)gridDim.x * POP_T) {
+            const unsigned long long wv = rw[v];
+            if (is_queued(wv)) {
+                const int64_t r = (int64_t)(wv & R_MASK);
+                if (bv < 0 || r > bk) { bk = r; bv = (int32_t)v; }
+            }
+        }
+        int32_t aux = 0;
+        wave_argmax(bk, bv, aux);
+        __syncthreads();
+        if (lane_id() == 0) { sk[threadIdx.x / MC_WAVE] = bk; si[threadIdx.x / MC_WAVE] = bv; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < POP_T / MC_WAVE; k++)
+                if (si[k] >= 0 && (bv < 0 || sk[k] > bk || (sk[k] == bk && si[k] < bv))) { bk = sk[k]; bv = si[k]; }
+            a.popk[(int64_t)p * POP_BLOCKS + blockIdx.x] = bk;
+            a.popv[(int64_t)p * POP_BLOCKS + blockIdx.x] = bv;
+        }
+    }
+}
+
+// pick the batch of every running pass
+__global__ __launch_bounds__(T) void k_cfs_plan(StepArgs a) {
+    __shared__ Red R;
+    __shared__ int32_t s_x;
+    const int p = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wid = tid / MC_WAVE;
+    PassView w = view(a, p);
+    StepCtl& c = *w.ctl;
+    const int32_t cap = a.pv.len_cap;
+    if (c.done) return;                          // uniform: read by every thread
+    if (cap > 0 && c.nscan >= cap) {
+        __syncthreads();
+        if (tid == 0) { c.done = 1; c.bcount = 0; c.E = 0; }
+        return;
+    }
+    int32_t B = 0;
+    bool single = false;
+    if (c.single_pending) {
+        single = true;
+        B = 1;
+    } else if (c.head < c.tail) {
+        B = c.tail - c.head;
+        if (cap > 0 && B > cap - c.nscan) B = cap - c.nscan;
+    } else {
+        // the largest key, from the parts of k_cfs_popscan; a pass that has
+        // spent its single pops stops here (it ends at a valid prefix)
+        if (a.max_singles > 0 && c.singles >= a.max_singles) {
+            __syncthreads();
+            if (tid == 0) { c.done = 1; c.bcount = 0; c.E = 0; }
+            return;
+        }
+        int64_t bk = -1;
+        int32_t bv = -1;
+        for (int32_t i = tid; i < POP_BLOCKS; i += T) {
+            const int64_t k2 = a.popk[(int64_t)p * POP_BLOCKS + i];
+            const int32_t v2 = a.popv[(int64_t)p * POP_BLOCKS + i];
+            if (v2 >= 0 && (bv < 0 || k2 > bk || (k2 == bk && v2 < bv))) { bk = k2; bv = v2; }
+        }
+        bargmax(bk, bv, R);
+        if (tid == 0) s_x = bv;
+        __syncthreads();
+        if (s_x < 0) {
+            if (tid == 0) { c.done = 1; c.bcount = 0; c.E = 0; }
+            return;
+        }
+        if (tid == 0) { *w.single = s_x; c.singles++; }
+        single = true;
+        B = 1;
+    }
+    __syncthreads();
+    // mark the batch, prefix of row lengths, sum of c(x) - 2 r(x)
+    const int32_t* src = single ? w.single : w.fifo + c.head;
+    int32_t run = 0;
+    int64_t part = 0;
+    for (int32_t c0 = 0; c0 < B; c0 += T) {
+        const int32_t i = c0 + tid;
+        int32_t dl = 0;
+        if (i < B) {
+            const int32_t x = src[i];
+            // every batch entry is queued (or the start vertex) by
+            // construction; anything else gets an empty range
+            const unsigned long long wv = ldw(&w.rw[x]);
+            if ((wv >> 62) == 0) {
+                atomicOr(&w.rw[x], SCAN_BIT | BATCH_BIT);
+                dl = a.pv.g.len[x];
+                part += a.pv.g.deg[x] - 2 * (int64_t)(wv & R_MASK);
+            }
+        }
+        int32_t tot;
+        const int32_t ex = bscan(dl, tot, R);
+        if (i < B) w.bpre[i] = run + ex;
+        run += tot;
+    }
+    part = bsum(part, R);
+    if (tid == 0) {
+        w.bpre[B] = run;
+        c.bcount = B;
+        c.bsingle = single ? 1 : 0;
+        c.E = run;
+        c.entries += run;
+        if (B > c.maxbatch) c.maxbatch = B;
+        c.part = part;
+        c.intra = 0;
+        if (!single) c.head += B;
+        c.single_pending = 0;
+    }
+}
+
+// tiles of every pass's batch entries
+__global__ __launch_bounds__(T) void k_cfs_tiles(StepArgs a) {
+    __shared__ Red R;
+    const int32_t P = a.pv.passes;
+    int32_t run = 0, active = 0;
+    for (int32_t c0 = 0; c0 < P; c0 += T) {
+        const int32_t p = c0 + threadIdx.x;
+        int32_t nt = 0;
+        if (p < P) {
+            const StepCtl& c = a.ctl[p];
+            if (!c.done) { nt = (c.E + ETILE - 1) / ETILE; active++; }
+        }
+        int32_t tot;
+        const int32_t ex = bscan(nt, tot, R);
+        if (p < P) a.ptile[p] = run + ex;
+        run += tot;
+    }
+    active = (int32_t)bsum(active, R);
+    if (threadIdx.x == 0) {
+        a.ptile[P] = run;
+        *a.running = active;
+    }
+}
+
+__device__ __forceinline__ int32_t last_le(const int32_t* x, int32_t n, int32_t key) {
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (x[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// process the entries of all batches, one 1024-entry tile per workgroup pass
+__global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
+    __shared__ int32_t win[ETILE + 2];
+    __shared__ int32_t info[4];
+    __shared__ long long s_intra[ET / MC_WAVE];
+    __shared__ unsigned long long s_marks[ET / MC_WAVE];
+    const int32_t P = a.pv.passes;
+    const int32_t ntiles = a.ptile[P];
+    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int32_t p = last_le(a.ptile, P, t);
+            info[0] = p;
+            const int32_t e0 = (t - a.ptile[p]) * ETILE;
+            const StepCtl& c = a.ctl[p];
+            const int32_t* bpre = a.bpre + (int64_t)p * (a.bcap + 1);
+            const int32_t k0 = last_le(bpre, c.bcount, e0);
+            info[1] = k0;
+            info[2] = e0;
+            info[3] = c.bcount - k0;              // batch vertices from k0 on
+        }
+        __syncthreads();
+        const int32_t p = info[0], k0 = info[1], e0 = info[2];
+        PassView w = view(a, p);
+        const StepCtl& c = *w.ctl;
+        const int32_t wc = info[3] < ETILE + 1 ? info[3] : ETILE + 1;
+        for (int i = threadIdx.x; i <= wc; i += ET) win[i] = w.bpre[k0 + i];
+        __syncthreads();
+        const int32_t e1 = e0 + ETILE < c.E ? e0 + ETILE : c.E;
+        const int64_t lam = c.lam;
+        const int32_t* src = c.bsingle ? w.single : w.fifo + (c.head - c.bcount);
+        int64_t intra = 0;
+        unsigned long long marks = 0;
+        for (int32_t e = e0 + threadIdx.x; e < e1; e += ET) {
+            int32_t k;
+            if (e < win[wc]) {
+                int32_t lo = 0, hi = wc;
+                while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (win[mid] <= e) lo = mid; else hi = mid; }
+                k = k0 + lo;
+            } else {
+                k = last_le(w.bpre, c.bcount, e);
+            }
+            const int32_t xs = src[k];
+            const int32_t j = e - w.bpre[k];
+            const int32_t o = a.pv.g.off[xs];
+            const int32_t y = a.pv.g.col[o + j];
+            const int64_t cw = a.pv.g.w[o + j];
+            const unsigned long long ow = atomicAdd(&w.rw[y], (unsigned long long)cw);
+            if (ow & SCAN_BIT) {
+                if (ow & BATCH_BIT) intra += cw;
+                continue;
+            }
+            if (ow == 0) w.tl[atomicAdd(&w.ctl->tn, 1)] = y;
+            const int64_t old = (int64_t)(ow & R_MASK);
+            const int64_t nw = old + cw;
+            if (old < lam && lam <= nw) {
+                if (uf_union(a.pv.parent, xs, y)) marks++;
+                w.fifo[atomicAdd(&w.ctl->tail, 1)] = y;
+            }
+        }
+        intra = wave_sum_i64(intra);
+        marks = (unsigned long long)wave_sum_i64((int64_t)marks);
+        if (lane_id() == 0) { s_intra[threadIdx.x / MC_WAVE] = intra; s_marks[threadIdx.x / MC_WAVE] = marks; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long si = 0;
+            unsigned long long sm = 0;
+            for (int k = 0; k < ET / MC_WAVE; k++) { si += s_intra[k]; sm += s_marks[k]; }
+            if (si) atomic_add_i64(&w.ctl->intra, si);
+            if (sm) { atomicAdd(&w.ctl->marks, sm); atomicAdd(a.pv.marks, sm); }
+        }
+    }
+}
+
+// the batch becomes scanned; alpha and the bound of the pass move on
+__global__ __launch_bounds__(T) void k_cfs_finish(StepArgs a) {
+    __shared__ Red R;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    PassView w = view(a, p);
+    StepCtl& c = *w.ctl;
+    if (c.done) return;
+    const int32_t B = c.bcount;
+    const int32_t* src = c.bsingle ? w.single : w.fifo + (c.head - B);
+    const int32_t base = c.nscan;
+    int32_t run = 0;
+    for (int32_t c0 = 0; c0 < B; c0 += T) {
+        const int32_t i = c0 + tid;
+        bool ok = false;
+        int32_t x = -1;
+        if (i < B) {
+            x = src[i];
+            ok = (ldw(&w.rw[x]) >> 62) == 3;
+        }
+        int32_t tot;
+        const int32_t ex = bscan(ok ? 1 : 0, tot, R);
+        if (ok) {
+            atomicAnd(&w.rw[x], ~BATCH_BIT);
+            w.order[base + run + ex] = x;
+        }
+        run += tot;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int32_t n = a.pv.g.n;
+        c.nscan = base + run;
+        c.alpha += c.part - c.intra;
+        if (c.nscan < n) {
+            if (c.alpha < c.best_alpha) { c.best_alpha = c.alpha; c.best_len = c.nscan; }
+            if (c.alpha < c.lam) c.lam = c.alpha;
+        }
+        c.steps++;
+    }
+}
+
+// leave the vertex words zero (many workgroups per pass); publish results
+constexpr int END_SPLIT = 64;
+
+__global__ __launch_bounds__(T) void k_cfs_end(StepArgs a) {
+    const int p = blockIdx.x / END_SPLIT, part = blockIdx.x % END_SPLIT;
+    PassView w = view(a, p);
+    const StepCtl& c = *w.ctl;
+    for (int32_t i = part * T + threadIdx.x; i < c.tn; i += END_SPLIT * T) w.rw[w.tl[i]] = 0;
+    if (part == 0 && threadIdx.x == 0) {
+        a.pv.nscan[p] = c.nscan;
+        a.pv.alpha[p] = c.best_alpha;
+        a.pv.alpha_len[p] = c.best_len;
+        a.pv.lam_out[p] = c.lam;
+        if (a.pv.steps) a.pv.steps[p] = c.steps;
+        if (a.pv.diag) {
+            int64_t* d = a.pv.diag + (int64_t)p * 8;
+            d[0] = c.steps; d[1] = c.singles; d[2] = c.tn; d[3] = c.entries;
+            d[4] = 0; d[5] = 0; d[6] = c.nscan; d[7] = c.maxbatch;
+        }
+    }
+}
+
+}  // namespace
+
+bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
+    const int32_t P = a.pv.passes;
+    if (P <= 0) return true;
+    if (a.pv.g.n > a.pv.stride) {
+        mc_hip_ok(hipErrorInvalidValue, "capforest_steps: per-pass arrays too small");
+        return false;
+    }
+    k_cfs_init<<<P, T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_init");
+    const int poll = 4;
+    for (int32_t step = 0;; step++) {
+        k_cfs_popscan<<<POP_BLOCKS, POP_T, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_popscan");
+        k_cfs_plan<<<P, T, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_plan");
+        k_cfs_tiles<<<1, T, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_tiles");
+        k_cfs_edges<<<4096, ET, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_edges");
+        k_cfs_finish<<<P, T, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_finish");
+        if (step % poll == poll - 1) {
+            MC_HIP(hipMemcpyAsync(running_host, a.running, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            MC_HIP(hipStreamSynchronize(s));
+            if (*running_host == 0) break;
+        }
+        if (step > 4 * (int64_t)a.pv.g.n + 64) {
+            mc_hip_ok(hipErrorUnknown, "capforest_steps: no progress");
+            return false;
+        }
+    }
+    k_cfs_end<<<P * END_SPLIT, T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_end");
+    return true;
+}

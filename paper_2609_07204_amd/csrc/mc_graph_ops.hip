@@ -38,6 +38,67 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
     }
 }
 
+// Connectivity in the manner of Afforest (Sutton, Ben-Nun and Barak, IPDPS
+// 2018): first every vertex points at its smallest neighbour when that is
+// smaller than itself (plain stores: it only writes its own entry, and the
+// parent stays smaller, so the union-find invariant holds), then the
+// component most sampled vertices fall into is found, and all edges are
+// linked only for vertices outside it; an edge between that component and
+// another one is seen from the other side.
+__global__ __launch_bounds__(256) void k_uf_hook_min(DGraph g, int32_t* par) {
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        const int32_t o = g.off[v], l = g.len[v];
+        int32_t m = (int32_t)v;
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = g.col[o + j];
+            if (x < m && g.w[o + j] > 0) m = x;
+        }
+        for (int k = SUB / 2; k > 0; k >>= 1) {
+            const int32_t t = __shfl_xor(m, k, SUB);
+            m = t < m ? t : m;
+        }
+        if (sl == 0) par[v] = m;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int32_t n, int32_t* mode) {
+    __shared__ int32_t smp[1024];
+    __shared__ int32_t bestc[1024], bestr[1024];
+    const uint32_t h = hash32(threadIdx.x * 2654435761u + 12345u);
+    const int32_t v = (int32_t)(((uint64_t)h * (uint64_t)n) >> 32);
+    int32_t x = v, p = ld_acq(&par[x]);
+    while (p != x) { x = p; p = ld_acq(&par[x]); }
+    smp[threadIdx.x] = x;
+    __syncthreads();
+    int32_t c = 0;
+    for (int k = 0; k < 1024; k++) c += smp[k] == x;
+    bestc[threadIdx.x] = c;
+    bestr[threadIdx.x] = x;
+    __syncthreads();
+    for (int s2 = 512; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2 && bestc[threadIdx.x + s2] > bestc[threadIdx.x]) {
+            bestc[threadIdx.x] = bestc[threadIdx.x + s2];
+            bestr[threadIdx.x] = bestr[threadIdx.x + s2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *mode = bestr[0];
+}
+
+__global__ __launch_bounds__(256) void k_uf_link_rest(DGraph g, int32_t* par, const int32_t* mode) {
+    const int32_t big = *mode;
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        if (ld_acq(&par[v]) == big) continue;
+        const int32_t o = g.off[v], l = g.len[v];
+        for (int32_t j = sl; j < l; j += SUB)
+            if (g.w[o + j] > 0) uf_union(par, (int32_t)v, g.col[o + j]);
+    }
+}
+
 // After all unions: point every vertex at its root. Each thread writes only
 // its own entry, so concurrent finds still see valid ancestors.
 __global__ void k_uf_compress(int32_t* par, int32_t n) {
@@ -294,6 +355,18 @@ bool uf_init(int32_t* parent, int32_t n, hipStream_t s) {
 bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
     k_uf_all_edges<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent);
     MC_LAUNCHED("k_uf_all_edges");
+    return true;
+}
+
+bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s) {
+    k_uf_hook_min<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent);
+    MC_LAUNCHED("k_uf_hook_min");
+    k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
+    MC_LAUNCHED("k_uf_compress");
+    k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, tmp);
+    MC_LAUNCHED("k_uf_sample_mode");
+    k_uf_link_rest<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent, tmp);
+    MC_LAUNCHED("k_uf_link_rest");
     return true;
 }
 

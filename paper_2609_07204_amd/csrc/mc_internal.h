@@ -79,6 +79,9 @@ bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s);
 bool uf_init(int32_t* parent, int32_t n, hipStream_t s);
 // Union the endpoints of every entry with positive weight.
 bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s);
+// Same components with far fewer unions on graphs with a giant component
+// (sampling-based linking); tmp holds one int.
+bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s);
 // Compress parent[] and write canonical labels (components numbered by
 // their smallest vertex) to L; the count goes to sc->n2.
 bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp,
@@ -178,6 +181,32 @@ constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
 bool capforest_private(const PrivateArgs& a, hipStream_t s);
 // clear st/r of a fresh workspace region (once per solve)
 bool capforest_private_reset(const PrivateArgs& a, hipStream_t s);
+
+// The same private passes run level-synchronously over the whole GPU: per
+// step, one launch picks every pass's batch, one processes the entries of
+// all batches in tiles over all compute units, one finishes the step.
+struct StepCtl {
+    int32_t head, tail, tn, dn;
+    int32_t nscan, done, bcount, bsingle;
+    int32_t E, single_pending, best_len, steps;
+    int32_t singles, maxbatch;
+    int64_t entries;
+    int64_t alpha, best_alpha, lam, part, intra;
+    unsigned long long marks;
+};
+struct StepArgs {
+    PrivateArgs pv;
+    StepCtl* ctl;       // [passes]
+    int32_t* bpre;      // [passes*(bcap+1)] prefix of the batch's row lengths
+    int32_t bcap;       // largest batch
+    int32_t* single;    // [passes]
+    int32_t* ptile;     // [passes+1]
+    int32_t* running;   // [1]
+    int64_t* popk;      // [passes*512] parts of the single-pop maximum
+    int32_t* popv;
+    int32_t max_singles;  // single pops per pass before it stops (0: none)
+};
+bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s);
 
 // -------------------------------------------------------- side tracking
 bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s);

@@ -86,6 +86,7 @@ extern "C" void mc_default_options(mc_options* o) {
     o->capforest_passes = 0;
     o->pass_len_cap = 0;
     o->capforest_mode = MC_CF_PRIVATE;
+    o->levels_min_n = 0;
     o->deterministic = 0;
     o->validate = 0;
 }
@@ -158,9 +159,11 @@ struct SolveWS {
     int64_t* clamout = nullptr;
     Pr12WS prw{};
     PrivateArgs pv{};             // per-pass arrays of the private passes
+    StepArgs sa{};                // control of the level-synchronous form
     int32_t* psteps = nullptr;
     DevScalars* sc = nullptr;
     unsigned long long* vpart = nullptr;
+    int32_t* vpart_i32() { return reinterpret_cast<int32_t*>(vpart); }
 };
 
 void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
@@ -171,6 +174,20 @@ void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
     g.deg = a.take<int64_t>((size_t)n + 1);
     g.col = a.take<int32_t>((size_t)cap + 1);
     g.w = a.take<int64_t>((size_t)cap + 1);
+}
+
+void carve_steps(Arena& a, int32_t n, int32_t passes, int32_t len_cap, StepArgs& sa) {
+    sa.ctl = a.take<StepCtl>((size_t)passes);
+    sa.bcap = len_cap > 0 && len_cap < n ? len_cap : n;
+    const size_t per = (size_t)sa.bcap + 1;
+    const size_t total = std::max((size_t)passes * per, (size_t)n + 1);
+    sa.bpre = a.take<int32_t>(total);
+    sa.single = a.take<int32_t>((size_t)passes);
+    sa.ptile = a.take<int32_t>((size_t)passes + 1);
+    sa.running = a.take<int32_t>(1);
+    sa.popk = a.take<int64_t>((size_t)passes * 512);
+    sa.popv = a.take<int32_t>((size_t)passes * 512);
+    sa.max_singles = 0;
 }
 
 void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t*& psteps) {
@@ -194,8 +211,8 @@ void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t
     pv.diag = a.take<int64_t>((size_t)passes * 8);
 }
 
-void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, bool host_input, int ngraphs,
-           SolveWS& w) {
+void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, int32_t len_cap, bool host_input,
+           int ngraphs, SolveWS& w) {
     w.sc = a.take<DevScalars>(1);
     if (host_input) {
         w.in_rp = a.take<int32_t>((size_t)n + 1);
@@ -228,6 +245,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, bo
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
     carve_private(a, n, ppasses, w.pv, w.psteps);
+    carve_steps(a, n, ppasses, len_cap, w.sa);
 }
 
 // passes of the shared-visited-array form (one wavefront each)
@@ -238,23 +256,22 @@ int32_t pass_count(const mc_ctx* c) {
     return p;
 }
 
-// passes of the private form (one workgroup each); per-pass state costs
-// PRIV_BYTES_PER_VERTEX * n, kept under 16 GiB by default
+// passes of the private form. Graphs large enough for the whole-GPU step
+// form run one long pass (measured fastest on power-law graphs: every pass
+// repeats the traversal of the dense core); smaller graphs run one
+// workgroup per pass, so several passes keep several compute units busy.
+int32_t levels_min_n(const mc_ctx* c) { return c->opt.levels_min_n > 0 ? c->opt.levels_min_n : (1 << 16); }
+
 int32_t private_pass_count(const mc_ctx* c, int32_t n) {
     if (c->opt.capforest_mode == MC_CF_SHARED || c->opt.deterministic) return 1;
-    int32_t p = c->opt.capforest_passes;
-    if (p > 0) return p;
-    const double budget = 16.0 * (1 << 30);
-    int64_t fit = (int64_t)(budget / ((double)PRIV_BYTES_PER_VERTEX * (n > 0 ? n : 1)));
-    p = 128;
-    if (fit < p) p = (int32_t)(fit < 8 ? 8 : fit);
-    return p;
+    if (c->opt.capforest_passes > 0) return c->opt.capforest_passes;
+    return n >= levels_min_n(c) ? 1 : 32;
 }
 
 int32_t private_len_cap(const mc_ctx* c) {
     if (c->opt.pass_len_cap < 0) return 0;
     if (c->opt.pass_len_cap > 0) return c->opt.pass_len_cap;
-    return 8192;
+    return 32768;
 }
 
 // Host-side checks of a host CSR (exact, including symmetry when asked).
@@ -326,7 +343,7 @@ extern "C" mc_status mc_workspace_size(const mc_ctx* c, int32_t n, int32_t nnz, 
     if (n < 2 || nnz < 0) return fail(MC_E_INVALID_ARG, "mc_workspace_size: need n >= 2 and nnz >= 0");
     Arena a;
     SolveWS w;
-    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), true, 3, w);
+    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), private_len_cap(c), true, 3, w);
     *bytes = a.used + 256;
     return MC_OK;
 }
@@ -393,7 +410,19 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     pa.start = -1;
     pa.marks = &w.sc->marks_cf;
     pa.steps = w.psteps;
-    if (!capforest_private(pa, S.s)) return false;
+    if (g.n >= levels_min_n(S.c)) {
+        StepArgs sa = w.sa;
+        sa.pv = pa;
+        int32_t running = 0;
+        if (len_cap <= 0 || len_cap > sa.bcap) sa.bcap = g.n;   // unlimited pass: one pass, n+1 prefix slots
+        // a truncated pass that has run out of capped vertices continues one
+        // vertex per whole-GPU step; bound that tail (the complete fallback
+        // pass is never bounded)
+        sa.max_singles = len_cap > 0 ? 256 : 0;
+        if (!capforest_steps(sa, &running, S.s)) return false;
+    } else if (!capforest_private(pa, S.s)) {
+        return false;
+    }
     CapforestArgs ra{};
     ra.alpha = pa.alpha;
     ra.alpha_len = pa.alpha_len;
@@ -523,7 +552,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     Arena a;
     a.base = (char*)dev_ws;
     a.size = ws_bytes;
-    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), host_input, 3, S.w);
+    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), private_len_cap(c), host_input, 3, S.w);
     if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
     SolveWS& w = S.w;
     hipStream_t s = S.s;
@@ -561,7 +590,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
     if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected
-    if (!uf_init(w.parent, n, s) || !uf_all_edges(w.g[0], w.parent, s) ||
+    if (!uf_init(w.parent, n, s) || !uf_connectivity(w.g[0], w.parent, w.vpart_i32(), s) ||
         !uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
         return MC_E_DEVICE;
     DevScalars h = *c->hsc;
@@ -628,6 +657,7 @@ struct StepWS {
     PrivateArgs pv;
     int32_t* psteps;
     Pr12WS prw;
+    StepArgs sa;
 };
 
 void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
@@ -648,6 +678,7 @@ void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.cr = a.take<int64_t>((size_t)n + 1);
     w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
     carve_private(a, n, passes, w.pv, w.psteps);
+    carve_steps(a, n, passes, 0, w.sa);
 }
 
 mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws, size_t bytes, StepWS& w) {
@@ -731,7 +762,7 @@ extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t la
                                        int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,
                                        int64_t* lam_out, void* ws, size_t bytes) {
     if (!g || !labels || !order) return fail(MC_E_INVALID_ARG, "mc_step_capforest: NULL argument");
-    if (mode < MC_STEP_CF_SHARED || mode > MC_STEP_CF_PRIVATE) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad mode");
+    if (mode < MC_STEP_CF_SHARED || mode > MC_STEP_CF_LEVELS) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad mode");
     if ((mode == MC_STEP_CF_SEQUENTIAL && start < 0) || start >= g->n)
         return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
     if (mode != MC_STEP_CF_SEQUENTIAL && passes < 1) return fail(MC_E_INVALID_ARG, "mc_step_capforest: passes must be >= 1");
@@ -802,7 +833,16 @@ extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t la
         pa.start = start;
         pa.marks = &w.sc->marks_cf;
         pa.steps = w.psteps;
-        if (!capforest_private_reset(pa, s) || !capforest_private(pa, s)) return MC_E_DEVICE;
+        if (!capforest_private_reset(pa, s)) return MC_E_DEVICE;
+        if (mode == MC_STEP_CF_LEVELS) {
+            StepArgs sa = w.sa;
+            sa.pv = pa;
+            sa.bcap = g->n;
+            int32_t running = 0;
+            if (!capforest_steps(sa, &running, s)) return MC_E_DEVICE;
+        } else if (!capforest_private(pa, s)) {
+            return MC_E_DEVICE;
+        }
         red.alpha = pa.alpha;
         red.alpha_len = pa.alpha_len;
         red.passes = passes;

@@ -13,7 +13,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE = 0, 1, 2
+CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE, CF_LEVELS = 0, 1, 2, 3
 
 
 def say(*a):
@@ -209,7 +209,7 @@ def test_capforest_lds_pass_matches_oracle(ctx, name, mk):
             check_cf_equal(res, cf_oracle(g, dmin, start, cap))
 
 
-@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("mode", [0, 2, 3])
 def test_capforest_parallel_marks_are_safe(ctx, mode):
     for seed in range(12):
         g = gen.random_small(12 + seed % 5, 0.5, 4000 + seed, 1, 9)
@@ -312,8 +312,9 @@ def test_bad_device_input_rejected(ctx):
     assert e.value.code == -3
 
 
+@pytest.mark.parametrize("mode", [CF_PRIVATE, CF_LEVELS])
 @pytest.mark.parametrize("name,mk", CF_GRAPHS)
-def test_capforest_private_complete_pass_is_valid(ctx, name, mk):
+def test_capforest_private_complete_pass_is_valid(ctx, name, mk, mode):
     # one private pass without a length cap scans every vertex once; its
     # recorded alpha is the capacity of its scanned prefix; contracting its
     # marks keeps lambda whenever the final bound is above lambda
@@ -322,7 +323,7 @@ def test_capforest_private_complete_pass_is_valid(ctx, name, mk):
     dev, dmin, _ = canon_dev(ctx, g)
     lam_true = oracle.stoer_wagner(g)[0]
     for start in (0, g.n // 2):
-        res = ctx.step_capforest(dev, dmin, start=start, mode=CF_PRIVATE, passes=1)
+        res = ctx.step_capforest(dev, dmin, start=start, mode=mode, passes=1)
         order = res["order"]
         assert order.size == g.n and np.array_equal(np.sort(order), np.arange(g.n))
         assert order[0] == start
@@ -340,12 +341,13 @@ def test_capforest_private_complete_pass_is_valid(ctx, name, mk):
             assert thr == lam_true
 
 
-def test_capforest_private_truncated_passes_valid(ctx):
+@pytest.mark.parametrize("mode", [CF_PRIVATE, CF_LEVELS])
+def test_capforest_private_truncated_passes_valid(ctx, mode):
     g = gen.config_chung_lu(14)
     say("capforest private truncated", g.n)
     dev, dmin, _ = canon_dev(ctx, g)
     lam_true = oracle.noi(g)[0]
-    res = ctx.step_capforest(dev, dmin, start=-1, mode=CF_PRIVATE, passes=32, len_cap=300)
+    res = ctx.step_capforest(dev, dmin, start=-1, mode=mode, passes=32, len_cap=300)
     assert res["n2"] < g.n  # the passes mark edges
     thr = min(dmin, res["best_alpha"])
     rp, col, w = oracle.contract(g, res["labels"], res["n2"])
@@ -354,10 +356,11 @@ def test_capforest_private_truncated_passes_valid(ctx):
         assert oracle.noi(h)[0] == lam_true
 
 
-@pytest.mark.parametrize("mode", ["shared", "deterministic"])
+@pytest.mark.parametrize("mode", ["shared", "deterministic", "levels"])
 def test_solver_modes(ctx, mode):
     import paper_2609_07204_amd as mc
-    c = mc.Context(0, capforest_mode=1 if mode == "shared" else 0, deterministic=1 if mode == "deterministic" else 0)
+    c = mc.Context(0, capforest_mode=1 if mode == "shared" else 0, deterministic=1 if mode == "deterministic" else 0,
+                   levels_min_n=2 if mode == "levels" else 0)
     for g in [gen.config_planted_2x1000(), gen.mixed_graph(3000, 12, 2, 5, 1, 100), gen.wheel(30)]:
         say("mode", mode, g.name)
         lam, side = c.mincut(g)
