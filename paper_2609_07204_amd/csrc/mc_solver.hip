@@ -262,10 +262,19 @@ int32_t pass_count(const mc_ctx* c) {
 // workgroup per pass, so several passes keep several compute units busy.
 int32_t levels_min_n(const mc_ctx* c) { return c->opt.levels_min_n > 0 ? c->opt.levels_min_n : (1 << 16); }
 
+// passes used on a current graph with n vertices
 int32_t private_pass_count(const mc_ctx* c, int32_t n) {
     if (c->opt.capforest_mode == MC_CF_SHARED || c->opt.deterministic) return 1;
     if (c->opt.capforest_passes > 0) return c->opt.capforest_passes;
     return n >= levels_min_n(c) ? 1 : 32;
+}
+
+// passes the workspace holds (the most any round of this solve uses)
+int32_t private_pass_alloc(const mc_ctx* c, int32_t n) {
+    int32_t p = private_pass_count(c, n);
+    if (c->opt.capforest_passes <= 0 && c->opt.capforest_mode != MC_CF_SHARED && !c->opt.deterministic)
+        p = std::max(p, private_pass_count(c, 2));
+    return p;
 }
 
 int32_t private_len_cap(const mc_ctx* c) {
@@ -343,7 +352,7 @@ extern "C" mc_status mc_workspace_size(const mc_ctx* c, int32_t n, int32_t nnz, 
     if (n < 2 || nnz < 0) return fail(MC_E_INVALID_ARG, "mc_workspace_size: need n >= 2 and nnz >= 0");
     Arena a;
     SolveWS w;
-    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), private_len_cap(c), true, 3, w);
+    carve(a, n, nnz, pass_count(c), private_pass_alloc(c, n), private_len_cap(c), true, 3, w);
     *bytes = a.used + 256;
     return MC_OK;
 }
@@ -468,11 +477,12 @@ static mc_status exact_rounds(Solver& S, int src) {
             ca.marks = &w.sc->marks_cf;
             if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
         } else {
-            if (!private_passes(S, *cur, round, w.pv.passes, private_len_cap(S.c))) return MC_E_DEVICE;
+            if (!private_passes(S, *cur, round, std::min(w.pv.passes, private_pass_count(S.c, n)), private_len_cap(S.c)))
+                return MC_E_DEVICE;
         }
         if (!S.readback()) return MC_E_DEVICE;
         DevScalars h = *S.c->hsc;
-        if (S.debug) debug_round(S, *cur, round, det || shared ? 0 : w.pv.passes);
+        if (S.debug) debug_round(S, *cur, round, det || shared ? 0 : std::min(w.pv.passes, private_pass_count(S.c, n)));
         if (h.best_pass >= 0 && h.best_alpha < S.lam) {
             if (det) pref_order = w.corder;
             else if (shared) pref_order = w.order + (int64_t)h.best_pass * CF_HC;
@@ -552,7 +562,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     Arena a;
     a.base = (char*)dev_ws;
     a.size = ws_bytes;
-    carve(a, n, nnz, pass_count(c), private_pass_count(c, n), private_len_cap(c), host_input, 3, S.w);
+    carve(a, n, nnz, pass_count(c), private_pass_alloc(c, n), private_len_cap(c), host_input, 3, S.w);
     if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
     SolveWS& w = S.w;
     hipStream_t s = S.s;
