@@ -23,6 +23,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
+    or None when there is none or its kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -33,6 +53,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--len-cap", type=int, default=0)
+    ap.add_argument("--no-profile", action="store_true", help="time the steps without kernel events")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -60,6 +81,8 @@ def main():
         log("warmup %d: lambda=%d rounds=%d fallback=%d %.2f ms" % (i, lam, st["rounds"], st["fallback_passes"],
                                                                    st["ms_total"]))
     torch.cuda.synchronize()
+    if not args.no_profile:
+        ctx.profile(True)
     t0 = time.perf_counter()
     stats = []
     for i in range(args.steps):
@@ -70,6 +93,23 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1000.0 / args.steps
     log("timed %d steps: %.3f ms/step, lambda=%d, rounds=%d" % (args.steps, ms, lam, stats[-1]["rounds"]))
+    roofline = None
+    if not args.no_profile:
+        ctx.profile(False)
+        kt = ctx.profile_read()
+        for name, r in sorted(kt.items(), key=lambda kv: -kv[1]["ms"]):
+            if r["launches"]:
+                log("  %-16s %4d launches/step %8.3f ms/step  avg %8.1f us  %7.1f GB/s algorithmic" % (
+                    name, r["launches"] // args.steps, r["ms"] / args.steps, 1000.0 * r["ms"] / r["launches"],
+                    r["bytes"] / (r["ms"] * 1e6) if r["ms"] > 0 else 0.0))
+        name, r = max(kt.items(), key=lambda kv: kv[1]["ms"])
+        achieved = r["bytes"] / (r["ms"] * 1e6)          # GB/s = bytes per launch / avg launch time
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name),
+                    "kernel": name, "launches_per_step": r["launches"] / args.steps,
+                    "avg_launch_us": 1000.0 * r["ms"] / r["launches"],
+                    "bytes_per_launch": r["bytes"] / r["launches"],
+                    "kernel_ms_per_step": r["ms"] / args.steps}
 
     golden = {}
     gpath = os.path.join(ROOT, "tests", "golden", "lambda.json")
@@ -90,7 +130,7 @@ def main():
                "sample": "full workload, one NOI solve (repeated full CAPFOREST + contraction), %.1f s" % tc}
 
     out = {
-        "metric": "edges contracted/sec (exact min-cut solve)",
+        "metric": "edges contracted/sec",
         "value": g.m / (ms / 1000.0),
         "unit": "edges/s",
         "n_gpus": 1,
@@ -105,6 +145,7 @@ def main():
         "config": {"workload": "chung_lu n=2^%d beta=2.5 avg_deg=20 10-core LCC unit weights seed=%d"
                                % (args.log2n, args.seed), "n": g.n, "m": g.m, "lambda": lam,
                    "rounds": stats[-1]["rounds"]},
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -100,6 +100,9 @@ typedef struct {
     int32_t n_input;             /* vertices after normalisation */
     int64_t m_input;             /* undirected edges after normalisation */
     double ms_total;             /* wall time of the call */
+    int32_t rounds_pr_only;      /* rounds whose reduction tests alone at least
+                                    halved the graph (CAPFOREST left to the
+                                    next round) */
 } mc_stats;
 
 typedef struct mc_ctx mc_ctx;
@@ -128,6 +131,36 @@ mc_status mc_workspace_size(const mc_ctx* ctx, int32_t n, int32_t nnz, size_t* b
  * component of vertex 0. `st` may be NULL. Synchronises the stream. */
 mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws_bytes,
                     int64_t* lambda, uint8_t* side, mc_stats* st);
+
+/* Kernel timing, for measurement. While profiling is on, every launch of
+ * the kernels below made by mc_mincut on this context is bracketed by two
+ * HIP events on the context's stream, and the algorithmic bytes of the
+ * launches (what the method must read and write: entries scanned, labels
+ * gathered, rows written; no hash-table or scratch traffic) are counted.
+ * Timing adds two event records per timed launch. */
+enum {
+    MC_K_CAPFOREST_EDGES = 0,  /* k_cfs_edges: edges of the CAPFOREST batches (Algorithm 1) */
+    MC_K_CONTRACT_MERGE = 1,   /* k_merge_small: contraction of small groups */
+    MC_K_CONTRACT_BIG = 2,     /* k_big_insert: contraction of large groups */
+    MC_K_GROUP_COUNT = 3,      /* k_group_count: members per contracted vertex */
+    MC_K_GROUP_SCATTER = 4,    /* k_group_scatter: members grouped by label */
+    MC_K_PR12 = 5,             /* k_pr12: reduction tests 1 and 2 */
+    MC_K_CONNECT_LINK = 6,     /* k_uf_link_rest: connectivity unions */
+    MC_K_COUNT = 7
+};
+typedef struct {
+    char name[32];      /* kernel symbol name */
+    int64_t launches;   /* timed launches since profiling was switched on */
+    double ms;          /* summed time between each launch's two events */
+    double bytes;       /* summed algorithmic bytes of those launches */
+} mc_kernel_time;
+
+/* on != 0: switch timing on and zero the totals (the first call allocates
+ * 56 KiB of device counters, kept until mc_ctx_destroy); on = 0:
+ * switch it off and keep the totals. */
+mc_status mc_profile(mc_ctx* ctx, int32_t on);
+/* Totals of one kernel (kernel in [0, MC_K_COUNT)); synchronous. */
+mc_status mc_profile_read(mc_ctx* ctx, int32_t kernel, mc_kernel_time* out);
 
 /* Thread-local description of the last error (never NULL). */
 const char* mc_last_error(void);

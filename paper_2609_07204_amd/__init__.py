@@ -45,10 +45,18 @@ class Stats(ctypes.Structure):
                 ("lambda_min_degree", ctypes.c_int64), ("lambda_heuristic", ctypes.c_int64),
                 ("marks_pr", ctypes.c_int64), ("marks_capforest", ctypes.c_int64),
                 ("fallback_passes", ctypes.c_int32), ("n_input", ctypes.c_int32), ("m_input", ctypes.c_int64),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+MC_K_COUNT = 7  # kernels mc_profile times (MC_K_* in include/mincut.h)
 
 
 class DGraphC(ctypes.Structure):
@@ -66,6 +74,8 @@ SIGNATURES = {
     "mc_workspace_size": (ctypes.c_int, [P, I32, I32, P]),
     "mc_mincut": (ctypes.c_int, [P, P, P, SZ, P, P, P]),
     "mc_last_error": (ctypes.c_char_p, []),
+    "mc_profile": (ctypes.c_int, [P, I32]),
+    "mc_profile_read": (ctypes.c_int, [P, I32, P]),
     "mc_step_ws_size": (ctypes.c_int, [I32, I64, I32, P]),
     "mc_step_contract": (ctypes.c_int, [P, P, P, I32, P, P, SZ, P, P]),
     "mc_step_components": (ctypes.c_int, [P, I32, I64, P, P, P, P, P, SZ]),
@@ -189,6 +199,20 @@ class Context:
         if return_stats:
             return lam.value, side, st.as_dict()
         return lam.value, side
+
+    # ------------------------------------------------------------ timing
+    def profile(self, on=True):
+        """Switch kernel timing on (zeroing the totals) or off."""
+        _check(lib().mc_profile(self.h, int(bool(on))))
+
+    def profile_read(self):
+        """{kernel name: {"launches", "ms", "bytes"}} since profiling was switched on."""
+        out = {}
+        for k in range(MC_K_COUNT):
+            kt = KernelTime()
+            _check(lib().mc_profile_read(self.h, k, ctypes.byref(kt)))
+            out[kt.name.decode()] = {"launches": kt.launches, "ms": kt.ms, "bytes": kt.bytes}
+        return out
 
     # ------------------------------------------------------------ steps
     def step_workspace(self, n, cap, passes=1):

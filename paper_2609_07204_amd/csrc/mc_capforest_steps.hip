@@ -39,9 +39,6 @@ constexpr unsigned long long R_MASK = BATCH_BIT - 1;
 
 __device__ __forceinline__ bool is_queued(unsigned long long wv) { return (wv >> 62) == 0 && (wv & R_MASK) > 0; }
 
-__device__ __forceinline__ int64_t ld64(const int64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ unsigned long long ldw(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -131,6 +128,11 @@ __global__ __launch_bounds__(T) void k_cfs_init(StepArgs a) {
         *w.single = s;
         *w.ctl = c;
     }
+    if (threadIdx.x < SPREAD) {
+        unsigned long long* sp = a.spread + ((size_t)p * SPREAD + threadIdx.x) * SPREAD_STRIDE;
+        sp[0] = 0;
+        sp[1] = 0;
+    }
 }
 
 constexpr int POP_BLOCKS = 512;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(POP_T) void k_cfs_popscan(StepArgs a) {
 __global__ __launch_bounds__(T) void k_cfs_plan(StepArgs a) {
     __shared__ Red R;
     __shared__ int32_t s_x;
-    const int p = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wid = tid / MC_WAVE;
+    const int p = blockIdx.x, tid = threadIdx.x;
     PassView w = view(a, p);
     StepCtl& c = *w.ctl;
     const int32_t cap = a.pv.len_cap;
@@ -293,6 +295,21 @@ __device__ __forceinline__ int32_t last_le(const int32_t* x, int32_t n, int32_t 
     return lo;
 }
 
+static_assert(SPREAD == MC_WAVE, "k_cfs_finish folds one spread slot per lane");
+
+// append v to list for every lane with take set, one counter atomic per
+// wavefront (every lane of the wavefront must call this)
+__device__ __forceinline__ void wave_append(int32_t* list, int32_t* ctr, bool take, int32_t v) {
+    const unsigned long long m = __ballot(take);
+    if (m == 0) return;
+    const int lane = lane_id();
+    const int lead = __ffsll((long long)m) - 1;
+    int32_t base = 0;
+    if (lane == lead) base = atomicAdd(ctr, __popcll(m));
+    base = __shfl(base, lead, MC_WAVE);
+    if (take) list[base + __popcll(m & ((1ULL << lane) - 1))] = v;
+}
+
 // process the entries of all batches, one 1024-entry tile per workgroup pass
 __global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
     __shared__ int32_t win[ETILE + 2];
@@ -326,32 +343,37 @@ __global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
         const int32_t* src = c.bsingle ? w.single : w.fifo + (c.head - c.bcount);
         int64_t intra = 0;
         unsigned long long marks = 0;
-        for (int32_t e = e0 + threadIdx.x; e < e1; e += ET) {
-            int32_t k;
-            if (e < win[wc]) {
-                int32_t lo = 0, hi = wc;
-                while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (win[mid] <= e) lo = mid; else hi = mid; }
-                k = k0 + lo;
-            } else {
-                k = last_le(w.bpre, c.bcount, e);
+        // uniform trip count, so whole wavefronts reach the list appends
+        for (int32_t e = e0 + (int32_t)threadIdx.x; e - (int32_t)threadIdx.x < e1; e += ET) {
+            int32_t y = -1;
+            bool touch = false, cross = false;
+            if (e < e1) {
+                int32_t k;
+                if (e < win[wc]) {
+                    int32_t lo = 0, hi = wc;
+                    while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (win[mid] <= e) lo = mid; else hi = mid; }
+                    k = k0 + lo;
+                } else {
+                    k = last_le(w.bpre, c.bcount, e);
+                }
+                const int32_t xs = src[k];
+                const int32_t j = e - w.bpre[k];
+                const int32_t o = a.pv.g.off[xs];
+                y = a.pv.g.col[o + j];
+                const int64_t cw = a.pv.g.w[o + j];
+                const unsigned long long ow = atomicAdd(&w.rw[y], (unsigned long long)cw);
+                if (ow & SCAN_BIT) {
+                    if (ow & BATCH_BIT) intra += cw;
+                } else {
+                    touch = ow == 0;
+                    const int64_t old = (int64_t)(ow & R_MASK);
+                    const int64_t nw = old + cw;
+                    cross = old < lam && lam <= nw;
+                    if (cross && uf_union(a.pv.parent, xs, y)) marks++;
+                }
             }
-            const int32_t xs = src[k];
-            const int32_t j = e - w.bpre[k];
-            const int32_t o = a.pv.g.off[xs];
-            const int32_t y = a.pv.g.col[o + j];
-            const int64_t cw = a.pv.g.w[o + j];
-            const unsigned long long ow = atomicAdd(&w.rw[y], (unsigned long long)cw);
-            if (ow & SCAN_BIT) {
-                if (ow & BATCH_BIT) intra += cw;
-                continue;
-            }
-            if (ow == 0) w.tl[atomicAdd(&w.ctl->tn, 1)] = y;
-            const int64_t old = (int64_t)(ow & R_MASK);
-            const int64_t nw = old + cw;
-            if (old < lam && lam <= nw) {
-                if (uf_union(a.pv.parent, xs, y)) marks++;
-                w.fifo[atomicAdd(&w.ctl->tail, 1)] = y;
-            }
+            wave_append(w.tl, &w.ctl->tn, touch, y);
+            wave_append(w.fifo, &w.ctl->tail, cross, y);
         }
         intra = wave_sum_i64(intra);
         marks = (unsigned long long)wave_sum_i64((int64_t)marks);
@@ -361,8 +383,9 @@ __global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
             long long si = 0;
             unsigned long long sm = 0;
             for (int k = 0; k < ET / MC_WAVE; k++) { si += s_intra[k]; sm += s_marks[k]; }
-            if (si) atomic_add_i64(&w.ctl->intra, si);
-            if (sm) { atomicAdd(&w.ctl->marks, sm); atomicAdd(a.pv.marks, sm); }
+            unsigned long long* sp = a.spread + ((size_t)p * SPREAD + blockIdx.x % SPREAD) * SPREAD_STRIDE;
+            if (si) atomicAdd(&sp[0], (unsigned long long)si);
+            if (sm) atomicAdd(&sp[1], sm);
         }
     }
 }
@@ -394,9 +417,21 @@ __global__ __launch_bounds__(T) void k_cfs_finish(StepArgs a) {
         }
         run += tot;
     }
+    // fold the step's spread partial sums (intra-batch weight, marks)
+    __shared__ unsigned long long s_sum[2];
+    if (tid < MC_WAVE) {
+        unsigned long long* sp = a.spread + ((size_t)p * SPREAD + tid) * SPREAD_STRIDE;
+        const int64_t si = wave_sum_i64((int64_t)sp[0]);
+        const int64_t sm = wave_sum_i64((int64_t)sp[1]);
+        sp[0] = 0;
+        sp[1] = 0;
+        if (tid == 0) { s_sum[0] = (unsigned long long)si; s_sum[1] = (unsigned long long)sm; }
+    }
     __syncthreads();
     if (tid == 0) {
         const int32_t n = a.pv.g.n;
+        c.intra = (int64_t)s_sum[0];
+        if (s_sum[1]) { c.marks += s_sum[1]; atomicAdd(a.pv.marks, s_sum[1]); }
         c.nscan = base + run;
         c.alpha += c.part - c.intra;
         if (c.nscan < n) {
@@ -426,6 +461,10 @@ __global__ __launch_bounds__(T) void k_cfs_end(StepArgs a) {
             d[0] = c.steps; d[1] = c.singles; d[2] = c.tn; d[3] = c.entries;
             d[4] = 0; d[5] = 0; d[6] = c.nscan; d[7] = c.maxbatch;
         }
+        // algorithmic bytes of the pass's edge launches (profiling): 12 B
+        // per scanned entry (col, w), 5 B per scanned vertex
+        if (a.prof) atomicAdd(a.prof + (size_t)(p % PROF_LANES) * PROF_STRIDE,
+                              (unsigned long long)(12 * c.entries + 5 * (int64_t)c.nscan));
     }
 }
 
@@ -438,6 +477,7 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
         mc_hip_ok(hipErrorInvalidValue, "capforest_steps: per-pass arrays too small");
         return false;
     }
+    a.prof = prof_dev_bytes(PK_CFS_EDGES);
     k_cfs_init<<<P, T, 0, s>>>(a);
     MC_LAUNCHED("k_cfs_init");
     const int poll = 4;
@@ -448,8 +488,10 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
         MC_LAUNCHED("k_cfs_plan");
         k_cfs_tiles<<<1, T, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_tiles");
+        prof_begin(PK_CFS_EDGES, s);
         k_cfs_edges<<<4096, ET, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_edges");
+        prof_end(PK_CFS_EDGES, s);
         k_cfs_finish<<<P, T, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_finish");
         if (step % poll == poll - 1) {

@@ -29,58 +29,81 @@ namespace {
 
 constexpr int CHUNK = 512;          // chunk span in (entry offset + group index)
 constexpr int SMALL_MAX = 512;      // larger groups take the global-table path
-constexpr int HSLOTS = 2048;        // LDS hash slots per chunk (load <= 1/2)
+constexpr int HSLOTS = 1024;        // LDS hash slots per chunk (load <= 1/2)
 constexpr int TILE_SLOTS = 256;     // global-table allocation and extraction unit
 constexpr uint64_t EMPTY_KEY = ~0ULL;
 
-// Counting sort of vertices by label. Contraction often sends most of a
-// wavefront to one label (a giant group), so for a few rounds the lanes that
-// share the label of the first pending lane combine their atomics into one;
-// whatever is left goes alone.
-constexpr int AGG_ROUNDS = 4;
-__global__ void k_group_count(const int32_t* __restrict__ L, int32_t n, int32_t* __restrict__ gcnt) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t top = ((int64_t)n + MC_WAVE - 1) / MC_WAVE * MC_WAVE;
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < top; u += stride) {
-        bool pending = u < n;
-        const int32_t g = pending ? L[u] : -1;
-        for (int round = 0; round < AGG_ROUNDS; round++) {
-            const unsigned long long act = __ballot(pending);
-            if (act == 0) break;
-            const int lead = __ffsll((long long)act) - 1;
-            const int32_t gl = __shfl(g, lead, MC_WAVE);
-            const unsigned long long same = __ballot(pending && g == gl);
-            if (lane == lead) atomicAdd(&gcnt[gl], __popcll(same));
-            if (g == gl) pending = false;
+// Counting sort of vertices by label. Contraction often sends a large part
+// of the graph to one label (a giant group), and atomics on one address
+// serialise, so each workgroup first combines its tile of GT vertices in an
+// LDS table keyed by label and then issues one global atomic per distinct
+// label of the tile.
+constexpr int GT = 2048;            // vertices per workgroup tile
+constexpr int GT_SLOTS = 4096;      // LDS table slots (load <= 1/2)
+constexpr int GT_THREADS = 256;
+constexpr int GT_PER = GT / GT_THREADS;
+
+// insert label g into the tile table; returns its slot
+__device__ __forceinline__ int gt_insert(int32_t* key, int32_t* cnt, int32_t g) {
+    uint32_t h = hash32((uint32_t)g) & (GT_SLOTS - 1);
+    for (;;) {
+        const int32_t k = key[h];
+        if (k == g) break;
+        if (k == -1) {
+            const int32_t old = atomicCAS(&key[h], -1, g);
+            if (old == -1 || old == g) break;
         }
-        if (pending) atomicAdd(&gcnt[g], 1);
+        h = (h + 1) & (GT_SLOTS - 1);
+    }
+    atomicAdd(&cnt[h], 1);
+    return (int)h;
+}
+
+__global__ __launch_bounds__(GT_THREADS) void k_group_count(const int32_t* __restrict__ L, int32_t n,
+                                                           int32_t* __restrict__ gcnt) {
+    __shared__ int32_t key[GT_SLOTS], cnt[GT_SLOTS];
+    const int64_t tiles = ((int64_t)n + GT - 1) / GT;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS) { key[i] = -1; cnt[i] = 0; }
+        __syncthreads();
+        for (int k = 0; k < GT_PER; k++) {
+            const int64_t u = t * GT + k * GT_THREADS + threadIdx.x;
+            if (u < n) gt_insert(key, cnt, L[u]);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS)
+            if (key[i] >= 0) atomicAdd(&gcnt[key[i]], cnt[i]);
+        __syncthreads();
     }
 }
 
-__global__ void k_group_scatter(const int32_t* __restrict__ L, int32_t n, const int32_t* __restrict__ vstart,
-                                int32_t* __restrict__ gcur, int32_t* __restrict__ perm) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t top = ((int64_t)n + MC_WAVE - 1) / MC_WAVE * MC_WAVE;
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < top; u += stride) {
-        bool pending = u < n;
-        const int32_t g = pending ? L[u] : -1;
-        for (int round = 0; round < AGG_ROUNDS; round++) {
-            const unsigned long long act = __ballot(pending);
-            if (act == 0) break;
-            const int lead = __ffsll((long long)act) - 1;
-            const int32_t gl = __shfl(g, lead, MC_WAVE);
-            const unsigned long long same = __ballot(pending && g == gl);
-            int32_t base = 0;
-            if (lane == lead) base = atomicAdd(&gcur[gl], __popcll(same));
-            base = __shfl(base, lead, MC_WAVE);
-            if (pending && g == gl) {
-                perm[vstart[gl] + base + __popcll(same & ((1ULL << lane) - 1))] = (int32_t)u;
-                pending = false;
-            }
+// Same tiles: each distinct label of the tile reserves its members' places
+// with one global atomic; members then take consecutive places in LDS.
+__global__ __launch_bounds__(GT_THREADS) void k_group_scatter(const int32_t* __restrict__ L, int32_t n,
+                                                             const int32_t* __restrict__ vstart,
+                                                             int32_t* __restrict__ gcur, int32_t* __restrict__ perm) {
+    __shared__ int32_t key[GT_SLOTS], cnt[GT_SLOTS];
+    const int64_t tiles = ((int64_t)n + GT - 1) / GT;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS) { key[i] = -1; cnt[i] = 0; }
+        __syncthreads();
+        int slot[GT_PER];
+        for (int k = 0; k < GT_PER; k++) {
+            const int64_t u = t * GT + k * GT_THREADS + threadIdx.x;
+            slot[k] = u < n ? gt_insert(key, cnt, L[u]) : -1;
         }
-        if (pending) perm[vstart[g] + atomicAdd(&gcur[g], 1)] = (int32_t)u;
+        __syncthreads();
+        for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS) {
+            const int32_t g = key[i];
+            if (g >= 0) cnt[i] = vstart[g] + atomicAdd(&gcur[g], cnt[i]);
+        }
+        __syncthreads();
+        for (int k = 0; k < GT_PER; k++) {
+            if (slot[k] < 0) continue;
+            const int64_t u = t * GT + k * GT_THREADS + threadIdx.x;
+            perm[atomicAdd(&cnt[slot[k]], 1)] = (int32_t)u;
+        }
+        __syncthreads();
     }
 }
 
@@ -153,29 +176,34 @@ constexpr int MERGE_THREADS = 256;
 constexpr int SUB = 16;                              // lanes per group
 constexpr int NSUB = MERGE_THREADS / SUB;
 
+// first group of every chunk: cg[c] = first g with gstart[g] + g >= c CHUNK
+// (one independent search per thread, so their latencies overlap)
+__global__ void k_chunk_start(const int32_t* __restrict__ gstart, int32_t n2, int64_t nchunks,
+                              int32_t* __restrict__ cg) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += (int64_t)gridDim.x * blockDim.x)
+        cg[c] = first_key_ge(gstart, n2, c * CHUNK);
+}
+
+// Algorithmic bytes (profiling): per input entry 12 B (col, w) plus 4 B for
+// the label of its target; per output entry 12 B; per group 12 B (len, deg).
 __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const int32_t* __restrict__ L,
                                                               const int32_t* __restrict__ perm,
                                                               const int32_t* __restrict__ vstart,
                                                               const int32_t* __restrict__ gstart, int32_t n2,
-                                                              DGraph dst) {
+                                                              const int32_t* __restrict__ cg, DGraph dst,
+                                                              unsigned long long* pb) {
     __shared__ unsigned long long hkey[HSLOTS];
     __shared__ long long hval[HSLOTS];
     __shared__ int32_t gst[CHUNK + 1];
     __shared__ int32_t gvs[CHUNK + 1];
     __shared__ int32_t gcur[CHUNK];
     __shared__ long long gdeg[CHUNK];
-    __shared__ int32_t range[2];
 
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        int64_t k0 = (int64_t)blockIdx.x * CHUNK;
-        range[0] = first_key_ge(gstart, n2, k0);
-        range[1] = first_key_ge(gstart, n2, k0 + CHUNK);
-        if (range[1] > n2) range[1] = n2;
-    }
-    __syncthreads();
-    const int32_t g_lo = range[0], g_hi = range[1];
+    const int32_t g_lo = cg[blockIdx.x];
+    const int32_t g_hi = cg[blockIdx.x + 1] < n2 ? cg[blockIdx.x + 1] : n2;
     if (g_lo >= n2 || g_lo >= g_hi) return;
+    int64_t nin = 0, nout = 0, ngrp = 0;
     const int32_t ng = g_hi - g_lo;
     for (int i = tid; i < HSLOTS; i += MERGE_THREADS) { hkey[i] = EMPTY_KEY; hval[i] = 0; }
     for (int i = tid; i <= ng; i += MERGE_THREADS) {
@@ -192,6 +220,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
         for (int32_t m = gvs[gl]; m < gvs[gl + 1]; m++) {
             const int32_t u = perm ? perm[m] : m;
             const int32_t o = src.off[u], l = src.len[u];
+            if (sl == 0) nin += l;
             for (int32_t j = sl; j < l; j += SUB) {
                 const int32_t x = src.col[o + j];
                 const int64_t c = src.w[o + j];
@@ -224,13 +253,16 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
         dst.col[gst[gl] + pos] = t;
         dst.w[gst[gl] + pos] = s;
         atomicAdd((unsigned long long*)&gdeg[gl], (unsigned long long)s);
+        nout++;
     }
     __syncthreads();
     for (int gl = tid; gl < ng; gl += MERGE_THREADS) {
         if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
         dst.len[g_lo + gl] = gcur[gl];
         dst.deg[g_lo + gl] = gdeg[gl];
+        ngrp++;
     }
+    if (pb) prof_add(pb, nin * (L ? 16 : 12) + nout * 12 + ngrp * 12);
 }
 
 __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __restrict__ tkey,
@@ -250,6 +282,22 @@ __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __rest
 constexpr int BIG_TILE = 1024;
 constexpr int BIG_HSLOTS = 2048;
 
+// group and first member of every tile's first entry, searched for all
+// tiles at once so the searches' latencies overlap
+__global__ void k_big_tiles(const int32_t* __restrict__ vstart, const int32_t* __restrict__ mstart,
+                            const int32_t* __restrict__ gstart, const int32_t* __restrict__ bebase, int32_t n2,
+                            int32_t* __restrict__ tinfo) {
+    const int64_t ntiles = ((int64_t)bebase[n2] + BIG_TILE - 1) / BIG_TILE;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = t * BIG_TILE;
+        const int32_t g = last_le(bebase, n2, e);
+        const int32_t m0 = vstart ? vstart[g] : g;
+        const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
+        tinfo[2 * t] = g;
+        tinfo[2 * t + 1] = m0 + last_le(mstart + m0, mc, gstart[g] + (int32_t)(e - bebase[g]));
+    }
+}
+
 __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* __restrict__ L,
                                                    const int32_t* __restrict__ perm,
                                                    const int32_t* __restrict__ vstart,
@@ -259,13 +307,15 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
                                                    const int32_t* __restrict__ tbase, int32_t n2,
                                                    int32_t* __restrict__ tkey, int64_t* __restrict__ tval,
                                                    const int32_t* __restrict__ dslot, int64_t* __restrict__ dense,
-                                                   DGraph dst) {
+                                                   const int32_t* __restrict__ tinfo, DGraph dst,
+                                                   unsigned long long* pb) {
     __shared__ unsigned long long hkey[BIG_HSLOTS];
     __shared__ long long hval[BIG_HSLOTS];
     __shared__ int32_t wm[BIG_TILE + 2];     // member-space start of each member in the window
     __shared__ int32_t info[4];              // g, first member, member count in window, g's group end
     const int64_t total = bebase[n2];
     const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
+    int64_t nin = 0;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         for (int i = threadIdx.x; i < BIG_HSLOTS; i += blockDim.x) { hkey[i] = EMPTY_KEY; hval[i] = 0; }
         const int64_t e0 = tile * BIG_TILE;
@@ -275,11 +325,11 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
         while (e < e1) {
             __syncthreads();
             if (threadIdx.x == 0) {
-                const int32_t g = last_le(bebase, n2, e);
-                const int32_t ge = gstart[g] + (int32_t)(e - bebase[g]);
+                const int32_t g = e == e0 ? tinfo[2 * tile] : last_le(bebase, n2, e);
                 const int32_t m0 = vstart ? vstart[g] : g;
                 const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
-                const int32_t mf = m0 + last_le(mstart + m0, mc, ge);
+                const int32_t mf = e == e0 ? tinfo[2 * tile + 1]
+                                           : m0 + last_le(mstart + m0, mc, gstart[g] + (int32_t)(e - bebase[g]));
                 info[0] = g;
                 info[1] = mf;
                 info[2] = (m0 + mc) - mf;            // members from mf to the group's end
@@ -294,6 +344,7 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
             const int32_t gbase = gstart[g] - bebase[g];
             for (int64_t f = e + threadIdx.x; f < seg_end; f += blockDim.x) {
                 const int32_t ge = gbase + (int32_t)f;
+                nin++;
                 int32_t k;
                 if (ge < wm[wc]) {
                     int32_t lo = 0, hi = wc;
@@ -355,6 +406,7 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
         }
         __syncthreads();
     }
+    if (pb) prof_add(pb, nin * (L ? 16 : 12));
 }
 
 // Block-level allocation of output slots: one atomic per block for `take`
@@ -502,6 +554,8 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
     ws.scan_tmp = a.take<int32_t>(scan_tmp_elems((int64_t)n + 2) + 16);
     ws.red_val = a.take<int64_t>(1024);
     ws.red_id = a.take<int32_t>(1024);
+    ws.cg = a.take<int32_t>((size_t)((cap + n) / CHUNK) + 4);
+    ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
 }
 
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) {
@@ -522,11 +576,18 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     if (L) {
         if (!fill_i32(ws.gcnt, 0, (int64_t)n2 + 1, s)) return false;
         if (!fill_i32(ws.gcur, 0, n2, s)) return false;
-        k_group_count<<<grid_for(n, 256), 256, 0, s>>>(L, n, ws.gcnt);
+        const int gtiles = grid_for(n, GT, 4096);
+        prof_begin(PK_GROUP_COUNT, s);
+        k_group_count<<<gtiles, GT_THREADS, 0, s>>>(L, n, ws.gcnt);
         MC_LAUNCHED("k_group_count");
+        prof_end(PK_GROUP_COUNT, s);
+        prof_host_bytes(PK_GROUP_COUNT, 4.0 * n + 4.0 * n2);   // labels in, counts out
         if (!scan_i32(ws.gcnt, ws.vstart, n2, ws.scan_tmp, s)) return false;
-        k_group_scatter<<<grid_for(n, 256), 256, 0, s>>>(L, n, ws.vstart, ws.gcur, ws.perm);
+        prof_begin(PK_GROUP_SCATTER, s);
+        k_group_scatter<<<gtiles, GT_THREADS, 0, s>>>(L, n, ws.vstart, ws.gcur, ws.perm);
         MC_LAUNCHED("k_group_scatter");
+        prof_end(PK_GROUP_SCATTER, s);
+        prof_host_bytes(PK_GROUP_SCATTER, 8.0 * n + 4.0 * n2);  // labels in, perm out, group starts in
         perm = ws.perm;
         vstart = ws.vstart;
     }
@@ -546,13 +607,23 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
     if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
     const int64_t chunks = (src.cap + n2) / CHUNK + 2;
-    k_merge_small<<<(unsigned)chunks, MERGE_THREADS, 0, s>>>(src, L, perm, vstart, gstart, n2, dst);
+    k_chunk_start<<<grid_for(chunks + 1, 256), 256, 0, s>>>(gstart, n2, chunks, ws.cg);
+    MC_LAUNCHED("k_chunk_start");
+    prof_begin(PK_MERGE_SMALL, s);
+    k_merge_small<<<(unsigned)chunks, MERGE_THREADS, 0, s>>>(src, L, perm, vstart, gstart, n2, ws.cg, dst,
+                                                             prof_dev_bytes(PK_MERGE_SMALL));
     MC_LAUNCHED("k_merge_small");
+    prof_end(PK_MERGE_SMALL, s);
     k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);
     MC_LAUNCHED("k_big_clear");
+    k_big_tiles<<<grid_for(src.cap / BIG_TILE + 1, 256), 256, 0, s>>>(vstart, ws.mstart, gstart, ws.bigm, n2,
+                                                                      ws.tinfo);
+    MC_LAUNCHED("k_big_tiles");
+    prof_begin(PK_BIG_INSERT, s);
     k_big_insert<<<4096, 256, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.bigm, ws.tsize, n2, ws.tkey,
-                                      ws.tval, ws.dslot, ws.dense, dst);
+                                      ws.tval, ws.dslot, ws.dense, ws.tinfo, dst, prof_dev_bytes(PK_BIG_INSERT));
     MC_LAUNCHED("k_big_insert");
+    prof_end(PK_BIG_INSERT, s);
     k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.tkey, ws.tval, ws.bcur, dst);
     MC_LAUNCHED("k_big_extract");
     k_dense_extract<<<grid_for((int64_t)DENSE_SLOTS * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, gstart, n2, ws.dense,

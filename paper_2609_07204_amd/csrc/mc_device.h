@@ -127,3 +127,18 @@ __device__ __forceinline__ void wave_argmin(int64_t& val, int32_t& id) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (MC_WAVE - 1); }
+
+// ------------------------------------------------- profiling counters
+// Algorithmic-byte counters of the profiled kernels: PROF_LANES counters per
+// kernel, 128 B apart, so the once-per-wave adds of a large launch spread
+// over many L2 channels instead of queueing on one address. Every lane of
+// the wave calls prof_add.
+constexpr int PROF_LANES = 64;
+constexpr int PROF_STRIDE = 16;   // 16 x 8 B = 128 B
+__device__ __forceinline__ void prof_add(unsigned long long* pb, int64_t bytes) {
+    bytes = wave_sum_i64(bytes);
+    if (lane_id() == 0 && bytes) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % PROF_LANES;
+        atomicAdd(pb + (size_t)slot * PROF_STRIDE, (unsigned long long)bytes);
+    }
+}

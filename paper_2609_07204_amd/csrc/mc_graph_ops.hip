@@ -39,28 +39,39 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
 }
 
 // Connectivity in the manner of Afforest (Sutton, Ben-Nun and Barak, IPDPS
-// 2018): first every vertex points at its smallest neighbour when that is
-// smaller than itself (plain stores: it only writes its own entry, and the
-// parent stays smaller, so the union-find invariant holds), then the
-// component most sampled vertices fall into is found, and all edges are
-// linked only for vertices outside it; an edge between that component and
-// another one is seen from the other side.
-__global__ __launch_bounds__(256) void k_uf_hook_min(DGraph g, int32_t* par) {
+// 2018), on a graph whose entries all have positive weight (a normalised
+// graph). Two hooking sweeps first join most of the graph: in each, every
+// row lowers the root of its own tree to the smallest root among its
+// neighbours (parent[] is compressed before each sweep, so par[v] is a
+// root); pointers only ever decrease, so the forest stays acyclic and the
+// union-find invariant parent[x] <= x holds. The first sweep, from the
+// identity, hooks every vertex to its smallest neighbour; the second joins
+// those trees (on power-law graphs it leaves nearly all vertices in one
+// tree). Then the component most sampled vertices fall into is found, and
+// all edges are linked with full unions only for vertices outside it; an
+// edge between that component and another one is seen from the other side.
+__global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par, unsigned long long* pb) {
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
         const int32_t o = g.off[v], l = g.len[v];
-        int32_t m = (int32_t)v;
+        const int32_t r = ld_acq(&par[v]);
+        int32_t m = r;
         for (int32_t j = sl; j < l; j += SUB) {
-            const int32_t x = g.col[o + j];
-            if (x < m && g.w[o + j] > 0) m = x;
+            const int32_t px = ld_acq(&par[g.col[o + j]]);
+            m = px < m ? px : m;
         }
         for (int k = SUB / 2; k > 0; k >>= 1) {
             const int32_t t = __shfl_xor(m, k, SUB);
             m = t < m ? t : m;
         }
-        if (sl == 0) par[v] = m;
+        if (sl == 0) {
+            if (m < r && m < ld_acq(&par[r])) atomicMin(&par[r], m);
+            bytes += 8 + 8 * (int64_t)l;
+        }
     }
+    if (pb) prof_add(pb, bytes);
 }
 
 __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int32_t n, int32_t* mode) {
@@ -87,16 +98,20 @@ __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int
     if (threadIdx.x == 0) *mode = bestr[0];
 }
 
-__global__ __launch_bounds__(256) void k_uf_link_rest(DGraph g, int32_t* par, const int32_t* mode) {
+__global__ __launch_bounds__(256) void k_uf_link_rest(DGraph g, int32_t* par, const int32_t* mode,
+                                                     unsigned long long* pb) {
     const int32_t big = *mode;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        if (sl == 0) bytes += 4;
         if (ld_acq(&par[v]) == big) continue;
         const int32_t o = g.off[v], l = g.len[v];
-        for (int32_t j = sl; j < l; j += SUB)
-            if (g.w[o + j] > 0) uf_union(par, (int32_t)v, g.col[o + j]);
+        for (int32_t j = sl; j < l; j += SUB) uf_union(par, (int32_t)v, g.col[o + j]);
+        if (sl == 0) bytes += 8 + 8 * (int64_t)l;
     }
+    if (pb) prof_add(pb, bytes);
 }
 
 // After all unions: point every vertex at its root. Each thread writes only
@@ -132,19 +147,23 @@ __global__ void k_label(const int32_t* par, const int32_t* newid, int32_t n, int
 constexpr int32_t PR_LONG = 2048;
 constexpr int32_t PR_CHUNK = 4096;
 
+// Algorithmic bytes (profiling): 12 B per entry (col, w) and 16 B per row
+// (off, len, deg) of the rows this kernel tests.
 __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int32_t* par,
                                              unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
-                                             int32_t* long_list, int32_t* long_cnt) {
+                                             int32_t* long_list, int32_t* long_cnt, unsigned long long* pb) {
     const int64_t lam = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
         const int32_t o = g.off[v], l = g.len[v];
         if (l > PR_LONG) {
             if (sl == 0) long_list[atomicAdd(long_cnt, 1)] = (int32_t)v;
             continue;
         }
+        if (sl == 0) bytes += 16 + 12 * (int64_t)l;
         int64_t bw = -1;
         int32_t bx = -1;
         for (int32_t j = sl; j < l; j += SUB) {
@@ -166,8 +185,20 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int
             if (take && uf_union(par, (int32_t)v, bx)) joined++;
         }
     }
+    // marks go to one of SPREAD partial counters (128 B apart): a single
+    // counter would take one atomic from every wavefront of the launch
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
-    if (lane_id() == 0 && joined) atomicAdd(marks, joined);
+    if (lane_id() == 0 && joined) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
+        atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
+    }
+    if (pb) prof_add(pb, bytes);
+}
+
+// fold the partial counters of k_pr12 into the round's mark count
+__global__ __launch_bounds__(64) void k_pr12_fold(unsigned long long* spread, unsigned long long* marks) {
+    const int64_t v = wave_sum_i64((int64_t)spread[(size_t)threadIdx.x * SPREAD_STRIDE]);
+    if (threadIdx.x == 0 && v) atomicAdd(marks, (unsigned long long)v);
 }
 
 // task offsets of the long rows: ceil(len / PR_CHUNK) tasks each
@@ -359,14 +390,19 @@ bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
 }
 
 bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s) {
-    k_uf_hook_min<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent);
-    MC_LAUNCHED("k_uf_hook_min");
-    k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
-    MC_LAUNCHED("k_uf_compress");
+    const int rows = grid_for((int64_t)g.n * SUB, 256);
+    for (int sweep = 0; sweep < 2; sweep++) {
+        k_uf_root_min<<<rows, 256, 0, s>>>(g, parent, nullptr);
+        MC_LAUNCHED("k_uf_root_min");
+        k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
+        MC_LAUNCHED("k_uf_compress");
+    }
     k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, tmp);
     MC_LAUNCHED("k_uf_sample_mode");
-    k_uf_link_rest<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, parent, tmp);
+    prof_begin(PK_UF_LINK_REST, s);
+    k_uf_link_rest<<<rows, 256, 0, s>>>(g, parent, tmp, prof_dev_bytes(PK_UF_LINK_REST));
     MC_LAUNCHED("k_uf_link_rest");
+    prof_end(PK_UF_LINK_REST, s);
     return true;
 }
 
@@ -391,14 +427,20 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
     const size_t tasks = (size_t)(cap / PR_CHUNK) + nlong;
     w.part_w = a.take<int64_t>(tasks);
     w.part_x = a.take<int32_t>(tasks);
+    w.spread = a.take<unsigned long long>((size_t)SPREAD * SPREAD_STRIDE);
 }
 
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
           int32_t* ptr2, Pr12WS& w, hipStream_t s) {
     if (!fill_i32(w.counters, 0, 4, s)) return false;
-    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, marks, flag1, ptr2, w.long_list,
-                                                            w.counters);
+    if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s)) return false;
+    prof_begin(PK_PR12, s);
+    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, w.spread, flag1, ptr2, w.long_list,
+                                                            w.counters, prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
+    prof_end(PK_PR12, s);
+    k_pr12_fold<<<1, SPREAD, 0, s>>>(w.spread, marks);
+    MC_LAUNCHED("k_pr12_fold");
     k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);
     MC_LAUNCHED("k_pr12_long_scan");
     k_pr12_long<<<2048, 256, 0, s>>>(g, lam, parent, marks, flag1, w.long_list, w.counters, w.task_off, w.part_w,

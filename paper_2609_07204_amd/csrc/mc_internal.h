@@ -15,6 +15,28 @@ bool mc_hip_ok(hipError_t e, const char* what);
 #define MC_HIP(call) do { if (!mc_hip_ok((call), #call)) return false; } while (0)
 #define MC_LAUNCHED(what) do { if (!mc_hip_ok(hipGetLastError(), what)) return false; } while (0)
 
+// ------------------------------------------------------------ profiling
+// Optional timing of the hot kernels (mc_profile): while a solve runs on a
+// context with profiling on, each timed launch is bracketed by two HIP
+// events on its stream, and its algorithmic bytes go either to a device
+// counter the kernel adds to (prof_dev_bytes) or are added by the host when
+// the host knows them (prof_host_bytes). With profiling off, prof_dev_bytes
+// returns nullptr and the kernels skip the count.
+enum ProfKernel {
+    PK_CFS_EDGES = 0, PK_MERGE_SMALL, PK_BIG_INSERT, PK_GROUP_COUNT, PK_GROUP_SCATTER, PK_PR12, PK_UF_LINK_REST,
+    PK_COUNT
+};
+void prof_begin(int k, hipStream_t s);
+void prof_end(int k, hipStream_t s);
+unsigned long long* prof_dev_bytes(int k);
+void prof_host_bytes(int k, double bytes);
+
+// Counters that many workgroups add to are split into SPREAD partial
+// counters SPREAD_STRIDE words (128 B) apart and folded afterwards: atomics
+// on one address serialise.
+constexpr int SPREAD = 64;
+constexpr int SPREAD_STRIDE = 16;
+
 // Bump allocator over the caller's device workspace. With base == nullptr
 // it only measures, so mc_workspace_size and the solver carve identically.
 struct Arena {
@@ -62,6 +84,8 @@ struct ContractWS {
     int32_t* scan_tmp;
     int64_t* red_val; // [1024] per-block minima
     int32_t* red_id;  // [1024]
+    int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
+    int32_t* tinfo;   // [2*(cap/1024+2)] group and first member of every large-group tile
 };
 void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
 
@@ -79,8 +103,10 @@ bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s);
 bool uf_init(int32_t* parent, int32_t n, hipStream_t s);
 // Union the endpoints of every entry with positive weight.
 bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s);
-// Same components with far fewer unions on graphs with a giant component
-// (sampling-based linking); tmp holds one int.
+// The same components for a graph whose entries all have positive weight
+// (a normalised graph), with far fewer unions when there is a giant
+// component (hooking sweeps, then sampling-based linking); tmp holds one
+// int.
 bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s);
 // Compress parent[] and write canonical labels (components numbered by
 // their smallest vertex) to L; the count goes to sc->n2.
@@ -97,6 +123,7 @@ struct Pr12WS {
     int32_t* task_off;
     int64_t* part_w;
     int32_t* part_x;
+    unsigned long long* spread;   // [SPREAD * SPREAD_STRIDE] partial mark counts
 };
 void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
@@ -205,7 +232,13 @@ struct StepArgs {
     int64_t* popk;      // [passes*512] parts of the single-pop maximum
     int32_t* popv;
     int32_t max_singles;  // single pops per pass before it stops (0: none)
+    unsigned long long* prof;  // algorithmic-byte counter (profiling) or nullptr
+    // per pass, SPREAD partial sums 128 B apart of the step's intra-batch
+    // weight ([0]) and marks ([1]), so the edge tiles do not all add to one
+    // address; k_cfs_finish folds and clears them
+    unsigned long long* spread;   // [passes * SPREAD * SPREAD_STRIDE]
 };
+
 bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s);
 
 // -------------------------------------------------------- side tracking

@@ -40,6 +40,8 @@ __global__ void k_reset_round(DevScalars* sc) {
     sc->marks_pr = 0;
     sc->marks_cf = 0;
     sc->err = 0;
+    sc->best_pass = -1;
+    sc->best_alpha = INT64_MAX;
 }
 __global__ void k_uf_pairs(const int32_t* a, const int32_t* b, int64_t np, int32_t* par) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
@@ -68,6 +70,88 @@ bool mc_hip_ok(hipError_t e, const char* what) {
     return false;
 }
 
+// ------------------------------------------------------------ profiling
+namespace {
+struct Prof {
+    bool on = false;
+    unsigned long long* dbytes = nullptr;   // device counters [PK_COUNT]
+    double hbytes[PK_COUNT] = {};
+    int64_t launches[PK_COUNT] = {};
+    double ms[PK_COUNT] = {};
+    hipEvent_t open[PK_COUNT] = {};
+    std::vector<hipEvent_t> pool;
+    struct Pending { int k; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) { e = pool.back(); pool.pop_back(); return e; }
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // fold finished event pairs into the totals (the stream has been synchronised)
+    void resolve() {
+        for (const Pending& p : pending) {
+            float t = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess)
+                ms[p.k] += t;
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    ~Prof() {
+        for (const Pending& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        if (dbytes) (void)hipFree(dbytes);
+    }
+};
+thread_local Prof* g_prof = nullptr;   // the profiler of the solve running on this thread
+constexpr size_t kProfCounterBytes = sizeof(unsigned long long) * PK_COUNT * PROF_LANES * PROF_STRIDE;
+
+const char* const kProfNames[PK_COUNT] = {"k_cfs_edges",     "k_merge_small", "k_big_insert",  "k_group_count",
+                                          "k_group_scatter", "k_pr12",        "k_uf_link_rest"};
+
+// sets g_prof for the duration of one call and resolves its events at the end
+struct ProfScope {
+    explicit ProfScope(Prof* p) { g_prof = p && p->on ? p : nullptr; }
+    ~ProfScope() {
+        if (g_prof) g_prof->resolve();
+        g_prof = nullptr;
+    }
+};
+}  // namespace
+
+void prof_begin(int k, hipStream_t s) {
+    Prof* p = g_prof;
+    if (!p) return;
+    hipEvent_t e = p->take();
+    if (e && hipEventRecord(e, s) != hipSuccess) { p->pool.push_back(e); e = nullptr; }
+    p->open[k] = e;
+}
+
+void prof_end(int k, hipStream_t s) {
+    Prof* p = g_prof;
+    if (!p || !p->open[k]) return;
+    hipEvent_t e = p->take();
+    if (!e || hipEventRecord(e, s) != hipSuccess) {
+        if (e) p->pool.push_back(e);
+        p->pool.push_back(p->open[k]);
+    } else {
+        p->pending.push_back({k, p->open[k], e});
+        p->launches[k]++;
+    }
+    p->open[k] = nullptr;
+}
+
+unsigned long long* prof_dev_bytes(int k) {
+    return g_prof ? g_prof->dbytes + (size_t)k * PROF_LANES * PROF_STRIDE : nullptr;
+}
+
+void prof_host_bytes(int k, double bytes) {
+    if (g_prof) g_prof->hbytes[k] += bytes;
+}
+
 struct mc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -75,6 +159,7 @@ struct mc_ctx {
     int cus = 256;
     DevScalars* hsc = nullptr;   // pinned readback slot
     int32_t tag = 0;             // round tag for visited arrays (never reset)
+    Prof* prof = nullptr;        // kernel timing, allocated by mc_profile
 };
 
 extern "C" void mc_default_options(mc_options* o) {
@@ -117,7 +202,52 @@ extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_option
 extern "C" mc_status mc_ctx_destroy(mc_ctx* c) {
     if (!c) return MC_OK;
     if (c->hsc) (void)hipHostFree(c->hsc);
+    delete c->prof;
     delete c;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_profile(mc_ctx* c, int32_t on) {
+    if (!c) return fail(MC_E_INVALID_ARG, "mc_profile: ctx is NULL");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
+    if (!on) {
+        if (c->prof) c->prof->on = false;
+        return MC_OK;
+    }
+    if (!c->prof) {
+        c->prof = new (std::nothrow) Prof();
+        if (!c->prof) return fail(MC_E_OOM, "mc_profile: out of host memory");
+        if (hipMalloc((void**)&c->prof->dbytes, kProfCounterBytes) != hipSuccess) {
+            delete c->prof;
+            c->prof = nullptr;
+            return fail(MC_E_DEVICE, "mc_profile: hipMalloc of the byte counters failed");
+        }
+    }
+    Prof* p = c->prof;
+    if (hipMemsetAsync(p->dbytes, 0, kProfCounterBytes, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(MC_E_DEVICE, "mc_profile: clearing the byte counters failed");
+    for (int k = 0; k < PK_COUNT; k++) { p->hbytes[k] = 0; p->launches[k] = 0; p->ms[k] = 0; }
+    p->on = true;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_profile_read(mc_ctx* c, int32_t kernel, mc_kernel_time* out) {
+    if (!c || !out) return fail(MC_E_INVALID_ARG, "mc_profile_read: NULL argument");
+    if (kernel < 0 || kernel >= PK_COUNT) return fail(MC_E_INVALID_ARG, "mc_profile_read: no such kernel");
+    std::memset(out, 0, sizeof(*out));
+    std::snprintf(out->name, sizeof(out->name), "%s", kProfNames[kernel]);
+    if (!c->prof) return MC_OK;
+    Prof* p = c->prof;
+    std::vector<unsigned long long> db(kProfCounterBytes / sizeof(unsigned long long));
+    if (hipSetDevice(c->device) != hipSuccess ||
+        hipMemcpy(db.data(), p->dbytes, kProfCounterBytes, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(MC_E_DEVICE, "mc_profile_read: reading the byte counters failed");
+    double dev_bytes = 0;
+    for (int i = 0; i < PROF_LANES; i++) dev_bytes += (double)db[((size_t)kernel * PROF_LANES + i) * PROF_STRIDE];
+    out->launches = p->launches[kernel];
+    out->ms = p->ms[kernel];
+    out->bytes = dev_bytes + p->hbytes[kernel];
     return MC_OK;
 }
 
@@ -187,6 +317,7 @@ void carve_steps(Arena& a, int32_t n, int32_t passes, int32_t len_cap, StepArgs&
     sa.running = a.take<int32_t>(1);
     sa.popk = a.take<int64_t>((size_t)passes * 512);
     sa.popv = a.take<int32_t>((size_t)passes * 512);
+    sa.spread = a.take<unsigned long long>((size_t)passes * SPREAD * SPREAD_STRIDE);
     sa.max_singles = 0;
 }
 
@@ -455,7 +586,14 @@ static mc_status exact_rounds(Solver& S, int src) {
         const bool det = S.c->opt.deterministic != 0;
         const bool shared = S.c->opt.capforest_mode == MC_CF_SHARED && !det;
         const int32_t* pref_order = nullptr;   // scan order of the pass with the best alpha
-        if (det) {
+        // when the reduction tests alone at least halve the graph, contract
+        // now and leave CAPFOREST to the smaller graph of the next round
+        // (any set of contractible edges is a valid round)
+        if (!S.readback()) return MC_E_DEVICE;
+        const bool skip_cf = 2 * (int64_t)S.c->hsc->marks_pr >= n;
+        if (skip_cf) {
+            S.stats.rounds_pr_only++;
+        } else if (det) {
             if (!sequential_pass(S, *cur, round)) return MC_E_DEVICE;
         } else if (shared) {
             CapforestArgs ca{};
@@ -482,7 +620,8 @@ static mc_status exact_rounds(Solver& S, int src) {
         }
         if (!S.readback()) return MC_E_DEVICE;
         DevScalars h = *S.c->hsc;
-        if (S.debug) debug_round(S, *cur, round, det || shared ? 0 : std::min(w.pv.passes, private_pass_count(S.c, n)));
+        if (S.debug)
+            debug_round(S, *cur, round, det || shared || skip_cf ? 0 : std::min(w.pv.passes, private_pass_count(S.c, n)));
         if (h.best_pass >= 0 && h.best_alpha < S.lam) {
             if (det) pref_order = w.corder;
             else if (shared) pref_order = w.order + (int64_t)h.best_pass * CF_HC;
@@ -553,6 +692,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     }
     if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
 
+    ProfScope prof_scope(c->prof);
     Solver S;
     S.c = c;
     S.s = c->stream;
