@@ -15,11 +15,24 @@
 //   k_cfs_tiles  one workgroup: cut every pass's entries into 1024-entry
 //                tiles, and count the passes still running;
 //   k_cfs_edges  all workgroups, one tile at a time: one 64-bit atomic add
-//                per entry raises r and reports the target's state; marks,
-//                capped FIFO and touched list follow from it;
+//                per entry raises r and reports the target's state; marks
+//                and the capped FIFO follow from it;
+//   k_cfs_hubfix targets of high degree (hubs) are not updated entry by
+//                entry: atomics on one address serialise, and a hub can
+//                receive thousands of entries in one step. Their entries
+//                go to HUB_SLOTS partial sums per hub instead, together
+//                with the heaviest entry; this launch folds them into r;
 //   k_cfs_finish one workgroup per pass: batch becomes scanned, alpha and
 //                the bound are updated.
+// Within a batch the entries may be applied in any order (all batch
+// vertices are scanned together), so a hub's step total may be applied at
+// once: if it lifts r from below lam to at least lam, the heaviest entry of
+// the step is one that crosses lam in some order of the entries (put the
+// others first until the remaining gap is at most its weight, which no
+// other entry exceeds), and its edge is contracted as Algorithm 1 does.
 // The host issues steps and reads the running-pass count every few steps.
+#include <algorithm>
+
 #include "mc_internal.h"
 
 namespace {
@@ -93,8 +106,16 @@ __device__ void bargmax(int64_t& key, int32_t& id, Red& R) {
 struct PassView {
     int32_t *fifo, *tl, *order, *bpre, *single;
     unsigned long long* rw;
+    unsigned long long* hacc;   // [max_hubs * HUB_SLOTS * 2] (sum, heaviest entry)
     StepCtl* ctl;
 };
+
+// heaviest entry key: weight (saturated at 2^31 - 1) above the source vertex
+constexpr unsigned long long HUB_WSAT = 0x7FFFFFFFULL;
+__device__ __forceinline__ unsigned long long hub_key(int64_t c, int32_t x) {
+    const unsigned long long cw = (unsigned long long)c < HUB_WSAT ? (unsigned long long)c : HUB_WSAT;
+    return (cw << 32) | (uint32_t)x;
+}
 
 __device__ __forceinline__ PassView view(const StepArgs& a, int p) {
     const PrivateArgs& v = a.pv;
@@ -106,7 +127,38 @@ __device__ __forceinline__ PassView view(const StepArgs& a, int p) {
     w.bpre = a.bpre + (int64_t)p * (a.bcap + 1);
     w.single = a.single + p;
     w.ctl = a.ctl + p;
+    w.hacc = a.hacc + (size_t)p * a.max_hubs * HUB_SLOTS * 2;
     return w;
+}
+
+// hub index of every vertex with at least HUB_LEN entries (else -1); the
+// hub's partial sums start at zero
+__global__ __launch_bounds__(256) void k_cfs_hubs(StepArgs a) {
+    const int32_t n = a.pv.g.n;
+    const int64_t top = ((int64_t)n + MC_WAVE - 1) / MC_WAVE * MC_WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < top; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool hub = v < n && a.pv.g.len[v] >= HUB_LEN;
+        const unsigned long long m = __ballot(hub);
+        int32_t base = 0;
+        const int lead = m ? __ffsll((long long)m) - 1 : 0;
+        if (m && lane_id() == lead) base = atomicAdd(a.nhub, __popcll(m));
+        base = __shfl(base, lead, MC_WAVE);
+        if (v < n) {
+            int32_t h = -1;
+            if (hub) {
+                h = base + __popcll(m & ((1ULL << lane_id()) - 1));
+                if (h >= a.max_hubs) h = -1;   // cannot happen: max_hubs >= entries / HUB_LEN
+                else {
+                    a.hv[h] = (int32_t)v;
+                    for (int32_t p = 0; p < a.pv.passes; p++) {
+                        unsigned long long* hs = a.hacc + ((size_t)p * a.max_hubs + h) * HUB_SLOTS * 2;
+                        for (int k = 0; k < 2 * HUB_SLOTS; k++) hs[k] = 0;
+                    }
+                }
+            }
+            a.hid[v] = h;
+        }
+    }
 }
 
 __global__ __launch_bounds__(T) void k_cfs_init(StepArgs a) {
@@ -119,9 +171,7 @@ __global__ __launch_bounds__(T) void k_cfs_init(StepArgs a) {
             uint64_t h = splitmix64(a.pv.seed ^ splitmix64(((uint64_t)(uint32_t)a.pv.round << 32) | (uint32_t)p));
             s = (int32_t)(((h >> 32) * (uint64_t)n) >> 32);
         }
-        w.tl[0] = s;
         StepCtl c{};
-        c.tn = 1;
         c.lam = *a.pv.lam;
         c.best_alpha = INT64_MAX;
         c.single_pending = 1;
@@ -297,83 +347,86 @@ __device__ __forceinline__ int32_t last_le(const int32_t* x, int32_t n, int32_t 
 
 static_assert(SPREAD == MC_WAVE, "k_cfs_finish folds one spread slot per lane");
 
-// append v to list for every lane with take set, one counter atomic per
-// wavefront (every lane of the wavefront must call this)
-__device__ __forceinline__ void wave_append(int32_t* list, int32_t* ctr, bool take, int32_t v) {
-    const unsigned long long m = __ballot(take);
-    if (m == 0) return;
-    const int lane = lane_id();
-    const int lead = __ffsll((long long)m) - 1;
-    int32_t base = 0;
-    if (lane == lead) base = atomicAdd(ctr, __popcll(m));
-    base = __shfl(base, lead, MC_WAVE);
-    if (take) list[base + __popcll(m & ((1ULL << lane) - 1))] = v;
+// pass and first batch vertex of every edge tile, searched for all tiles
+// at once so the searches' latencies overlap
+__global__ __launch_bounds__(256) void k_cfs_tileinfo(StepArgs a) {
+    const int32_t P = a.pv.passes;
+    const int32_t ntiles = a.ptile[P];
+    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+        const int32_t p = last_le(a.ptile, P, t);
+        const int32_t e0 = (t - a.ptile[p]) * ETILE;
+        const int32_t* bpre = a.bpre + (int64_t)p * (a.bcap + 1);
+        a.tinfo[2 * (int64_t)t] = p;
+        a.tinfo[2 * (int64_t)t + 1] = last_le(bpre, a.ctl[p].bcount, e0);
+    }
 }
 
-// process the entries of all batches, one 1024-entry tile per workgroup pass
+// process the entries of all batches, one 1024-entry tile per workgroup
+// pass. Newly capped targets are staged in LDS and appended to the pass's
+// FIFO with one counter atomic per tile.
 __global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
     __shared__ int32_t win[ETILE + 2];
-    __shared__ int32_t info[4];
+    __shared__ int32_t s_cross[ETILE];
+    __shared__ int32_t s_nc, s_base;
     __shared__ long long s_intra[ET / MC_WAVE];
     __shared__ unsigned long long s_marks[ET / MC_WAVE];
     const int32_t P = a.pv.passes;
     const int32_t ntiles = a.ptile[P];
+    const unsigned hslot = (blockIdx.x * (ET / MC_WAVE) + threadIdx.x / MC_WAVE) % HUB_SLOTS;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int32_t p = last_le(a.ptile, P, t);
-            info[0] = p;
-            const int32_t e0 = (t - a.ptile[p]) * ETILE;
-            const StepCtl& c = a.ctl[p];
-            const int32_t* bpre = a.bpre + (int64_t)p * (a.bcap + 1);
-            const int32_t k0 = last_le(bpre, c.bcount, e0);
-            info[1] = k0;
-            info[2] = e0;
-            info[3] = c.bcount - k0;              // batch vertices from k0 on
-        }
-        __syncthreads();
-        const int32_t p = info[0], k0 = info[1], e0 = info[2];
+        const int32_t p = a.tinfo[2 * (int64_t)t], k0 = a.tinfo[2 * (int64_t)t + 1];
+        const int32_t e0 = (t - a.ptile[p]) * ETILE;
         PassView w = view(a, p);
         const StepCtl& c = *w.ctl;
-        const int32_t wc = info[3] < ETILE + 1 ? info[3] : ETILE + 1;
+        const int32_t rest = c.bcount - k0;      // batch vertices from k0 on
+        const int32_t wc = rest < ETILE + 1 ? rest : ETILE + 1;
+        __syncthreads();
         for (int i = threadIdx.x; i <= wc; i += ET) win[i] = w.bpre[k0 + i];
+        if (threadIdx.x == 0) s_nc = 0;
         __syncthreads();
         const int32_t e1 = e0 + ETILE < c.E ? e0 + ETILE : c.E;
         const int64_t lam = c.lam;
         const int32_t* src = c.bsingle ? w.single : w.fifo + (c.head - c.bcount);
         int64_t intra = 0;
         unsigned long long marks = 0;
-        // uniform trip count, so whole wavefronts reach the list appends
-        for (int32_t e = e0 + (int32_t)threadIdx.x; e - (int32_t)threadIdx.x < e1; e += ET) {
-            int32_t y = -1;
-            bool touch = false, cross = false;
-            if (e < e1) {
-                int32_t k;
-                if (e < win[wc]) {
-                    int32_t lo = 0, hi = wc;
-                    while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (win[mid] <= e) lo = mid; else hi = mid; }
-                    k = k0 + lo;
+        for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += ET) {
+            int32_t k, j;
+            if (e < win[wc]) {
+                int32_t lo = 0, hi = wc;
+                while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (win[mid] <= e) lo = mid; else hi = mid; }
+                k = k0 + lo;
+                j = e - win[lo];
+            } else {
+                k = last_le(w.bpre, c.bcount, e);
+                j = e - w.bpre[k];
+            }
+            const int32_t xs = src[k];
+            const int32_t o = a.pv.g.off[xs];
+            const int32_t y = a.pv.g.col[o + j];
+            const int64_t cw = a.pv.g.w[o + j];
+            const int32_t h = a.hid[y];
+            if (h >= 0) {
+                // hub: its state bits do not change during this launch
+                const unsigned long long sv = ldw(&w.rw[y]);
+                if (sv & SCAN_BIT) {
+                    if (sv & BATCH_BIT) intra += cw;
                 } else {
-                    k = last_le(w.bpre, c.bcount, e);
+                    unsigned long long* hs = w.hacc + ((size_t)h * HUB_SLOTS + hslot) * 2;
+                    atomicAdd(&hs[0], (unsigned long long)cw);
+                    atomicMax(&hs[1], hub_key(cw, xs));
                 }
-                const int32_t xs = src[k];
-                const int32_t j = e - w.bpre[k];
-                const int32_t o = a.pv.g.off[xs];
-                y = a.pv.g.col[o + j];
-                const int64_t cw = a.pv.g.w[o + j];
+            } else {
                 const unsigned long long ow = atomicAdd(&w.rw[y], (unsigned long long)cw);
                 if (ow & SCAN_BIT) {
                     if (ow & BATCH_BIT) intra += cw;
                 } else {
-                    touch = ow == 0;
                     const int64_t old = (int64_t)(ow & R_MASK);
-                    const int64_t nw = old + cw;
-                    cross = old < lam && lam <= nw;
-                    if (cross && uf_union(a.pv.parent, xs, y)) marks++;
+                    if (old < lam && lam <= old + cw) {
+                        if (uf_union(a.pv.parent, xs, y)) marks++;
+                        s_cross[atomicAdd(&s_nc, 1)] = y;
+                    }
                 }
             }
-            wave_append(w.tl, &w.ctl->tn, touch, y);
-            wave_append(w.fifo, &w.ctl->tail, cross, y);
         }
         intra = wave_sum_i64(intra);
         marks = (unsigned long long)wave_sum_i64((int64_t)marks);
@@ -386,6 +439,53 @@ __global__ __launch_bounds__(ET) void k_cfs_edges(StepArgs a) {
             unsigned long long* sp = a.spread + ((size_t)p * SPREAD + blockIdx.x % SPREAD) * SPREAD_STRIDE;
             if (si) atomicAdd(&sp[0], (unsigned long long)si);
             if (sm) atomicAdd(&sp[1], sm);
+            s_base = s_nc ? atomicAdd(&w.ctl->tail, s_nc) : 0;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < s_nc; i += ET) w.fifo[s_base + i] = s_cross[i];
+    }
+}
+
+// fold every hub's partial sums of the step into its r (one wavefront per
+// hub and pass; the hub's word has no other writer during this launch)
+__global__ __launch_bounds__(256) void k_cfs_hubfix(StepArgs a) {
+    static_assert(HUB_SLOTS <= MC_WAVE, "one lane per partial sum");
+    const int32_t nh = *a.nhub;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / MC_WAVE);
+    const int lane = lane_id();
+    for (int64_t t = (int64_t)blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE;
+         t < (int64_t)nh * a.pv.passes; t += nwaves) {
+        const int32_t p = (int32_t)(t / nh), h = (int32_t)(t % nh);
+        PassView w = view(a, p);
+        StepCtl& c = *w.ctl;
+        if (c.done) continue;                     // uniform over the wavefront
+        unsigned long long* hs = w.hacc + (size_t)h * HUB_SLOTS * 2;
+        int64_t sum = 0;
+        unsigned long long best = 0;
+        if (lane < HUB_SLOTS) {
+            sum = (int64_t)hs[2 * lane];
+            best = hs[2 * lane + 1];
+            if (sum) { hs[2 * lane] = 0; hs[2 * lane + 1] = 0; }
+        }
+        sum = wave_sum_i64(sum);
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long b2 = __shfl_xor(best, o, MC_WAVE);
+            best = b2 > best ? b2 : best;
+        }
+        if (lane == 0 && sum > 0) {
+            const int32_t y = a.hv[h];
+            const unsigned long long ow = w.rw[y];
+            w.rw[y] = ow + (unsigned long long)sum;
+            const int64_t old = (int64_t)(ow & R_MASK);
+            if (old < c.lam && c.lam <= old + sum) {
+                // the heaviest entry crosses lam in some order of the step's
+                // entries (only when its weight is exact, below saturation)
+                if ((best >> 32) < HUB_WSAT && uf_union(a.pv.parent, (int32_t)(best & 0xFFFFFFFFu), y)) {
+                    unsigned long long* sp = a.spread + ((size_t)p * SPREAD + h % SPREAD) * SPREAD_STRIDE;
+                    atomicAdd(&sp[1], 1ULL);
+                }
+                w.fifo[atomicAdd(&c.tail, 1)] = y;
+            }
         }
     }
 }
@@ -449,7 +549,7 @@ __global__ __launch_bounds__(T) void k_cfs_end(StepArgs a) {
     const int p = blockIdx.x / END_SPLIT, part = blockIdx.x % END_SPLIT;
     PassView w = view(a, p);
     const StepCtl& c = *w.ctl;
-    for (int32_t i = part * T + threadIdx.x; i < c.tn; i += END_SPLIT * T) w.rw[w.tl[i]] = 0;
+    for (int32_t i = part * T + threadIdx.x; i < a.pv.g.n; i += END_SPLIT * T) w.rw[i] = 0;
     if (part == 0 && threadIdx.x == 0) {
         a.pv.nscan[p] = c.nscan;
         a.pv.alpha[p] = c.best_alpha;
@@ -458,7 +558,7 @@ __global__ __launch_bounds__(T) void k_cfs_end(StepArgs a) {
         if (a.pv.steps) a.pv.steps[p] = c.steps;
         if (a.pv.diag) {
             int64_t* d = a.pv.diag + (int64_t)p * 8;
-            d[0] = c.steps; d[1] = c.singles; d[2] = c.tn; d[3] = c.entries;
+            d[0] = c.steps; d[1] = c.singles; d[2] = 0; d[3] = c.entries;
             d[4] = 0; d[5] = 0; d[6] = c.nscan; d[7] = c.maxbatch;
         }
         // algorithmic bytes of the pass's edge launches (profiling): 12 B
@@ -478,6 +578,13 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
         return false;
     }
     a.prof = prof_dev_bytes(PK_CFS_EDGES);
+    if (!fill_i32(a.nhub, 0, 1, s)) return false;
+    k_cfs_hubs<<<std::max(1, std::min<int>((a.pv.g.n + 255) / 256, 8192)), 256, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_hubs");
+    // enough wavefronts for every (pass, hub) pair of a typical graph in one
+    // sweep; the kernel strides over the rest
+    const int hub_blocks = std::max(1, std::min<int>((int)(((int64_t)P * a.max_hubs + 3) / 4), 2048));
+    const int tile_blocks = std::max(1, std::min<int>((int)((a.max_tiles + 255) / 256), 1024));
     k_cfs_init<<<P, T, 0, s>>>(a);
     MC_LAUNCHED("k_cfs_init");
     const int poll = 4;
@@ -488,10 +595,14 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
         MC_LAUNCHED("k_cfs_plan");
         k_cfs_tiles<<<1, T, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_tiles");
+        k_cfs_tileinfo<<<tile_blocks, 256, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_tileinfo");
         prof_begin(PK_CFS_EDGES, s);
         k_cfs_edges<<<4096, ET, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_edges");
         prof_end(PK_CFS_EDGES, s);
+        k_cfs_hubfix<<<hub_blocks, 256, 0, s>>>(a);
+        MC_LAUNCHED("k_cfs_hubfix");
         k_cfs_finish<<<P, T, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_finish");
         if (step % poll == poll - 1) {

@@ -237,7 +237,18 @@ struct StepArgs {
     // weight ([0]) and marks ([1]), so the edge tiles do not all add to one
     // address; k_cfs_finish folds and clears them
     unsigned long long* spread;   // [passes * SPREAD * SPREAD_STRIDE]
+    // vertices with at least HUB_LEN entries receive their entries through
+    // HUB_SLOTS partial sums per pass (see k_cfs_hubfix)
+    int32_t* hid;                 // [n] hub index or -1
+    int32_t* hv;                  // [max_hubs] vertex of each hub
+    int32_t* nhub;                // [1]
+    int32_t max_hubs;             // >= entries / HUB_LEN
+    unsigned long long* hacc;     // [passes * max_hubs * HUB_SLOTS * 2]
+    int32_t* tinfo;               // [2 * max_tiles] pass and first batch vertex of each edge tile
+    int64_t max_tiles;            // >= edge tiles of one step
 };
+constexpr int HUB_LEN = 512;
+constexpr int HUB_SLOTS = 16;
 
 bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s);
 

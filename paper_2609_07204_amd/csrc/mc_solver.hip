@@ -306,7 +306,7 @@ void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
     g.w = a.take<int64_t>((size_t)cap + 1);
 }
 
-void carve_steps(Arena& a, int32_t n, int32_t passes, int32_t len_cap, StepArgs& sa) {
+void carve_steps(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t len_cap, StepArgs& sa) {
     sa.ctl = a.take<StepCtl>((size_t)passes);
     sa.bcap = len_cap > 0 && len_cap < n ? len_cap : n;
     const size_t per = (size_t)sa.bcap + 1;
@@ -318,6 +318,15 @@ void carve_steps(Arena& a, int32_t n, int32_t passes, int32_t len_cap, StepArgs&
     sa.popk = a.take<int64_t>((size_t)passes * 512);
     sa.popv = a.take<int32_t>((size_t)passes * 512);
     sa.spread = a.take<unsigned long long>((size_t)passes * SPREAD * SPREAD_STRIDE);
+    sa.hid = a.take<int32_t>((size_t)n);
+    sa.max_hubs = (int32_t)std::min<int64_t>(n, cap / HUB_LEN + 1);
+    sa.hv = a.take<int32_t>((size_t)sa.max_hubs);
+    sa.nhub = a.take<int32_t>(1);
+    sa.hacc = a.take<unsigned long long>((size_t)passes * sa.max_hubs * HUB_SLOTS * 2);
+    // a step's batches hold at most every row once per pass: entries <= cap
+    // per pass, in 1024-entry tiles
+    sa.max_tiles = (int64_t)passes * (cap / 1024 + 2);
+    sa.tinfo = a.take<int32_t>((size_t)(2 * sa.max_tiles));
     sa.max_singles = 0;
 }
 
@@ -376,7 +385,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
     carve_private(a, n, ppasses, w.pv, w.psteps);
-    carve_steps(a, n, ppasses, len_cap, w.sa);
+    carve_steps(a, n, cap, ppasses, len_cap, w.sa);
 }
 
 // passes of the shared-visited-array form (one wavefront each)
@@ -550,7 +559,11 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     pa.start = -1;
     pa.marks = &w.sc->marks_cf;
     pa.steps = w.psteps;
-    if (g.n >= levels_min_n(S.c)) {
+    // a complete pass (len_cap 0) of a sparse graph can be mostly single
+    // pops, one whole-GPU step each; below 4x the level threshold it runs in
+    // one workgroup, which pops a vertex in microseconds
+    const int64_t lmin = levels_min_n(S.c);
+    if (g.n >= lmin && (len_cap > 0 || g.n >= 4 * lmin)) {
         StepArgs sa = w.sa;
         sa.pv = pa;
         int32_t running = 0;
@@ -828,7 +841,7 @@ void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.cr = a.take<int64_t>((size_t)n + 1);
     w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
     carve_private(a, n, passes, w.pv, w.psteps);
-    carve_steps(a, n, passes, 0, w.sa);
+    carve_steps(a, n, cap, passes, 0, w.sa);
 }
 
 mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws, size_t bytes, StepWS& w) {
