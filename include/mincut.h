@@ -103,6 +103,8 @@ typedef struct {
     int32_t rounds_pr_only;      /* rounds whose reduction tests alone at least
                                     halved the graph (CAPFOREST left to the
                                     next round) */
+    int32_t input_normal;        /* 1: the input was already a simple graph
+                                    with sorted rows and was used in place */
 } mc_stats;
 
 typedef struct mc_ctx mc_ctx;

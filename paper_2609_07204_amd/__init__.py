@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
                 ("lambda_min_degree", ctypes.c_int64), ("lambda_heuristic", ctypes.c_int64),
                 ("marks_pr", ctypes.c_int64), ("marks_capforest", ctypes.c_int64),
                 ("fallback_passes", ctypes.c_int32), ("n_input", ctypes.c_int32), ("m_input", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32)]
+                ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32), ("input_normal", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -34,7 +34,8 @@ struct DevScalars {
     int32_t best_len;       // its scanned-prefix length
     int32_t n2;             // vertex count after relabelling
     int32_t err;            // validation error code (0 = fine)
-    int32_t pad[3];
+    int32_t noncanon;       // 1: the input CSR needs the merging normalisation
+    int32_t pad[2];
 };
 
 // ------------------------------------------------------------- atomics

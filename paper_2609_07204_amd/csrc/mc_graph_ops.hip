@@ -40,38 +40,33 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
 
 // Connectivity in the manner of Afforest (Sutton, Ben-Nun and Barak, IPDPS
 // 2018), on a graph whose entries all have positive weight (a normalised
-// graph). Two hooking sweeps first join most of the graph: in each, every
-// row lowers the root of its own tree to the smallest root among its
-// neighbours (parent[] is compressed before each sweep, so par[v] is a
-// root); pointers only ever decrease, so the forest stays acyclic and the
-// union-find invariant parent[x] <= x holds. The first sweep, from the
-// identity, hooks every vertex to its smallest neighbour; the second joins
-// those trees (on power-law graphs it leaves nearly all vertices in one
-// tree). Then the component most sampled vertices fall into is found, and
-// all edges are linked with full unions only for vertices outside it; an
-// edge between that component and another one is seen from the other side.
-__global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par, unsigned long long* pb) {
-    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
-    const int sl = threadIdx.x % SUB;
-    int64_t bytes = 0;
-    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
-        const int32_t o = g.off[v], l = g.len[v];
+// graph). Two hooking sweeps over the first CONNECT_K entries of every row
+// first join most of the graph: in each, a row lowers the root of its own
+// tree to the smallest root among those neighbours (parent[] is compressed
+// before each sweep, so par[v] is a root); pointers only ever decrease, so
+// the forest stays acyclic and the union-find invariant parent[x] <= x
+// holds. The first sweep, from the identity, hooks every vertex to its
+// smallest such neighbour; the second joins those trees (on power-law
+// graphs the largest tree then holds nearly every vertex). Then the
+// component most sampled vertices fall into is found, and all edges are
+// linked with full unions only for vertices outside it; an edge between that
+// component and another one is seen from the other side. Which edges the
+// sweeps looked at does not matter for exactness: they only join connected
+// vertices, and every edge with an endpoint outside the sampled component is
+// linked afterwards.
+constexpr int CONNECT_K = 8;   // entries per row the hooking sweeps look at
+
+__global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = g.off[v], l = g.len[v] < CONNECT_K ? g.len[v] : CONNECT_K;
         const int32_t r = ld_acq(&par[v]);
         int32_t m = r;
-        for (int32_t j = sl; j < l; j += SUB) {
+        for (int32_t j = 0; j < l; j++) {
             const int32_t px = ld_acq(&par[g.col[o + j]]);
             m = px < m ? px : m;
         }
-        for (int k = SUB / 2; k > 0; k >>= 1) {
-            const int32_t t = __shfl_xor(m, k, SUB);
-            m = t < m ? t : m;
-        }
-        if (sl == 0) {
-            if (m < r && m < ld_acq(&par[r])) atomicMin(&par[r], m);
-            bytes += 8 + 8 * (int64_t)l;
-        }
+        if (m < r && m < ld_acq(&par[r])) atomicMin(&par[r], m);
     }
-    if (pb) prof_add(pb, bytes);
 }
 
 __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int32_t n, int32_t* mode) {
@@ -369,10 +364,53 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* rp, const int32
     }
 }
 
-__global__ void k_validate_sum(const unsigned long long* part, int nb, DevScalars* sc) {
+// saturating sum of the block partials (each at most WCAP, so a pairwise
+// sum fits in 64 bits before it saturates)
+__global__ __launch_bounds__(256) void k_validate_sum(const unsigned long long* part, int nb, DevScalars* sc) {
+    __shared__ unsigned long long bs[256];
     unsigned long long t = 0;
-    for (int k = 0; k < nb; k++) { t += part[k]; if (t >= WCAP) t = WCAP; }
-    if (t >= WCAP) set_err(sc, MC_E_OVERFLOW);
+    for (int k = threadIdx.x; k < nb; k += 256) { t += part[k]; if (t >= WCAP) t = WCAP; }
+    bs[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            unsigned long long u = bs[threadIdx.x] + bs[threadIdx.x + o];
+            bs[threadIdx.x] = u >= WCAP ? WCAP : u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bs[0] >= WCAP) set_err(sc, MC_E_OVERFLOW);
+}
+
+// Normalisation fast path: a row whose targets strictly increase, with no
+// loop and only positive weights, is already in normal form (a simple
+// graph, nothing to merge). Writes len and the degrees of every row, and
+// sets *noncanon when some row is not normal.
+__global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                              const int64_t* __restrict__ w, int32_t n, int32_t* __restrict__ len,
+                                              int64_t* __restrict__ deg, int32_t* noncanon) {
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < n; v += nsub) {
+        const int32_t o = rp[v], l = rp[v + 1] - o;
+        int64_t d = 0;
+        bool bad = false;
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = col[o + j];
+            const int64_t c = w[o + j];
+            d += c;
+            bad |= x == v || c <= 0 || (j > 0 && col[o + j - 1] >= x);
+        }
+        for (int k = SUB / 2; k > 0; k >>= 1) {
+            d += __shfl_xor(d, k, SUB);
+            bad |= __shfl_xor((int)bad, k, SUB) != 0;
+        }
+        if (sl == 0) {
+            len[v] = l;
+            deg[v] = d;
+            if (bad && ld_acq(noncanon) == 0) st_rel(noncanon, 1);
+        }
+    }
 }
 
 }  // namespace
@@ -392,7 +430,7 @@ bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
 bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s) {
     const int rows = grid_for((int64_t)g.n * SUB, 256);
     for (int sweep = 0; sweep < 2; sweep++) {
-        k_uf_root_min<<<rows, 256, 0, s>>>(g, parent, nullptr);
+        k_uf_root_min<<<grid_for(g.n, 256), 256, 0, s>>>(g, parent);
         MC_LAUNCHED("k_uf_root_min");
         k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
         MC_LAUNCHED("k_uf_compress");
@@ -486,12 +524,20 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
     return true;
 }
 
+bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t* len,
+                 int64_t* deg, int32_t* noncanon, hipStream_t s) {
+    if (!fill_i32(noncanon, 0, 1, s)) return false;
+    k_canon<<<grid_for((int64_t)n * SUB, 256), 256, 0, s>>>(row_ptr, col, w, n, len, deg, noncanon);
+    MC_LAUNCHED("k_canon");
+    return true;
+}
+
 bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
                   DevScalars* sc, unsigned long long* part, hipStream_t s) {
     const int nb = grid_for(nnz > n ? nnz : n, 256, 1024);
     k_validate<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, sc, part);
     MC_LAUNCHED("k_validate");
-    k_validate_sum<<<1, 1, 0, s>>>(part, nb, sc);
+    k_validate_sum<<<1, 256, 0, s>>>(part, nb, sc);
     MC_LAUNCHED("k_validate_sum");
     return true;
 }

@@ -267,6 +267,11 @@ bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipS
 // ------------------------------------------------------- input handling
 // Turn a user CSR (row_ptr) into padded form (off = row_ptr, len = diff).
 bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len, hipStream_t s);
+// Normalisation fast path: len[v] and deg[v] of every row of a user CSR,
+// and *noncanon = 1 if some row is not already normal (targets strictly
+// increasing, no loop, positive weights).
+bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t* len,
+                 int64_t* deg, int32_t* noncanon, hipStream_t s);
 // Device-side validation of a user CSR: sets sc->err to an mc_status code.
 bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
                   DevScalars* sc, unsigned long long* part, hipStream_t s);

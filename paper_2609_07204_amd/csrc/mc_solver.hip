@@ -741,15 +741,30 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
             return fail((mc_status)c->hsc->err, c->hsc->err == MC_E_OVERFLOW ? "total weight must be below 2^62"
                                                                               : "malformed CSR (row_ptr, col or w)");
     }
-    // normalise: contraction by the identity folds loops, parallel entries
-    // and zero weights; the padded view of the input reuses g[1]'s arrays
-    DGraph user = w.g[1];
-    user.n = n;
-    user.cap = nnz;
-    user.col = const_cast<int32_t*>(col);
-    user.w = const_cast<int64_t*>(wt);
-    if (!csr_to_padded(rp, n, user.off, user.len, s)) return MC_E_DEVICE;
-    if (!contract(user, nullptr, n, w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
+    // normalise. An input already in normal form (rows strictly increasing,
+    // no loops, positive weights) is used in place as the first graph: no
+    // kernel writes the current graph's off/col/w. Otherwise contraction by
+    // the identity folds loops, parallel entries and zero weights; the
+    // padded view of the input reuses g[1]'s arrays.
+    if (!canon_check(rp, col, wt, n, w.g[0].len, w.g[0].deg, &w.sc->noncanon, s) || !S.readback())
+        return MC_E_DEVICE;
+    if (c->hsc->noncanon == 0) {
+        w.g[0].n = n;
+        w.g[0].cap = nnz;
+        w.g[0].off = const_cast<int32_t*>(rp);
+        w.g[0].col = const_cast<int32_t*>(col);
+        w.g[0].w = const_cast<int64_t*>(wt);
+        if (!min_degree(w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
+    } else {
+        DGraph user = w.g[1];
+        user.n = n;
+        user.cap = nnz;
+        user.col = const_cast<int32_t*>(col);
+        user.w = const_cast<int64_t*>(wt);
+        if (!csr_to_padded(rp, n, user.off, user.len, s)) return MC_E_DEVICE;
+        if (!contract(user, nullptr, n, w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
+    }
+    S.stats.input_normal = c->hsc->noncanon == 0;
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
     if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected

@@ -449,3 +449,28 @@ def test_solver_levels_chung_lu_hubs(ctx, log2n, seed):
     say("  lambda", lam, "rounds", st["rounds"], "fallback", st["fallback_passes"])
     assert lam == oracle.noi(g)[0] and oracle.cut_value(g, side) == lam
     c.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_raw_input_takes_merging_normalisation(ctx, seed):
+    # loops, parallel entries, zero weights and unsorted rows go through the
+    # merging normalisation; the same graph in normal form is used in place;
+    # both give the oracle's lambda
+    r = np.random.default_rng(seed)
+    n, m = 600, 4000
+    u = r.integers(0, n, m)
+    v = r.integers(0, n, m)
+    w = r.integers(0, 6, m)
+    u = np.concatenate([u, np.arange(n), (np.arange(n) + 1) % n])   # a cycle keeps it connected
+    v = np.concatenate([v, np.arange(n), np.arange(n)])
+    w = np.concatenate([w, np.full(n, 3), np.full(n, 1)])
+    raw = gen.raw_csr(n, u, v, w)
+    pos = w > 0
+    norm = gen.from_edges(n, u[pos], v[pos], w[pos])
+    lam_ref = oracle.noi(norm)[0]
+    lam1, side1, st1 = ctx.mincut(raw, return_stats=True)
+    lam2, side2, st2 = ctx.mincut(norm, return_stats=True)
+    say("raw vs normal", seed, lam_ref, st1["input_normal"], st2["input_normal"])
+    assert st1["input_normal"] == 0 and st2["input_normal"] == 1
+    assert lam1 == lam2 == lam_ref
+    assert oracle.cut_value(norm, side1) == lam_ref and oracle.cut_value(norm, side2) == lam_ref
