@@ -78,7 +78,8 @@ struct Prof {
     double hbytes[PK_COUNT] = {};
     int64_t launches[PK_COUNT] = {};
     double ms[PK_COUNT] = {};
-    hipEvent_t open[PK_COUNT] = {};
+    hipEvent_t open[PK_COUNT] = {};      // start event of the launch in flight
+    hipEvent_t close[PK_COUNT] = {};     // its end event, taken before the launch
     std::vector<hipEvent_t> pool;
     struct Pending { int k; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -122,26 +123,32 @@ struct ProfScope {
 };
 }  // namespace
 
+// Both events of a launch are taken before it is issued, so nothing slow
+// (an event creation) sits between the kernel and its end event.
 void prof_begin(int k, hipStream_t s) {
     Prof* p = g_prof;
     if (!p) return;
-    hipEvent_t e = p->take();
-    if (e && hipEventRecord(e, s) != hipSuccess) { p->pool.push_back(e); e = nullptr; }
-    p->open[k] = e;
+    hipEvent_t a = p->take(), b = p->take();
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        if (a) p->pool.push_back(a);
+        if (b) p->pool.push_back(b);
+        a = b = nullptr;
+    }
+    p->open[k] = a;
+    p->close[k] = b;
 }
 
 void prof_end(int k, hipStream_t s) {
     Prof* p = g_prof;
     if (!p || !p->open[k]) return;
-    hipEvent_t e = p->take();
-    if (!e || hipEventRecord(e, s) != hipSuccess) {
-        if (e) p->pool.push_back(e);
+    if (hipEventRecord(p->close[k], s) != hipSuccess) {
         p->pool.push_back(p->open[k]);
+        p->pool.push_back(p->close[k]);
     } else {
-        p->pending.push_back({k, p->open[k], e});
+        p->pending.push_back({k, p->open[k], p->close[k]});
         p->launches[k]++;
     }
-    p->open[k] = nullptr;
+    p->open[k] = p->close[k] = nullptr;
 }
 
 unsigned long long* prof_dev_bytes(int k) {
@@ -228,6 +235,13 @@ extern "C" mc_status mc_profile(mc_ctx* c, int32_t on) {
         hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(MC_E_DEVICE, "mc_profile: clearing the byte counters failed");
     for (int k = 0; k < PK_COUNT; k++) { p->hbytes[k] = 0; p->launches[k] = 0; p->ms[k] = 0; }
+    // events for a few solves up front: creating one inside a timed solve
+    // would delay the host between launches
+    while (p->pool.size() < 512) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return fail(MC_E_DEVICE, "mc_profile: hipEventCreate failed");
+        p->pool.push_back(e);
+    }
     p->on = true;
     return MC_OK;
 }
