@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--len-cap", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="time the steps without kernel events")
+    ap.add_argument("--heuristic-min-n", type=int, default=10000,
+                    help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -70,7 +72,8 @@ def main():
     t = time.time()
     g = gen.config_chung_lu(args.log2n, args.seed)
     log("generated %s: n=%d m=%d in %.1fs" % (g.name, g.n, g.m, time.time() - t))
-    ctx = mc.Context(0, capforest_passes=args.passes, pass_len_cap=args.len_cap)
+    ctx = mc.Context(0, capforest_passes=args.passes, pass_len_cap=args.len_cap,
+                     heuristic_min_n=args.heuristic_min_n)
     dev = ctx.upload(g)
     ws = torch.empty(ctx.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device=ctx.device)
     torch.cuda.synchronize()
@@ -78,8 +81,9 @@ def main():
     for i in range(args.warmup):
         lam, _, st = ctx.mincut(dev=dev, workspace=ws, want_side=(i == 0), return_stats=True)
         lam0 = lam
-        log("warmup %d: lambda=%d rounds=%d fallback=%d %.2f ms" % (i, lam, st["rounds"], st["fallback_passes"],
-                                                                   st["ms_total"]))
+        log("warmup %d: lambda=%d rounds=%d fallback=%d heuristic levels=%d bound=%d %.2f ms" % (
+            i, lam, st["rounds"], st["fallback_passes"], st["heuristic_levels"], st["lambda_heuristic"],
+            st["ms_total"]))
     torch.cuda.synchronize()
     if not args.no_profile:
         ctx.profile(True)
@@ -144,7 +148,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "chung_lu n=2^%d beta=2.5 avg_deg=20 10-core LCC unit weights seed=%d"
                                % (args.log2n, args.seed), "n": g.n, "m": g.m, "lambda": lam,
-                   "rounds": stats[-1]["rounds"]},
+                   "rounds": stats[-1]["rounds"], "heuristic_levels": stats[-1]["heuristic_levels"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -57,6 +57,16 @@ mc_status mc_step_components(mc_ctx* ctx, int32_t n, int64_t npairs, const int32
 mc_status mc_step_pr12(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, uint8_t* flag1, int32_t* ptr2,
                        int32_t* labels, int32_t* n2, void* ws, size_t ws_bytes);
 
+/* One synchronous label-propagation round, the clustering step of the
+ * bound heuristic (Section 2.1, "Lowering the upper bound"): lab_out[v] is
+ * the label (among lab_in of v's neighbours, loops ignored) with the
+ * largest total edge weight to v, except that v keeps lab_in[v] unless
+ * another label is strictly heavier; ties among other labels go to the
+ * smallest label. lab_in / lab_out: [g->n] labels in [0, n), distinct
+ * arrays. */
+mc_status mc_step_lp(mc_ctx* ctx, const mc_dgraph* g, const int32_t* lab_in, int32_t* lab_out, void* ws,
+                     size_t ws_bytes);
+
 /* CAPFOREST (Algorithm 1), in one of three forms (mode):
  *  MC_STEP_CF_SHARED (0): `passes` concurrent passes, one wavefront each,
  *     state in LDS (at most 1536 vertices touched per pass), sharing the

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mc_step_contract": (ctypes.c_int, [P, P, P, I32, P, P, SZ, P, P]),
     "mc_step_components": (ctypes.c_int, [P, I32, I64, P, P, P, P, P, SZ]),
     "mc_step_pr12": (ctypes.c_int, [P, P, I64, P, P, P, P, P, SZ]),
+    "mc_step_lp": (ctypes.c_int, [P, P, P, P, P, SZ]),
     "mc_step_capforest": (ctypes.c_int, [P, P, I64, I32, I32, I32, I32, I32, P, P, P, P, P, P, P, P, SZ]),
 }
 
@@ -264,6 +265,16 @@ class Context:
         _check(lib().mc_step_pr12(self.h, ctypes.byref(g.c()), lam, _ptr(flag), _ptr(ptr), _ptr(lab),
                                   ctypes.byref(n2), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return flag, ptr.cpu().numpy(), lab.cpu().numpy(), n2.value
+
+    def step_lp(self, g, lab_in):
+        """One label-propagation round on device graph g (see mc_step_lp)."""
+        torch = _torch()
+        a = torch.as_tensor(np.ascontiguousarray(lab_in, np.int32)).to(self.device)
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        ws = self.step_workspace(g.n, g.cap)
+        _check(lib().mc_step_lp(self.h, ctypes.byref(g.c()), _ptr(a), _ptr(out), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel()))
+        return out[:g.n].cpu().numpy()
 
     def step_capforest(self, g, lam, start=0, mode=CF_SEQUENTIAL, passes=1, shared=False, len_cap=0):
         """One CAPFOREST launch in the given mode (CF_SHARED, CF_SEQUENTIAL,

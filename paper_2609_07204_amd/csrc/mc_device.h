@@ -45,6 +45,12 @@ __device__ __forceinline__ int32_t ld_acq(const int32_t* p) {
 __device__ __forceinline__ void st_rel(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int64_t ld64_dev(const int64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64_dev(int64_t* p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int64_t atomic_add_i64(int64_t* p, int64_t v) {
     return (int64_t)atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }

@@ -1,0 +1,406 @@
+// Label propagation for the upper-bound heuristic (paper, Section 2.1
+// "Lowering the upper bound": the heuristic clusters the graph by label
+// propagation, contracts every cluster to one vertex, applies the
+// Padberg-Rinaldi tests, and solves the small graph that remains exactly;
+// the cut it returns is a cut of the input, so its value bounds lambda).
+//
+// One synchronous round over all vertices: lab_out[v] is the label that
+// carries the most edge weight among v's neighbours (labels of lab_in), with
+// two rules that make the round a pure function: v keeps lab_in[v] unless
+// another label is strictly heavier, and among equally heavy other labels
+// the smallest wins.
+//
+// Rows of at most LP_SMALL entries are packed into chunks of at most
+// LP_CHUNK (entries + rows), as the contraction packs small groups: one
+// workgroup sums the (row, label) weights of a chunk in an LDS hash table and
+// then takes every row's maximum in two sweeps over the table. Longer rows
+// go to a list and are cut into tasks of LP_TASK entries that any workgroup
+// may take: a task merges its entries in LDS and adds the sums to the row's
+// global hash table (about twice the row's length); two more sweeps over the
+// tables, split the same way, find each row's maximum.
+#include <algorithm>
+
+#include "mc_internal.h"
+
+namespace {
+
+constexpr int LP_CHUNK = 512;
+constexpr int LP_SMALL = 512;
+constexpr int LP_HSLOTS = 1024;
+constexpr int LP_T = 256;
+constexpr int LP_SUB = 16;
+constexpr int LP_NSUB = LP_T / LP_SUB;
+constexpr int LP_TASK = 1024;     // entries per task of a long row (multiple of 128)
+constexpr int LP_TSLOTS = 2048;   // LDS slots of a task's pre-merge
+constexpr unsigned long long LP_EMPTY = ~0ULL;
+
+inline int grid_for(int64_t count, int threads, int cap = 8192) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+__global__ void k_row_len(const int32_t* __restrict__ len, int32_t n, int32_t* __restrict__ out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = len[v];
+}
+
+// cg[c] = first row v with rstart[v] + v >= c LP_CHUNK
+__global__ void k_lp_chunks(const int32_t* __restrict__ rstart, int32_t n, int64_t nchunks, int32_t* __restrict__ cg) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t key = c * LP_CHUNK;
+        int32_t lo = 0, hi = n + 1;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if ((int64_t)rstart[mid] + mid >= key) hi = mid; else lo = mid + 1;
+        }
+        cg[c] = lo;
+    }
+}
+
+__device__ __forceinline__ uint32_t lp_hash(uint32_t gl, uint32_t lbl) { return hash32(lbl ^ (gl * 0x9E3779B1u)); }
+
+__global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __restrict__ lab_in,
+                                                  int32_t* __restrict__ lab_out, const int32_t* __restrict__ rstart,
+                                                  const int32_t* __restrict__ cg, int32_t* __restrict__ long_list,
+                                                  int32_t* __restrict__ long_base, int32_t* __restrict__ counters,
+                                                  unsigned long long* __restrict__ long_best,
+                                                  unsigned long long* __restrict__ long_own,
+                                                  int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
+                                                  int32_t* __restrict__ task_idx) {
+    __shared__ unsigned long long hkey[LP_HSLOTS];
+    __shared__ unsigned long long hval[LP_HSLOTS];
+    __shared__ int32_t own[LP_CHUNK];
+    __shared__ unsigned long long own_w[LP_CHUNK], best_w[LP_CHUNK];
+    __shared__ int32_t best_l[LP_CHUNK];
+    const int tid = threadIdx.x;
+    const int32_t g_lo = cg[blockIdx.x];
+    const int32_t g_hi = cg[blockIdx.x + 1] < g.n ? cg[blockIdx.x + 1] : g.n;
+    if (g_lo >= g.n || g_lo >= g_hi) return;
+    const int32_t ng = g_hi - g_lo;
+    for (int i = tid; i < LP_HSLOTS; i += LP_T) { hkey[i] = LP_EMPTY; hval[i] = 0; }
+    for (int i = tid; i < ng; i += LP_T) {
+        const int32_t v = g_lo + i;
+        own[i] = lab_in[v];
+        own_w[i] = 0;
+        best_w[i] = 0;
+        best_l[i] = INT32_MAX;
+        const int32_t l = g.len[v];
+        if (l > LP_SMALL) {
+            const int32_t k = atomicAdd(&counters[0], 1);
+            const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
+            const int32_t t0 = atomicAdd(&counters[2], nt);
+            long_list[k] = v;
+            long_base[k] = atomicAdd(&counters[1], (2 * l + 255) / 256 * 256);
+            long_best[k] = 0;
+            long_own[k] = 0;
+            long_lab[k] = INT32_MAX;
+            for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
+        }
+    }
+    __syncthreads();
+    const int sg = tid / LP_SUB, sl = tid % LP_SUB;
+    for (int gl = sg; gl < ng; gl += LP_NSUB) {
+        const int32_t v = g_lo + gl;
+        const int32_t o = g.off[v], l = g.len[v];
+        if (l > LP_SMALL) continue;
+        for (int32_t j = sl; j < l; j += LP_SUB) {
+            const int32_t x = g.col[o + j];
+            if (x == v) continue;
+            const unsigned long long c = (unsigned long long)g.w[o + j];
+            const uint32_t lbl = (uint32_t)lab_in[x];
+            const unsigned long long key = ((unsigned long long)gl << 32) | lbl;
+            uint32_t h = lp_hash((uint32_t)gl, lbl) & (LP_HSLOTS - 1);
+            for (;;) {
+                const unsigned long long k = hkey[h];
+                if (k == key) break;
+                if (k == LP_EMPTY) {
+                    const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, key);
+                    if (old == LP_EMPTY || old == key) break;
+                }
+                h = (h + 1) & (LP_HSLOTS - 1);
+            }
+            atomicAdd(&hval[h], c);
+        }
+    }
+    __syncthreads();
+    // sweep 1: own weight, heaviest other weight
+    for (int i = tid; i < LP_HSLOTS; i += LP_T) {
+        const unsigned long long k = hkey[i];
+        if (k == LP_EMPTY) continue;
+        const int gl = (int)(k >> 32);
+        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
+        if (lbl == own[gl]) own_w[gl] = hval[i];
+        else atomicMax(&best_w[gl], hval[i]);
+    }
+    __syncthreads();
+    // sweep 2: smallest other label of that weight
+    for (int i = tid; i < LP_HSLOTS; i += LP_T) {
+        const unsigned long long k = hkey[i];
+        if (k == LP_EMPTY) continue;
+        const int gl = (int)(k >> 32);
+        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
+        if (lbl != own[gl] && hval[i] == best_w[gl]) atomicMin(&best_l[gl], lbl);
+    }
+    __syncthreads();
+    for (int i = tid; i < ng; i += LP_T) {
+        const int32_t v = g_lo + i;
+        if (g.len[v] > LP_SMALL) continue;
+        lab_out[v] = best_l[i] != INT32_MAX && best_w[i] > own_w[i] ? best_l[i] : own[i];
+    }
+}
+
+// Long rows are cut into tasks of LP_TASK entries; task t of row k owns the
+// entries [t LP_TASK, (t+1) LP_TASK) and the table slots
+// [2 t LP_TASK, 2 (t+1) LP_TASK) of the row's global table, which covers the
+// table (LP_TASK is a multiple of 128, the table a multiple of 256 slots).
+struct LongTask {
+    int32_t k, t, v, o, l, ts;
+    int64_t tb;
+};
+__device__ __forceinline__ LongTask long_task(const DGraph& g, const int32_t* long_list, const int32_t* long_base,
+                                              const int32_t* task_row, const int32_t* task_idx, int32_t i) {
+    LongTask x;
+    x.k = task_row[i];
+    x.t = task_idx[i];
+    x.v = long_list[x.k];
+    x.o = g.off[x.v];
+    x.l = g.len[x.v];
+    x.ts = (2 * x.l + 255) / 256 * 256;
+    x.tb = long_base[x.k];
+    return x;
+}
+
+__global__ __launch_bounds__(LP_T) void k_lp_long_clear(DGraph g, const int32_t* __restrict__ long_list,
+                                                       const int32_t* __restrict__ long_base,
+                                                       const int32_t* __restrict__ counters,
+                                                       const int32_t* __restrict__ task_row,
+                                                       const int32_t* __restrict__ task_idx, int32_t* __restrict__ tkey,
+                                                       int64_t* __restrict__ tval) {
+    const int32_t ntask = counters[2];
+    for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const LongTask x = long_task(g, long_list, long_base, task_row, task_idx, i);
+        const int32_t s1 = 2 * (x.t + 1) * LP_TASK < x.ts ? 2 * (x.t + 1) * LP_TASK : x.ts;
+        for (int32_t k = 2 * x.t * LP_TASK + threadIdx.x; k < s1; k += LP_T) {
+            tkey[x.tb + k] = -1;
+            tval[x.tb + k] = 0;
+        }
+    }
+}
+
+// each task merges its entries in LDS, then adds the sums to the row's table
+__global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t* __restrict__ lab_in,
+                                                        const int32_t* __restrict__ long_list,
+                                                        const int32_t* __restrict__ long_base,
+                                                        const int32_t* __restrict__ counters,
+                                                        const int32_t* __restrict__ task_row,
+                                                        const int32_t* __restrict__ task_idx,
+                                                        int32_t* __restrict__ tkey, int64_t* __restrict__ tval) {
+    __shared__ unsigned long long hkey[LP_TSLOTS];
+    __shared__ unsigned long long hval[LP_TSLOTS];
+    const int32_t ntask = counters[2];
+    for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const LongTask x = long_task(g, long_list, long_base, task_row, task_idx, i);
+        __syncthreads();
+        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) { hkey[k] = LP_EMPTY; hval[k] = 0; }
+        __syncthreads();
+        const int32_t j1 = (x.t + 1) * LP_TASK < x.l ? (x.t + 1) * LP_TASK : x.l;
+        for (int32_t j = x.t * LP_TASK + threadIdx.x; j < j1; j += LP_T) {
+            const int32_t y = g.col[x.o + j];
+            if (y == x.v) continue;
+            const uint32_t lbl = (uint32_t)lab_in[y];
+            uint32_t h = hash32(lbl) & (LP_TSLOTS - 1);
+            for (;;) {
+                const unsigned long long kk = hkey[h];
+                if (kk == lbl) break;
+                if (kk == LP_EMPTY) {
+                    const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, (unsigned long long)lbl);
+                    if (old == LP_EMPTY || old == lbl) break;
+                }
+                h = (h + 1) & (LP_TSLOTS - 1);
+            }
+            atomicAdd(&hval[h], (unsigned long long)g.w[x.o + j]);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) {
+            const unsigned long long kk = hkey[k];
+            if (kk == LP_EMPTY) continue;
+            const int32_t lbl = (int32_t)kk;
+            uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)lbl) * (uint32_t)x.ts) >> 32);
+            for (;;) {
+                const int32_t cur = ld_acq(&tkey[x.tb + h]);
+                if (cur == lbl) break;
+                if (cur == -1) {
+                    const int32_t old = atomicCAS(&tkey[x.tb + h], -1, lbl);
+                    if (old == -1 || old == lbl) break;
+                }
+                if (++h == (uint32_t)x.ts) h = 0;
+            }
+            atomic_add_i64(&tval[x.tb + h], (int64_t)hval[k]);
+        }
+    }
+}
+
+// sweep 1 over each task's table slots: the row's own-label weight and its
+// heaviest other weight (one atomic per workgroup and row)
+__global__ __launch_bounds__(LP_T) void k_lp_long_max(DGraph g, const int32_t* __restrict__ lab_in,
+                                                     const int32_t* __restrict__ long_list,
+                                                     const int32_t* __restrict__ long_base,
+                                                     const int32_t* __restrict__ counters,
+                                                     const int32_t* __restrict__ task_row,
+                                                     const int32_t* __restrict__ task_idx,
+                                                     const int32_t* __restrict__ tkey, const int64_t* __restrict__ tval,
+                                                     unsigned long long* __restrict__ long_best,
+                                                     unsigned long long* __restrict__ long_own) {
+    __shared__ unsigned long long r_w[LP_T / MC_WAVE];
+    const int32_t ntask = counters[2];
+    for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const LongTask x = long_task(g, long_list, long_base, task_row, task_idx, i);
+        const int32_t ownl = lab_in[x.v];
+        const int32_t s1 = 2 * (x.t + 1) * LP_TASK < x.ts ? 2 * (x.t + 1) * LP_TASK : x.ts;
+        unsigned long long bw = 0;
+        for (int32_t k = 2 * x.t * LP_TASK + threadIdx.x; k < s1; k += LP_T) {
+            const int32_t lbl = tkey[x.tb + k];
+            if (lbl < 0) continue;
+            const unsigned long long sum = (unsigned long long)tval[x.tb + k];
+            if (lbl == ownl) long_own[x.k] = sum;   // one slot holds the own label
+            else if (sum > bw) bw = sum;
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            const unsigned long long b2 = __shfl_xor(bw, d, MC_WAVE);
+            bw = b2 > bw ? b2 : bw;
+        }
+        __syncthreads();
+        if (lane_id() == 0) r_w[threadIdx.x / MC_WAVE] = bw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long b = 0;
+            for (int k = 0; k < LP_T / MC_WAVE; k++) b = r_w[k] > b ? r_w[k] : b;
+            if (b) atomicMax(&long_best[x.k], b);
+        }
+    }
+}
+
+// sweep 2: the smallest other label of the heaviest weight
+__global__ __launch_bounds__(LP_T) void k_lp_long_min(DGraph g, const int32_t* __restrict__ lab_in,
+                                                     const int32_t* __restrict__ long_list,
+                                                     const int32_t* __restrict__ long_base,
+                                                     const int32_t* __restrict__ counters,
+                                                     const int32_t* __restrict__ task_row,
+                                                     const int32_t* __restrict__ task_idx,
+                                                     const int32_t* __restrict__ tkey, const int64_t* __restrict__ tval,
+                                                     const unsigned long long* __restrict__ long_best,
+                                                     int32_t* __restrict__ long_lab) {
+    __shared__ int32_t r_l[LP_T / MC_WAVE];
+    const int32_t ntask = counters[2];
+    for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const LongTask x = long_task(g, long_list, long_base, task_row, task_idx, i);
+        const int32_t ownl = lab_in[x.v];
+        const unsigned long long best = long_best[x.k];
+        const int32_t s1 = 2 * (x.t + 1) * LP_TASK < x.ts ? 2 * (x.t + 1) * LP_TASK : x.ts;
+        int32_t bl = INT32_MAX;
+        for (int32_t k = 2 * x.t * LP_TASK + threadIdx.x; k < s1; k += LP_T) {
+            const int32_t lbl = tkey[x.tb + k];
+            if (lbl >= 0 && lbl != ownl && (unsigned long long)tval[x.tb + k] == best && lbl < bl) bl = lbl;
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            const int32_t b2 = __shfl_xor(bl, d, MC_WAVE);
+            bl = b2 < bl ? b2 : bl;
+        }
+        __syncthreads();
+        if (lane_id() == 0) r_l[threadIdx.x / MC_WAVE] = bl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t m = INT32_MAX;
+            for (int k = 0; k < LP_T / MC_WAVE; k++) m = r_l[k] < m ? r_l[k] : m;
+            if (m != INT32_MAX) atomicMin(&long_lab[x.k], m);
+        }
+    }
+}
+
+__global__ void k_lp_long_final(const int32_t* __restrict__ lab_in, int32_t* __restrict__ lab_out,
+                                const int32_t* __restrict__ long_list, const int32_t* __restrict__ counters,
+                                const unsigned long long* __restrict__ long_best,
+                                const unsigned long long* __restrict__ long_own, const int32_t* __restrict__ long_lab) {
+    const int32_t nl = counters[0];
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += gridDim.x * blockDim.x) {
+        const int32_t v = long_list[k];
+        lab_out[v] = long_lab[k] != INT32_MAX && long_best[k] > long_own[k] ? long_lab[k] : lab_in[v];
+    }
+}
+
+// flag[l] = 1 for every label in use (flag zeroed before)
+__global__ void k_label_used(const int32_t* __restrict__ lab, int32_t n, int32_t* __restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[lab[v]] = 1;
+}
+
+__global__ void k_label_rank(const int32_t* __restrict__ lab, const int32_t* __restrict__ rank, int32_t n,
+                             int32_t* __restrict__ L, DevScalars* sc) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        L[v] = rank[lab[v]];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->n2 = rank[n];
+}
+
+}  // namespace
+
+void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w) {
+    const size_t nlong = (size_t)std::min<int64_t>(n, cap / LP_SMALL + 1) + 64;
+    w.long_list = a.take<int32_t>(nlong);
+    w.long_base = a.take<int32_t>(nlong);
+    w.long_lab = a.take<int32_t>(nlong);
+    w.long_best = a.take<unsigned long long>(nlong);
+    w.long_own = a.take<unsigned long long>(nlong);
+    // tasks: at most cap / LP_TASK + one per long row
+    const size_t ntask = (size_t)(cap / LP_TASK) + nlong;
+    w.task_row = a.take<int32_t>(ntask);
+    w.task_idx = a.take<int32_t>(ntask);
+    w.counters = a.take<int32_t>(4);
+    w.cg = a.take<int32_t>((size_t)((cap + n) / LP_CHUNK) + 4);
+}
+
+bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s) {
+    const int32_t n = g.n;
+    // row prefix (entries) of the current rows -> chunk starts
+    k_row_len<<<grid_for(n, 256), 256, 0, s>>>(g.len, n, cw.mstart);
+    MC_LAUNCHED("k_row_len");
+    if (!scan_i32(cw.mstart, cw.mstart, n, cw.scan_tmp, s)) return false;
+    // chunk keys run up to (entries + rows) <= cap + n
+    const int64_t nchunks = (g.cap + n) / LP_CHUNK + 2;
+    k_lp_chunks<<<grid_for(nchunks + 1, 256), 256, 0, s>>>(cw.mstart, n, nchunks, w.cg);
+    MC_LAUNCHED("k_lp_chunks");
+    if (!fill_i32(w.counters, 0, 4, s)) return false;
+    k_lp_small<<<(unsigned)nchunks, LP_T, 0, s>>>(g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base,
+                                                  w.counters, w.long_best, w.long_own, w.long_lab, w.task_row,
+                                                  w.task_idx);
+    MC_LAUNCHED("k_lp_small");
+    const int tb = 2048;
+    k_lp_long_clear<<<tb, LP_T, 0, s>>>(g, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx, cw.tkey,
+                                        cw.tval);
+    MC_LAUNCHED("k_lp_long_clear");
+    k_lp_long_insert<<<tb, LP_T, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
+                                         cw.tkey, cw.tval);
+    MC_LAUNCHED("k_lp_long_insert");
+    k_lp_long_max<<<tb, LP_T, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
+                                      cw.tkey, cw.tval, w.long_best, w.long_own);
+    MC_LAUNCHED("k_lp_long_max");
+    k_lp_long_min<<<tb, LP_T, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
+                                      cw.tkey, cw.tval, w.long_best, w.long_lab);
+    MC_LAUNCHED("k_lp_long_min");
+    k_lp_long_final<<<64, 256, 0, s>>>(lab_in, lab_out, w.long_list, w.counters, w.long_best, w.long_own,
+                                       w.long_lab);
+    MC_LAUNCHED("k_lp_long_final");
+    return true;
+}
+
+bool lp_relabel(const int32_t* lab, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp, DevScalars* sc,
+                hipStream_t s) {
+    if (!fill_i32(flag_tmp, 0, (int64_t)n + 1, s)) return false;
+    k_label_used<<<grid_for(n, 256), 256, 0, s>>>(lab, n, flag_tmp);
+    MC_LAUNCHED("k_label_used");
+    if (!scan_i32(flag_tmp, flag_tmp, n, scan_tmp, s)) return false;
+    k_label_rank<<<grid_for(n, 256), 256, 0, s>>>(lab, flag_tmp, n, L, sc);
+    MC_LAUNCHED("k_label_rank");
+    return true;
+}

@@ -129,6 +129,31 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
           uint8_t* flag1, int32_t* ptr2, Pr12WS& w, hipStream_t s);
 
+// ---------------------------------------------------- label propagation
+// Scratch of lp_round besides the contraction scratch it borrows (row
+// prefix, scan temp, global tables).
+struct LpWS {
+    int32_t* long_list;   // rows longer than the chunked path takes
+    int32_t* long_base;   // their global-table offsets
+    int32_t* long_lab;    // smallest other label of the heaviest weight
+    unsigned long long* long_best;   // heaviest other-label weight
+    unsigned long long* long_own;    // weight of the row's own label
+    int32_t* task_row;    // long row of every task
+    int32_t* task_idx;    // task index within its row
+    int32_t* counters;    // long rows, table slots, tasks
+    int32_t* cg;          // first row of every chunk
+};
+void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w);
+// One synchronous label-propagation round over g (Section 2.1 heuristic):
+// lab_out[v] = heaviest neighbour label, keeping lab_in[v] unless another
+// label is strictly heavier, smallest label on ties. Uses cw.mstart,
+// cw.scan_tmp, cw.tkey and cw.tval as scratch.
+bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s);
+// Canonical relabel of arbitrary labels in [0, n): L[v] = rank of lab[v]
+// among the labels in use; the count goes to sc->n2.
+bool lp_relabel(const int32_t* lab, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp, DevScalars* sc,
+                hipStream_t s);
+
 // ----------------------------------------------------------- CAPFOREST
 struct CapforestArgs {
     DGraph g;

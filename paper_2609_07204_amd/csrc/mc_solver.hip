@@ -302,6 +302,8 @@ struct SolveWS {
     int32_t* calen = nullptr;
     int64_t* clamout = nullptr;
     Pr12WS prw{};
+    LpWS lw{};                    // label propagation of the heuristic
+    int32_t* lab2 = nullptr;      // second label array of the synchronous rounds
     PrivateArgs pv{};             // per-pass arrays of the private passes
     StepArgs sa{};                // control of the level-synchronous form
     int32_t* psteps = nullptr;
@@ -398,6 +400,8 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     w.calen = a.take<int32_t>(1);
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
+    lp_ws_carve(a, n, cap, w.lw);
+    w.lab2 = a.take<int32_t>((size_t)n + 1);
     carve_private(a, n, ppasses, w.pv, w.psteps);
     carve_steps(a, n, cap, ppasses, len_cap, w.sa);
 }
@@ -703,6 +707,79 @@ static mc_status exact_rounds(Solver& S, int src) {
     return MC_OK;
 }
 
+// Contract cur by labels L (n2 groups) into g[*nxt_idx]; the collapsed
+// degrees of the result bound lambda (Section 2.1 "Overall algorithm"; only
+// while at least two vertices remain). Returns the new current graph.
+static DGraph* contract_and_bound(Solver& S, DGraph* cur, int32_t n2, int* nxt_idx, mc_status* err) {
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    DGraph* nxt = &w.g[*nxt_idx];
+    *err = MC_E_DEVICE;
+    if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s) || !map_update(w.map0, w.L, S.n0, s) || !S.readback())
+        return nullptr;
+    const DevScalars h = *S.c->hsc;
+    if (n2 >= 2 && h.dmin < S.lam) {
+        if (!side_from_vertex(w.side, w.map0, S.n0, &w.sc->dmin_arg, s) || !S.set_lam(h.dmin)) return nullptr;
+    }
+    *nxt_idx = *nxt_idx == 1 ? 2 : 1;
+    *err = MC_OK;
+    return nxt;
+}
+
+// The inexact heuristic that lowers the bound before the exact rounds
+// (Section 2.1 "Lowering the upper bound"; Algorithm 2's first step). While
+// the graph has more than heuristic_min_n vertices: lp_iters synchronous
+// label-propagation rounds from singleton labels, contraction of every
+// cluster, then the reduction tests 1 and 2 against the bound and their
+// contraction. The coarse graph that remains is solved exactly by the same
+// rounds. Every bound found is a cut of the input (clusters are unions of
+// input vertices), so the side snapshots stay valid. Coarsening stops when a
+// level removes fewer than 5 percent of the vertices.
+static mc_status heuristic(Solver& S) {
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    const int32_t nh = S.c->opt.heuristic_min_n;
+    const int iters = S.c->opt.lp_iters > 0 ? S.c->opt.lp_iters : 2;
+    DGraph* cur = &w.g[0];
+    int nxt_idx = 1;
+    mc_status err = MC_OK;
+    while (cur->n > nh && cur->n > 2) {
+        const int32_t n = cur->n;
+        int32_t* a = w.parent;   // labels ping-pong between parent[] and lab2[]
+        int32_t* b = w.lab2;
+        if (!iota_i32(a, n, s)) return MC_E_DEVICE;
+        for (int it = 0; it < iters; it++) {
+            if (!lp_round(*cur, a, b, w.lw, w.cw, s)) return MC_E_DEVICE;
+            std::swap(a, b);
+        }
+        if (!lp_relabel(a, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback()) return MC_E_DEVICE;
+        const int32_t n2 = S.c->hsc->n2;
+        if ((int64_t)n2 * 20 > (int64_t)n * 19) break;
+        cur = contract_and_bound(S, cur, n2, &nxt_idx, &err);
+        if (!cur) return err;
+        S.stats.heuristic_levels++;
+        // reduction tests 1 and 2 on the clustered graph
+        k_reset_round<<<1, 1, 0, s>>>(w.sc);
+        if (!uf_init(w.parent, cur->n, s) ||
+            !pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, w.prw, s) ||
+            !uf_labels(w.parent, cur->n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
+            return MC_E_DEVICE;
+        const int32_t n3 = S.c->hsc->n2;
+        if (n3 < cur->n) {
+            S.stats.marks_pr += (int64_t)S.c->hsc->marks_pr;
+            cur = contract_and_bound(S, cur, n3, &nxt_idx, &err);
+            if (!cur) return err;
+        }
+    }
+    if (cur == &w.g[0]) return MC_OK;   // nothing coarsened: the exact rounds start from the min degree
+    if (cur->n > 2) {
+        mc_status r = exact_rounds(S, nxt_idx == 1 ? 2 : 1);
+        if (r != MC_OK) return r;
+    }
+    S.stats.lambda_heuristic = S.lam;
+    return MC_OK;
+}
+
 extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t ws_bytes, int64_t* lambda,
                                uint8_t* side_out, mc_stats* st) {
     auto t0 = std::chrono::steady_clock::now();
@@ -796,8 +873,13 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         if (!side_from_vertex(w.side, w.map0, n, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
         if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
         S.stats.lambda_min_degree = h.dmin;
-        mc_status r = exact_rounds(S, 0);
-        if (r != MC_OK) return r;
+        mc_status r = MC_OK;
+        if (c->opt.heuristic_min_n > 0 && n >= c->opt.heuristic_min_n) {
+            if ((r = heuristic(S)) != MC_OK) return r;
+            // the exact rounds start again from the normalised input
+            if (!iota_i32(w.map0, n, s)) return MC_E_DEVICE;
+        }
+        if ((r = exact_rounds(S, 0)) != MC_OK) return r;
         result = S.lam;
     }
     if (side_out) {
@@ -832,6 +914,7 @@ DGraph to_dgraph(const mc_dgraph* g) {
 }
 
 struct StepWS {
+    LpWS lw;
     DevScalars* sc;
     int32_t* parent;
     int32_t* flag;
@@ -854,6 +937,7 @@ struct StepWS {
 
 void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.sc = a.take<DevScalars>(1);
+    lp_ws_carve(a, n, cap, w.lw);
     w.lam = a.take<int64_t>(1);
     w.parent = a.take<int32_t>((size_t)n + 1);
     w.flag = a.take<int32_t>((size_t)n + 2);
@@ -947,6 +1031,17 @@ extern "C" mc_status mc_step_pr12(mc_ctx* c, const mc_dgraph* g, int64_t lam, ui
     if ((r = sync_read(c, w)) != MC_OK) return r;
     if (n2) *n2 = c->hsc->n2;
     return MC_OK;
+}
+
+extern "C" mc_status mc_step_lp(mc_ctx* c, const mc_dgraph* g, const int32_t* lab_in, int32_t* lab_out, void* ws,
+                                size_t bytes) {
+    if (!g || !lab_in || !lab_out) return fail(MC_E_INVALID_ARG, "mc_step_lp: NULL argument");
+    if (lab_in == lab_out) return fail(MC_E_INVALID_ARG, "mc_step_lp: lab_in and lab_out must differ");
+    StepWS w;
+    mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
+    if (r != MC_OK) return r;
+    if (!lp_round(to_dgraph(g), lab_in, lab_out, w.lw, w.cw, c->stream)) return MC_E_DEVICE;
+    return sync_read(c, w);
 }
 
 extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t lam, int32_t start, int32_t mode,

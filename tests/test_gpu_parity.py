@@ -474,3 +474,54 @@ def test_raw_input_takes_merging_normalisation(ctx, seed):
     assert st1["input_normal"] == 0 and st2["input_normal"] == 1
     assert lam1 == lam2 == lam_ref
     assert oracle.cut_value(norm, side1) == lam_ref and oracle.cut_value(norm, side2) == lam_ref
+
+
+# ------------------------------------------------------ label propagation
+@pytest.mark.parametrize("seed,nlab", [(1, 0), (2, 5), (3, 40), (4, 3000)])
+def test_lp_round_matches_oracle(ctx, seed, nlab):
+    # rows of up to ~2000 entries (hubs take the long-row path), labels from
+    # singletons (nlab = 0) to a few large clusters: bit-exact
+    g = hub_graph(3000, 5, 1800, 6, seed, 1, 9)
+    r = np.random.default_rng(seed)
+    lab = np.arange(g.n, dtype=np.int32) if nlab == 0 else r.integers(0, nlab, g.n).astype(np.int32)
+    dev = ctx.dgraph(g)
+    got = ctx.step_lp(dev, lab)
+    want = oracle.lp_round(g, lab)
+    say("lp round", seed, nlab, int(np.sum(got != lab)), "changed")
+    assert np.array_equal(got, want)
+    # a second round from the first round's labels
+    assert np.array_equal(ctx.step_lp(dev, want), oracle.lp_round(g, want))
+
+
+def test_lp_round_ties_and_own_label(ctx):
+    # star-like rows with equal weights: ties go to the smallest label, and a
+    # vertex keeps its label unless another is strictly heavier
+    n = 40
+    u, v, w = [], [], []
+    for k in range(1, n):
+        u.append(0); v.append(k); w.append(1)
+    for k in range(1, n - 1):
+        u.append(k); v.append(k + 1); w.append(1)
+    g = gen.from_edges(n, u, v, w)
+    for lab in (np.arange(n, dtype=np.int32), (np.arange(n) % 3).astype(np.int32),
+                np.array([7] + [3] * 19 + [5] * 20, np.int32)):
+        dev = ctx.dgraph(g)
+        assert np.array_equal(ctx.step_lp(dev, lab), oracle.lp_round(g, lab))
+
+
+@pytest.mark.parametrize("fam,seed", [(0, 1), (1, 2), (2, 3), (2, 4)])
+def test_heuristic_solve_matches_oracle(ctx, fam, seed):
+    # graphs above the heuristic threshold: the label-propagation bound is a
+    # real cut (lambda <= bound <= min degree) and the exact rounds that
+    # follow still reach lambda
+    import paper_2609_07204_amd as mc
+    g = gen.mixed_graph(30000, 10 + 4 * seed, fam, 500 + seed, 1, 100)
+    lam_ref = oracle.noi(g)[0]
+    c = mc.Context(0, heuristic_min_n=10000)
+    lam, side, st = c.mincut(g, return_stats=True)
+    say("heuristic", g.name, g.n, g.m, "levels", st["heuristic_levels"], "bound", st["lambda_heuristic"],
+        "lambda", lam_ref, "min degree", st["lambda_min_degree"])
+    assert lam == lam_ref and oracle.cut_value(g, side) == lam
+    assert st["heuristic_levels"] >= 1
+    assert lam_ref <= st["lambda_heuristic"] <= st["lambda_min_degree"]
+    c.close()
