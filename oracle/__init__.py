@@ -54,6 +54,8 @@ def _L():
         lib.orc_contract.restype = i64
         lib.orc_pr12.argtypes = [i32, P, P, P, i64, P, P]
         lib.orc_pr12.restype = None
+        lib.orc_pr34.argtypes = [i32, P, P, P, i64, i32, P, P, P, P]
+        lib.orc_pr34.restype = None
         lib.orc_lp.argtypes = [i32, P, P, P, P, P]
         lib.orc_lp.restype = None
         lib.orc_capforest_pass.argtypes = [i32, P, P, P, P, i32, i32, P, P, P, P, P]
@@ -168,6 +170,21 @@ def pr12(g, lam):
     ptr = np.zeros(max(g.n, 1), np.int32)
     _L().orc_pr12(g.n, _ptr(rp), _ptr(col), _ptr(w), lam, flag.ctypes.data, ptr.ctypes.data)
     return flag[:g.nnz], ptr[:g.n]
+
+
+def pr34(g, lam, D, ptr2):
+    """Padberg-Rinaldi tests 3 and 4 on candidate edges whose rows both have
+    at most D entries (see orc_pr34): test-4 flag per entry, smallest test-3
+    partner per vertex, accepted test-3 partner per vertex (a matching that
+    avoids test-2 pointers)."""
+    rp, col, w = _csr(g)
+    ptr2 = np.ascontiguousarray(ptr2, np.int32)
+    flag = np.zeros(max(g.nnz, 1), np.uint8)
+    part = np.zeros(max(g.n, 1), np.int32)
+    acc = np.zeros(max(g.n, 1), np.int32)
+    _L().orc_pr34(g.n, _ptr(rp), _ptr(col), _ptr(w), lam, D, ptr2.ctypes.data, flag.ctypes.data,
+                  part.ctypes.data, acc.ctypes.data)
+    return flag[:g.nnz], part[:g.n], acc[:g.n]
 
 
 def lp_round(g, lab_in):

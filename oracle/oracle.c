@@ -22,7 +22,7 @@
  *                       current bound, contraction of every marked edge,
  *                       collapsed degrees as bounds, until <= 2 vertices
  * Step oracles (pure functions used for bit-exact kernel parity):
- *   orc_degrees, orc_contract, orc_components, orc_pr12, orc_lp,
+ *   orc_degrees, orc_contract, orc_components, orc_pr12, orc_pr34, orc_lp,
  *   orc_capforest_pass
  */
 #include <stdint.h>
@@ -450,6 +450,63 @@ void orc_pr12(int32_t n, const int32_t* rp, const int32_t* col, const int64_t* w
         }
         ptr2[v] = (bp >= 0 && 2 * bw >= deg) ? bp : -1;
     }
+}
+
+/* ------------------------------------------ Padberg-Rinaldi tests 3, 4 */
+/* Tests 3 and 4 (Section 2.1 names the four local tests of Padberg and
+ * Rinaldi; App. A: sweeps may skip edges) on the candidate edges {v,x} of a
+ * simple graph whose rows both have at most D entries; skipping the other
+ * edges is always safe. With c(v) the degree of v:
+ *   s(v,x) = c(v,x) + sum over common neighbours u of min(c(v,u), c(x,u))
+ *   test 4: s(v,x) >= lam. The edge and the two-edge paths through common
+ *           neighbours are edge-disjoint, so s bounds the connectivity of v
+ *           and x from below.
+ *   test 3: some common neighbour u has 2 (c(v,x) + c(v,u)) >= c(v) and
+ *           2 (c(v,x) + c(x,u)) >= c(x).
+ * Outputs: flag4[j] = 1 for every entry j of a candidate edge passing test
+ * 4; part3[v] = the smallest x such that {v,x} is a candidate passing test 3
+ * (-1: none); acc3[v] = x when part3[v] = x, part3[x] = v and neither v nor x
+ * is the source or the target of a test-2 pointer (ptr2, as orc_pr12 gives
+ * it), else -1. Rows must be those of a simple graph (no loops, no parallel
+ * entries). */
+void orc_pr34(int32_t n, const int32_t* rp, const int32_t* col, const int64_t* w, int64_t lam, int32_t D,
+              const int32_t* ptr2, uint8_t* flag4, int32_t* part3, int32_t* acc3) {
+    int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    uint8_t* touch = (uint8_t*)calloc((size_t)n + 1, 1);
+    for (int32_t v = 0; v < n; v++) {
+        for (int64_t j = rp[v]; j < rp[v + 1]; j++) deg[v] += w[j];
+        part3[v] = -1;
+        acc3[v] = -1;
+        if (ptr2[v] >= 0) { touch[v] = 1; touch[ptr2[v]] = 1; }
+    }
+    for (int32_t v = 0; v < n; v++) {
+        for (int64_t j = rp[v]; j < rp[v + 1]; j++) {
+            flag4[j] = 0;
+            const int32_t x = col[j];
+            if (rp[v + 1] - rp[v] > D || rp[x + 1] - rp[x] > D) continue;
+            const int64_t cvx = w[j];
+            int64_t sum = cvx;
+            int t3 = 0;
+            for (int64_t a = rp[v]; a < rp[v + 1]; a++) {
+                const int32_t u = col[a];
+                if (u == x) continue;
+                for (int64_t b = rp[x]; b < rp[x + 1]; b++) {
+                    if (col[b] != u) continue;
+                    const int64_t cvu = w[a], cxu = w[b];
+                    sum += cvu < cxu ? cvu : cxu;
+                    if (2 * (cvx + cvu) >= deg[v] && 2 * (cvx + cxu) >= deg[x]) t3 = 1;
+                }
+            }
+            flag4[j] = sum >= lam;
+            if (t3 && (part3[v] < 0 || x < part3[v])) part3[v] = x;
+        }
+    }
+    for (int32_t v = 0; v < n; v++) {
+        const int32_t x = part3[v];
+        if (x >= 0 && part3[x] == v && !touch[v] && !touch[x]) acc3[v] = x;
+    }
+    free(deg);
+    free(touch);
 }
 
 /* ------------------------------------------------- label propagation */

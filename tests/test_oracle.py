@@ -355,3 +355,135 @@ def test_capforest_truncated_pass():
     assert list(res["order"]) == [3, 0, 1]
     # after two scans every vertex has r = 4; at the third scan r = 6, below 14
     assert res["marks"] == 0
+
+
+# ------------------------------------------------ Padberg-Rinaldi tests 3, 4
+def test_pr34_hand_example():
+    # a 4-cycle 0-1-2-3 with chord 0-2 (weights below) and a pendant 4 on 3:
+    # edge {0,2} has common neighbours 1 and 3:
+    #   s(0,2) = 5 + min(2, 3) + min(4, 1) = 8
+    # edge {0,1}: common neighbour 2: s = 2 + min(5, 3) = 5
+    g = gen.from_edges(5, [0, 1, 2, 3, 0, 3], [1, 2, 3, 0, 2, 4], [2, 3, 1, 4, 5, 6])
+    deg = oracle.degrees(g)
+    assert list(deg) == [11, 5, 9, 11, 6]
+    flag1, ptr = oracle.pr12(g, 100)
+    flag4, part, acc = oracle.pr34(g, 8, 10, np.full(5, -1, np.int32))
+    s = {}
+    for v in range(5):
+        for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            s[(v, int(g.col[j]))] = bool(flag4[j])
+    assert s[(0, 2)] and s[(2, 0)]           # 8 >= 8
+    assert not s[(0, 1)] and not s[(3, 4)]   # 5 < 8; no common neighbour
+    # test 3 on {0,2} with u = 3: 2 (5 + 4) = 18 >= 11 and 2 (5 + 1) = 12 >= 9
+    # on {0,1} with u = 2: 2 (2 + 5) = 14 >= 11 and 2 (2 + 3) = 10 >= 5
+    # so vertex 0's smallest partner is 1, vertex 1's is 0 (its only
+    # candidate with a common neighbour), vertex 2's is 0
+    assert part[0] == 1 and part[1] == 0 and part[2] == 0
+    assert acc[0] == 1 and acc[1] == 0 and acc[2] == -1
+    # a test-2 pointer on vertex 1 blocks the pair
+    flag4, part, acc = oracle.pr34(g, 8, 10, np.array([-1, 2, -1, -1, -1], np.int32))
+    assert acc[0] == -1 and acc[1] == -1
+    # the degree cap: rows of vertices 0 and 2 have 3 entries
+    flag4, part, acc = oracle.pr34(g, 8, 2, np.full(5, -1, np.int32))
+    assert not flag4.any()
+
+
+def test_pr34_wheel_fires_test3_only():
+    # rim edges of the weighted wheel: test 3 holds with the hub as witness,
+    # test 4 does not (s = (n-2) + 2 < 2n-2); accepted pairs form a matching
+    n = 12
+    g = gen.wheel(n)
+    lam = 2 * n - 2
+    assert int(oracle.degrees(g).min()) == lam
+    flag1, ptr = oracle.pr12(g, lam)
+    assert not flag1.any() and (ptr < 0).all()
+    flag4, part, acc = oracle.pr34(g, lam, 3, ptr)
+    assert not flag4.any()
+    rim = [v for v in range(g.n) if g.row_ptr[v + 1] - g.row_ptr[v] == 3]
+    assert len(rim) == n - 1 and all(part[v] >= 0 for v in rim)
+    matched = [v for v in range(g.n) if acc[v] >= 0]
+    assert matched and all(acc[acc[v]] == v for v in matched)
+
+
+def two_blocks(seed):
+    """Two dense random blocks (weights 1..9) joined by one to three light
+    bridges: small graphs whose minimum cut is usually below the minimum
+    degree, so the tests run with a bound above lambda."""
+    r = np.random.default_rng(seed)
+    a, b = int(r.integers(3, 8)), int(r.integers(3, 8))
+    u, v, w = [], [], []
+    for lo, hi in ((0, a), (a, a + b)):
+        for i in range(lo, hi):
+            for j in range(i + 1, hi):
+                if r.random() < 0.8:
+                    u.append(i); v.append(j); w.append(int(r.integers(1, 10)))
+    for _ in range(int(r.integers(1, 4))):
+        u.append(int(r.integers(0, a))); v.append(int(r.integers(a, a + b))); w.append(int(r.integers(1, 4)))
+    return gen.from_edges(a + b, u, v, w)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_pr1234_safe_contraction(seed):
+    # contracting every test-1 and test-4 edge, every test-2 pointer and the
+    # accepted test-3 pairs together keeps lambda whenever the bound is
+    # above it (brute force on small graphs)
+    g = two_blocks(7000 + seed) if seed % 2 else gen.random_small(6 + seed % 9, 0.55, 7000 + seed, 1, 9)
+    lam = oracle.brute(g)[0]
+    lam_hat = int(oracle.degrees(g).min())
+    if seed % 3 == 0:
+        # bounds between lambda and the min degree too (the solver's bound
+        # never exceeds the min degree: that is what makes a trivial cut
+        # impossible as a cut below the bound)
+        lam_hat = min(lam_hat, lam + 1 + seed % 4)
+    if lam_hat <= lam:
+        return
+    flag1, ptr = oracle.pr12(g, lam_hat)
+    flag4, part, acc = oracle.pr34(g, lam_hat, 64, ptr)
+    pairs = [(x, int(g.col[j])) for x in range(g.n) for j in range(g.row_ptr[x], g.row_ptr[x + 1])
+             if flag1[j] or flag4[j]]
+    pairs += [(x, int(ptr[x])) for x in range(g.n) if ptr[x] >= 0]
+    pairs += [(x, int(acc[x])) for x in range(g.n) if acc[x] >= 0]
+    if not pairs:
+        return
+    h, nc = _contract_marks(g, pairs)
+    assert nc >= 2
+    assert oracle.brute(h)[0] == lam
+
+
+def test_pr4_is_a_connectivity_bound():
+    # s(v,x) never exceeds the true connectivity of v and x
+    for seed in range(30):
+        g = gen.random_small(10, 0.6, 9100 + seed, 1, 7)
+        flag4, part, acc = oracle.pr34(g, 1, 64, np.full(g.n, -1, np.int32))
+        for v in range(g.n):
+            for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
+                x = int(g.col[j])
+                # the largest lam for which test 4 holds is s(v,x)
+                lo, hi = 0, 10 ** 6
+                while lo < hi:
+                    mid = (lo + hi + 1) // 2
+                    f, _, _ = oracle.pr34(g, mid, 64, np.full(g.n, -1, np.int32))
+                    if f[j]:
+                        lo = mid
+                    else:
+                        hi = mid - 1
+                assert lo <= oracle.brute_st(g, v, x)
+
+
+@pytest.mark.parametrize("seed", [103230, 105901, 106297])
+def test_pr3_needs_the_matching(seed):
+    # graphs (found by search) where contracting every vertex's test-3
+    # partner at once loses the minimum cut, while the accepted matching
+    # alone keeps it
+    g = two_blocks(seed)
+    lam = oracle.brute(g)[0]
+    lam_hat = int(oracle.degrees(g).min())
+    assert lam_hat > lam
+    none = np.full(g.n, -1, np.int32)
+    flag4, part, acc = oracle.pr34(g, lam_hat, 64, none)
+    h, nc = _contract_marks(g, [(v, int(part[v])) for v in range(g.n) if part[v] >= 0])
+    assert nc < 2 or oracle.brute(h)[0] != lam
+    matched = [(v, int(acc[v])) for v in range(g.n) if acc[v] >= 0]
+    if matched:
+        h, nc = _contract_marks(g, matched)
+        assert nc >= 2 and oracle.brute(h)[0] == lam
