@@ -70,7 +70,11 @@ typedef struct {
                                  default 10000; <= 0 disables it) */
     int32_t lp_iters;         /* label-propagation rounds per coarsening level
                                  (default 2) */
-    int32_t pr_tri_deg_cap;   /* reserved (triangle tests); 0 = off */
+    int32_t pr_tri_deg_cap;   /* reduction tests 3 and 4 on edges whose two
+                                 rows have at most this many entries (<= 64;
+                                 default 16; 0 = off); they stop for the rest
+                                 of a solve once a round gains fewer than one
+                                 contraction per 100 vertices */
     int32_t capforest_passes; /* concurrent CAPFOREST passes per round
                                  (0 = automatic) */
     int32_t pass_len_cap;     /* scans per pass (0 = automatic; < 0 = until
@@ -105,6 +109,7 @@ typedef struct {
                                     next round) */
     int32_t input_normal;        /* 1: the input was already a simple graph
                                     with sorted rows and was used in place */
+    int64_t marks_tri;           /* of marks_pr: edges unioned by tests 3, 4 */
 } mc_stats;
 
 typedef struct mc_ctx mc_ctx;

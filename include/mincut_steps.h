@@ -57,6 +57,20 @@ mc_status mc_step_components(mc_ctx* ctx, int32_t n, int64_t npairs, const int32
 mc_status mc_step_pr12(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, uint8_t* flag1, int32_t* ptr2,
                        int32_t* labels, int32_t* n2, void* ws, size_t ws_bytes);
 
+/* Padberg-Rinaldi tests 3 and 4 (the other two local reduction tests of
+ * Section 2.1; App. A) on the candidate edges {v,x} whose two rows both have
+ * at most D entries (0 <= D <= 64). g must be a simple graph (a normalised
+ * or contracted one) with deg set. With s = c(v,x) + sum over common
+ * neighbours u of min(c(v,u), c(x,u)): test 4 holds when s >= lam; test 3
+ * when some common u has 2 (c(v,x) + c(v,u)) >= c(v) and
+ * 2 (c(v,x) + c(x,u)) >= c(x). Test-4 edges are unioned; of the test-3
+ * edges only mutual smallest partners that touch no test-2 pointer of ptr2
+ * ([n] device array, -1 = none, as mc_step_pr12 writes it) are unioned.
+ * Outputs: flag4[entry] (may be NULL), acc3[v] = accepted test-3 partner or
+ * -1 (may be NULL), canonical labels of the unions (labels[n], *n2). */
+mc_status mc_step_pr34(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t D, const int32_t* ptr2,
+                       uint8_t* flag4, int32_t* acc3, int32_t* labels, int32_t* n2, void* ws, size_t ws_bytes);
+
 /* One synchronous label-propagation round, the clustering step of the
  * bound heuristic (Section 2.1, "Lowering the upper bound"): lab_out[v] is
  * the label (among lab_in of v's neighbours, loops ignored) with the

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("lambda_min_degree", ctypes.c_int64), ("lambda_heuristic", ctypes.c_int64),
                 ("marks_pr", ctypes.c_int64), ("marks_capforest", ctypes.c_int64),
                 ("fallback_passes", ctypes.c_int32), ("n_input", ctypes.c_int32), ("m_input", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32), ("input_normal", ctypes.c_int32)]
+                ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32), ("input_normal", ctypes.c_int32),
+                ("marks_tri", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +82,7 @@ SIGNATURES = {
     "mc_step_components": (ctypes.c_int, [P, I32, I64, P, P, P, P, P, SZ]),
     "mc_step_pr12": (ctypes.c_int, [P, P, I64, P, P, P, P, P, SZ]),
     "mc_step_lp": (ctypes.c_int, [P, P, P, P, P, SZ]),
+    "mc_step_pr34": (ctypes.c_int, [P, P, I64, I32, P, P, P, P, P, P, SZ]),
     "mc_step_capforest": (ctypes.c_int, [P, P, I64, I32, I32, I32, I32, I32, P, P, P, P, P, P, P, P, SZ]),
 }
 
@@ -265,6 +267,20 @@ class Context:
         _check(lib().mc_step_pr12(self.h, ctypes.byref(g.c()), lam, _ptr(flag), _ptr(ptr), _ptr(lab),
                                   ctypes.byref(n2), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return flag, ptr.cpu().numpy(), lab.cpu().numpy(), n2.value
+
+    def step_pr34(self, g, lam, D, ptr2):
+        """Reduction tests 3 and 4 (see mc_step_pr34): (flag4 per entry as a
+        device tensor, accepted test-3 partner per vertex, labels, n2)."""
+        torch = _torch()
+        p = torch.as_tensor(np.ascontiguousarray(ptr2, np.int32)).to(self.device)
+        flag = torch.zeros(g.cap, dtype=torch.uint8, device=self.device)
+        acc = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        lab = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
+        n2 = ctypes.c_int32()
+        ws = self.step_workspace(g.n, g.cap)
+        _check(lib().mc_step_pr34(self.h, ctypes.byref(g.c()), lam, D, _ptr(p), _ptr(flag), _ptr(acc), _ptr(lab),
+                                  ctypes.byref(n2), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return flag, acc[:g.n].cpu().numpy(), lab[:g.n].cpu().numpy(), n2.value
 
     def step_lp(self, g, lab_in):
         """One label-propagation round on device graph g (see mc_step_lp)."""

@@ -29,6 +29,7 @@ struct DevScalars {
     int64_t best_alpha;     // smallest alpha of the last CAPFOREST launch
     unsigned long long marks_pr;
     unsigned long long marks_cf;
+    unsigned long long marks_tri;   // of which reduction tests 3 and 4
     int32_t dmin_arg;       // vertex of minimum degree (smallest id on ties)
     int32_t best_pass;      // pass that found best_alpha
     int32_t best_len;       // its scanned-prefix length

@@ -298,6 +298,129 @@ __global__ __launch_bounds__(64) void k_pr12_long_final(DGraph g, int32_t* par, 
     }
 }
 
+// Padberg-Rinaldi tests 3 and 4 (the remaining two of the four local tests;
+// applied in one sweep over candidate edges, which may miss edges, as the
+// linear-time sweeps of App. A do): candidates are the edges {v,x} whose
+// rows both have at most D entries. With c(.) the degrees:
+//   s = c(v,x) + sum over common neighbours u of min(c(v,u), c(x,u));
+//   test 4: s >= lam -- the edge and the two-edge paths through the common
+//           neighbours are edge-disjoint, so v and x are at least s-connected
+//           and the edge joins the union-find like test 1;
+//   test 3: some common u has 2 (c(v,x) + c(v,u)) >= c(v) and
+//           2 (c(v,x) + c(x,u)) >= c(x) -- an exchange argument like test 2,
+//           so only a matching is applied: every vertex proposes its
+//           smallest test-3 partner, mutual proposals between vertices that
+//           touch no test-2 pointer are accepted (k_pr3_accept).
+// One group of TRI_SUB lanes per vertex v of at most D entries: N(v) goes
+// to an LDS hash, then for every neighbour x > v with a short row the lanes
+// scan N(x) against it.
+constexpr int TRI_SUB = 16;
+constexpr int TRI_T = 256;
+constexpr int TRI_MAXD = 64;
+constexpr int TRI_SLOTS = 2 * TRI_MAXD;
+constexpr int32_t TRI_NONE = INT32_MAX;
+
+__global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, int32_t D, int32_t* par,
+                                               unsigned long long* marks, int32_t* part3, uint8_t* flag4) {
+    __shared__ int32_t hk[TRI_T / TRI_SUB][TRI_SLOTS];
+    __shared__ int64_t hv[TRI_T / TRI_SUB][TRI_SLOTS];
+    const int64_t lam = *lamp;
+    const int grp = threadIdx.x / TRI_SUB, sl = threadIdx.x % TRI_SUB;
+    int32_t* K = hk[grp];
+    int64_t* W = hv[grp];
+    const int64_t ngrp = (int64_t)gridDim.x * (TRI_T / TRI_SUB);
+    unsigned long long joined = 0;
+    // uniform trip count over the workgroup (the LDS tables are per group,
+    // but the loop shape keeps every lane in step for the shuffles)
+    const int64_t top = ((int64_t)g.n + ngrp - 1) / ngrp * ngrp;
+    for (int64_t v0 = (int64_t)blockIdx.x * (TRI_T / TRI_SUB) + grp; v0 < top; v0 += ngrp) {
+        const int32_t v = (int32_t)v0;
+        const bool live = v0 < g.n && g.len[v] <= D && g.len[v] > 0;
+        const int32_t o = live ? g.off[v] : 0, l = live ? g.len[v] : 0;
+        for (int k = sl; k < TRI_SLOTS; k += TRI_SUB) K[k] = -1;
+        __syncwarp();
+        for (int32_t j = sl; j < l; j += TRI_SUB) {
+            const int32_t x = g.col[o + j];
+            uint32_t h = hash32((uint32_t)x) & (TRI_SLOTS - 1);
+            while (atomicCAS(&K[h], -1, x) != -1) h = (h + 1) & (TRI_SLOTS - 1);
+            W[h] = g.w[o + j];
+        }
+        __syncwarp();
+        const int64_t cv = live ? g.deg[v] : 0;
+        for (int32_t j = 0; j < l; j++) {
+            const int32_t x = g.col[o + j];
+            if (x <= v || g.len[x] > D) continue;          // uniform over the group
+            const int64_t cvx = g.w[o + j];
+            const int64_t cx = g.deg[x];
+            const int32_t ox = g.off[x], lx = g.len[x];
+            int64_t sum = 0;
+            int t3 = 0;
+            int32_t back = -1;
+            for (int32_t b = sl; b < lx; b += TRI_SUB) {
+                const int32_t u = g.col[ox + b];
+                if (u == v) { back = ox + b; continue; }
+                uint32_t h = hash32((uint32_t)u) & (TRI_SLOTS - 1);
+                for (;;) {
+                    const int32_t k = K[h];
+                    if (k == u || k == -1) break;
+                    h = (h + 1) & (TRI_SLOTS - 1);
+                }
+                if (K[h] != u) continue;
+                const int64_t cvu = W[h], cxu = g.w[ox + b];
+                sum += cvu < cxu ? cvu : cxu;
+                if (2 * (cvx + cvu) >= cv && 2 * (cvx + cxu) >= cx) t3 = 1;
+            }
+            for (int d = TRI_SUB / 2; d > 0; d >>= 1) {
+                sum += __shfl_xor(sum, d, TRI_SUB);
+                t3 |= __shfl_xor(t3, d, TRI_SUB);
+                const int32_t b2 = __shfl_xor(back, d, TRI_SUB);
+                back = b2 > back ? b2 : back;
+            }
+            if (sl == 0) {
+                const bool t4 = cvx + sum >= lam;
+                if (flag4) {
+                    flag4[o + j] = t4;
+                    if (back >= 0) flag4[back] = t4;
+                }
+                if (t4 && uf_union(par, v, x)) joined++;
+                if (t3) {
+                    atomicMin(&part3[v], x);
+                    atomicMin(&part3[x], v);
+                }
+            }
+        }
+        __syncwarp();
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
+        atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
+    }
+}
+
+// vertices that are the source or the target of a test-2 pointer
+__global__ void k_pr2_touch(const int32_t* ptr2, int32_t n, uint8_t* touch) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (ptr2[v] >= 0) { touch[v] = 1; touch[ptr2[v]] = 1; }
+}
+
+// mutual smallest test-3 partners away from test-2 pointers are contracted
+__global__ void k_pr3_accept(const int32_t* part3, const uint8_t* touch, int32_t n, int32_t* par,
+                             unsigned long long* marks, int32_t* acc3) {
+    unsigned long long joined = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = part3[v];
+        const bool ok = x != TRI_NONE && part3[x] == (int32_t)v && !touch[v] && !touch[x];
+        if (acc3) acc3[v] = ok ? x : -1;
+        if (ok && x > v && uf_union(par, (int32_t)v, x)) joined++;
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
+        atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
+    }
+}
+
 __global__ void k_map_update(int32_t* map0, const int32_t* L, int32_t n0) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
         map0[v] = L[map0[v]];
@@ -488,6 +611,31 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
                                          w.part_x);
     MC_LAUNCHED("k_pr12_long_final");
     return true;
+}
+
+bool pr34(const DGraph& g, const int64_t* lam, int32_t D, int32_t* parent, unsigned long long* marks,
+          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s) {
+    if (D > TRI_MAXD) D = TRI_MAXD;
+    if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s) || !fill_i32(w.part3, TRI_NONE, g.n, s) ||
+        !fill_u8(w.touch, 0, g.n, s))
+        return false;
+    if (flag4 && !fill_u8(flag4, 0, g.cap, s)) return false;
+    k_pr2_touch<<<grid_for(g.n, 256), 256, 0, s>>>(ptr2, g.n, w.touch);
+    MC_LAUNCHED("k_pr2_touch");
+    k_pr34<<<grid_for((int64_t)g.n * TRI_SUB, TRI_T), TRI_T, 0, s>>>(g, lam, D, parent, w.spread, w.part3, flag4);
+    MC_LAUNCHED("k_pr34");
+    k_pr3_accept<<<grid_for(g.n, 256), 256, 0, s>>>(w.part3, w.touch, g.n, parent, w.spread, acc3);
+    MC_LAUNCHED("k_pr3_accept");
+    k_pr12_fold<<<1, SPREAD, 0, s>>>(w.spread, marks);
+    MC_LAUNCHED("k_pr12_fold");
+    return true;
+}
+
+void pr34_ws_carve(Arena& a, int32_t n, Pr34WS& w) {
+    w.part3 = a.take<int32_t>((size_t)n + 1);
+    w.touch = a.take<uint8_t>((size_t)n + 1);
+    w.ptr2 = a.take<int32_t>((size_t)n + 1);
+    w.spread = a.take<unsigned long long>((size_t)SPREAD * SPREAD_STRIDE);
 }
 
 bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s) {

@@ -129,6 +129,20 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
           uint8_t* flag1, int32_t* ptr2, Pr12WS& w, hipStream_t s);
 
+// Padberg-Rinaldi tests 3 and 4 on the edges whose rows both have at most
+// D (<= 64) entries; test-4 edges and the accepted test-3 matching (mutual
+// smallest partners touching no test-2 pointer of ptr2) are unioned into
+// parent. Optional parity outputs: flag4[entry], acc3[vertex] (-1: none).
+struct Pr34WS {
+    int32_t* part3;   // [n] smallest test-3 partner
+    uint8_t* touch;   // [n] test-2 pointer endpoints
+    int32_t* ptr2;    // [n] test-2 pointers of the round (filled by pr12)
+    unsigned long long* spread;
+};
+void pr34_ws_carve(Arena& a, int32_t n, Pr34WS& w);
+bool pr34(const DGraph& g, const int64_t* lam, int32_t D, int32_t* parent, unsigned long long* marks,
+          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s);
+
 // ---------------------------------------------------- label propagation
 // Scratch of lp_round besides the contraction scratch it borrows (row
 // prefix, scan temp, global tables).

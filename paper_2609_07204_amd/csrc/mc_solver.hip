@@ -39,6 +39,7 @@ __global__ void k_set_lam(DevScalars* sc, int64_t lam) { sc->lam = lam; }
 __global__ void k_reset_round(DevScalars* sc) {
     sc->marks_pr = 0;
     sc->marks_cf = 0;
+    sc->marks_tri = 0;
     sc->err = 0;
     sc->best_pass = -1;
     sc->best_alpha = INT64_MAX;
@@ -174,7 +175,7 @@ extern "C" void mc_default_options(mc_options* o) {
     o->seed = 1;
     o->heuristic_min_n = 10000;
     o->lp_iters = 2;
-    o->pr_tri_deg_cap = 0;
+    o->pr_tri_deg_cap = 16;
     o->capforest_passes = 0;
     o->pass_len_cap = 0;
     o->capforest_mode = MC_CF_PRIVATE;
@@ -302,6 +303,7 @@ struct SolveWS {
     int32_t* calen = nullptr;
     int64_t* clamout = nullptr;
     Pr12WS prw{};
+    Pr34WS tw{};                  // reduction tests 3 and 4
     LpWS lw{};                    // label propagation of the heuristic
     int32_t* lab2 = nullptr;      // second label array of the synchronous rounds
     PrivateArgs pv{};             // per-pass arrays of the private passes
@@ -401,6 +403,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
     lp_ws_carve(a, n, cap, w.lw);
+    pr34_ws_carve(a, n, w.tw);
     w.lab2 = a.take<int32_t>((size_t)n + 1);
     carve_private(a, n, ppasses, w.pv, w.psteps);
     carve_steps(a, n, cap, ppasses, len_cap, w.sa);
@@ -488,7 +491,30 @@ struct Solver {
     int32_t n0 = 0;
     int64_t lam = 0;
     bool debug = false;
+    bool tri_on = false;          // reduction tests 3 and 4 still pay off
     mc_stats stats{};
+
+    // Reduction tests of one round on g into parent (reset beforehand):
+    // tests 1 and 2, then tests 3 and 4 while they keep finding at least
+    // one contraction per 100 vertices (as repeated linear sweeps stop once
+    // they stop shrinking the graph, App. A).
+    bool reduction_tests(const DGraph& g) {
+        const bool tri = tri_on && c->opt.pr_tri_deg_cap > 0;
+        if (!pr12(g, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, tri ? w.tw.ptr2 : nullptr, w.prw, s))
+            return false;
+        if (!tri) return true;
+        if (!pr34(g, &w.sc->lam, c->opt.pr_tri_deg_cap, w.parent, &w.sc->marks_tri, w.tw.ptr2, w.tw, nullptr,
+                  nullptr, s))
+            return false;
+        return true;
+    }
+    // after the round's readback: fold the test-3/4 marks into the PR count
+    void tri_account(int32_t n) {
+        if (!tri_on || c->opt.pr_tri_deg_cap <= 0) return;
+        const unsigned long long t = c->hsc->marks_tri;
+        stats.marks_tri += (int64_t)t;
+        if (t * 100 < (unsigned long long)n) tri_on = false;
+    }
 
     bool readback() {
         MC_HIP(hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
@@ -613,7 +639,7 @@ static mc_status exact_rounds(Solver& S, int src) {
         const int32_t n = cur->n;
         k_reset_round<<<1, 1, 0, s>>>(w.sc);
         if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
-        if (!pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, w.prw, s)) return MC_E_DEVICE;
+        if (!S.reduction_tests(*cur)) return MC_E_DEVICE;
         const bool det = S.c->opt.deterministic != 0;
         const bool shared = S.c->opt.capforest_mode == MC_CF_SHARED && !det;
         const int32_t* pref_order = nullptr;   // scan order of the pass with the best alpha
@@ -621,7 +647,8 @@ static mc_status exact_rounds(Solver& S, int src) {
         // now and leave CAPFOREST to the smaller graph of the next round
         // (any set of contractible edges is a valid round)
         if (!S.readback()) return MC_E_DEVICE;
-        const bool skip_cf = 2 * (int64_t)S.c->hsc->marks_pr >= n;
+        S.tri_account(n);
+        const bool skip_cf = 2 * (int64_t)(S.c->hsc->marks_pr + S.c->hsc->marks_tri) >= n;
         if (skip_cf) {
             S.stats.rounds_pr_only++;
         } else if (det) {
@@ -661,9 +688,9 @@ static mc_status exact_rounds(Solver& S, int src) {
                 return MC_E_DEVICE;
             if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
         }
-        S.stats.marks_pr += (int64_t)h.marks_pr;
+        S.stats.marks_pr += (int64_t)(h.marks_pr + h.marks_tri);
         S.stats.marks_capforest += (int64_t)h.marks_cf;
-        if (h.marks_pr + h.marks_cf == 0) {
+        if (h.marks_pr + h.marks_tri + h.marks_cf == 0) {
             // Algorithm 2: no contractible edge found, run CAPFOREST over the
             // whole graph without a length limit; with a fixed bound it marks
             // at least one edge, otherwise it lowered the bound
@@ -760,13 +787,13 @@ static mc_status heuristic(Solver& S) {
         S.stats.heuristic_levels++;
         // reduction tests 1 and 2 on the clustered graph
         k_reset_round<<<1, 1, 0, s>>>(w.sc);
-        if (!uf_init(w.parent, cur->n, s) ||
-            !pr12(*cur, &w.sc->lam, w.parent, &w.sc->marks_pr, nullptr, nullptr, w.prw, s) ||
+        if (!uf_init(w.parent, cur->n, s) || !S.reduction_tests(*cur) ||
             !uf_labels(w.parent, cur->n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
             return MC_E_DEVICE;
+        S.tri_account(cur->n);
         const int32_t n3 = S.c->hsc->n2;
         if (n3 < cur->n) {
-            S.stats.marks_pr += (int64_t)S.c->hsc->marks_pr;
+            S.stats.marks_pr += (int64_t)(S.c->hsc->marks_pr + S.c->hsc->marks_tri);
             cur = contract_and_bound(S, cur, n3, &nxt_idx, &err);
             if (!cur) return err;
         }
@@ -801,6 +828,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     S.c = c;
     S.s = c->stream;
     S.debug = getenv("MC_DEBUG") != nullptr;
+    S.tri_on = c->opt.pr_tri_deg_cap > 0;
     const int32_t n = g->n;
     const int64_t nnz = g->nnz;
     Arena a;
@@ -915,6 +943,7 @@ DGraph to_dgraph(const mc_dgraph* g) {
 
 struct StepWS {
     LpWS lw;
+    Pr34WS tw;
     DevScalars* sc;
     int32_t* parent;
     int32_t* flag;
@@ -938,6 +967,7 @@ struct StepWS {
 void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.sc = a.take<DevScalars>(1);
     lp_ws_carve(a, n, cap, w.lw);
+    pr34_ws_carve(a, n, w.tw);
     w.lam = a.take<int64_t>(1);
     w.parent = a.take<int32_t>((size_t)n + 1);
     w.flag = a.take<int32_t>((size_t)n + 2);
@@ -1027,6 +1057,24 @@ extern "C" mc_status mc_step_pr12(mc_ctx* c, const mc_dgraph* g, int64_t lam, ui
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
     if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
     if (!pr12(to_dgraph(g), &w.sc->lam, w.parent, &w.sc->marks_pr, flag1, ptr2, w.prw, s)) return MC_E_DEVICE;
+    if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+    if ((r = sync_read(c, w)) != MC_OK) return r;
+    if (n2) *n2 = c->hsc->n2;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_step_pr34(mc_ctx* c, const mc_dgraph* g, int64_t lam, int32_t D, const int32_t* ptr2,
+                                  uint8_t* flag4, int32_t* acc3, int32_t* labels, int32_t* n2, void* ws, size_t bytes) {
+    if (!g || !ptr2) return fail(MC_E_INVALID_ARG, "mc_step_pr34: NULL graph or ptr2");
+    if (D < 0 || D > 64) return fail(MC_E_INVALID_ARG, "mc_step_pr34: D must be in [0, 64]");
+    StepWS w;
+    mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
+    if (r != MC_OK) return r;
+    hipStream_t s = c->stream;
+    k_set_lam<<<1, 1, 0, s>>>(w.sc, lam);
+    k_reset_round<<<1, 1, 0, s>>>(w.sc);
+    if (!uf_init(w.parent, g->n, s)) return MC_E_DEVICE;
+    if (!pr34(to_dgraph(g), &w.sc->lam, D, w.parent, &w.sc->marks_tri, ptr2, w.tw, flag4, acc3, s)) return MC_E_DEVICE;
     if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
     if ((r = sync_read(c, w)) != MC_OK) return r;
     if (n2) *n2 = c->hsc->n2;

@@ -525,3 +525,72 @@ def test_heuristic_solve_matches_oracle(ctx, fam, seed):
     assert st["heuristic_levels"] >= 1
     assert lam_ref <= st["lambda_heuristic"] <= st["lambda_min_degree"]
     c.close()
+
+
+# ------------------------------------------------- reduction tests 3 and 4
+def tri_graph(seed, n=2000):
+    """Clustered weighted graph: dense random blocks of 4..12 vertices joined
+    by light edges, so many short rows share neighbours (tests 3 and 4
+    fire), plus a few long rows."""
+    r = np.random.default_rng(seed)
+    u, v, w = [], [], []
+    start = 0
+    blocks = []
+    while start < n:
+        b = int(r.integers(4, 13))
+        b = min(b, n - start)
+        blocks.append((start, start + b))
+        for i in range(start, start + b):
+            for j in range(i + 1, start + b):
+                if r.random() < 0.7:
+                    u.append(i); v.append(j); w.append(int(r.integers(1, 20)))
+        start += b
+    for _ in range(n):
+        u.append(int(r.integers(0, n))); v.append(int(r.integers(0, n))); w.append(int(r.integers(1, 4)))
+    for i in range(n):   # a ring keeps it connected
+        u.append(i); v.append((i + 1) % n); w.append(3)
+    for h in range(3):
+        t = r.choice(n, size=200, replace=False)
+        u += [h] * 200; v += list(t); w += [1] * 200
+    return gen.from_edges(n, u, v, w, name="tri(seed=%d)" % seed)
+
+
+@pytest.mark.parametrize("seed,D", [(1, 16), (2, 8), (3, 64), (4, 24)])
+def test_pr34_matches_oracle(ctx, seed, D):
+    g = tri_graph(seed)
+    dev, dmin, _ = canon_dev(ctx, g)
+    for lam in (dmin, max(1, dmin // 2), 10 ** 9):
+        _, ptr = oracle.pr12(g, lam)
+        flag_t, acc, lab, n2 = ctx.step_pr34(dev, lam, D, ptr)
+        f4, part, acc_ref = oracle.pr34(g, lam, D, ptr)
+        # entries of the canonical device graph are the host graph's rows
+        # in some order: compare per (row, target)
+        off = dev.off[:g.n].cpu().numpy().astype(np.int64)
+        ln = dev.len[:g.n].cpu().numpy().astype(np.int64)
+        flag = flag_t.cpu().numpy()
+        col_dev = dev.col.cpu().numpy()
+        got = {(x, int(col_dev[j])) for x in range(g.n) for j in range(off[x], off[x] + ln[x]) if flag[j]}
+        want = {(x, int(g.col[j])) for x in range(g.n) for j in range(g.row_ptr[x], g.row_ptr[x + 1]) if f4[j]}
+        say("pr34", seed, D, lam, len(want), "test-4 entries", int((acc_ref >= 0).sum()), "matched")
+        assert got == want
+        assert np.array_equal(acc, acc_ref)
+        pairs = [(a, b) for a, b in want] + [(v, int(acc_ref[v])) for v in range(g.n) if acc_ref[v] >= 0]
+        a = np.array([p[0] for p in pairs], np.int32)
+        b = np.array([p[1] for p in pairs], np.int32)
+        lab_ref, nc = oracle.components(g.n, a, b)
+        assert n2 == nc and np.array_equal(lab, lab_ref)
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7])
+def test_solver_with_tests34_matches_oracle(ctx, seed):
+    import paper_2609_07204_amd as mc
+    g = tri_graph(seed, 6000)
+    lam_ref = oracle.noi(g)[0]
+    for D in (0, 16, 64):
+        c = mc.Context(0, pr_tri_deg_cap=D)
+        lam, side, st = c.mincut(g, return_stats=True)
+        say("solve tri", seed, D, lam_ref, "tests 3/4 marks", st["marks_tri"])
+        assert lam == lam_ref and oracle.cut_value(g, side) == lam
+        if D == 0:
+            assert st["marks_tri"] == 0
+        c.close()
