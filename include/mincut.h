@@ -139,6 +139,20 @@ mc_status mc_workspace_size(const mc_ctx* ctx, int32_t n, int32_t nnz, size_t* b
 mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws_bytes,
                     int64_t* lambda, uint8_t* side, mc_stats* st);
 
+/* Batched solves: k graphs (all in host memory or all in device memory,
+ * each n >= 2, together fewer than 2^30 vertices and 2^30 entries) solved
+ * in one call, with one set of launches per round of Algorithm 2 for all of
+ * them (the graphs are laid side by side as one union graph; each keeps its
+ * own bound, CAPFOREST pass and side). Results are those of mc_mincut:
+ * lambdas[i] (host, k values) is graph i's minimum cut; if sides != NULL and
+ * sides[i] != NULL, sides[i] (host, n_i bytes) receives one side of it with
+ * sides[i][0] = 0. per_graph (host, k values, may be NULL) receives MC_OK
+ * for every graph. The label-propagation heuristic is not run in this form
+ * (every graph starts from its minimum degree). Synchronises the stream. */
+mc_status mc_batch_workspace_size(const mc_ctx* ctx, int32_t k, const mc_csr* graphs, size_t* bytes);
+mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
+                          int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
+
 /* Kernel timing, for measurement. While profiling is on, every launch of
  * the kernels below made by mc_mincut on this context is bracketed by two
  * HIP events on the context's stream, and the algorithmic bytes of the

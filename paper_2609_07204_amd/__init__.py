@@ -75,6 +75,8 @@ SIGNATURES = {
     "mc_workspace_size": (ctypes.c_int, [P, I32, I32, P]),
     "mc_mincut": (ctypes.c_int, [P, P, P, SZ, P, P, P]),
     "mc_last_error": (ctypes.c_char_p, []),
+    "mc_batch_workspace_size": (ctypes.c_int, [P, I32, P, P]),
+    "mc_mincut_batch": (ctypes.c_int, [P, I32, P, P, SZ, P, P, P]),
     "mc_profile": (ctypes.c_int, [P, I32]),
     "mc_profile_read": (ctypes.c_int, [P, I32, P]),
     "mc_step_ws_size": (ctypes.c_int, [I32, I64, I32, P]),
@@ -202,6 +204,54 @@ class Context:
         if return_stats:
             return lam.value, side, st.as_dict()
         return lam.value, side
+
+    # ------------------------------------------------------------ batch
+    def _csr_array(self, graphs=None, devs=None):
+        """ctypes array of mc_csr for host graphs or device (rp, col, w)
+        tuples, and the objects that must stay alive while it is used."""
+        keep = []
+        if devs is not None:
+            arr = (CSR * len(devs))()
+            for i, (rp, col, w) in enumerate(devs):
+                nnz = int(col.numel())
+                arr[i] = CSR(int(rp.numel() - 1), nnz, rp.data_ptr(), col.data_ptr() if nnz else 0,
+                             w.data_ptr() if nnz else 0, MC_DEVICE)
+                keep.append((rp, col, w))
+        else:
+            arr = (CSR * len(graphs))()
+            for i, g in enumerate(graphs):
+                rp = np.ascontiguousarray(g.row_ptr, np.int32)
+                col = np.ascontiguousarray(g.col, np.int32)
+                w = np.ascontiguousarray(g.w, np.int64)
+                nnz = int(rp[-1])
+                arr[i] = CSR(int(g.n), nnz, rp.ctypes.data, col.ctypes.data if nnz else 0,
+                             w.ctypes.data if nnz else 0, MC_HOST)
+                keep.append((rp, col, w))
+        return arr, keep
+
+    def batch_workspace_bytes(self, graphs=None, devs=None):
+        arr, keep = self._csr_array(graphs, devs)
+        b = ctypes.c_size_t()
+        _check(lib().mc_batch_workspace_size(self.h, len(arr), arr, ctypes.byref(b)))
+        return b.value
+
+    def mincut_batch(self, graphs=None, devs=None, workspace=None, want_sides=True):
+        """Minimum cuts of many graphs in one call (mc_mincut_batch): host
+        graphs or device (rp, col, w) tuples. Returns (lambdas, sides)."""
+        torch = _torch()
+        arr, keep = self._csr_array(graphs, devs)
+        k = len(arr)
+        if workspace is None:
+            b = ctypes.c_size_t()
+            _check(lib().mc_batch_workspace_size(self.h, k, arr, ctypes.byref(b)))
+            workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        lams = np.zeros(k, np.int64)
+        sides = [np.zeros(arr[i].n, np.uint8) for i in range(k)] if want_sides else None
+        sp = (ctypes.c_void_p * k)(*[s.ctypes.data for s in sides]) if want_sides else None
+        _check(lib().mc_mincut_batch(self.h, k, arr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     lams.ctypes.data, sp, None))
+        del keep
+        return lams, sides
 
     # ------------------------------------------------------------ timing
     def profile(self, on=True):

@@ -122,28 +122,57 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
     __shared__ PassLds L;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / MC_WAVE;
     const int p = blockIdx.x;
-    const int32_t n = a.g.n;
+    // the pass's vertices are [base, base + n); st and r are indexed by
+    // vertex id, the per-pass lists and the index by position in the range
+    int32_t base = 0, n = a.g.n;
+    int32_t *st, *fifo, *tl, *order, *dlist;
+    int64_t *r, *l1;
+    uint32_t* dbits;
+    if (a.pvoff) {
+        base = a.pvoff[p];
+        n = a.pvoff[p + 1] - base;
+        if (n < 3 || (a.prun && !a.prun[p])) {
+            if (tid == 0) {
+                a.nscan[p] = 0;
+                a.alpha[p] = INT64_MAX;
+                a.alpha_len[p] = 0;
+                a.lam_out[p] = a.plam[p];
+                if (a.steps) a.steps[p] = 0;
+                if (a.pmarks) a.pmarks[p] = 0;
+            }
+            return;
+        }
+        st = a.st;
+        r = a.r;
+        fifo = a.fifo + base;
+        tl = a.touched + base;
+        order = a.order + base;
+        l1 = a.l1 + (base >> 6) + p;
+        dlist = a.dlist + (base >> 6) + p;
+        dbits = a.dbits + (base >> 11) + 2 * p;
+    } else {
+        st = a.st + (int64_t)p * a.stride;
+        r = a.r + (int64_t)p * a.stride;
+        fifo = a.fifo + (int64_t)p * a.stride;
+        tl = a.touched + (int64_t)p * a.stride;
+        order = a.order + (int64_t)p * a.stride;
+        l1 = a.l1 + (int64_t)p * a.stride1;
+        dlist = a.dlist + (int64_t)p * a.stride1;
+        dbits = a.dbits + (int64_t)p * (a.stride1 / 32 + 1);
+    }
     const int32_t nb1 = (n + 63) / 64;
     const int32_t nb2 = (nb1 + 63) / 64;
-    int32_t* st = a.st + (int64_t)p * a.stride;
-    int64_t* r = a.r + (int64_t)p * a.stride;
-    int32_t* fifo = a.fifo + (int64_t)p * a.stride;
-    int32_t* tl = a.touched + (int64_t)p * a.stride;
-    int32_t* order = a.order + (int64_t)p * a.stride;
-    int64_t* l1 = a.l1 + (int64_t)p * a.stride1;
-    int32_t* dlist = a.dlist + (int64_t)p * a.stride1;
-    uint32_t* dbits = a.dbits + (int64_t)p * (a.stride1 / 32 + 1);
 
     for (int32_t b = tid; b < nb1; b += PT) l1[b] = -1;
     for (int32_t b = tid; b <= nb1 / 32; b += PT) dbits[b] = 0;
     for (int32_t g = tid; g < nb2; g += PT) l2[g] = -1;
     for (int32_t g = tid; g < L2_MAX / 32; g += PT) L.l2dirty[g] = 0;
-    int64_t lam = *a.lam;
+    int64_t lam = a.plam ? a.plam[p] : *a.lam;
     if (tid == 0) {
         int32_t s = a.start;
         if (s < 0) {
             uint64_t h = splitmix64(a.seed ^ splitmix64(((uint64_t)(uint32_t)a.round << 32) | (uint32_t)p));
-            s = (int32_t)(((h >> 32) * (uint64_t)n) >> 32);
+            s = base + (int32_t)(((h >> 32) * (uint64_t)n) >> 32);
         }
         st[s] = S_QUEUED;
         tl[0] = s;
@@ -185,11 +214,11 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
             const int32_t dn = L.dn;
             for (int32_t i = wid; i < dn; i += PW) {
                 const int32_t b = dlist[i];
-                const int32_t v = b * 64 + lane;
+                const int32_t lv = b * 64 + lane;
                 // every queued vertex counts: one whose r reached a lowered
                 // bound has the largest key and must stay findable
                 int64_t val = -1;
-                if (v < n && ld32(&st[v]) == S_QUEUED) val = ld64(&r[v]);
+                if (lv < n && ld32(&st[base + lv]) == S_QUEUED) val = ld64(&r[base + lv]);
                 for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(val, o, MC_WAVE); val = t > val ? t : val; }
                 if (lane == 0) {
                     __hip_atomic_store(&l1[b], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -228,8 +257,8 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                 int32_t x = -1;
                 int64_t rx = -1;
                 if (bb >= 0) {
-                    const int32_t v = bb * 64 + lane;
-                    if (v < n && ld32(&st[v]) == S_QUEUED) { rx = ld64(&r[v]); x = v; }
+                    const int32_t lv = bb * 64 + lane;
+                    if (lv < n && ld32(&st[base + lv]) == S_QUEUED) { rx = ld64(&r[base + lv]); x = base + lv; }
                 }
                 wave_argmax(rx, x, aux);
                 if (lane == 0) L.single_x = x;
@@ -266,7 +295,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                     dl = a.g.len[x];
                     part = a.g.deg[x] - 2 * ld64(&r[x]);
                     order[nscan + opos] = x;
-                    mark_dirty(dbits, dlist, x >> 6, L);
+                    mark_dirty(dbits, dlist, (x - base) >> 6, L);
                 }
             }
             int32_t E;
@@ -295,10 +324,10 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                 if (old < lam && lam <= nw) {
                     if (uf_union(a.parent, xs, y)) marks++;
                     fifo[atomicAdd(&L.tail, 1)] = y;
-                    mark_dirty(dbits, dlist, y >> 6, L);
+                    mark_dirty(dbits, dlist, (y - base) >> 6, L);
                 } else if (nw < lam) {
-                    atomicMax((long long*)&l1[y >> 6], (long long)nw);
-                    atomicMax(&l2[y >> 12], (long long)nw);
+                    atomicMax((long long*)&l1[(y - base) >> 6], (long long)nw);
+                    atomicMax(&l2[(y - base) >> 12], (long long)nw);
                 }
             }
             const int64_t I = block_sum(intra, L);
@@ -330,6 +359,14 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
     }
     marks = (unsigned long long)wave_sum_i64((int64_t)marks);
     if (lane == 0 && marks) atomicAdd(a.marks, marks);
+    if (a.pmarks) {
+        __shared__ unsigned long long s_marks;
+        if (tid == 0) s_marks = 0;
+        __syncthreads();
+        if (lane == 0 && marks) atomicAdd(&s_marks, marks);
+        __syncthreads();
+        if (tid == 0) a.pmarks[p] = s_marks;
+    }
     if (tid == 0) {
         a.nscan[p] = nscan;
         a.alpha[p] = best_alpha;
@@ -348,8 +385,19 @@ __global__ void k_private_reset(int32_t* st, int64_t* r, int64_t count) {
 
 }  // namespace
 
-bool capforest_private(const PrivateArgs& a, hipStream_t s) {
+bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) {
     if (a.passes <= 0) return true;
+    if (a.pvoff) {
+        // instance mode: the index of the largest range sets the LDS size
+        const int32_t nb2 = ((max_pass_n + 63) / 64 + 63) / 64;
+        if (nb2 > L2_MAX) {
+            mc_hip_ok(hipErrorInvalidValue, "capforest_private: instance too large for the pass index");
+            return false;
+        }
+        k_capforest_private<<<a.passes, PT, (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long), s>>>(a);
+        MC_LAUNCHED("k_capforest_private");
+        return true;
+    }
     if (a.g.n > a.stride) {
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: per-pass stride smaller than n");
         return false;

@@ -144,10 +144,10 @@ constexpr int32_t PR_CHUNK = 4096;
 
 // Algorithmic bytes (profiling): 12 B per entry (col, w) and 16 B per row
 // (off, len, deg) of the rows this kernel tests.
-__global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int32_t* par,
+__global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                              unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
                                              int32_t* long_list, int32_t* long_cnt, unsigned long long* pb) {
-    const int64_t lam = *lamp;
+    const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, int
             continue;
         }
         if (sl == 0) bytes += 16 + 12 * (int64_t)l;
+        const int64_t lam = vinst ? lamp[vinst[v]] : lam0;   // bound of v's instance
         int64_t bw = -1;
         int32_t bx = -1;
         for (int32_t j = sl; j < l; j += SUB) {
@@ -231,13 +232,13 @@ __device__ __forceinline__ int32_t last_le_g(const int32_t* a, int32_t n, int64_
 
 // one workgroup per PR_CHUNK-entry piece of a long row: test 1 unions and
 // the piece's heaviest entry
-__global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp, int32_t* par,
+__global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                                   unsigned long long* marks, uint8_t* flag1,
                                                   const int32_t* long_list, const int32_t* long_cnt,
                                                   const int32_t* task_off, int64_t* part_w, int32_t* part_x) {
     __shared__ int64_t sw[4];
     __shared__ int32_t sx[4];
-    const int64_t lam = *lamp;
+    const int64_t lam0 = *lamp;
     const int32_t nl = *long_cnt;
     const int32_t ntask = task_off[nl];
     unsigned long long joined = 0;
@@ -245,6 +246,7 @@ __global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp
         const int32_t i = last_le_g(task_off, nl, t);
         const int32_t v = long_list[i];
         const int32_t o = g.off[v], l = g.len[v];
+        const int64_t lam = vinst ? lamp[vinst[v]] : lam0;
         const int32_t j0 = (t - task_off[i]) * PR_CHUNK;
         const int32_t j1 = j0 + PR_CHUNK < l ? j0 + PR_CHUNK : l;
         int64_t bw = -1;
@@ -320,11 +322,12 @@ constexpr int TRI_MAXD = 64;
 constexpr int TRI_SLOTS = 2 * TRI_MAXD;
 constexpr int32_t TRI_NONE = INT32_MAX;
 
-__global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, int32_t D, int32_t* par,
-                                               unsigned long long* marks, int32_t* part3, uint8_t* flag4) {
+__global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t D,
+                                               int32_t* par, unsigned long long* marks, int32_t* part3,
+                                               uint8_t* flag4) {
     __shared__ int32_t hk[TRI_T / TRI_SUB][TRI_SLOTS];
     __shared__ int64_t hv[TRI_T / TRI_SUB][TRI_SLOTS];
-    const int64_t lam = *lamp;
+    const int64_t lam0 = *lamp;
     const int grp = threadIdx.x / TRI_SUB, sl = threadIdx.x % TRI_SUB;
     int32_t* K = hk[grp];
     int64_t* W = hv[grp];
@@ -347,6 +350,7 @@ __global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, i
         }
         __syncwarp();
         const int64_t cv = live ? g.deg[v] : 0;
+        const int64_t lam = live && vinst ? lamp[vinst[v]] : lam0;   // bound of v's instance
         for (int32_t j = 0; j < l; j++) {
             const int32_t x = g.col[o + j];
             if (x <= v || g.len[x] > D) continue;          // uniform over the group
@@ -592,11 +596,11 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
 }
 
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
-          int32_t* ptr2, Pr12WS& w, hipStream_t s) {
+          int32_t* ptr2, Pr12WS& w, hipStream_t s, const int32_t* vinst) {
     if (!fill_i32(w.counters, 0, 4, s)) return false;
     if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s)) return false;
     prof_begin(PK_PR12, s);
-    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, parent, w.spread, flag1, ptr2, w.long_list,
+    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.spread, flag1, ptr2, w.long_list,
                                                             w.counters, prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
@@ -604,7 +608,7 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
     MC_LAUNCHED("k_pr12_fold");
     k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);
     MC_LAUNCHED("k_pr12_long_scan");
-    k_pr12_long<<<2048, 256, 0, s>>>(g, lam, parent, marks, flag1, w.long_list, w.counters, w.task_off, w.part_w,
+    k_pr12_long<<<2048, 256, 0, s>>>(g, lam, vinst, parent, marks, flag1, w.long_list, w.counters, w.task_off, w.part_w,
                                      w.part_x);
     MC_LAUNCHED("k_pr12_long");
     k_pr12_long_final<<<256, 64, 0, s>>>(g, parent, marks, ptr2, w.long_list, w.counters, w.task_off, w.part_w,
@@ -614,7 +618,7 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
 }
 
 bool pr34(const DGraph& g, const int64_t* lam, int32_t D, int32_t* parent, unsigned long long* marks,
-          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s) {
+          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s, const int32_t* vinst) {
     if (D > TRI_MAXD) D = TRI_MAXD;
     if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s) || !fill_i32(w.part3, TRI_NONE, g.n, s) ||
         !fill_u8(w.touch, 0, g.n, s))
@@ -622,7 +626,7 @@ bool pr34(const DGraph& g, const int64_t* lam, int32_t D, int32_t* parent, unsig
     if (flag4 && !fill_u8(flag4, 0, g.cap, s)) return false;
     k_pr2_touch<<<grid_for(g.n, 256), 256, 0, s>>>(ptr2, g.n, w.touch);
     MC_LAUNCHED("k_pr2_touch");
-    k_pr34<<<grid_for((int64_t)g.n * TRI_SUB, TRI_T), TRI_T, 0, s>>>(g, lam, D, parent, w.spread, w.part3, flag4);
+    k_pr34<<<grid_for((int64_t)g.n * TRI_SUB, TRI_T), TRI_T, 0, s>>>(g, lam, vinst, D, parent, w.spread, w.part3, flag4);
     MC_LAUNCHED("k_pr34");
     k_pr3_accept<<<grid_for(g.n, 256), 256, 0, s>>>(w.part3, w.touch, g.n, parent, w.spread, acc3);
     MC_LAUNCHED("k_pr3_accept");

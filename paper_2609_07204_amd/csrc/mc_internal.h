@@ -126,8 +126,10 @@ struct Pr12WS {
     unsigned long long* spread;   // [SPREAD * SPREAD_STRIDE] partial mark counts
 };
 void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
+// With vinst (per-vertex instance) the bound of vertex v is lam[vinst[v]]
+// (batched solves of many graphs in one union graph); else lam[0].
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks,
-          uint8_t* flag1, int32_t* ptr2, Pr12WS& w, hipStream_t s);
+          uint8_t* flag1, int32_t* ptr2, Pr12WS& w, hipStream_t s, const int32_t* vinst = nullptr);
 
 // Padberg-Rinaldi tests 3 and 4 on the edges whose rows both have at most
 // D (<= 64) entries; test-4 edges and the accepted test-3 matching (mutual
@@ -141,7 +143,8 @@ struct Pr34WS {
 };
 void pr34_ws_carve(Arena& a, int32_t n, Pr34WS& w);
 bool pr34(const DGraph& g, const int64_t* lam, int32_t D, int32_t* parent, unsigned long long* marks,
-          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s);
+          const int32_t* ptr2, Pr34WS& w, uint8_t* flag4, int32_t* acc3, hipStream_t s,
+          const int32_t* vinst = nullptr);
 
 // ---------------------------------------------------- label propagation
 // Scratch of lp_round besides the contraction scratch it borrows (row
@@ -242,9 +245,20 @@ struct PrivateArgs {
     unsigned long long* marks;
     int32_t* steps;         // [passes] batches + single pops (diagnostics)
     int64_t* diag;          // [passes*8] optional counters (nullptr: off)
+    // Instance mode (batched solves, k_capforest_private only): pass p runs
+    // on the vertex range [pvoff[p], pvoff[p+1]) of a union graph whose
+    // ranges share no edge. st and r are then indexed by vertex id (one
+    // array for all passes); fifo, touched and order start at pvoff[p]; l1
+    // and dlist at pvoff[p]/64 + p; dbits at pvoff[p]/2048 + 2p. The bound
+    // of pass p is plam[p]; passes with prun[p] = 0 or fewer than 3 vertices
+    // do nothing (nscan 0, alpha INT64_MAX). pmarks[p] counts its marks.
+    const int32_t* pvoff = nullptr;
+    const int64_t* plam = nullptr;
+    const uint8_t* prun = nullptr;
+    unsigned long long* pmarks = nullptr;
 };
 constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
-bool capforest_private(const PrivateArgs& a, hipStream_t s);
+bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n = 0);
 // clear st/r of a fresh workspace region (once per solve)
 bool capforest_private_reset(const PrivateArgs& a, hipStream_t s);
 
@@ -316,3 +330,16 @@ bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, 
                   DevScalars* sc, unsigned long long* part, hipStream_t s);
 
 std::string& mc_error_slot();
+// Sets the thread-local error message and returns code.
+mc_status mc_fail(mc_status code, const std::string& msg);
+
+// The library context (opaque to callers).
+struct mc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mc_options opt{};
+    int cus = 256;
+    DevScalars* hsc = nullptr;   // pinned readback slot
+    int32_t tag = 0;             // round tag for visited arrays (never reset)
+    void* prof = nullptr;        // kernel timing (mc_profile), owned by the solver file
+};

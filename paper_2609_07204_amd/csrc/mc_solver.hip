@@ -63,6 +63,8 @@ mc_status fail(mc_status code, const std::string& msg) {
 
 }  // namespace
 
+mc_status mc_fail(mc_status code, const std::string& msg) { return fail(code, msg); }
+
 std::string& mc_error_slot() { return g_err; }
 
 bool mc_hip_ok(hipError_t e, const char* what) {
@@ -160,15 +162,6 @@ void prof_host_bytes(int k, double bytes) {
     if (g_prof) g_prof->hbytes[k] += bytes;
 }
 
-struct mc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    mc_options opt{};
-    int cus = 256;
-    DevScalars* hsc = nullptr;   // pinned readback slot
-    int32_t tag = 0;             // round tag for visited arrays (never reset)
-    Prof* prof = nullptr;        // kernel timing, allocated by mc_profile
-};
 
 extern "C" void mc_default_options(mc_options* o) {
     std::memset(o, 0, sizeof(*o));
@@ -210,7 +203,7 @@ extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_option
 extern "C" mc_status mc_ctx_destroy(mc_ctx* c) {
     if (!c) return MC_OK;
     if (c->hsc) (void)hipHostFree(c->hsc);
-    delete c->prof;
+    delete static_cast<Prof*>(c->prof);
     delete c;
     return MC_OK;
 }
@@ -219,19 +212,19 @@ extern "C" mc_status mc_profile(mc_ctx* c, int32_t on) {
     if (!c) return fail(MC_E_INVALID_ARG, "mc_profile: ctx is NULL");
     if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
     if (!on) {
-        if (c->prof) c->prof->on = false;
+        if (c->prof) static_cast<Prof*>(c->prof)->on = false;
         return MC_OK;
     }
     if (!c->prof) {
-        c->prof = new (std::nothrow) Prof();
-        if (!c->prof) return fail(MC_E_OOM, "mc_profile: out of host memory");
-        if (hipMalloc((void**)&c->prof->dbytes, kProfCounterBytes) != hipSuccess) {
-            delete c->prof;
-            c->prof = nullptr;
+        Prof* np = new (std::nothrow) Prof();
+        if (!np) return fail(MC_E_OOM, "mc_profile: out of host memory");
+        if (hipMalloc((void**)&np->dbytes, kProfCounterBytes) != hipSuccess) {
+            delete np;
             return fail(MC_E_DEVICE, "mc_profile: hipMalloc of the byte counters failed");
         }
+        c->prof = np;
     }
-    Prof* p = c->prof;
+    Prof* p = static_cast<Prof*>(c->prof);
     if (hipMemsetAsync(p->dbytes, 0, kProfCounterBytes, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(MC_E_DEVICE, "mc_profile: clearing the byte counters failed");
@@ -253,7 +246,7 @@ extern "C" mc_status mc_profile_read(mc_ctx* c, int32_t kernel, mc_kernel_time* 
     std::memset(out, 0, sizeof(*out));
     std::snprintf(out->name, sizeof(out->name), "%s", kProfNames[kernel]);
     if (!c->prof) return MC_OK;
-    Prof* p = c->prof;
+    Prof* p = static_cast<Prof*>(c->prof);
     std::vector<unsigned long long> db(kProfCounterBytes / sizeof(unsigned long long));
     if (hipSetDevice(c->device) != hipSuccess ||
         hipMemcpy(db.data(), p->dbytes, kProfCounterBytes, hipMemcpyDeviceToHost) != hipSuccess)
@@ -823,7 +816,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     }
     if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
 
-    ProfScope prof_scope(c->prof);
+    ProfScope prof_scope(static_cast<Prof*>(c->prof));
     Solver S;
     S.c = c;
     S.s = c->stream;

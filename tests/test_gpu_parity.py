@@ -594,3 +594,85 @@ def test_solver_with_tests34_matches_oracle(ctx, seed):
         if D == 0:
             assert st["marks_tri"] == 0
         c.close()
+
+
+# ------------------------------------------------------------ batched form
+def batch_mix(seed, count, nmax=3000):
+    r = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        kind = i % 7
+        if kind == 0:
+            gs.append(gen.random_small(int(r.integers(2, 16)), 0.5, seed * 1000 + i, 0, 9))
+        elif kind == 1:
+            gs.append(gen.complete(int(r.integers(2, 9))))
+        elif kind == 2:
+            n = int(r.integers(3, 30))
+            gs.append(gen.cycle([int(x) for x in r.integers(1, 9, n)]))
+        elif kind == 3:
+            a, b = gen.complete(int(r.integers(2, 6))), gen.cycle([1, 2, 3])
+            gs.append(gen.disjoint_union(a, b))            # disconnected: lambda 0
+        elif kind == 4:
+            n = int(r.integers(50, nmax))
+            gs.append(gen.mixed_graph(n, int(r.integers(6, 20)), int(r.integers(0, 3)), seed * 1000 + i, 1, 100))
+        elif kind == 5:
+            n = int(r.integers(10, 200))
+            m = 4 * n
+            u = r.integers(0, n, m); v = r.integers(0, n, m); w = r.integers(0, 5, m)
+            u = np.concatenate([u, np.arange(n)]); v = np.concatenate([v, (np.arange(n) + 1) % n])
+            w = np.concatenate([w, np.ones(n, np.int64)])
+            gs.append(gen.raw_csr(n, u, v, w))          # loops, parallel entries, zero weights
+        else:
+            gs.append(gen.wheel(int(r.integers(4, 40))))
+    return gs
+
+
+def oracle_lambda(g):
+    return oracle.stoer_wagner(g)[0] if g.n <= 400 else oracle.noi(g)[0]
+
+
+@pytest.mark.parametrize("seed,count", [(1, 40), (2, 200), (3, 700)])
+def test_batch_matches_oracle(ctx, seed, count):
+    gs = batch_mix(seed, count)
+    lams, sides = ctx.mincut_batch(gs)
+    bad = []
+    for i, g in enumerate(gs):
+        ref = oracle_lambda(g)
+        if lams[i] != ref or oracle.cut_value(g, sides[i]) != ref or sides[i][0] != 0:
+            bad.append((i, g.name, int(lams[i]), int(ref)))
+    say("batch", seed, count, "graphs,", sum(g.nnz for g in gs), "entries; mismatches", bad[:5])
+    assert not bad
+
+
+def test_batch_device_input_same_as_host(ctx):
+    gs = batch_mix(9, 120)
+    devs = [ctx.upload(g) for g in gs]
+    lam_h, _ = ctx.mincut_batch(gs, want_sides=False)
+    lam_d, sides = ctx.mincut_batch(devs=devs)
+    assert np.array_equal(lam_h, lam_d)
+    for i, g in enumerate(gs):
+        assert oracle.cut_value(g, sides[i]) == lam_d[i]
+
+
+def test_batch_same_as_alone(ctx):
+    # each result in the batch equals the graph's result alone
+    gs = [gen.config_batch_graph(i) for i in range(0, 64)]
+    lams, sides = ctx.mincut_batch(gs)
+    for i, g in enumerate(gs):
+        lam1, _ = ctx.mincut(g, want_side=False)
+        assert lams[i] == lam1
+        assert oracle.cut_value(g, sides[i]) == lam1
+
+
+def test_batch_rejects_bad_graphs(ctx):
+    import paper_2609_07204_amd as mc
+    g = gen.complete(5)
+    bad = gen.Graph(5, g.row_ptr.copy(), g.col.copy(), g.w.copy())
+    bad.col[3] = 9
+    with pytest.raises(mc.MincutError) as e:
+        ctx.mincut_batch([g, bad])
+    assert e.value.code == -2
+    devs = [ctx.upload(g), ctx.upload(bad)]
+    with pytest.raises(mc.MincutError) as e:
+        ctx.mincut_batch(devs=devs)
+    assert e.value.code == -2
