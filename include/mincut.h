@@ -153,6 +153,46 @@ mc_status mc_batch_workspace_size(const mc_ctx* ctx, int32_t k, const mc_csr* gr
 mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
                           int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
 
+/* Served form: a request loop with continuous batching. The server holds
+ * one device allocation of hbm_bytes (made at create) for the graphs in
+ * flight. mc_server_submit copies a host graph into a queue. Each
+ * mc_server_step admits queued requests in arrival order while they fit
+ * (graphs in flight <= max_inflight, vertices and entries within what the
+ * budget holds), runs one round of Algorithm 2 for every graph in flight
+ * (admitted graphs join graphs already half way through their rounds, in
+ * the same launches), and collects finished graphs. A graph's result does
+ * not depend on the others in flight. Calls on one server must not overlap
+ * (one thread at a time). */
+typedef struct {
+    size_t hbm_bytes;          /* device memory of the server (>= 64 MiB) */
+    int32_t max_inflight;      /* graphs in the rounds at once (0: 1024) */
+    int32_t max_request_n;     /* largest request, vertices (0: 2^20) */
+    int64_t max_request_nnz;   /* largest request, entries (0: 2^25) */
+} mc_server_opts;
+typedef struct {
+    double t_submit_ms, t_admit_ms, t_done_ms;   /* since the server was created */
+    int32_t rounds;                              /* rounds the graph took part in */
+} mc_req_stats;
+typedef struct mc_server mc_server;
+mc_status mc_server_create(mc_ctx* ctx, const mc_server_opts* opts, mc_server** out);
+mc_status mc_server_destroy(mc_server* srv);
+/* Queue a copy of host graph g; *ticket identifies it. MC_E_OOM when the
+ * graph alone exceeds what the server can ever admit. */
+mc_status mc_server_submit(mc_server* srv, const mc_csr* g, uint64_t* ticket);
+/* Admit, run one round, collect. *in_flight / *queued (may be NULL): graphs
+ * in the rounds and waiting after the step. Synchronises the stream. */
+mc_status mc_server_step(mc_server* srv, int32_t* in_flight, int32_t* queued);
+/* MC_OK with lambda, side (host, n bytes, side[0] = 0; may be NULL) and
+ * timing once done (the ticket is then released); MC_E_NOT_READY before;
+ * MC_E_CANCELLED for a cancelled request (released). */
+mc_status mc_server_poll(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_req_stats* st);
+/* Cancel a request: a queued one is never admitted, one in flight is
+ * dropped when its rounds end. */
+mc_status mc_server_cancel(mc_server* srv, uint64_t ticket);
+/* Capacity the budget gives (entries, vertices, graphs in flight, bytes). */
+mc_status mc_server_capacity(const mc_server* srv, int64_t* entries, int32_t* vertices, int32_t* graphs,
+                             size_t* bytes);
+
 /* Kernel timing, for measurement. While profiling is on, every launch of
  * the kernels below made by mc_mincut on this context is bracketed by two
  * HIP events on the context's stream, and the algorithmic bytes of the

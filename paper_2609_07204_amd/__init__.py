@@ -60,6 +60,19 @@ class KernelTime(ctypes.Structure):
 MC_K_COUNT = 7  # kernels mc_profile times (MC_K_* in include/mincut.h)
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_request_n", ctypes.c_int32),
+                ("max_request_nnz", ctypes.c_int64)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("rounds", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class DGraphC(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("cap", ctypes.c_int64), ("off", ctypes.c_void_p), ("len", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("deg", ctypes.c_void_p)]
@@ -77,6 +90,13 @@ SIGNATURES = {
     "mc_last_error": (ctypes.c_char_p, []),
     "mc_batch_workspace_size": (ctypes.c_int, [P, I32, P, P]),
     "mc_mincut_batch": (ctypes.c_int, [P, I32, P, P, SZ, P, P, P]),
+    "mc_server_create": (ctypes.c_int, [P, P, P]),
+    "mc_server_destroy": (ctypes.c_int, [P]),
+    "mc_server_submit": (ctypes.c_int, [P, P, P]),
+    "mc_server_step": (ctypes.c_int, [P, P, P]),
+    "mc_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, P, P]),
+    "mc_server_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
+    "mc_server_capacity": (ctypes.c_int, [P, P, P, P, P]),
     "mc_profile": (ctypes.c_int, [P, I32]),
     "mc_profile_read": (ctypes.c_int, [P, I32, P]),
     "mc_step_ws_size": (ctypes.c_int, [I32, I64, I32, P]),
@@ -357,6 +377,65 @@ class Context:
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return {"labels": lab.cpu().numpy(), "n2": n2.value, "order": order[:ns.value].cpu().numpy(),
                 "best_alpha": ba.value, "best_len": bl.value, "lam": lo.value}
+
+
+class Server:
+    """Continuous-batching request server (mc_server_*) on a context."""
+
+    def __init__(self, ctx, hbm_bytes, max_inflight=0, max_request_n=0, max_request_nnz=0):
+        self.ctx = ctx
+        self.opts = ServerOpts(hbm_bytes, max_inflight, max_request_n, max_request_nnz)
+        h = ctypes.c_void_p()
+        _check(lib().mc_server_create(ctx.h, ctypes.byref(self.opts), ctypes.byref(h)))
+        self.h = h
+        self.n = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def capacity(self):
+        e, v, k, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().mc_server_capacity(self.h, ctypes.byref(e), ctypes.byref(v), ctypes.byref(k), ctypes.byref(b)))
+        return {"entries": e.value, "vertices": v.value, "graphs": k.value, "bytes": b.value}
+
+    def submit(self, g):
+        rp = np.ascontiguousarray(g.row_ptr, np.int32)
+        col = np.ascontiguousarray(g.col, np.int32)
+        w = np.ascontiguousarray(g.w, np.int64)
+        nnz = int(rp[-1])
+        csr = CSR(int(g.n), nnz, rp.ctypes.data, col.ctypes.data if nnz else 0, w.ctypes.data if nnz else 0, MC_HOST)
+        t = ctypes.c_uint64()
+        _check(lib().mc_server_submit(self.h, ctypes.byref(csr), ctypes.byref(t)))
+        self.n[t.value] = int(g.n)
+        return t.value
+
+    def step(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mc_server_step(self.h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, ticket):
+        """None while running, else (lambda, side, stats dict)."""
+        lam = ctypes.c_int64()
+        side = np.zeros(self.n[ticket], np.uint8)
+        st = ReqStats()
+        rc = lib().mc_server_poll(self.h, ticket, ctypes.byref(lam), side.ctypes.data, ctypes.byref(st))
+        if rc == -6:
+            return None
+        _check(rc)
+        del self.n[ticket]
+        return lam.value, side, st.as_dict()
+
+    def cancel(self, ticket):
+        _check(lib().mc_server_cancel(self.h, ticket))
 
 
 class DeviceGraph:

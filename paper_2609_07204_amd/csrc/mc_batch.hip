@@ -126,33 +126,6 @@ __global__ void k_bg_offsets(const int32_t* scan, const int32_t* voff, int32_t k
         voff2[i] = scan[voff[i]];
 }
 
-// start of the rounds: bound = minimum degree (snapshot of its vertex);
-// graphs in more than one component have lambda = 0
-__global__ void k_bg_start(const int32_t* voff, const int32_t* voff2, int32_t k, const int64_t* dmin, int64_t* lam,
-                           uint8_t* done, uint8_t* snap) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        const int32_t ni = voff[i + 1] - voff[i];
-        if (voff2[i + 1] - voff2[i] > 1) {
-            lam[i] = 0;
-            done[i] = 1;
-            snap[i] = 3;
-        } else {
-            lam[i] = dmin[i];
-            done[i] = ni <= 2;
-            snap[i] = 1;
-        }
-    }
-}
-
-// side of the graphs with snap = 3: outside the component of their first vertex
-__global__ void k_bg_side_comp(uint8_t* side, const int32_t* parent, const int32_t* inst0, const int32_t* ioff,
-                               const uint8_t* snap, int32_t N0) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N0; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = inst0[v];
-        if (snap[i] == 3) side[v] = parent[v] != parent[ioff[i]];
-    }
-}
-
 // CAPFOREST results: a smaller alpha (a cut of its scanned prefix) lowers
 // the graph's bound; the prefix becomes the side (snap = 2)
 __global__ void k_bg_alpha(const int64_t* alpha, const uint8_t* done, int32_t k, int64_t* lam, uint8_t* snap) {
@@ -178,10 +151,12 @@ __global__ void k_bg_prefix(const int32_t* order, const int32_t* voff, const int
 __global__ void k_bg_side(uint8_t* side, const int32_t* map0, const int32_t* inst0, int32_t N0, const uint8_t* snap,
                           const int32_t* darg, const uint8_t* inpref) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N0; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t m = map0[v];
+        if (m < 0) continue;                      // input vertex no longer tracked
         const int32_t i = inst0[v];
         const uint8_t s = snap[i];
-        if (s == 1) side[v] = map0[v] == darg[i];
-        else if (s == 2) side[v] = inpref[map0[v]];
+        if (s == 1) side[v] = m == darg[i];
+        else if (s == 2) side[v] = inpref[m];
     }
 }
 
@@ -220,25 +195,107 @@ __global__ void k_bg_bound(const int32_t* voff2, const int64_t* dmin, int32_t k,
             lam[i] = dmin[i];
             snap[i] = 1;
         }
-        if (ni <= 2) done[i] = 1;
+        if (ni <= 2 || lam[i] == 0) done[i] = 1;   // nothing lower than 0
         else c++;
     }
     c = wave_sum_i32(c);
     if (lane_id() == 0 && c) atomicAdd(cnt, c);
 }
 
-struct BatchWS {
+// ----------------------------------------------------------- the engine
+// Labels of a round with dropped graphs: roots of live graphs are numbered
+// in vertex order; every vertex of a graph marked dead gets -1, so the
+// contraction removes it.
+__global__ void k_root_flag_live(const int32_t* par, const int32_t* vinst, const uint8_t* dead, int32_t n,
+                                 int32_t* flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = par[v] == v && !dead[vinst[v]];
+}
+
+__global__ void k_label_live(const int32_t* par, const int32_t* newid, const int32_t* vinst, const uint8_t* dead,
+                             int32_t n, int32_t* L, DevScalars* sc) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        L[v] = dead[vinst[v]] ? -1 : newid[par[v]];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->n2 = newid[n];
+}
+
+// Append the staged (normal-form) graphs S behind the current graph: vertex
+// v of S becomes vbase + v, its row moves behind the current graph's last
+// window (ebase).
+__global__ void k_eg_append(DGraph S, int64_t s_entries, DGraph cur, int32_t vbase, int64_t ebase) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < S.n; v += nth) {
+        cur.off[vbase + v] = (int32_t)(S.off[v] + ebase);
+        cur.len[vbase + v] = S.len[v];
+        cur.deg[vbase + v] = S.deg[v];
+    }
+    for (int64_t e = tid; e < s_entries; e += nth) {
+        cur.col[ebase + e] = S.col[e] + vbase;
+        cur.w[ebase + e] = S.w[e];
+    }
+}
+
+// input vertices of newly admitted graphs: map to their current vertex
+__global__ void k_eg_admit_map(int32_t* map0, uint8_t* side, int32_t n0base, int32_t vbase, int32_t count) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count; v += (int64_t)gridDim.x * blockDim.x) {
+        map0[n0base + v] = vbase + (int32_t)v;
+        side[n0base + v] = 0;
+    }
+}
+
+// move the input-vertex ranges of the graphs still tracked to the front:
+// position q of the new layout belongs to graph j (new offsets nio), whose
+// old range started at oio[j]
+__global__ void k_eg_n0_compact(const int32_t* nio, const int32_t* oio, int32_t k, int32_t used, const int32_t* map0,
+                                const uint8_t* side, int32_t* map0b, uint8_t* sideb) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < used; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = seg_of(nio, k, q);
+        const int64_t old = oio[j] + (q - nio[j]);
+        map0b[q] = map0[old];
+        sideb[q] = side[old];
+    }
+}
+
+__global__ void k_eg_untrack(int32_t* map0, int32_t from, int32_t count) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count; v += (int64_t)gridDim.x * blockDim.x)
+        map0[from + v] = -1;
+}
+
+// first-round bound of newly admitted graphs: minimum degree, side = its vertex
+__global__ void k_eg_start(const int64_t* dmin, const int32_t* darg, int32_t k, int64_t* lam, uint8_t* snap) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        lam[i] = dmin[i];
+        snap[i] = 1;
+    }
+}
+
+struct Caps {
+    int32_t N = 0;        // vertices of the union graph
+    int64_t C = 0;        // entry capacity of the union graph
+    int32_t N0 = 0;       // input vertices tracked at once (sides)
+    int32_t K = 0;        // graphs in the rounds at once
+    int32_t Ns = 0;       // vertices staged by one admission
+    int64_t Cs = 0;       // entries staged by one admission
+    int32_t nmax = 0;     // largest graph (vertices)
+};
+
+struct EngineWS {
     DevScalars* sc;
-    int32_t* cnt;                  // [4] counters read by the host
-    int32_t *voff, *voff2, *ioff, *eoff;
+    int32_t* cnt;
+    int32_t *voff, *voff2, *ioff, *ioff2, *s_voff, *s_eoff;
+    int64_t *lam, *dmin;
+    int32_t* darg;
+    uint8_t *done, *snap, *prun, *dead;
+    int32_t* gstart_total;
     BatchGraph* tab;
     int32_t *in_rp, *in_col;
     int64_t* in_w;
     DGraph g[3];
-    int32_t *L, *parent, *flag, *map0, *vinst, *inst0;
-    uint8_t *side, *inpref, *done, *snap, *prun;
-    int64_t *lam, *dmin;
-    int32_t* darg;
+    DGraph stage;
+    int32_t *L, *parent, *flag, *vinst, *inst0;
+    uint8_t* inpref;
+    int32_t *map0, *map0b;
+    uint8_t *side, *sideb;
     ContractWS cw;
     Pr12WS prw;
     Pr34WS tw;
@@ -247,309 +304,746 @@ struct BatchWS {
     unsigned long long* vpart;
 };
 
-void carve_batch(Arena& a, int32_t k, int32_t N, int64_t C, BatchWS& w) {
+void carve_engine(Arena& a, const Caps& cp, EngineWS& w) {
+    const int32_t N = cp.N, K = cp.K, Ns = cp.Ns;
+    const int64_t C = cp.C, Cs = cp.Cs;
     w.sc = a.take<DevScalars>(1);
     w.cnt = a.take<int32_t>(4);
-    w.voff = a.take<int32_t>((size_t)k + 1);
-    w.voff2 = a.take<int32_t>((size_t)k + 1);
-    w.ioff = a.take<int32_t>((size_t)k + 1);
-    w.eoff = a.take<int32_t>((size_t)k + 1);
-    w.tab = a.take<BatchGraph>((size_t)k);
-    w.in_rp = a.take<int32_t>((size_t)N + 1);
-    w.in_col = a.take<int32_t>((size_t)C + 1);
-    w.in_w = a.take<int64_t>((size_t)C + 1);
-    for (int q = 0; q < 3; q++) {
-        DGraph& g = w.g[q];
-        g.n = N;
-        g.cap = C;
-        g.off = a.take<int32_t>((size_t)N + 1);
-        g.len = a.take<int32_t>((size_t)N + 1);
-        g.col = a.take<int32_t>((size_t)C + 1);
-        g.w = a.take<int64_t>((size_t)C + 1);
-        g.deg = a.take<int64_t>((size_t)N + 1);
-    }
+    w.voff = a.take<int32_t>((size_t)K + 1);
+    w.voff2 = a.take<int32_t>((size_t)K + 1);
+    w.ioff = a.take<int32_t>((size_t)K + 1);
+    w.ioff2 = a.take<int32_t>((size_t)K + 1);
+    w.s_voff = a.take<int32_t>((size_t)K + 1);
+    w.s_eoff = a.take<int32_t>((size_t)K + 1);
+    w.lam = a.take<int64_t>((size_t)K + 1);
+    w.dmin = a.take<int64_t>((size_t)K + 1);
+    w.darg = a.take<int32_t>((size_t)K + 1);
+    w.done = a.take<uint8_t>((size_t)K + 1);
+    w.snap = a.take<uint8_t>((size_t)K + 1);
+    w.prun = a.take<uint8_t>((size_t)K + 1);
+    w.dead = a.take<uint8_t>((size_t)K + 1);
+    w.gstart_total = a.take<int32_t>(1);
+    w.tab = a.take<BatchGraph>((size_t)K);
+    w.in_rp = a.take<int32_t>((size_t)Ns + 1);
+    w.in_col = a.take<int32_t>((size_t)Cs + 1);
+    w.in_w = a.take<int64_t>((size_t)Cs + 1);
+    auto graph = [&](DGraph& g, int32_t n, int64_t cap) {
+        g.n = n;
+        g.cap = cap;
+        g.off = a.take<int32_t>((size_t)n + 1);
+        g.len = a.take<int32_t>((size_t)n + 1);
+        g.col = a.take<int32_t>((size_t)cap + 1);
+        g.w = a.take<int64_t>((size_t)cap + 1);
+        g.deg = a.take<int64_t>((size_t)n + 1);
+    };
+    for (int q = 0; q < 3; q++) graph(w.g[q], N, C);
+    graph(w.stage, Ns, Cs);
     w.L = a.take<int32_t>((size_t)N + 1);
     w.parent = a.take<int32_t>((size_t)N + 1);
-    w.flag = a.take<int32_t>((size_t)N + 2);
-    w.map0 = a.take<int32_t>((size_t)N + 1);
+    w.flag = a.take<int32_t>((size_t)std::max(N, Ns) + 2);
     w.vinst = a.take<int32_t>((size_t)N + 1);
-    w.inst0 = a.take<int32_t>((size_t)N + 1);
-    w.side = a.take<uint8_t>((size_t)N + 1);
+    w.inst0 = a.take<int32_t>((size_t)cp.N0 + 1);
     w.inpref = a.take<uint8_t>((size_t)N + 1);
-    w.done = a.take<uint8_t>((size_t)k + 1);
-    w.snap = a.take<uint8_t>((size_t)k + 1);
-    w.prun = a.take<uint8_t>((size_t)k + 1);
-    w.lam = a.take<int64_t>((size_t)k + 1);
-    w.dmin = a.take<int64_t>((size_t)k + 1);
-    w.darg = a.take<int32_t>((size_t)k + 1);
-    contract_ws_carve(a, N, C, w.cw);
+    w.map0 = a.take<int32_t>((size_t)cp.N0 + 1);
+    w.map0b = a.take<int32_t>((size_t)cp.N0 + 1);
+    w.side = a.take<uint8_t>((size_t)cp.N0 + 1);
+    w.sideb = a.take<uint8_t>((size_t)cp.N0 + 1);
+    contract_ws_carve(a, std::max(N, Ns), std::max(C, Cs), w.cw);
     pr12_ws_carve(a, N, C, w.prw);
     pr34_ws_carve(a, N, w.tw);
-    // CAPFOREST passes in instance mode: one set of per-vertex arrays
     PrivateArgs& pv = w.pv;
     pv = PrivateArgs{};
-    pv.passes = k;
+    pv.passes = K;
     pv.stride = N;
     pv.st = a.take<int32_t>((size_t)N + 1);
     pv.r = a.take<int64_t>((size_t)N + 1);
     pv.fifo = a.take<int32_t>((size_t)N + 1);
     pv.touched = a.take<int32_t>((size_t)N + 1);
     pv.order = a.take<int32_t>((size_t)N + 1);
-    pv.stride1 = (int64_t)N / 64 + k + 2;
+    pv.stride1 = (int64_t)N / 64 + K + 2;
     pv.l1 = a.take<int64_t>((size_t)pv.stride1);
     pv.dlist = a.take<int32_t>((size_t)pv.stride1);
-    pv.dbits = a.take<uint32_t>((size_t)N / 2048 + 2 * (size_t)k + 4);
-    pv.nscan = a.take<int32_t>((size_t)k);
-    pv.alpha = a.take<int64_t>((size_t)k);
-    pv.alpha_len = a.take<int32_t>((size_t)k);
-    pv.lam_out = a.take<int64_t>((size_t)k);
-    w.pmarks = a.take<unsigned long long>((size_t)k);
+    pv.dbits = a.take<uint32_t>((size_t)N / 2048 + 2 * (size_t)K + 4);
+    pv.nscan = a.take<int32_t>((size_t)K);
+    pv.alpha = a.take<int64_t>((size_t)K);
+    pv.alpha_len = a.take<int32_t>((size_t)K);
+    pv.lam_out = a.take<int64_t>((size_t)K);
+    w.pmarks = a.take<unsigned long long>((size_t)K);
     w.vpart = a.take<unsigned long long>(1024);
 }
 
-bool batch_sizes(int32_t k, const mc_csr* gs, int32_t& N, int64_t& C, int32_t& nmax) {
-    int64_t n = 0, c = 0;
-    nmax = 0;
-    for (int32_t i = 0; i < k; i++) {
-        n += gs[i].n;
-        c += gs[i].nnz;
-        nmax = std::max(nmax, gs[i].n);
-    }
-    if (n >= INT32_MAX / 2 || c >= INT32_MAX / 2) return false;
-    N = (int32_t)n;
-    C = c;
-    return true;
-}
+#define EG_HIP(x) do { if ((x) != hipSuccess) return mc_fail(MC_E_DEVICE, #x); } while (0)
+#define EG_OK(x) do { if (!(x)) return MC_E_DEVICE; } while (0)
 
 }  // namespace
 
-extern "C" mc_status mc_batch_workspace_size(const mc_ctx* c, int32_t k, const mc_csr* gs, size_t* bytes) {
-    if (!c || !gs || !bytes || k <= 0) return mc_fail(MC_E_INVALID_ARG, "mc_batch_workspace_size: bad argument");
-    int32_t N, nmax;
-    int64_t C;
-    if (!batch_sizes(k, gs, N, C, nmax)) return mc_fail(MC_E_OVERFLOW, "batch too large (vertices or entries >= 2^30)");
-    Arena a;
-    BatchWS w;
-    carve_batch(a, k, N, C, w);
-    *bytes = a.used + 256;
-    return MC_OK;
-}
+// One graph in the rounds.
+struct EngineInst {
+    uint64_t id = 0;
+    int32_t n0 = 0;           // input vertices
+    int32_t ioff = 0;         // start of its input vertices in the side arrays
+    int32_t voff = 0, nv = 0; // its vertex range in the current union graph
+    int64_t lam = 0;
+    bool done = false;        // at most two vertices left (or lambda = 0): result final
+    bool dead = false;        // result taken; its vertices leave in the next contraction
+    int32_t rounds = 0;
+};
 
-#define BG_HIP(x) do { if ((x) != hipSuccess) return mc_fail(MC_E_DEVICE, #x); } while (0)
-#define BG_OK(x) do { if (!(x)) return MC_E_DEVICE; } while (0)
+// The round engine shared by the batched and the served forms: a union
+// graph of independent graphs, admitted at round boundaries, that all move
+// through the rounds of Algorithm 2 together.
+struct Engine {
+    mc_ctx* c = nullptr;
+    hipStream_t s = nullptr;
+    Caps cap;
+    EngineWS w{};
+    int cur = 0;                  // index of the current graph in w.g
+    int32_t n = 0;                // its vertices
+    int64_t used = 0;             // entries up to its last row window
+    int32_t n0_used = 0;
+    std::vector<EngineInst> insts;
+    bool tri_on = true;
+    int32_t round = 0;
 
-extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, void* dev_ws, size_t ws_bytes,
-                                     int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph) {
-    if (!c || !gs || !lambdas || k <= 0 || !dev_ws) return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: bad argument");
-    const int32_t loc = gs[0].location;
-    for (int32_t i = 0; i < k; i++) {
-        if (gs[i].n < 2) return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: every graph needs n >= 2");
-        if (gs[i].location != loc || (loc != MC_HOST && loc != MC_DEVICE))
-            return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: all graphs must share one location");
-        if (!gs[i].row_ptr || gs[i].nnz < 0 || (gs[i].nnz > 0 && (!gs[i].col || !gs[i].w)))
-            return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: bad CSR pointers");
-    }
-    int32_t N, nmax;
-    int64_t C64;
-    if (!batch_sizes(k, gs, N, C64, nmax)) return mc_fail(MC_E_OVERFLOW, "batch too large (vertices or entries >= 2^30)");
-    const int32_t C = (int32_t)C64;
-    Arena a;
-    a.base = (char*)dev_ws;
-    a.size = ws_bytes;
-    BatchWS w;
-    carve_batch(a, k, N, C, w);
-    if (a.used > ws_bytes) return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: workspace too small");
-    if (hipSetDevice(c->device) != hipSuccess) return mc_fail(MC_E_DEVICE, "hipSetDevice failed");
-    hipStream_t s = c->stream;
-    auto readback = [&]() -> bool {
-        return hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s) == hipSuccess &&
-               hipStreamSynchronize(s) == hipSuccess;
-    };
-    std::vector<int32_t> hcnt(4);
-    auto read_cnt = [&]() -> bool {
-        return hipMemcpyAsync(hcnt.data(), w.cnt, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
-               hipStreamSynchronize(s) == hipSuccess;
-    };
-
-    // offsets and the union CSR
-    std::vector<int32_t> voff(k + 1), eoff(k + 1);
-    voff[0] = eoff[0] = 0;
-    for (int32_t i = 0; i < k; i++) {
-        voff[i + 1] = voff[i] + gs[i].n;
-        eoff[i + 1] = eoff[i] + gs[i].nnz;
-    }
-    BG_HIP(hipMemcpyAsync(w.voff, voff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
-    BG_HIP(hipMemcpyAsync(w.ioff, voff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
-    BG_HIP(hipMemcpyAsync(w.eoff, eoff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
-    BG_OK(fill_i32((int32_t*)w.sc, 0, sizeof(DevScalars) / 4, s));
-    BG_OK(fill_i32(w.cnt, 0, 4, s));
-    if (loc == MC_DEVICE) {
-        std::vector<BatchGraph> tab(k);
-        for (int32_t i = 0; i < k; i++) tab[i] = {gs[i].row_ptr, gs[i].col, gs[i].w, gs[i].n, gs[i].nnz};
-        BG_HIP(hipMemcpyAsync(w.tab, tab.data(), sizeof(BatchGraph) * k, hipMemcpyHostToDevice, s));
-        k_bg_gather<<<grid_for((int64_t)C + N + 1, 256), 256, 0, s>>>(w.tab, k, w.voff, w.eoff, N, C, w.in_rp, w.in_col,
-                                                                     w.in_w, w.sc);
-        BG_OK(mc_hip_ok(hipGetLastError(), "k_bg_gather"));
-    } else {
-        for (int32_t i = 0; i < k; i++) {
-            // host checks of each graph (row_ptr, targets in range, weights)
-            const mc_csr& g = gs[i];
-            if (g.row_ptr[0] != 0 || g.row_ptr[g.n] != g.nnz) return mc_fail(MC_E_BAD_GRAPH, "malformed row_ptr");
-            for (int32_t v = 0; v < g.n; v++)
-                if (g.row_ptr[v + 1] < g.row_ptr[v]) return mc_fail(MC_E_BAD_GRAPH, "row_ptr not monotone");
-            for (int32_t j = 0; j < g.nnz; j++)
-                if (g.col[j] < 0 || g.col[j] >= g.n || g.w[j] < 0) return mc_fail(MC_E_BAD_GRAPH, "bad entry");
-            BG_HIP(hipMemcpyAsync(w.in_rp + voff[i], g.row_ptr, sizeof(int32_t) * g.n, hipMemcpyHostToDevice, s));
-            if (g.nnz > 0) {
-                BG_HIP(hipMemcpyAsync(w.in_col + eoff[i], g.col, sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice, s));
-                BG_HIP(hipMemcpyAsync(w.in_w + eoff[i], g.w, sizeof(int64_t) * g.nnz, hipMemcpyHostToDevice, s));
-            }
-        }
-        k_bg_shift<<<grid_for((int64_t)C + N + 1, 256), 256, 0, s>>>(k, w.voff, w.eoff, N, C, w.in_rp, w.in_col);
-        BG_OK(mc_hip_ok(hipGetLastError(), "k_bg_shift"));
-    }
-    // total weight (2^62 limit) over the union
-    BG_OK(validate_csr(w.in_rp, w.in_col, w.in_w, N, C, w.sc, w.vpart, s));
-    if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
-    if (c->hsc->err) return mc_fail((mc_status)c->hsc->err, "malformed graph in the batch");
-
-    // normalise (in place when already normal)
-    BG_OK(canon_check(w.in_rp, w.in_col, w.in_w, N, w.g[0].len, w.g[0].deg, &w.sc->noncanon, s));
-    if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
-    if (c->hsc->noncanon == 0) {
-        w.g[0].off = w.in_rp;
-        w.g[0].col = w.in_col;
-        w.g[0].w = w.in_w;
-    } else {
-        DGraph user = w.g[1];
-        user.n = N;
-        user.cap = C;
-        user.col = w.in_col;
-        user.w = w.in_w;
-        BG_OK(csr_to_padded(w.in_rp, N, user.off, user.len, s));
-        BG_OK(contract(user, nullptr, N, w.g[0], w.cw, w.sc, s));
-    }
-    BG_OK(iota_i32(w.map0, N, s));
-    k_bg_vinst<<<grid_for(N, 256), 256, 0, s>>>(w.voff, k, N, w.inst0);
-    BG_OK(mc_hip_ok(hipGetLastError(), "k_bg_vinst"));
-    {
+    mc_status init(mc_ctx* ctx, const Caps& cp, void* ws, size_t bytes) {
+        c = ctx;
+        s = ctx->stream;
+        cap = cp;
+        Arena a;
+        a.base = (char*)ws;
+        a.size = bytes;
+        carve_engine(a, cp, w);
+        if (a.used > bytes) return mc_fail(MC_E_INVALID_ARG, "engine: workspace too small");
+        if (hipSetDevice(c->device) != hipSuccess) return mc_fail(MC_E_DEVICE, "hipSetDevice failed");
         PrivateArgs one = w.pv;   // st and r: one vertex-indexed array for all passes
         one.passes = 1;
-        BG_OK(capforest_private_reset(one, s));
+        EG_OK(capforest_private_reset(one, s));
+        EG_OK(fill_i32((int32_t*)w.sc, 0, sizeof(DevScalars) / 4, s));
+        // prefix marks are set and cleared per round; they start all zero
+        EG_OK(fill_u8(w.inpref, 0, (int64_t)cp.N + 1, s));
+        tri_on = c->opt.pr_tri_deg_cap > 0;
+        cur = 0;
+        n = 0;
+        used = 0;
+        n0_used = 0;
+        insts.clear();
+        return MC_OK;
     }
-    // per-graph connectivity and minimum degree
-    BG_OK(uf_init(w.parent, N, s));
-    BG_OK(uf_connectivity(w.g[0], w.parent, (int32_t*)w.vpart, s));
-    BG_OK(uf_labels(w.parent, N, w.L, w.flag, w.cw.scan_tmp, w.sc, s));
-    k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, w.voff, k, w.voff2);
-    k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(w.g[0].deg, w.voff, k, w.dmin, w.darg);
-    k_bg_start<<<grid_for(k, 256), 256, 0, s>>>(w.voff, w.voff2, k, w.dmin, w.lam, w.done, w.snap);
-    k_bg_side_comp<<<grid_for(N, 256), 256, 0, s>>>(w.side, w.parent, w.inst0, w.ioff, w.snap, N);
-    k_bg_side<<<grid_for(N, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, N, w.snap, w.darg, w.inpref);
-    k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
-    BG_OK(mc_hip_ok(hipGetLastError(), "batch start"));
-    BG_OK(fill_u8(w.inpref, 0, N, s));
 
-    const int32_t len_cap = c->opt.pass_len_cap > 0 ? c->opt.pass_len_cap : (c->opt.pass_len_cap < 0 ? 0 : 32768);
-    const int32_t D = c->opt.pr_tri_deg_cap;
-    bool tri_on = D > 0;
-    DGraph* cur = &w.g[0];
-    int nxt_idx = 1;
-    int32_t* voff_d = w.voff;
-    int32_t* voff2_d = w.voff2;
-    for (int32_t round = 0;; round++) {
-        if (round > N + 64) return mc_fail(MC_E_DEVICE, "mc_mincut_batch: no progress");
-        DGraph* nxt = &w.g[nxt_idx];
-        const int32_t n = cur->n;
-        BG_OK(fill_i32(w.cnt, 0, 4, s));
-        // marks counters of the round
-        BG_OK(fill_i64((int64_t*)&w.sc->marks_pr, 0, 3, s));
-        BG_OK(uf_init(w.parent, n, s));
-        k_bg_vinst<<<grid_for(n, 256), 256, 0, s>>>(voff_d, k, n, w.vinst);
-        BG_OK(mc_hip_ok(hipGetLastError(), "k_bg_vinst"));
+    bool readback() {
+        return hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s) == hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    }
+
+    // Room for k more graphs of nv vertices and ne entries in total?
+    bool fits(int32_t k, int64_t nv, int64_t ne) const {
+        int32_t live0 = 0;
+        for (const EngineInst& x : insts) live0 += x.dead ? 0 : x.n0;
+        return (int64_t)insts.size() + k <= cap.K && n + nv <= cap.N && used + ne <= cap.C && nv <= cap.Ns &&
+               ne <= cap.Cs && live0 + nv <= cap.N0;
+    }
+
+    // Append graphs (normalised on the way) behind the current graph.
+    mc_status admit(const mc_csr* gs, int32_t k, const uint64_t* ids) {
+        if (k <= 0) return MC_OK;
+        const int32_t loc = gs[0].location;
+        int64_t nv = 0, ne = 0;
+        std::vector<int32_t> sv(k + 1), se(k + 1);
+        sv[0] = se[0] = 0;
+        for (int32_t i = 0; i < k; i++) {
+            const mc_csr& g = gs[i];
+            if (g.n < 2) return mc_fail(MC_E_INVALID_ARG, "every graph needs n >= 2");
+            if (g.location != loc || (loc != MC_HOST && loc != MC_DEVICE))
+                return mc_fail(MC_E_INVALID_ARG, "all graphs of one call must share one location");
+            if (!g.row_ptr || g.nnz < 0 || (g.nnz > 0 && (!g.col || !g.w)))
+                return mc_fail(MC_E_INVALID_ARG, "bad CSR pointers");
+            if (g.n > cap.nmax) return mc_fail(MC_E_OOM, "graph larger than the engine's largest graph");
+            sv[i + 1] = sv[i] + g.n;
+            se[i + 1] = se[i] + g.nnz;
+            nv += g.n;
+            ne += g.nnz;
+        }
+        if (!fits(k, nv, ne)) return mc_fail(MC_E_OOM, "the graphs do not fit the engine's capacity");
+        if (n0_used + nv > cap.N0) {
+            // input-vertex ranges of finished graphs leave holes: close them
+            if (!compact_n0()) return MC_E_DEVICE;
+            if (n0_used + nv > cap.N0) return mc_fail(MC_E_OOM, "the graphs do not fit the engine's capacity");
+        }
+        const int32_t NS = (int32_t)nv, CS = (int32_t)ne;
+        EG_HIP(hipMemcpyAsync(w.s_voff, sv.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        EG_HIP(hipMemcpyAsync(w.s_eoff, se.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        EG_OK(fill_i32(&w.sc->err, 0, 1, s));
+        if (loc == MC_DEVICE) {
+            std::vector<BatchGraph> tab(k);
+            for (int32_t i = 0; i < k; i++) tab[i] = {gs[i].row_ptr, gs[i].col, gs[i].w, gs[i].n, gs[i].nnz};
+            EG_HIP(hipMemcpyAsync(w.tab, tab.data(), sizeof(BatchGraph) * k, hipMemcpyHostToDevice, s));
+            k_bg_gather<<<grid_for((int64_t)CS + NS + 1, 256), 256, 0, s>>>(w.tab, k, w.s_voff, w.s_eoff, NS, CS,
+                                                                           w.in_rp, w.in_col, w.in_w, w.sc);
+            EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_gather"));
+        } else {
+            for (int32_t i = 0; i < k; i++) {
+                const mc_csr& g = gs[i];
+                if (g.row_ptr[0] != 0 || g.row_ptr[g.n] != g.nnz) return mc_fail(MC_E_BAD_GRAPH, "malformed row_ptr");
+                for (int32_t v = 0; v < g.n; v++)
+                    if (g.row_ptr[v + 1] < g.row_ptr[v]) return mc_fail(MC_E_BAD_GRAPH, "row_ptr not monotone");
+                for (int32_t j = 0; j < g.nnz; j++)
+                    if (g.col[j] < 0 || g.col[j] >= g.n || g.w[j] < 0) return mc_fail(MC_E_BAD_GRAPH, "bad entry");
+                EG_HIP(hipMemcpyAsync(w.in_rp + sv[i], g.row_ptr, sizeof(int32_t) * g.n, hipMemcpyHostToDevice, s));
+                if (g.nnz > 0) {
+                    EG_HIP(hipMemcpyAsync(w.in_col + se[i], g.col, sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice, s));
+                    EG_HIP(hipMemcpyAsync(w.in_w + se[i], g.w, sizeof(int64_t) * g.nnz, hipMemcpyHostToDevice, s));
+                }
+            }
+            k_bg_shift<<<grid_for((int64_t)CS + NS + 1, 256), 256, 0, s>>>(k, w.s_voff, w.s_eoff, NS, CS, w.in_rp,
+                                                                          w.in_col);
+            EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_shift"));
+        }
+        EG_OK(validate_csr(w.in_rp, w.in_col, w.in_w, NS, CS, w.sc, w.vpart, s));
+        if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
+        if (c->hsc->err) return mc_fail((mc_status)c->hsc->err, "malformed graph");
+        // normal form: in place when already normal, else contraction by
+        // the identity into the staging graph
+        DGraph S = w.stage;
+        S.n = NS;
+        S.cap = CS;
+        EG_OK(canon_check(w.in_rp, w.in_col, w.in_w, NS, w.stage.len, w.stage.deg, &w.sc->noncanon, s));
+        if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
+        if (c->hsc->noncanon == 0) {
+            S.off = w.in_rp;
+            S.col = w.in_col;
+            S.w = w.in_w;
+        } else {
+            DGraph user = w.g[(cur + 1) % 3];   // its off/len arrays serve as scratch
+            user.n = NS;
+            user.cap = CS;
+            user.col = w.in_col;
+            user.w = w.in_w;
+            EG_OK(csr_to_padded(w.in_rp, NS, user.off, user.len, s));
+            EG_OK(contract(user, nullptr, NS, S, w.cw, w.sc, s));
+        }
+        DGraph& G = w.g[cur];
+        k_eg_append<<<grid_for((int64_t)CS + NS, 256), 256, 0, s>>>(S, CS, G, n, used);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_eg_append"));
+        k_eg_admit_map<<<grid_for(NS, 256), 256, 0, s>>>(w.map0, w.side, n0_used, n, NS);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_eg_admit_map"));
+        // first bounds: minimum degrees of the new ranges, and their vertices as sides
+        std::vector<int32_t> vo(k + 1);
+        for (int32_t i = 0; i <= k; i++) vo[i] = n + sv[i];
+        EG_HIP(hipMemcpyAsync(w.voff, vo.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(G.deg, w.voff, k, w.dmin, w.darg);
+        k_eg_start<<<grid_for(k, 256), 256, 0, s>>>(w.dmin, w.darg, k, w.lam, w.snap);
+        // graph index (among the k new graphs) of each new input vertex; the
+        // rounds recompute it for the whole table
+        k_bg_vinst<<<grid_for(NS, 256), 256, 0, s>>>(w.s_voff, k, NS, w.inst0 + n0_used);
+        EG_OK(mc_hip_ok(hipGetLastError(), "admit bounds"));
+        k_bg_side<<<grid_for(NS, 256), 256, 0, s>>>(w.side + n0_used, w.map0 + n0_used, w.inst0 + n0_used, NS, w.snap,
+                                                    w.darg, w.inpref);
+        k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
+        EG_OK(mc_hip_ok(hipGetLastError(), "admit sides"));
+        std::vector<int64_t> lam(k);
+        EG_HIP(hipMemcpyAsync(lam.data(), w.lam, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < k; i++) {
+            EngineInst x;
+            x.id = ids ? ids[i] : (uint64_t)i;
+            x.n0 = gs[i].n;
+            x.ioff = n0_used + sv[i];
+            x.voff = n + sv[i];
+            x.nv = gs[i].n;
+            x.lam = lam[i];
+            x.done = x.nv <= 2 || x.lam == 0;
+            insts.push_back(x);
+        }
+        n += NS;
+        used += CS;
+        n0_used += NS;
+        return MC_OK;
+    }
+
+    // Move the input-vertex ranges of live graphs to the front.
+    bool compact_n0() {
+        const int32_t k = (int32_t)insts.size();
+        if (k == 0) { n0_used = 0; return true; }
+        std::vector<int32_t> nio(k + 1), oio(k + 1);
+        int32_t run = 0;
+        for (int32_t i = 0; i < k; i++) {
+            oio[i] = insts[i].ioff;
+            nio[i] = run;
+            run += insts[i].n0;
+        }
+        nio[k] = oio[k] = run;
+        if (hipMemcpyAsync(w.ioff, nio.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(w.ioff2, oio.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+            return false;
+        k_eg_n0_compact<<<grid_for(run, 256), 256, 0, s>>>(w.ioff, w.ioff2, k, run, w.map0, w.side, w.map0b, w.sideb);
+        if (!mc_hip_ok(hipGetLastError(), "k_eg_n0_compact")) return false;
+        std::swap(w.map0, w.map0b);
+        std::swap(w.side, w.sideb);
+        for (int32_t i = 0; i < k; i++) insts[i].ioff = nio[i];
+        n0_used = run;
+        return true;
+    }
+
+    int32_t live() const {
+        int32_t a = 0;
+        for (const EngineInst& x : insts) a += !x.done;
+        return a;
+    }
+
+    // One round for every graph in the engine. Graphs whose result became
+    // final are appended to `finished` (their sides are then read with
+    // side_of); graphs finished in the previous round leave the union graph.
+    mc_status step(std::vector<EngineInst>& finished) {
+        const int32_t k = (int32_t)insts.size();
+        if (k == 0) return MC_OK;
+        DGraph& G = w.g[cur];
+        G.n = n;
+        DGraph& Nx = w.g[(cur + 1) % 3];
+        // instance arrays of the round
+        std::vector<int32_t> vo(k + 1), io(k + 1);
+        std::vector<int64_t> lam(k);
+        std::vector<uint8_t> done(k), dead(k);
+        for (int32_t i = 0; i < k; i++) {
+            vo[i] = insts[i].voff;
+            io[i] = insts[i].ioff;
+            lam[i] = insts[i].lam;
+            done[i] = insts[i].done || insts[i].dead;
+            dead[i] = insts[i].dead;
+        }
+        vo[k] = n;
+        io[k] = n0_used;
+        EG_HIP(hipMemcpyAsync(w.voff, vo.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        EG_HIP(hipMemcpyAsync(w.ioff, io.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        EG_HIP(hipMemcpyAsync(w.lam, lam.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+        EG_HIP(hipMemcpyAsync(w.done, done.data(), k, hipMemcpyHostToDevice, s));
+        EG_HIP(hipMemcpyAsync(w.dead, dead.data(), k, hipMemcpyHostToDevice, s));
+        EG_OK(fill_u8(w.snap, 0, k, s));
+        EG_OK(fill_i32(w.cnt, 0, 4, s));
+        EG_OK(fill_i64((int64_t*)&w.sc->marks_pr, 0, 3, s));
+        k_bg_vinst<<<grid_for(n, 256), 256, 0, s>>>(w.voff, k, n, w.vinst);
+        k_bg_vinst<<<grid_for(n0_used, 256), 256, 0, s>>>(w.ioff, k, n0_used, w.inst0);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_vinst"));
+        EG_OK(uf_init(w.parent, n, s));
         // reduction tests with each graph's own bound
-        BG_OK(pr12(*cur, w.lam, w.parent, &w.sc->marks_pr, nullptr, tri_on ? w.tw.ptr2 : nullptr, w.prw, s, w.vinst));
-        if (tri_on) BG_OK(pr34(*cur, w.lam, D, w.parent, &w.sc->marks_tri, w.tw.ptr2, w.tw, nullptr, nullptr, s, w.vinst));
+        EG_OK(pr12(G, w.lam, w.parent, &w.sc->marks_pr, nullptr, tri_on ? w.tw.ptr2 : nullptr, w.prw, s, w.vinst));
+        if (tri_on)
+            EG_OK(pr34(G, w.lam, c->opt.pr_tri_deg_cap, w.parent, &w.sc->marks_tri, w.tw.ptr2, w.tw, nullptr, nullptr,
+                       s, w.vinst));
         // one CAPFOREST pass per graph still in the rounds
         k_bg_active<<<grid_for(k, 256), 256, 0, s>>>(w.done, k, w.prun);
         PrivateArgs pa = w.pv;
-        pa.g = *cur;
+        pa.g = G;
         pa.lam = w.lam;
         pa.parent = w.parent;
-        pa.len_cap = len_cap;
+        pa.passes = k;
+        pa.len_cap = c->opt.pass_len_cap > 0 ? c->opt.pass_len_cap : (c->opt.pass_len_cap < 0 ? 0 : 32768);
         pa.seed = c->opt.seed;
         pa.round = round;
         pa.start = -1;
         pa.marks = &w.sc->marks_cf;
         pa.steps = nullptr;
         pa.diag = nullptr;
-        pa.pvoff = voff_d;
+        pa.pvoff = w.voff;
         pa.plam = w.lam;
         pa.prun = w.prun;
         pa.pmarks = w.pmarks;
-        BG_OK(capforest_private(pa, s, nmax));
+        EG_OK(capforest_private(pa, s, cap.nmax));
         k_bg_alpha<<<grid_for(k, 256), 256, 0, s>>>(pa.alpha, w.done, k, w.lam, w.snap);
-        BG_OK(uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s));
-        k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, voff_d, k, voff2_d);
-        k_bg_fallback<<<grid_for(k, 256), 256, 0, s>>>(voff_d, voff2_d, w.done, k, w.prun, w.cnt);
-        BG_OK(mc_hip_ok(hipGetLastError(), "batch round"));
-        if (!read_cnt()) return mc_fail(MC_E_DEVICE, "readback failed");
-        if (tri_on && !readback()) return mc_fail(MC_E_DEVICE, "readback failed");
-        if (tri_on && c->hsc->marks_tri * 100 < (unsigned long long)n) tri_on = false;
+        EG_OK(labels(k));
+        k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, w.voff, k, w.voff2);
+        k_bg_fallback<<<grid_for(k, 256), 256, 0, s>>>(w.voff, w.voff2, w.done, k, w.prun, w.cnt);
+        EG_OK(mc_hip_ok(hipGetLastError(), "round"));
+        int32_t hcnt[4];
+        EG_HIP(hipMemcpyAsync(hcnt, w.cnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+        if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
+        if (tri_on && c->hsc->marks_tri * 100 < (unsigned long long)std::max(n, 1)) tri_on = false;
         if (hcnt[0] > 0) {
             // Algorithm 2: graphs without a contractible edge get one complete
-            // pass (with a fixed bound it marks an edge, else the bound drops)
-            // first record the truncated passes' prefixes (their alpha may
-            // have lowered the bound)
-            k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, voff_d, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 1);
-            k_bg_side<<<grid_for(N, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, N, w.snap, w.darg, w.inpref);
-            k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, voff_d, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 0);
-            k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
+            // pass; first take the sides of the truncated passes' prefixes
+            EG_OK(prefix_sides(pa, k));
             PrivateArgs pf = pa;
             pf.len_cap = 0;
             pf.round = round + 7777;
-            BG_OK(capforest_private(pf, s, nmax));
+            EG_OK(capforest_private(pf, s, cap.nmax));
             k_bg_alpha<<<grid_for(k, 256), 256, 0, s>>>(pf.alpha, w.done, k, w.lam, w.snap);
-            BG_OK(uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s));
-            k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, voff_d, k, voff2_d);
-            BG_OK(mc_hip_ok(hipGetLastError(), "batch fallback"));
+            EG_OK(labels(k));
+            k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, w.voff, k, w.voff2);
+            EG_OK(mc_hip_ok(hipGetLastError(), "fallback"));
         }
-        // sides of graphs whose bound dropped to a pass's prefix
-        k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, voff_d, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 1);
-        k_bg_side<<<grid_for(N, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, N, w.snap, w.darg, w.inpref);
-        k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, voff_d, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 0);
-        k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
+        EG_OK(prefix_sides(pa, k));
         if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
         const int32_t n2 = c->hsc->n2;
-        // contraction of the union graph, collapsed degrees per graph
-        BG_OK(contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s));
-        BG_OK(map_update(w.map0, w.L, N, s));
-        k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(nxt->deg, voff2_d, k, w.dmin, w.darg);
-        BG_OK(fill_i32(w.cnt, 0, 4, s));
-        k_bg_bound<<<grid_for(k, 256), 256, 0, s>>>(voff2_d, w.dmin, k, w.lam, w.done, w.snap, w.cnt);
-        k_bg_side<<<grid_for(N, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, N, w.snap, w.darg, w.inpref);
-        k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
-        BG_OK(mc_hip_ok(hipGetLastError(), "batch bound"));
-        if (!read_cnt()) return mc_fail(MC_E_DEVICE, "readback failed");
-        std::swap(voff_d, voff2_d);
-        cur = nxt;
-        nxt_idx = nxt_idx == 1 ? 2 : 1;
-        if (hcnt[0] == 0) break;
-    }
-    // results
-    BG_HIP(hipMemcpyAsync(lambdas, w.lam, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
-    std::vector<uint8_t> hside;
-    if (sides) {
-        hside.resize(N);
-        BG_HIP(hipMemcpyAsync(hside.data(), w.side, N, hipMemcpyDeviceToHost, s));
-    }
-    BG_HIP(hipStreamSynchronize(s));
-    for (int32_t i = 0; i < k; i++) {
-        if (per_graph) per_graph[i] = MC_OK;
-        if (sides && sides[i]) {
-            const uint8_t flip = hside[voff[i]];
-            for (int32_t v = 0; v < gs[i].n; v++) sides[i][v] = hside[voff[i] + v] ^ flip;
+        // contraction (dead graphs leave), collapsed degrees per graph
+        EG_OK(contract(G, w.L, n2, Nx, w.cw, w.sc, s));
+        EG_OK(map_update(w.map0, w.L, n0_used, s));
+        k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(Nx.deg, w.voff2, k, w.dmin, w.darg);
+        k_bg_bound<<<grid_for(k, 256), 256, 0, s>>>(w.voff2, w.dmin, k, w.lam, w.done, w.snap, w.cnt);
+        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref);
+        EG_OK(mc_hip_ok(hipGetLastError(), "bound"));
+        // new ranges, bounds and states; the entries in use of the new graph
+        std::vector<int32_t> v2(k + 1);
+        EG_HIP(hipMemcpyAsync(v2.data(), w.voff2, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipMemcpyAsync(lam.data(), w.lam, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        EG_HIP(hipMemcpyAsync(done.data(), w.done, k, hipMemcpyDeviceToHost, s));
+        int32_t total = 0;
+        EG_HIP(hipMemcpyAsync(&total, w.cw.gstart + n2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        std::vector<EngineInst> keep;
+        keep.reserve(k);
+        for (int32_t i = 0; i < k; i++) {
+            EngineInst x = insts[i];
+            if (x.dead) continue;                 // left the union graph in this contraction
+            x.voff = v2[i];
+            x.nv = v2[i + 1] - v2[i];
+            x.lam = lam[i];
+            x.rounds++;
+            if (!x.done && (done[i] || x.lam == 0 || x.nv <= 2)) {
+                x.done = true;
+                finished.push_back(x);
+                x.dead = true;                    // leaves in the next round
+            } else if (x.done) {
+                x.dead = true;
+            }
+            keep.push_back(x);
         }
+        insts.swap(keep);
+        n = n2;
+        used = total;
+        cur = &Nx - w.g;
+        round++;
+        return MC_OK;
     }
+
+    // labels of the round: canonical components, -1 for dead graphs
+    bool labels(int32_t k) {
+        const int32_t nn = n;
+        (void)k;
+        if (!uf_labels(w.parent, nn, w.L, w.flag, w.cw.scan_tmp, w.sc, s)) return false;   // compresses
+        k_root_flag_live<<<grid_for(nn, 256), 256, 0, s>>>(w.parent, w.vinst, w.dead, nn, w.flag);
+        if (!mc_hip_ok(hipGetLastError(), "k_root_flag_live")) return false;
+        if (!scan_i32(w.flag, w.flag, nn, w.cw.scan_tmp, s)) return false;
+        k_label_live<<<grid_for(nn, 256), 256, 0, s>>>(w.parent, w.flag, w.vinst, w.dead, nn, w.L, w.sc);
+        return mc_hip_ok(hipGetLastError(), "k_label_live");
+    }
+
+    // sides of graphs whose bound dropped to a pass's prefix this round
+    bool prefix_sides(const PrivateArgs& pa, int32_t k) {
+        k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, w.voff, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 1);
+        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref);
+        k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, w.voff, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 0);
+        k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
+        return mc_hip_ok(hipGetLastError(), "prefix sides");
+    }
+
+    // side of a finished graph (host, n0 bytes, side[0] = 0); then its input
+    // vertices are no longer tracked
+    mc_status side_of(const EngineInst& x, uint8_t* out) {
+        if (out) {
+            EG_HIP(hipMemcpyAsync(out, w.side + x.ioff, x.n0, hipMemcpyDeviceToHost, s));
+            EG_HIP(hipStreamSynchronize(s));
+            const uint8_t flip = out[0];
+            if (flip)
+                for (int32_t v = 0; v < x.n0; v++) out[v] ^= 1;
+        }
+        k_eg_untrack<<<grid_for(x.n0, 256), 256, 0, s>>>(w.map0, x.ioff, x.n0);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_eg_untrack"));
+        return MC_OK;
+    }
+};
+
+namespace {
+
+Caps batch_caps(int32_t k, const mc_csr* gs, bool& ok) {
+    Caps cp;
+    int64_t n = 0, e = 0;
+    int32_t nmax = 0;
+    for (int32_t i = 0; i < k; i++) {
+        n += gs[i].n;
+        e += gs[i].nnz;
+        nmax = std::max(nmax, gs[i].n);
+    }
+    ok = n < INT32_MAX / 2 && e < INT32_MAX / 2;
+    cp.N = cp.N0 = cp.Ns = (int32_t)n;
+    cp.C = cp.Cs = e;
+    cp.K = k;
+    cp.nmax = nmax;
+    return cp;
+}
+
+}  // namespace
+
+extern "C" mc_status mc_batch_workspace_size(const mc_ctx* c, int32_t k, const mc_csr* gs, size_t* bytes) {
+    if (!c || !gs || !bytes || k <= 0) return mc_fail(MC_E_INVALID_ARG, "mc_batch_workspace_size: bad argument");
+    bool ok;
+    Caps cp = batch_caps(k, gs, ok);
+    if (!ok) return mc_fail(MC_E_OVERFLOW, "batch too large (vertices or entries >= 2^30)");
+    Arena a;
+    EngineWS w;
+    carve_engine(a, cp, w);
+    *bytes = a.used + 256;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, void* dev_ws, size_t ws_bytes,
+                                     int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph) {
+    if (!c || !gs || !lambdas || k <= 0 || !dev_ws) return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: bad argument");
+    bool ok;
+    Caps cp = batch_caps(k, gs, ok);
+    if (!ok) return mc_fail(MC_E_OVERFLOW, "batch too large (vertices or entries >= 2^30)");
+    Engine E;
+    mc_status r = E.init(c, cp, dev_ws, ws_bytes);
+    if (r != MC_OK) return r;
+    std::vector<uint64_t> ids(k);
+    for (int32_t i = 0; i < k; i++) ids[i] = (uint64_t)i;
+    if ((r = E.admit(gs, k, ids.data())) != MC_OK) return r;
+    std::vector<EngineInst> fin;
+    // graphs final at admission (two vertices, or lambda 0)
+    for (EngineInst& x : E.insts)
+        if (x.done) fin.push_back(x);
+    for (EngineInst& x : E.insts)
+        if (x.done) x.dead = true;
+    size_t got = 0;
+    for (int32_t rounds = 0;; rounds++) {
+        for (; got < fin.size(); got++) {
+            const EngineInst& x = fin[got];
+            lambdas[x.id] = x.lam;
+            if ((r = E.side_of(x, sides ? sides[x.id] : nullptr)) != MC_OK) return r;
+            if (per_graph) per_graph[x.id] = MC_OK;
+        }
+        if (E.live() == 0) break;
+        if (rounds > cp.N + 64) return mc_fail(MC_E_DEVICE, "mc_mincut_batch: no progress");
+        if ((r = E.step(fin)) != MC_OK) return r;
+    }
+    return MC_OK;
+}
+
+// ------------------------------------------------------------ the server
+// Continuous batching over the engine: requests are copied at submission
+// and queued; every mc_server_step admits queued requests in arrival order
+// while they fit the engine's capacity (graphs in flight, vertices,
+// entries; all carved from one device allocation of the configured HBM
+// budget), runs one round for every graph in flight, and collects the
+// graphs whose result became final. Graphs admitted while others are half
+// way through their rounds join them in the same launches; a graph's rounds
+// do not depend on the others (its bound, passes and contractions touch
+// only its own range), so its result is the one it gets alone.
+#include <chrono>
+#include <deque>
+#include <unordered_map>
+
+struct mc_server {
+    mc_ctx* c = nullptr;
+    void* mem = nullptr;
+    size_t bytes = 0;
+    Engine E;
+    std::chrono::steady_clock::time_point t0;
+    struct Req {
+        std::vector<int32_t> rp, col;
+        std::vector<int64_t> w;
+        int32_t n = 0, nnz = 0;
+        int state = 0;             // 0 queued, 1 in flight, 2 done, 3 cancelled
+        bool cancel = false;
+        int64_t lam = 0;
+        std::vector<uint8_t> side;
+        mc_req_stats st{};
+    };
+    std::unordered_map<uint64_t, Req> reqs;
+    std::deque<uint64_t> queue;
+    uint64_t next = 1;
+    double now() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+Caps server_caps(const mc_server_opts& o, int64_t C) {
+    Caps cp;
+    cp.K = o.max_inflight > 0 ? o.max_inflight : 1024;
+    cp.nmax = o.max_request_n > 0 ? o.max_request_n : (1 << 20);
+    const int64_t rn = o.max_request_nnz > 0 ? o.max_request_nnz : ((int64_t)1 << 25);
+    cp.C = C;
+    cp.N = (int32_t)std::min<int64_t>(C / 2 + 4 * (int64_t)cp.K, INT32_MAX / 4);
+    cp.N0 = cp.N;
+    cp.Ns = (int32_t)std::min<int64_t>(std::max<int64_t>(cp.nmax, cp.N / 4), cp.N);
+    cp.Cs = std::min<int64_t>(std::max<int64_t>(rn, C / 4), C);
+    return cp;
+}
+
+size_t engine_bytes(const Caps& cp) {
+    Arena a;
+    EngineWS w;
+    carve_engine(a, cp, w);
+    return a.used + 256;
+}
+
+mc_status finish(mc_server* S, const EngineInst& x) {
+    auto it = S->reqs.find(x.id);
+    if (it == S->reqs.end()) return mc_fail(MC_E_DEVICE, "server: unknown graph in flight");
+    mc_server::Req& r = it->second;
+    r.side.assign((size_t)r.n, 0);
+    mc_status st = S->E.side_of(x, r.side.data());
+    if (st != MC_OK) return st;
+    r.lam = x.lam;
+    r.state = r.cancel ? 3 : 2;
+    r.st.t_done_ms = S->now();
+    r.st.rounds = x.rounds;
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" mc_status mc_server_create(mc_ctx* c, const mc_server_opts* opts, mc_server** out) {
+    if (!c || !opts || !out) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: NULL argument");
+    if (opts->hbm_bytes < ((size_t)64 << 20)) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget below 64 MiB");
+    // the largest entry capacity whose engine fits the budget
+    int64_t lo = 1024, hi = (int64_t)1 << 30;
+    if (engine_bytes(server_caps(*opts, lo)) > opts->hbm_bytes)
+        return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget too small for the options");
+    while (hi - lo > 1024) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (engine_bytes(server_caps(*opts, mid)) <= opts->hbm_bytes) lo = mid; else hi = mid;
+    }
+    const Caps cp = server_caps(*opts, lo);
+    mc_server* S = new (std::nothrow) mc_server();
+    if (!S) return mc_fail(MC_E_OOM, "mc_server_create: out of host memory");
+    S->c = c;
+    S->bytes = engine_bytes(cp);
+    if (hipSetDevice(c->device) != hipSuccess || hipMalloc(&S->mem, S->bytes) != hipSuccess) {
+        delete S;
+        return mc_fail(MC_E_OOM, "mc_server_create: device allocation of the budget failed");
+    }
+    mc_status r = S->E.init(c, cp, S->mem, S->bytes);
+    if (r != MC_OK) {
+        (void)hipFree(S->mem);
+        delete S;
+        return r;
+    }
+    S->t0 = std::chrono::steady_clock::now();
+    *out = S;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_destroy(mc_server* S) {
+    if (!S) return MC_OK;
+    if (S->mem) (void)hipFree(S->mem);
+    delete S;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_submit(mc_server* S, const mc_csr* g, uint64_t* ticket) {
+    if (!S || !g || !ticket) return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: NULL argument");
+    if (g->location != MC_HOST) return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: host graphs only");
+    if (g->n < 2 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
+        return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: bad graph");
+    const Caps& cp = S->E.cap;
+    if (g->n > cp.nmax || g->n > cp.Ns || g->nnz > cp.Cs || g->n > cp.N || g->nnz > cp.C)
+        return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
+    mc_server::Req r;
+    r.n = g->n;
+    r.nnz = g->nnz;
+    r.rp.assign(g->row_ptr, g->row_ptr + g->n + 1);
+    r.col.assign(g->col, g->col + g->nnz);
+    r.w.assign(g->w, g->w + g->nnz);
+    r.st.t_submit_ms = S->now();
+    const uint64_t id = S->next++;
+    S->reqs.emplace(id, std::move(r));
+    S->queue.push_back(id);
+    *ticket = id;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* queued) {
+    if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_step: NULL server");
+    Engine& E = S->E;
+    // admission in arrival order while the graphs fit
+    std::vector<mc_csr> adm;
+    std::vector<uint64_t> ids;
+    int64_t nv = 0, ne = 0;
+    while (!S->queue.empty()) {
+        const uint64_t id = S->queue.front();
+        mc_server::Req& r = S->reqs[id];
+        if (r.cancel) { S->queue.pop_front(); r.state = 3; continue; }
+        if (!E.fits((int32_t)adm.size() + 1, nv + r.n, ne + r.nnz)) {
+            if (adm.empty() && E.live() == 0) {
+                E.compact_n0();
+                if (!E.fits(1, r.n, r.nnz)) return mc_fail(MC_E_OOM, "mc_server_step: request does not fit");
+            } else {
+                break;
+            }
+        }
+        mc_csr g;
+        g.n = r.n;
+        g.nnz = r.nnz;
+        g.row_ptr = r.rp.data();
+        g.col = r.col.data();
+        g.w = r.w.data();
+        g.location = MC_HOST;
+        adm.push_back(g);
+        ids.push_back(id);
+        nv += r.n;
+        ne += r.nnz;
+        S->queue.pop_front();
+    }
+    mc_status st;
+    if (!adm.empty()) {
+        const size_t before = E.insts.size();
+        if ((st = E.admit(adm.data(), (int32_t)adm.size(), ids.data())) != MC_OK) return st;
+        const double t = S->now();
+        for (uint64_t id : ids) { S->reqs[id].state = 1; S->reqs[id].st.t_admit_ms = t; }
+        for (size_t i = before; i < E.insts.size(); i++)
+            if (E.insts[i].done) {
+                if ((st = finish(S, E.insts[i])) != MC_OK) return st;
+                E.insts[i].dead = true;
+            }
+    }
+    if (E.live() > 0) {
+        std::vector<EngineInst> fin;
+        if ((st = E.step(fin)) != MC_OK) return st;
+        for (const EngineInst& x : fin)
+            if ((st = finish(S, x)) != MC_OK) return st;
+    } else if (!E.insts.empty()) {
+        // only finished graphs left: one round drops them from the union graph
+        std::vector<EngineInst> fin;
+        if ((st = E.step(fin)) != MC_OK) return st;
+    }
+    if (in_flight) *in_flight = E.live();
+    if (queued) *queued = (int32_t)S->queue.size();
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_poll(mc_server* S, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_req_stats* st) {
+    if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_poll: NULL server");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return mc_fail(MC_E_INVALID_ARG, "mc_server_poll: unknown ticket");
+    mc_server::Req& r = it->second;
+    if (r.state == 3) {
+        S->reqs.erase(it);
+        return mc_fail(MC_E_CANCELLED, "mc_server_poll: request cancelled");
+    }
+    if (r.state != 2) return MC_E_NOT_READY;
+    if (lambda) *lambda = r.lam;
+    if (side) std::copy(r.side.begin(), r.side.end(), side);
+    if (st) *st = r.st;
+    S->reqs.erase(it);
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_cancel(mc_server* S, uint64_t ticket) {
+    if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_cancel: NULL server");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return mc_fail(MC_E_INVALID_ARG, "mc_server_cancel: unknown ticket");
+    it->second.cancel = true;
+    if (it->second.state == 2) it->second.state = 3;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_server_capacity(const mc_server* S, int64_t* entries, int32_t* vertices, int32_t* graphs,
+                                        size_t* bytes) {
+    if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_capacity: NULL server");
+    if (entries) *entries = S->E.cap.C;
+    if (vertices) *vertices = S->E.cap.N;
+    if (graphs) *graphs = S->E.cap.K;
+    if (bytes) *bytes = S->bytes;
     return MC_OK;
 }

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_group_count(const int32_t* __res
         __syncthreads();
         for (int k = 0; k < GT_PER; k++) {
             const int64_t u = t * GT + k * GT_THREADS + threadIdx.x;
-            if (u < n) gt_insert(key, cnt, L[u]);
+            if (u < n && L[u] >= 0) gt_insert(key, cnt, L[u]);   // label -1: the vertex is dropped
         }
         __syncthreads();
         for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS)
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_group_scatter(const int32_t* __r
         int slot[GT_PER];
         for (int k = 0; k < GT_PER; k++) {
             const int64_t u = t * GT + k * GT_THREADS + threadIdx.x;
-            slot[k] = u < n ? gt_insert(key, cnt, L[u]) : -1;
+            slot[k] = u < n && L[u] >= 0 ? gt_insert(key, cnt, L[u]) : -1;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < GT_SLOTS; i += GT_THREADS) {
@@ -107,10 +107,13 @@ __global__ __launch_bounds__(GT_THREADS) void k_group_scatter(const int32_t* __r
     }
 }
 
+// row length of every member in perm order; positions past the kept
+// members (vertices dropped with label -1) get 0
 __global__ void k_member_len(const int32_t* __restrict__ len, const int32_t* __restrict__ perm, int32_t n,
-                             int32_t* __restrict__ mlen) {
+                             const int32_t* __restrict__ kept, int32_t* __restrict__ mlen) {
+    const int64_t nk = kept ? *kept : n;
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (int64_t)gridDim.x * blockDim.x)
-        mlen[m] = len[perm ? perm[m] : m];
+        mlen[m] = m < nk ? len[perm ? perm[m] : m] : 0;
 }
 
 __global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t* __restrict__ mstart, int32_t n2,
@@ -591,7 +594,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
         perm = ws.perm;
         vstart = ws.vstart;
     }
-    k_member_len<<<grid_for(n, 256), 256, 0, s>>>(src.len, perm, n, ws.mstart);
+    k_member_len<<<grid_for(n, 256), 256, 0, s>>>(src.len, perm, n, vstart ? vstart + n2 : nullptr, ws.mstart);
     MC_LAUNCHED("k_member_len");
     if (!scan_i32(ws.mstart, ws.mstart, n, ws.scan_tmp, s)) return false;
     const int32_t* gstart = ws.mstart;

@@ -425,9 +425,12 @@ __global__ void k_pr3_accept(const int32_t* part3, const uint8_t* touch, int32_t
     }
 }
 
+// (entries of -1 stand for input vertices no longer tracked and stay -1)
 __global__ void k_map_update(int32_t* map0, const int32_t* L, int32_t n0) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
-        map0[v] = L[map0[v]];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t m = map0[v];
+        if (m >= 0) map0[v] = L[m];
+    }
 }
 
 __global__ void k_side_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int32_t* target) {

@@ -91,6 +91,8 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
 
 // Contract `src` by labels L (L == nullptr: identity, which only folds
 // loops, parallel and zero-weight entries) into `dst` with n2 vertices.
+// A vertex with label -1 is dropped (with its row; no kept row may point at
+// it).
 // dst.cap must be >= the sum of src.len. Writes dst.off/len/col/w/deg and
 // the minimum degree (and its vertex) into sc->dmin / sc->dmin_arg.
 bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws,

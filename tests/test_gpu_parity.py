@@ -633,8 +633,11 @@ def oracle_lambda(g):
 
 @pytest.mark.parametrize("seed,count", [(1, 40), (2, 200), (3, 700)])
 def test_batch_matches_oracle(ctx, seed, count):
+    import torch
     gs = batch_mix(seed, count)
-    lams, sides = ctx.mincut_batch(gs)
+    # a workspace full of stale bytes: nothing may rely on fresh memory
+    ws = torch.full((ctx.batch_workspace_bytes(gs),), 0xA5, dtype=torch.uint8, device=ctx.device)
+    lams, sides = ctx.mincut_batch(gs, workspace=ws)
     bad = []
     for i, g in enumerate(gs):
         ref = oracle_lambda(g)
@@ -676,3 +679,81 @@ def test_batch_rejects_bad_graphs(ctx):
     with pytest.raises(mc.MincutError) as e:
         ctx.mincut_batch(devs=devs)
     assert e.value.code == -2
+
+
+# ------------------------------------------------------------ served form
+def test_server_results_same_alone_and_in_the_mix(ctx):
+    # requests submitted while others are in flight join their rounds; every
+    # result equals the graph's result alone (and the oracle's)
+    import paper_2609_07204_amd as mc
+    srv = mc.Server(ctx, hbm_bytes=2 << 30, max_inflight=64, max_request_n=1 << 16, max_request_nnz=1 << 21)
+    say("server capacity", srv.capacity())
+    gs = batch_mix(21, 90) + [gen.config_batch_graph(i) for i in range(8)]
+    tickets = {}
+    results = {}
+    pending = list(range(len(gs)))
+    steps = 0
+    while pending or len(results) < len(gs):
+        # a few arrivals per step, so later graphs join rounds in progress
+        for _ in range(3):
+            if pending:
+                i = pending.pop(0)
+                tickets[srv.submit(gs[i])] = i
+        srv.step()
+        steps += 1
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+        assert steps < 10000
+    say("served", len(gs), "graphs in", steps, "steps")
+    joined_late = 0
+    for i, g in enumerate(gs):
+        lam, side, st = results[i]
+        alone, _ = ctx.mincut(g, want_side=False)
+        assert lam == alone == oracle_lambda(g), (i, g.name)
+        assert oracle.cut_value(g, side) == lam and side[0] == 0
+        assert st["t_submit_ms"] <= st["t_admit_ms"] <= st["t_done_ms"]
+        joined_late += st["rounds"] > 0
+    assert joined_late > 0
+    srv.close()
+
+
+def test_server_admits_by_memory_and_cancels(ctx):
+    import paper_2609_07204_amd as mc
+    srv = mc.Server(ctx, hbm_bytes=256 << 20, max_inflight=8, max_request_n=1 << 14, max_request_nnz=1 << 18)
+    cap = srv.capacity()
+    g_big = gen.mixed_graph(12000, 16, 2, 5, 1, 100)
+    with pytest.raises(mc.MincutError):
+        srv.submit(gen.mixed_graph(40000, 8, 1, 6, 1, 100))    # larger than any admission
+    ts = [srv.submit(g_big) for _ in range(6)]
+    t_small = srv.submit(gen.complete(6))
+    srv.cancel(ts[-1])
+    done = {}
+    for _ in range(5000):
+        a, q = srv.step()
+        for t in ts[:-1] + [t_small]:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        if len(done) == len(ts):
+            break
+    assert len(done) == len(ts)
+    ref = oracle.noi(g_big)[0]
+    assert all(done[t][0] == ref for t in ts[:-1]) and done[t_small][0] == 5
+    with pytest.raises(mc.MincutError) as e:
+        srv.poll(ts[-1])
+    assert e.value.code == -7
+    say("server capacity", cap)
+    srv.close()
+
+
+@pytest.mark.parametrize("fill", [0x00, 0xA5, 0xFF])
+def test_single_solve_ignores_stale_workspace(ctx, fill):
+    import torch
+    for g in (gen.config_planted_2x1000(), gen.mixed_graph(20000, 12, 2, 7, 1, 100), gen.wheel(50)):
+        ws = torch.full((ctx.workspace_bytes(g.n, g.nnz),), fill, dtype=torch.uint8, device=ctx.device)
+        lam, side = ctx.mincut(g, workspace=ws)
+        ref = oracle_lambda(g)
+        assert lam == ref and oracle.cut_value(g, side) == ref
