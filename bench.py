@@ -67,7 +67,7 @@ def batch_main(args, log):
     N = sum(g.n for g in gs)
     M = sum(g.nnz for g in gs)
     log("generated %d graphs: %d vertices, %d entries in %.1fs" % (len(gs), N, M, time.time() - t))
-    ctx = mc.Context(0, heuristic_min_n=0)
+    ctx = mc.Context(0)
     devs = [ctx.upload(g) for g in gs]
     ws = torch.empty(ctx.batch_workspace_bytes(devs=devs), dtype=torch.uint8, device=ctx.device)
     log("batch workspace %.2f GB" % (ws.numel() / 1e9))
@@ -130,6 +130,104 @@ def batch_main(args, log):
     print(json.dumps(out))
 
 
+def _served_graph(j):
+    import gen
+    g = gen.config_served_graph(j)
+    return g.n, g.row_ptr, g.col, g.w, g.name
+
+
+def served_main(args, log):
+    """Served workload: Poisson arrivals (seed 7) at each rate of --rates,
+    each request a graph drawn from a pool of pre-generated graphs (edge
+    counts log-uniform in [10^3, 10^7], the three families, weights 1-1000),
+    handled by the continuous-batching server (mc_server_*). Latency =
+    completion - arrival. Prints one JSON line; value = completed solves per
+    second at the highest rate."""
+    import multiprocessing as mp
+    import numpy as np
+    import gen
+    import paper_2609_07204_amd as mc
+
+    t = time.time()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        raw = pool.map(_served_graph, range(args.pool), chunksize=2)
+    gs = [gen.Graph(n, rp, col, w, name) for n, rp, col, w, name in raw]
+    log("pool of %d graphs: %d entries in %.1fs" % (len(gs), sum(g.nnz for g in gs), time.time() - t))
+    ctx = mc.Context(0)
+    alone = {}
+    srv = mc.Server(ctx, hbm_bytes=int(args.hbm_gb * (1 << 30)), max_inflight=args.max_inflight,
+                    max_request_n=max(g.n for g in gs), max_request_nnz=max(g.nnz for g in gs))
+    log("server capacity", srv.capacity())
+    rates = [float(x) for x in args.rates.split(",")]
+    per_rate = []
+    rng = np.random.default_rng(7)
+    for rate in rates:
+        picks = rng.integers(0, len(gs), args.requests)
+        gaps = rng.exponential(1.0 / rate, args.requests)
+        arrive = np.cumsum(gaps)
+        t0 = time.perf_counter()
+        nxt = 0
+        out = {}
+        lat = []
+        steps = 0
+        while len(lat) < args.requests:
+            now = time.perf_counter() - t0
+            while nxt < args.requests and arrive[nxt] <= now:
+                out[srv.submit(gs[picks[nxt]])] = nxt
+                nxt += 1
+            if out:
+                srv.step()
+                steps += 1
+                tdone = time.perf_counter() - t0
+                for tk in list(out):
+                    r = srv.poll(tk)
+                    if r is not None:
+                        i = out.pop(tk)
+                        lat.append(tdone - arrive[i])
+                        j = int(picks[i])
+                        if j not in alone:
+                            alone[j] = r[0]
+                        assert r[0] == alone[j], "served result differs between requests of one graph"
+            elif nxt < args.requests:
+                time.sleep(max(0.0, min(0.001, arrive[nxt] - now)))
+        el = time.perf_counter() - t0
+        lat_ms = np.array(lat) * 1000.0
+        rec = {"rate_per_s": rate, "requests": args.requests, "solves_per_s": args.requests / el,
+               "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+               "steps": steps}
+        per_rate.append(rec)
+        log("rate %.0f/s: %.1f solves/s, p50 %.1f ms, p99 %.1f ms, %d steps" % (
+            rate, rec["solves_per_s"], rec["p50_ms"], rec["p99_ms"], steps))
+    # every distinct graph served: its result equals the graph solved alone
+    for j, lam in alone.items():
+        lam1, _ = ctx.mincut(gs[j], want_side=False)
+        assert lam == lam1, ("served and alone differ", j)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        done = 0
+        for j in sorted(alone):
+            assert oracle.noi(gs[j])[0] == alone[j]
+            done += 1
+            if time.perf_counter() - t > 15.0:
+                break
+        tc = time.perf_counter() - t
+        cpu = {"value": done / tc, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "%d distinct pool graphs, one NOI solve each, %.1f s" % (done, tc)}
+    top = per_rate[-1]
+    out = {
+        "metric": "served min-cut solves/sec", "value": top["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": 0, "ms_per_step": 1000.0 / top["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "served: Poisson arrivals, pool of %d graphs (m log-uniform [1e3, 1e7], planted / "
+                               "Erdos-Renyi / Chung-Lu, weights 1-1000, seeds 2000000+j)" % len(gs),
+                   "hbm_gb": args.hbm_gb, "max_inflight": args.max_inflight, "rates": per_rate},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,10 +239,15 @@ def main():
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--len-cap", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="time the steps without kernel events")
-    ap.add_argument("--workload", choices=["chung_lu", "batch"], default="chung_lu",
+    ap.add_argument("--workload", choices=["chung_lu", "batch", "served"], default="chung_lu",
                     help="chung_lu: one exact solve of the Chung-Lu graph (default); batch: the mixed batch, "
-                         "batched against plain per-graph solves")
+                         "batched against plain per-graph solves; served: Poisson requests to the server")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--rates", default="50,200,1000")
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--hbm-gb", type=float, default=48.0)
+    ap.add_argument("--max-inflight", type=int, default=256)
     ap.add_argument("--heuristic-min-n", type=int, default=10000,
                     help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
     args = ap.parse_args()
@@ -158,6 +261,8 @@ def main():
 
     if args.workload == "batch":
         return batch_main(args, log)
+    if args.workload == "served":
+        return served_main(args, log)
 
     import torch
     import gen

@@ -350,6 +350,22 @@ def mixed_graph(n, d, fam, seed, wlo, whi):
     return chung_lu(n, 2.5, float(d), seed, wlo, whi, kcore=0, lcc=True)
 
 
+def served_params(j, seed0=2000000):
+    """Edge count, mean degree and family of pool graph j of the served
+    workload: m = floor(10^(3 + 4U)), mean degree uniform in {8..32},
+    family j mod 3; n = max(64, 2m / d)."""
+    r = SplitMix64(seed0 + j)
+    m = int(math.floor(10 ** (3 + 4 * r.unit())))
+    d = 8 + r.below(25)
+    n = max(64, (2 * m) // d)
+    return n, d, j % 3
+
+
+def config_served_graph(j, seed0=2000000):
+    n, d, fam = served_params(j, seed0)
+    return mixed_graph(n, d, fam, seed0 + j, 1, 1000)
+
+
 def config_batch_graph(i, seed0=1000):
     n, d, fam = batch_params(i, seed0)
     return mixed_graph(n, d, fam, seed0 + i, 1, 100)

@@ -147,8 +147,11 @@ mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws
  * lambdas[i] (host, k values) is graph i's minimum cut; if sides != NULL and
  * sides[i] != NULL, sides[i] (host, n_i bytes) receives one side of it with
  * sides[i][0] = 0. per_graph (host, k values, may be NULL) receives MC_OK
- * for every graph. The label-propagation heuristic is not run in this form
- * (every graph starts from its minimum degree). Synchronises the stream. */
+ * for every graph. When heuristic_min_n > 0, every graph first goes
+ * through the label-propagation heuristic's coarsening (LP rounds and
+ * cluster contraction while the graphs shrink; the smallest collapsed
+ * degree of each level bounds lambda), all graphs in the same launches, but
+ * without its reduction tests and exact finish. Synchronises the stream. */
 mc_status mc_batch_workspace_size(const mc_ctx* ctx, int32_t k, const mc_csr* graphs, size_t* bytes);
 mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
                           int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
@@ -168,6 +171,10 @@ typedef struct {
     int32_t max_inflight;      /* graphs in the rounds at once (0: 1024) */
     int32_t max_request_n;     /* largest request, vertices (0: 2^20) */
     int64_t max_request_nnz;   /* largest request, entries (0: 2^25) */
+    int32_t solo_min_n;        /* requests with at least this many vertices
+                                  are solved one per step by mc_mincut (whole
+                                  GPU, full heuristic) from a workspace set
+                                  aside in the budget (0: 65536) */
 } mc_server_opts;
 typedef struct {
     double t_submit_ms, t_admit_ms, t_done_ms;   /* since the server was created */
@@ -186,6 +193,8 @@ mc_status mc_server_step(mc_server* srv, int32_t* in_flight, int32_t* queued);
  * timing once done (the ticket is then released); MC_E_NOT_READY before;
  * MC_E_CANCELLED for a cancelled request (released). */
 mc_status mc_server_poll(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_req_stats* st);
+/* *state: 0 queued, 1 in flight, 2 done (poll returns it), 3 cancelled. */
+mc_status mc_server_state(const mc_server* srv, uint64_t ticket, int32_t* state);
 /* Cancel a request: a queued one is never admitted, one in flight is
  * dropped when its rounds end. */
 mc_status mc_server_cancel(mc_server* srv, uint64_t ticket);

@@ -62,7 +62,7 @@ MC_K_COUNT = 7  # kernels mc_profile times (MC_K_* in include/mincut.h)
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_request_n", ctypes.c_int32),
-                ("max_request_nnz", ctypes.c_int64)]
+                ("max_request_nnz", ctypes.c_int64), ("solo_min_n", ctypes.c_int32)]
 
 
 class ReqStats(ctypes.Structure):
@@ -96,6 +96,7 @@ SIGNATURES = {
     "mc_server_step": (ctypes.c_int, [P, P, P]),
     "mc_server_poll": (ctypes.c_int, [P, ctypes.c_uint64, P, P, P]),
     "mc_server_cancel": (ctypes.c_int, [P, ctypes.c_uint64]),
+    "mc_server_state": (ctypes.c_int, [P, ctypes.c_uint64, P]),
     "mc_server_capacity": (ctypes.c_int, [P, P, P, P, P]),
     "mc_profile": (ctypes.c_int, [P, I32]),
     "mc_profile_read": (ctypes.c_int, [P, I32, P]),
@@ -382,9 +383,9 @@ class Context:
 class Server:
     """Continuous-batching request server (mc_server_*) on a context."""
 
-    def __init__(self, ctx, hbm_bytes, max_inflight=0, max_request_n=0, max_request_nnz=0):
+    def __init__(self, ctx, hbm_bytes, max_inflight=0, max_request_n=0, max_request_nnz=0, solo_min_n=0):
         self.ctx = ctx
-        self.opts = ServerOpts(hbm_bytes, max_inflight, max_request_n, max_request_nnz)
+        self.opts = ServerOpts(hbm_bytes, max_inflight, max_request_n, max_request_nnz, solo_min_n)
         h = ctypes.c_void_p()
         _check(lib().mc_server_create(ctx.h, ctypes.byref(self.opts), ctypes.byref(h)))
         self.h = h
@@ -422,8 +423,15 @@ class Server:
         _check(lib().mc_server_step(self.h, ctypes.byref(a), ctypes.byref(q)))
         return a.value, q.value
 
+    def state(self, ticket):
+        st = ctypes.c_int32()
+        _check(lib().mc_server_state(self.h, ticket, ctypes.byref(st)))
+        return st.value
+
     def poll(self, ticket):
         """None while running, else (lambda, side, stats dict)."""
+        if self.state(ticket) < 2:
+            return None
         lam = ctypes.c_int64()
         side = np.zeros(self.n[ticket], np.uint8)
         st = ReqStats()

@@ -15,8 +15,9 @@
 //  - bounds, collapsed degrees (Section 2.1 "Overall algorithm"), the
 //    sequential fallback of Algorithm 2 and the sides are kept per graph.
 // A graph leaves the rounds when at most two of its vertices remain. The
-// label-propagation heuristic is not run here: every graph starts from its
-// minimum degree (the bound only changes the work, not the result).
+// label-propagation heuristic coarsens every graph at admission and bounds
+// its lambda with the collapsed degrees it meets (the bound only changes the
+// work, not the result).
 #include <algorithm>
 #include <vector>
 
@@ -269,6 +270,49 @@ __global__ void k_eg_start(const int64_t* dmin, const int32_t* darg, int32_t k, 
     }
 }
 
+// The label-propagation heuristic of Section 2.1 ("Lowering the upper
+// bound") on newly admitted graphs, all at once: label propagation, every
+// cluster contracted to one vertex, and again on the coarse graphs, while
+// they shrink. A collapsed vertex's degree is the capacity of the cut
+// around the input vertices it stands for, so each level's smallest
+// collapsed degree (while a graph still has two or more coarse vertices)
+// bounds that graph's lambda, with those input vertices as the side.
+// Clusters never join two graphs (no edge does), so the coarse vertices of
+// each graph stay one contiguous range.
+__global__ void k_eg_level_bound(const int32_t* coff2, const int64_t* dmin, int32_t k, int64_t* best, uint8_t* hit) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        hit[i] = 0;
+        if (coff2[i + 1] - coff2[i] >= 2 && dmin[i] < best[i]) {
+            best[i] = dmin[i];
+            hit[i] = 1;
+        }
+    }
+}
+
+// side of graphs whose bound dropped at this level: stage vertex v is on the
+// side iff its coarse vertex is the graph's smallest-degree one
+__global__ void k_eg_level_side(const int32_t* maps, const int32_t* inst_rel, const uint8_t* hit, const int32_t* darg,
+                                int32_t ns, uint8_t* sideh) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < ns; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = inst_rel[v];
+        if (hit[i]) sideh[v] = maps[v] == darg[i];
+    }
+}
+
+// the heuristic's bound replaces the minimum degree where it is smaller
+__global__ void k_eg_apply_heuristic(const int64_t* best, int32_t k, int64_t* lam, uint8_t* use) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        use[i] = best[i] < lam[i];
+        if (use[i]) lam[i] = best[i];
+    }
+}
+
+__global__ void k_eg_side_heuristic(uint8_t* side, const int32_t* inst_rel, const uint8_t* use, const uint8_t* sideh,
+                                    int32_t ns) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < ns; v += (int64_t)gridDim.x * blockDim.x)
+        if (use[inst_rel[v]]) side[v] = sideh[v];
+}
+
 struct Caps {
     int32_t N = 0;        // vertices of the union graph
     int64_t C = 0;        // entry capacity of the union graph
@@ -299,6 +343,13 @@ struct EngineWS {
     ContractWS cw;
     Pr12WS prw;
     Pr34WS tw;
+    LpWS lw;
+    int32_t *h_lab, *h_map;   // [Ns] canonical cluster labels; stage vertex -> coarse vertex
+    uint8_t* h_side;          // [Ns] side of the heuristic's best bound
+    int32_t *h_off, *h_off2;  // [K+1] coarse ranges of the graphs
+    int64_t *best, *h_dmin;   // [K]
+    int32_t* h_darg;          // [K]
+    uint8_t* h_hit;           // [K]
     PrivateArgs pv;
     unsigned long long* pmarks;
     unsigned long long* vpart;
@@ -351,6 +402,16 @@ void carve_engine(Arena& a, const Caps& cp, EngineWS& w) {
     contract_ws_carve(a, std::max(N, Ns), std::max(C, Cs), w.cw);
     pr12_ws_carve(a, N, C, w.prw);
     pr34_ws_carve(a, N, w.tw);
+    lp_ws_carve(a, Ns, Cs, w.lw);
+    w.h_lab = a.take<int32_t>((size_t)Ns + 1);
+    w.h_map = a.take<int32_t>((size_t)Ns + 1);
+    w.h_side = a.take<uint8_t>((size_t)Ns + 1);
+    w.h_off = a.take<int32_t>((size_t)K + 1);
+    w.h_off2 = a.take<int32_t>((size_t)K + 1);
+    w.best = a.take<int64_t>((size_t)K + 1);
+    w.h_dmin = a.take<int64_t>((size_t)K + 1);
+    w.h_darg = a.take<int32_t>((size_t)K + 1);
+    w.h_hit = a.take<uint8_t>((size_t)K + 1);
     PrivateArgs& pv = w.pv;
     pv = PrivateArgs{};
     pv.passes = K;
@@ -521,6 +582,10 @@ struct Engine {
             EG_OK(csr_to_padded(w.in_rp, NS, user.off, user.len, s));
             EG_OK(contract(user, nullptr, NS, S, w.cw, w.sc, s));
         }
+        // the label-propagation heuristic on the staged graphs (every graph
+        // at once); its best bounds are applied after the minimum degrees
+        const bool lp = c->opt.heuristic_min_n > 0;
+        if (lp) EG_OK(heuristic_levels(S, k, NS, sv));
         DGraph& G = w.g[cur];
         k_eg_append<<<grid_for((int64_t)CS + NS, 256), 256, 0, s>>>(S, CS, G, n, used);
         EG_OK(mc_hip_ok(hipGetLastError(), "k_eg_append"));
@@ -539,6 +604,11 @@ struct Engine {
         k_bg_side<<<grid_for(NS, 256), 256, 0, s>>>(w.side + n0_used, w.map0 + n0_used, w.inst0 + n0_used, NS, w.snap,
                                                     w.darg, w.inpref);
         k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
+        if (lp) {
+            k_eg_apply_heuristic<<<grid_for(k, 256), 256, 0, s>>>(w.best, k, w.lam, w.h_hit);
+            k_eg_side_heuristic<<<grid_for(NS, 256), 256, 0, s>>>(w.side + n0_used, w.inst0 + n0_used, w.h_hit,
+                                                                  w.h_side, NS);
+        }
         EG_OK(mc_hip_ok(hipGetLastError(), "admit sides"));
         std::vector<int64_t> lam(k);
         EG_HIP(hipMemcpyAsync(lam.data(), w.lam, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
@@ -558,6 +628,55 @@ struct Engine {
         used += CS;
         n0_used += NS;
         return MC_OK;
+    }
+
+    // Multi-level label propagation on the staged graphs S (k graphs, NS
+    // vertices, ranges sv): w.best receives each graph's best collapsed
+    // degree and w.h_side the matching side. The coarse graphs live in the
+    // two union-graph buffers that are not current.
+    bool heuristic_levels(const DGraph& S, int32_t k, int32_t NS, const std::vector<int32_t>& sv) {
+        const int iters = c->opt.lp_iters > 0 ? c->opt.lp_iters : 2;
+        if (!fill_i64(w.best, INT64_MAX, k, s) || !fill_u8(w.h_side, 0, NS, s) || !iota_i32(w.h_map, NS, s))
+            return false;
+        MC_HIP(hipMemcpyAsync(w.h_off, sv.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+        // graph index of every stage vertex (relative ranges)
+        k_bg_vinst<<<grid_for(NS, 256), 256, 0, s>>>(w.s_voff, k, NS, w.vinst);
+        MC_LAUNCHED("k_bg_vinst");
+        DGraph Gc = S;
+        int bi = (cur + 1) % 3;
+        std::vector<int32_t> co(k + 1);
+        for (int level = 0; level < 32; level++) {
+            const int32_t nc = Gc.n;
+            int32_t* la = w.parent;
+            int32_t* lb = w.L;
+            if (!iota_i32(la, nc, s)) return false;
+            for (int it = 0; it < iters; it++) {
+                if (!lp_round(Gc, la, lb, w.lw, w.cw, s)) return false;
+                std::swap(la, lb);
+            }
+            if (!lp_relabel(la, nc, w.h_lab, w.flag, w.cw.scan_tmp, w.sc, s)) return false;
+            k_bg_offsets<<<grid_for(k + 1, 256), 256, 0, s>>>(w.flag, w.h_off, k, w.h_off2);
+            MC_LAUNCHED("k_bg_offsets");
+            if (!readback()) return false;
+            const int32_t n2 = c->hsc->n2;
+            if ((int64_t)n2 * 20 > (int64_t)nc * 19) break;   // shrank by less than 5 percent
+            DGraph& Gn = w.g[bi];
+            if (!contract(Gc, w.h_lab, n2, Gn, w.cw, w.sc, s) || !map_update(w.h_map, w.h_lab, NS, s)) return false;
+            k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(Gn.deg, w.h_off2, k, w.h_dmin, w.h_darg);
+            k_eg_level_bound<<<grid_for(k, 256), 256, 0, s>>>(w.h_off2, w.h_dmin, k, w.best, w.h_hit);
+            k_eg_level_side<<<grid_for(NS, 256), 256, 0, s>>>(w.h_map, w.vinst, w.h_hit, w.h_darg, NS, w.h_side);
+            MC_LAUNCHED("heuristic level");
+            std::swap(w.h_off, w.h_off2);
+            Gc = Gn;
+            bi = bi == (cur + 1) % 3 ? (cur + 2) % 3 : (cur + 1) % 3;
+            // stop once no graph has more than two coarse vertices
+            MC_HIP(hipMemcpyAsync(co.data(), w.h_off, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
+            MC_HIP(hipStreamSynchronize(s));
+            bool more = false;
+            for (int32_t i = 0; i < k && !more; i++) more = co[i + 1] - co[i] > 2;
+            if (!more) break;
+        }
+        return true;
     }
 
     // Move the input-vertex ranges of live graphs to the front.
@@ -836,6 +955,9 @@ struct mc_server {
     void* mem = nullptr;
     size_t bytes = 0;
     Engine E;
+    void* solo_ws = nullptr;      // workspace of one large request solved on its own
+    size_t solo_bytes = 0;
+    int32_t solo_min_n = 0;
     std::chrono::steady_clock::time_point t0;
     struct Req {
         std::vector<int32_t> rp, col;
@@ -896,23 +1018,42 @@ mc_status finish(mc_server* S, const EngineInst& x) {
 extern "C" mc_status mc_server_create(mc_ctx* c, const mc_server_opts* opts, mc_server** out) {
     if (!c || !opts || !out) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: NULL argument");
     if (opts->hbm_bytes < ((size_t)64 << 20)) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget below 64 MiB");
+    // requests of at least solo_min_n vertices are solved one at a time by
+    // the single-graph solver (whole-GPU CAPFOREST steps, the full
+    // heuristic); the rest of the budget holds the engine
+    const int32_t rn = opts->max_request_n > 0 ? opts->max_request_n : (1 << 20);
+    const int64_t re = opts->max_request_nnz > 0 ? opts->max_request_nnz : ((int64_t)1 << 25);
+    const int32_t solo_min_n = opts->solo_min_n > 0 ? opts->solo_min_n : (1 << 16);
+    size_t solo = 0;
+    if (rn >= solo_min_n) {
+        if (mc_workspace_size(c, rn, (int32_t)std::min<int64_t>(re, INT32_MAX / 2), &solo) != MC_OK) return MC_E_INVALID_ARG;
+        solo = (solo + 4095) & ~(size_t)4095;
+    }
+    if (solo + ((size_t)64 << 20) > opts->hbm_bytes)
+        return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget too small for the largest request");
+    const size_t engine_budget = opts->hbm_bytes - solo;
     // the largest entry capacity whose engine fits the budget
+    mc_server_opts eo = *opts;
+    if (rn >= solo_min_n) eo.max_request_n = solo_min_n - 1;
     int64_t lo = 1024, hi = (int64_t)1 << 30;
-    if (engine_bytes(server_caps(*opts, lo)) > opts->hbm_bytes)
+    if (engine_bytes(server_caps(eo, lo)) > engine_budget)
         return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget too small for the options");
     while (hi - lo > 1024) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (engine_bytes(server_caps(*opts, mid)) <= opts->hbm_bytes) lo = mid; else hi = mid;
+        if (engine_bytes(server_caps(eo, mid)) <= engine_budget) lo = mid; else hi = mid;
     }
-    const Caps cp = server_caps(*opts, lo);
+    const Caps cp = server_caps(eo, lo);
     mc_server* S = new (std::nothrow) mc_server();
     if (!S) return mc_fail(MC_E_OOM, "mc_server_create: out of host memory");
     S->c = c;
-    S->bytes = engine_bytes(cp);
-    if (hipSetDevice(c->device) != hipSuccess || hipMalloc(&S->mem, S->bytes) != hipSuccess) {
+    S->bytes = (engine_bytes(cp) + 4095) & ~(size_t)4095;
+    S->solo_bytes = solo;
+    S->solo_min_n = solo_min_n;
+    if (hipSetDevice(c->device) != hipSuccess || hipMalloc(&S->mem, S->bytes + solo) != hipSuccess) {
         delete S;
         return mc_fail(MC_E_OOM, "mc_server_create: device allocation of the budget failed");
     }
+    if (solo) S->solo_ws = (char*)S->mem + S->bytes;
     mc_status r = S->E.init(c, cp, S->mem, S->bytes);
     if (r != MC_OK) {
         (void)hipFree(S->mem);
@@ -937,8 +1078,13 @@ extern "C" mc_status mc_server_submit(mc_server* S, const mc_csr* g, uint64_t* t
     if (g->n < 2 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
         return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: bad graph");
     const Caps& cp = S->E.cap;
-    if (g->n > cp.nmax || g->n > cp.Ns || g->nnz > cp.Cs || g->n > cp.N || g->nnz > cp.C)
+    if (g->n >= S->solo_min_n) {
+        size_t need = 0;
+        if (!S->solo_ws || mc_workspace_size(S->c, g->n, g->nnz, &need) != MC_OK || need > S->solo_bytes)
+            return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
+    } else if (g->n > cp.nmax || g->n > cp.Ns || g->nnz > cp.Cs || g->n > cp.N || g->nnz > cp.C) {
         return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
+    }
     mc_server::Req r;
     r.n = g->n;
     r.nnz = g->nnz;
@@ -956,6 +1102,34 @@ extern "C" mc_status mc_server_submit(mc_server* S, const mc_csr* g, uint64_t* t
 extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* queued) {
     if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_step: NULL server");
     Engine& E = S->E;
+    mc_status st;
+    auto host_csr = [](const mc_server::Req& r) {
+        mc_csr g;
+        g.n = r.n;
+        g.nnz = r.nnz;
+        g.row_ptr = r.rp.data();
+        g.col = r.col.data();
+        g.w = r.w.data();
+        g.location = MC_HOST;
+        return g;
+    };
+    // a large request at the head of the queue is solved on its own now
+    while (!S->queue.empty() && S->reqs[S->queue.front()].cancel) {
+        S->reqs[S->queue.front()].state = 3;
+        S->queue.pop_front();
+    }
+    if (!S->queue.empty() && S->reqs[S->queue.front()].n >= S->solo_min_n) {
+        const uint64_t id = S->queue.front();
+        S->queue.pop_front();
+        mc_server::Req& r = S->reqs[id];
+        r.st.t_admit_ms = S->now();
+        r.side.assign((size_t)r.n, 0);
+        const mc_csr g = host_csr(r);
+        if ((st = mc_mincut(S->c, &g, S->solo_ws, S->solo_bytes, &r.lam, r.side.data(), nullptr)) != MC_OK) return st;
+        r.state = r.cancel ? 3 : 2;
+        r.st.t_done_ms = S->now();
+        r.st.rounds = 0;
+    }
     // admission in arrival order while the graphs fit
     std::vector<mc_csr> adm;
     std::vector<uint64_t> ids;
@@ -964,6 +1138,7 @@ extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* q
         const uint64_t id = S->queue.front();
         mc_server::Req& r = S->reqs[id];
         if (r.cancel) { S->queue.pop_front(); r.state = 3; continue; }
+        if (r.n >= S->solo_min_n) break;          // waits for its own step
         if (!E.fits((int32_t)adm.size() + 1, nv + r.n, ne + r.nnz)) {
             if (adm.empty() && E.live() == 0) {
                 E.compact_n0();
@@ -972,20 +1147,12 @@ extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* q
                 break;
             }
         }
-        mc_csr g;
-        g.n = r.n;
-        g.nnz = r.nnz;
-        g.row_ptr = r.rp.data();
-        g.col = r.col.data();
-        g.w = r.w.data();
-        g.location = MC_HOST;
-        adm.push_back(g);
+        adm.push_back(host_csr(r));
         ids.push_back(id);
         nv += r.n;
         ne += r.nnz;
         S->queue.pop_front();
     }
-    mc_status st;
     if (!adm.empty()) {
         const size_t before = E.insts.size();
         if ((st = E.admit(adm.data(), (int32_t)adm.size(), ids.data())) != MC_OK) return st;
@@ -1029,6 +1196,14 @@ extern "C" mc_status mc_server_poll(mc_server* S, uint64_t ticket, int64_t* lamb
     return MC_OK;
 }
 
+extern "C" mc_status mc_server_state(const mc_server* S, uint64_t ticket, int32_t* state) {
+    if (!S || !state) return mc_fail(MC_E_INVALID_ARG, "mc_server_state: NULL argument");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return mc_fail(MC_E_INVALID_ARG, "mc_server_state: unknown ticket");
+    *state = it->second.state;
+    return MC_OK;
+}
+
 extern "C" mc_status mc_server_cancel(mc_server* S, uint64_t ticket) {
     if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_cancel: NULL server");
     auto it = S->reqs.find(ticket);
@@ -1044,6 +1219,6 @@ extern "C" mc_status mc_server_capacity(const mc_server* S, int64_t* entries, in
     if (entries) *entries = S->E.cap.C;
     if (vertices) *vertices = S->E.cap.N;
     if (graphs) *graphs = S->E.cap.K;
-    if (bytes) *bytes = S->bytes;
+    if (bytes) *bytes = S->bytes + S->solo_bytes;
     return MC_OK;
 }

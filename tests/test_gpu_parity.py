@@ -682,11 +682,14 @@ def test_batch_rejects_bad_graphs(ctx):
 
 
 # ------------------------------------------------------------ served form
-def test_server_results_same_alone_and_in_the_mix(ctx):
-    # requests submitted while others are in flight join their rounds; every
-    # result equals the graph's result alone (and the oracle's)
+@pytest.mark.parametrize("solo_min_n", [0, 2000])
+def test_server_results_same_alone_and_in_the_mix(ctx, solo_min_n):
+    # requests submitted while others are in flight join their rounds (or,
+    # from solo_min_n vertices on, are solved on their own between rounds);
+    # every result equals the graph's result alone (and the oracle's)
     import paper_2609_07204_amd as mc
-    srv = mc.Server(ctx, hbm_bytes=2 << 30, max_inflight=64, max_request_n=1 << 16, max_request_nnz=1 << 21)
+    srv = mc.Server(ctx, hbm_bytes=2 << 30, max_inflight=64, max_request_n=1 << 16, max_request_nnz=1 << 21,
+                    solo_min_n=solo_min_n)
     say("server capacity", srv.capacity())
     gs = batch_mix(21, 90) + [gen.config_batch_graph(i) for i in range(8)]
     tickets = {}
@@ -716,6 +719,8 @@ def test_server_results_same_alone_and_in_the_mix(ctx):
         assert st["t_submit_ms"] <= st["t_admit_ms"] <= st["t_done_ms"]
         joined_late += st["rounds"] > 0
     assert joined_late > 0
+    if solo_min_n:
+        assert any(results[i][2]["rounds"] == 0 for i, g in enumerate(gs) if g.n >= solo_min_n)
     srv.close()
 
 
