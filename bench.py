@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--hbm-gb", type=float, default=48.0)
     ap.add_argument("--max-inflight", type=int, default=256)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the solves, one device-to-device copy of this many MiB (the known-size kernel "
+                         "that scales hardware byte counters)")
     ap.add_argument("--heuristic-min-n", type=int, default=10000,
                     help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
     args = ap.parse_args()
@@ -313,6 +316,15 @@ def main():
                     "avg_launch_us": 1000.0 * r["ms"] / r["launches"],
                     "bytes_per_launch": r["bytes"] / r["launches"],
                     "kernel_ms_per_step": r["ms"] / args.steps}
+
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=ctx.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB device to device" % args.calibrate_copy)
+        del src, dst
 
     golden = {}
     gpath = os.path.join(ROOT, "tests", "golden", "lambda.json")

@@ -1,0 +1,76 @@
+"""HBM traffic per launch of the timed kernels, from two rocprofv3 counter
+runs of bench.py (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy MIB).
+
+The counters are scaled by what they read for the calibration copy, a
+device-to-device copy of known size (MIB MiB read and MIB MiB written), so
+the result is in bytes. Writes profiles/traffic.json: for every kernel, the
+average bytes per launch, the factors, and the SHA-256 of the source file
+that holds the kernel (bench.py reports the figure only while that file is
+unchanged).
+
+    python -m paper_2609_07204_amd.traffic FETCH_DIR WRITE_DIR MIB
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+
+KERNEL_SOURCE = {
+    "k_cfs_edges": "paper_2609_07204_amd/csrc/mc_capforest_steps.hip",
+    "k_merge_small": "paper_2609_07204_amd/csrc/mc_contract.hip",
+    "k_big_insert": "paper_2609_07204_amd/csrc/mc_contract.hip",
+    "k_group_count": "paper_2609_07204_amd/csrc/mc_contract.hip",
+    "k_group_scatter": "paper_2609_07204_amd/csrc/mc_contract.hip",
+    "k_pr12": "paper_2609_07204_amd/csrc/mc_graph_ops.hip",
+    "k_uf_link_rest": "paper_2609_07204_amd/csrc/mc_graph_ops.hip",
+}
+
+
+def per_kernel(d, counter):
+    """{short kernel name: [values per dispatch]} from a rocprofv3 counter
+    collection directory."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    out = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].strip()
+            out.setdefault(name, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def main(fetch_dir, write_dir, mib):
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
+    if not copy:
+        raise SystemExit("no copy kernel among the dispatches")
+    ck = max(copy, key=lambda k: max(fetch[k]))
+    nbytes = float(mib) * (1 << 20)
+    f_fetch = nbytes / max(fetch[ck])             # bytes per counter unit
+    f_write = nbytes / max(write.get(ck, [0.0]) or [1.0])
+    res = {"_calibration": {"copy_kernel": ck, "copy_bytes": nbytes, "fetch_factor": f_fetch,
+                            "write_factor": f_write}}
+    for k, src in KERNEL_SOURCE.items():
+        if k not in fetch or k not in write:
+            continue
+        fb = sum(fetch[k]) / len(fetch[k]) * f_fetch
+        wb = sum(write[k]) / len(write[k]) * f_write
+        res[k] = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                  "launches": len(fetch[k]), "source": src,
+                  "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    json.dump(res, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps(res, indent=1, sort_keys=True))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], sys.argv[2], sys.argv[3])
