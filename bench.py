@@ -233,15 +233,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--log2n", type=int, default=22)
+    ap.add_argument("--log2n", type=int, default=None, help="graph size (default 2^22 Chung-Lu, 2^23 hyperbolic)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--len-cap", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="time the steps without kernel events")
-    ap.add_argument("--workload", choices=["chung_lu", "batch", "served"], default="chung_lu",
-                    help="chung_lu: one exact solve of the Chung-Lu graph (default); batch: the mixed batch, "
-                         "batched against plain per-graph solves; served: Poisson requests to the server")
+    ap.add_argument("--workload", choices=["chung_lu", "rhg", "batch", "served"], default="chung_lu",
+                    help="chung_lu: one exact solve of the Chung-Lu graph (default); rhg: one exact solve of "
+                         "the random hyperbolic graph; batch: the mixed batch, batched against plain per-graph "
+                         "solves; served: Poisson requests to the server")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--rates", default="50,200,1000")
@@ -272,7 +273,16 @@ def main():
     import paper_2609_07204_amd as mc
 
     t = time.time()
-    g = gen.config_chung_lu(args.log2n, args.seed)
+    if args.workload == "rhg":
+        args.log2n = args.log2n or 23
+        g = gen.config_rhg(args.log2n, args.seed)
+        key = "rhg_2^%d_core32_seed%d" % (args.log2n, args.seed)
+        wname = ("rhg n=2^%d avg_deg=64 gamma=5 32-core LCC weights 1-100 seed=%d" % (args.log2n, args.seed))
+    else:
+        args.log2n = args.log2n or 22
+        g = gen.config_chung_lu(args.log2n, args.seed)
+        key = "chung_lu_2^%d_core10_seed%d" % (args.log2n, args.seed)
+        wname = ("chung_lu n=2^%d beta=2.5 avg_deg=20 10-core LCC unit weights seed=%d" % (args.log2n, args.seed))
     log("generated %s: n=%d m=%d in %.1fs" % (g.name, g.n, g.m, time.time() - t))
     ctx = mc.Context(0, capforest_passes=args.passes, pass_len_cap=args.len_cap,
                      heuristic_min_n=args.heuristic_min_n)
@@ -330,7 +340,6 @@ def main():
     gpath = os.path.join(ROOT, "tests", "golden", "lambda.json")
     if os.path.exists(gpath):
         golden = json.load(open(gpath))
-    key = "chung_lu_2^%d_core10_seed%d" % (args.log2n, args.seed)
     if key in golden:
         assert golden[key]["lambda"] == lam, ("lambda differs from the oracle's", lam, golden[key])
 
@@ -357,8 +366,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "chung_lu n=2^%d beta=2.5 avg_deg=20 10-core LCC unit weights seed=%d"
-                               % (args.log2n, args.seed), "n": g.n, "m": g.m, "lambda": lam,
+        "config": {"workload": wname, "n": g.n, "m": g.m, "lambda": lam,
                    "rounds": stats[-1]["rounds"], "heuristic_levels": stats[-1]["heuristic_levels"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -77,7 +77,10 @@ mc_status mc_step_pr34(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t D, 
  * largest total edge weight to v, except that v keeps lab_in[v] unless
  * another label is strictly heavier; ties among other labels go to the
  * smallest label. lab_in / lab_out: [g->n] labels in [0, n), distinct
- * arrays. */
+ * arrays. lab_in NULL means singleton labels (lab_in[v] = v), the
+ * heuristic's first round, taken by a streaming pass that needs g normal
+ * (as contraction writes it: no loop, no parallel entries, positive
+ * weights). */
 mc_status mc_step_lp(mc_ctx* ctx, const mc_dgraph* g, const int32_t* lab_in, int32_t* lab_out, void* ws,
                      size_t ws_bytes);
 

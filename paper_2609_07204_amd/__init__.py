@@ -354,13 +354,14 @@ class Context:
         return flag, acc[:g.n].cpu().numpy(), lab[:g.n].cpu().numpy(), n2.value
 
     def step_lp(self, g, lab_in):
-        """One label-propagation round on device graph g (see mc_step_lp)."""
+        """One label-propagation round on device graph g (see mc_step_lp);
+        lab_in None: singleton labels (g must be normal)."""
         torch = _torch()
-        a = torch.as_tensor(np.ascontiguousarray(lab_in, np.int32)).to(self.device)
+        a = None if lab_in is None else torch.as_tensor(np.ascontiguousarray(lab_in, np.int32)).to(self.device)
         out = torch.empty(max(g.n, 1), dtype=torch.int32, device=self.device)
         ws = self.step_workspace(g.n, g.cap)
-        _check(lib().mc_step_lp(self.h, ctypes.byref(g.c()), _ptr(a), _ptr(out), ctypes.c_void_p(ws.data_ptr()),
-                                ws.numel()))
+        _check(lib().mc_step_lp(self.h, ctypes.byref(g.c()), None if a is None else _ptr(a), _ptr(out),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return out[:g.n].cpu().numpy()
 
     def step_capforest(self, g, lam, start=0, mode=CF_SEQUENTIAL, passes=1, shared=False, len_cap=0):

@@ -480,6 +480,7 @@ struct Engine {
         one.passes = 1;
         EG_OK(capforest_private_reset(one, s));
         EG_OK(fill_i32((int32_t*)w.sc, 0, sizeof(DevScalars) / 4, s));
+        EG_OK(contract_ws_reset(w.cw, s));
         // prefix marks are set and cleared per round; they start all zero
         EG_OK(fill_u8(w.inpref, 0, (int64_t)cp.N + 1, s));
         tri_on = c->opt.pr_tri_deg_cap > 0;
@@ -649,8 +650,10 @@ struct Engine {
             const int32_t nc = Gc.n;
             int32_t* la = w.parent;
             int32_t* lb = w.L;
-            if (!iota_i32(la, nc, s)) return false;
-            for (int it = 0; it < iters; it++) {
+            // the first round starts from singleton labels on a normal graph
+            if (!lp_first(Gc, lb, w.lw, w.cw, s)) return false;
+            std::swap(la, lb);
+            for (int it = 1; it < iters; it++) {
                 if (!lp_round(Gc, la, lb, w.lw, w.cw, s)) return false;
                 std::swap(la, lb);
             }

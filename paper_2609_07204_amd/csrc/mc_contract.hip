@@ -123,24 +123,28 @@ __global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t*
 }
 
 // Split groups into the chunk path and the large-group path; every group
-// gets its output window start. A few giant groups (at least a quarter of
-// n2 entries) accumulate into a dense array over all n2 targets instead of a
-// hash table: no probing, and the extraction is a stream over n2 values.
-constexpr int DENSE_SLOTS = 4;
+// gets its output window start. Giant groups (at least a quarter of n2
+// entries, so a table of twice their entries would be at least half as long
+// as n2) accumulate into a dense array over all n2 targets instead of a hash
+// table: no probing, a footprint of 8 n2 bytes, and the extraction is a
+// stream over n2 values. The accumulator area is a fixed budget, so the
+// number of dense groups is at most budget / n2 (and DENSE_MAX).
+constexpr int DENSE_MAX = 1024;
 
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
-                           int32_t* __restrict__ tsize, int32_t* __restrict__ bigm, int32_t* __restrict__ bcur,
-                           int32_t* __restrict__ dslot, int32_t* __restrict__ dinfo, DGraph dst) {
-    const int64_t dense_min = n2 / 4 > 16384 ? n2 / 4 : 16384;
+                           int32_t nd_max, int32_t* __restrict__ tsize, int32_t* __restrict__ bigm,
+                           int32_t* __restrict__ bcur, int32_t* __restrict__ dslot, int32_t* __restrict__ dinfo,
+                           DGraph dst) {
+    const int64_t dense_min = n2 / 4;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x) {
         int32_t s = gstart[g + 1] - gstart[g];
         dst.off[g] = gstart[g];
         dslot[g] = -1;
         if (s > SMALL_MAX) {
             int32_t d = -1;
-            if (s >= dense_min) {
+            if (s >= dense_min && nd_max > 0) {
                 d = atomicAdd(&dinfo[0], 1);
-                if (d < DENSE_SLOTS) { dslot[g] = d; dinfo[1 + d] = (int32_t)g; } else d = -1;
+                if (d < nd_max) { dslot[g] = d; dinfo[1 + d] = (int32_t)g; } else d = -1;
             }
             const int64_t t = ((2 * (int64_t)s + TILE_SLOTS - 1) / TILE_SLOTS) * TILE_SLOTS;
             tsize[g] = d >= 0 ? 0 : (int32_t)t;
@@ -312,9 +316,12 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
                                                    const int32_t* __restrict__ dslot, int64_t* __restrict__ dense,
                                                    const int32_t* __restrict__ tinfo, DGraph dst,
                                                    unsigned long long* pb) {
+    constexpr int PER = BIG_TILE / 256;     // entries per thread and segment pass
+    constexpr int FL = BIG_HSLOTS / 256;    // table slots per thread in the flush
     __shared__ unsigned long long hkey[BIG_HSLOTS];
     __shared__ long long hval[BIG_HSLOTS];
     __shared__ int32_t wm[BIG_TILE + 2];     // member-space start of each member in the window
+    __shared__ int32_t wo[BIG_TILE + 1];     // row offset of each member in the window
     __shared__ int32_t info[4];              // g, first member, member count in window, g's group end
     const int64_t total = bebase[n2];
     const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
@@ -325,50 +332,86 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
         const int64_t e1 = e0 + BIG_TILE < total ? e0 + BIG_TILE : total;
         // a tile may straddle groups; handle it one group segment at a time
         int64_t e = e0;
+        int32_t gprev = -1;
         while (e < e1) {
             __syncthreads();
-            if (threadIdx.x == 0) {
-                const int32_t g = e == e0 ? tinfo[2 * tile] : last_le(bebase, n2, e);
-                const int32_t m0 = vstart ? vstart[g] : g;
-                const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
-                const int32_t mf = e == e0 ? tinfo[2 * tile + 1]
-                                           : m0 + last_le(mstart + m0, mc, gstart[g] + (int32_t)(e - bebase[g]));
-                info[0] = g;
-                info[1] = mf;
-                info[2] = (m0 + mc) - mf;            // members from mf to the group's end
-                info[3] = bebase[g + 1];
+            if (threadIdx.x < MC_WAVE) {
+                // the tile's first group and member were found beforehand; a
+                // later segment starts a large group at its first entry: the
+                // next large group after the previous one, looked for by the
+                // whole wavefront 64 groups at a time (small groups in
+                // between own no entries of this space)
+                int32_t g = -1;
+                if (e == e0) {
+                    g = tinfo[2 * tile];
+                } else {
+                    int32_t base = gprev + 1;
+                    for (int it = 0; it < 8 && g < 0; it++, base += MC_WAVE) {
+                        const int32_t gg = base + (int32_t)lane_id();
+                        const unsigned long long m = __ballot(gg < n2 && (int64_t)bebase[gg + 1] > e);
+                        if (m) g = base + __ffsll((long long)m) - 1;
+                    }
+                    if (g < 0) g = last_le(bebase, n2, e);
+                }
+                if (threadIdx.x == 0) {
+                    const int32_t m0 = vstart ? vstart[g] : g;
+                    const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
+                    const int32_t mf = e == e0 ? tinfo[2 * tile + 1] : m0;
+                    info[0] = g;
+                    info[1] = mf;
+                    info[2] = (m0 + mc) - mf;            // members from mf to the group's end
+                    info[3] = bebase[g + 1];
+                }
             }
             __syncthreads();
             const int32_t g = info[0], mf = info[1];
+            gprev = g;
             const int32_t wc = info[2] < BIG_TILE + 1 ? info[2] : BIG_TILE + 1;
             const int64_t seg_end = (int64_t)info[3] < e1 ? (int64_t)info[3] : e1;
-            for (int i = threadIdx.x; i <= wc; i += blockDim.x) wm[i] = mstart[mf + i];
+            for (int i = threadIdx.x; i <= wc; i += blockDim.x) {
+                wm[i] = mstart[mf + i];
+                if (i < wc) wo[i] = src.off[perm ? perm[mf + i] : mf + i];
+            }
             __syncthreads();
             const int32_t gbase = gstart[g] - bebase[g];
-            for (int64_t f = e + threadIdx.x; f < seg_end; f += blockDim.x) {
-                const int32_t ge = gbase + (int32_t)f;
+            // each thread's entries of the segment, their loads issued
+            // together: row offset (LDS), entry, label of its target
+            int32_t x[PER];
+            int64_t c[PER];
+#pragma unroll
+            for (int q = 0; q < PER; q++) {
+                const int64_t f = e + threadIdx.x + q * 256;
+                c[q] = 0;
+                x[q] = 0;
+                if (f >= seg_end) continue;
                 nin++;
-                int32_t k;
+                const int32_t ge = gbase + (int32_t)f;
+                int32_t o, j;
                 if (ge < wm[wc]) {
                     int32_t lo = 0, hi = wc;
                     while (hi - lo > 1) { int32_t mid = (lo + hi) >> 1; if (wm[mid] <= ge) lo = mid; else hi = mid; }
-                    k = mf + lo;
+                    o = wo[lo];
+                    j = ge - wm[lo];
                 } else {
                     // rows shorter than one entry cannot occur in a contracted
                     // graph; search HBM if a window is ever too short
                     const int32_t m0 = vstart ? vstart[g] : g;
                     const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
-                    k = m0 + last_le(mstart + m0, mc, ge);
+                    const int32_t k = m0 + last_le(mstart + m0, mc, ge);
+                    o = src.off[perm ? perm[k] : k];
+                    j = ge - mstart[k];
                 }
-                const int32_t u = perm ? perm[k] : k;
-                const int32_t j = ge - mstart[k];
-                const int32_t x = src.col[src.off[u] + j];
-                const int64_t c = src.w[src.off[u] + j];
-                if (c <= 0) continue;
-                const int32_t t = L ? L[x] : x;
-                if (t == g) continue;
-                const unsigned long long key = ((unsigned long long)(uint32_t)g << 32) | (uint32_t)t;
-                uint32_t h = hash32((uint32_t)t ^ hash32((uint32_t)g)) & (BIG_HSLOTS - 1);
+                x[q] = src.col[o + j];
+                c[q] = src.w[o + j];
+            }
+            int32_t t[PER];
+#pragma unroll
+            for (int q = 0; q < PER; q++) t[q] = c[q] > 0 ? (L ? L[x[q]] : x[q]) : g;
+#pragma unroll
+            for (int q = 0; q < PER; q++) {
+                if (t[q] == g) continue;   // loop, zero weight or no entry
+                const unsigned long long key = ((unsigned long long)(uint32_t)g << 32) | (uint32_t)t[q];
+                uint32_t h = hash32((uint32_t)t[q] ^ hash32((uint32_t)g)) & (BIG_HSLOTS - 1);
                 for (;;) {
                     unsigned long long kk = hkey[h];
                     if (kk == key) break;
@@ -378,34 +421,60 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
                     }
                     h = (h + 1) & (BIG_HSLOTS - 1);
                 }
-                atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c);
+                atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c[q]);
             }
             e = seg_end;
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < BIG_HSLOTS; i += blockDim.x) {
-            const unsigned long long k = hkey[i];
-            if (k == EMPTY_KEY) continue;
-            const int32_t g = (int32_t)(k >> 32);
-            const int32_t t = (int32_t)(k & 0xFFFFFFFFu);
-            const int32_t d = dslot[g];
+        // flush: each thread's table slots go out together; a probe is one
+        // compare-and-swap that claims an empty slot or finds the key, and
+        // all of a thread's pending probes are in flight at once
+        int32_t fg[FL], ft[FL], fb[FL], fs[FL];
+        uint32_t fh[FL];
+        long long fv[FL];
+        bool pend[FL];
+#pragma unroll
+        for (int q = 0; q < FL; q++) {
+            const unsigned long long k = hkey[threadIdx.x + q * 256];
+            pend[q] = k != EMPTY_KEY;
+            fg[q] = (int32_t)(k >> 32);
+            ft[q] = (int32_t)(k & 0xFFFFFFFFu);
+            fv[q] = hval[threadIdx.x + q * 256];
+        }
+#pragma unroll
+        for (int q = 0; q < FL; q++) {
+            fs[q] = 0;
+            fb[q] = 0;
+            fh[q] = 0;
+            if (!pend[q]) continue;
+            const int32_t d = dslot[fg[q]];
             if (d >= 0) {
-                atomic_add_i64(&dense[(int64_t)d * n2 + t], hval[i]);
+                atomic_add_i64(&dense[(int64_t)d * n2 + ft[q]], fv[q]);
+                pend[q] = false;
                 continue;
             }
-            const int32_t tb = tbase[g];
-            const uint32_t ts = (uint32_t)(tbase[g + 1] - tb);
-            uint32_t h = (uint32_t)(((uint64_t)hash32((uint32_t)t) * ts) >> 32);
-            for (;;) {
-                int32_t kk = ld_acq(&tkey[tb + h]);
-                if (kk == t) break;
-                if (kk == -1) {
-                    int32_t old = atomicCAS(&tkey[tb + h], -1, t);
-                    if (old == -1 || old == t) break;
+            fb[q] = tbase[fg[q]];
+            fs[q] = tbase[fg[q] + 1] - fb[q];
+            fh[q] = (uint32_t)(((uint64_t)hash32((uint32_t)ft[q]) * (uint32_t)fs[q]) >> 32);
+        }
+        for (;;) {
+            bool any = false;
+            int32_t old[FL];
+#pragma unroll
+            for (int q = 0; q < FL; q++)
+                if (pend[q]) old[q] = atomicCAS(&tkey[fb[q] + fh[q]], -1, ft[q]);
+#pragma unroll
+            for (int q = 0; q < FL; q++) {
+                if (!pend[q]) continue;
+                if (old[q] == -1 || old[q] == ft[q]) {
+                    atomic_add_i64(&tval[fb[q] + fh[q]], fv[q]);
+                    pend[q] = false;
+                } else {
+                    if (++fh[q] == (uint32_t)fs[q]) fh[q] = 0;
+                    any = true;
                 }
-                if (++h == ts) h = 0;
             }
-            atomic_add_i64(&tval[tb + h], hval[i]);
+            if (!any) break;
         }
         __syncthreads();
     }
@@ -433,21 +502,28 @@ __device__ __forceinline__ int32_t block_alloc(int32_t* ctr, bool take, int64_t 
     return s_base[0] + s_cnt[wid] + rank;
 }
 
+// group of every 256-slot table tile (tables are whole tiles), searched for
+// all tiles at once so the searches' latencies overlap
+__global__ void k_big_xtiles(const int32_t* __restrict__ tbase, int32_t n2, int32_t* __restrict__ xg) {
+    const int64_t ntiles = tbase[n2] / TILE_SLOTS;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x)
+        xg[t] = last_le(tbase, n2, t * TILE_SLOTS);
+}
+
 __global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __restrict__ tbase,
                                                             const int32_t* __restrict__ gstart, int32_t n2,
+                                                            const int32_t* __restrict__ xg,
                                                             const int32_t* __restrict__ tkey,
                                                             const int64_t* __restrict__ tval,
                                                             int32_t* __restrict__ bcur, DGraph dst) {
-    __shared__ int32_t sg, s_cnt[TILE_SLOTS / MC_WAVE], s_base[1];
+    __shared__ int32_t s_cnt[TILE_SLOTS / MC_WAVE], s_base[1];
     __shared__ long long s_sum[TILE_SLOTS / MC_WAVE];
     const int64_t ntiles = tbase[n2] / TILE_SLOTS;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * TILE_SLOTS;
-        __syncthreads();
-        if (threadIdx.x == 0) sg = last_le(tbase, n2, base);
-        __syncthreads();
-        const int32_t g = sg;
+        const int32_t g = xg[t];
         const int64_t k = base + threadIdx.x;
+        __syncthreads();   // the previous tile's block_alloc results are read
         const int32_t key = tkey[k];
         const int64_t v = key >= 0 ? tval[k] : 0;
         const int32_t pos = block_alloc(&bcur[g], key >= 0, v, &dst.deg[g], s_cnt, s_sum, s_base);
@@ -460,13 +536,13 @@ __global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __res
 
 // dense accumulators of the giant groups: stream over n2 targets, emit the
 // non-zero ones, and leave the array zero for the next contraction
-__global__ __launch_bounds__(256) void k_dense_extract(const int32_t* __restrict__ dinfo,
+__global__ __launch_bounds__(256) void k_dense_extract(const int32_t* __restrict__ dinfo, int32_t nd_max,
                                                        const int32_t* __restrict__ gstart, int32_t n2,
                                                        int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
                                                        DGraph dst) {
     __shared__ int32_t s_cnt[4], s_base[1];
     __shared__ long long s_sum[4];
-    const int32_t nd = dinfo[0] < DENSE_SLOTS ? dinfo[0] : DENSE_SLOTS;
+    const int32_t nd = dinfo[0] < nd_max ? dinfo[0] : nd_max;
     const int64_t per = ((int64_t)n2 + 255) / 256 * 256;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nd * per;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -552,14 +628,21 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
     ws.tkey = a.take<int32_t>(slots);
     ws.tval = a.take<int64_t>(slots);
     ws.dslot = a.take<int32_t>((size_t)n + 1);
-    ws.dinfo = a.take<int32_t>(1 + DENSE_SLOTS);
-    ws.dense = a.take<int64_t>((size_t)DENSE_SLOTS * ((size_t)n + 1));
+    ws.dinfo = a.take<int32_t>(1 + DENSE_MAX);
+    // accumulator budget: the entries' weight array at most, 512 MB at most,
+    // and never below four accumulators of n + 1
+    const int64_t lim = cap < ((int64_t)1 << 26) ? cap : ((int64_t)1 << 26);
+    ws.dense_elems = lim > 4 * ((int64_t)n + 1) ? lim : 4 * ((int64_t)n + 1);
+    ws.dense = a.take<int64_t>((size_t)ws.dense_elems);
     ws.scan_tmp = a.take<int32_t>(scan_tmp_elems((int64_t)n + 2) + 16);
     ws.red_val = a.take<int64_t>(1024);
     ws.red_id = a.take<int32_t>(1024);
     ws.cg = a.take<int32_t>((size_t)((cap + n) / CHUNK) + 4);
     ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
+    ws.xg = a.take<int32_t>(slots / TILE_SLOTS + 8);
 }
+
+bool contract_ws_reset(const ContractWS& ws, hipStream_t s) { return fill_i64(ws.dense, 0, ws.dense_elems, s); }
 
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) {
     int nb = grid_for(g.n, 256, 1024);
@@ -603,9 +686,13 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
         MC_LAUNCHED("k_group_start");
         gstart = ws.gstart;
     }
-    if (!fill_i32(ws.dinfo, 0, 1 + DENSE_SLOTS, s) || !fill_i64(ws.dense, 0, (int64_t)DENSE_SLOTS * n2, s)) return false;
-    k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, ws.tsize, ws.bigm, ws.bcur, ws.dslot, ws.dinfo,
-                                                 dst);
+    // the dense accumulators are zero here (reset after carving, and every
+    // extraction clears what it read)
+    const int64_t ndm = ws.dense_elems / (n2 > 0 ? n2 : 1);
+    const int32_t nd_max = (int32_t)(ndm < DENSE_MAX ? ndm : DENSE_MAX);
+    if (!fill_i32(ws.dinfo, 0, 1, s)) return false;
+    k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, nd_max, ws.tsize, ws.bigm, ws.bcur, ws.dslot,
+                                                 ws.dinfo, dst);
     MC_LAUNCHED("k_classify");
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
     if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
@@ -627,10 +714,12 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
                                       ws.tval, ws.dslot, ws.dense, ws.tinfo, dst, prof_dev_bytes(PK_BIG_INSERT));
     MC_LAUNCHED("k_big_insert");
     prof_end(PK_BIG_INSERT, s);
-    k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.tkey, ws.tval, ws.bcur, dst);
+    k_big_xtiles<<<grid_for((src.cap * 5 / 2) / TILE_SLOTS + 8, 256), 256, 0, s>>>(ws.tsize, n2, ws.xg);
+    MC_LAUNCHED("k_big_xtiles");
+    k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.xg, ws.tkey, ws.tval, ws.bcur, dst);
     MC_LAUNCHED("k_big_extract");
-    k_dense_extract<<<grid_for((int64_t)DENSE_SLOTS * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, gstart, n2, ws.dense,
-                                                                                   ws.bcur, dst);
+    k_dense_extract<<<grid_for((int64_t)nd_max * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, nd_max, gstart, n2, ws.dense,
+                                                                              ws.bcur, dst);
     MC_LAUNCHED("k_dense_extract");
     k_big_finalize<<<grid_for(n2, 256), 256, 0, s>>>(ws.bigm, n2, ws.bcur, dst);
     MC_LAUNCHED("k_big_finalize");

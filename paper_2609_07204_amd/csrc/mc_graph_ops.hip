@@ -41,19 +41,17 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
 // Connectivity in the manner of Afforest (Sutton, Ben-Nun and Barak, IPDPS
 // 2018), on a graph whose entries all have positive weight (a normalised
 // graph). Two hooking sweeps over the first CONNECT_K entries of every row
-// first join most of the graph: in each, a row lowers the root of its own
+// first join much of the graph: in each, a row lowers the root of its own
 // tree to the smallest root among those neighbours (parent[] is compressed
 // before each sweep, so par[v] is a root); pointers only ever decrease, so
 // the forest stays acyclic and the union-find invariant parent[x] <= x
-// holds. The first sweep, from the identity, hooks every vertex to its
-// smallest such neighbour; the second joins those trees (on power-law
-// graphs the largest tree then holds nearly every vertex). Then the
-// component most sampled vertices fall into is found, and all edges are
-// linked with full unions only for vertices outside it; an edge between that
-// component and another one is seen from the other side. Which edges the
-// sweeps looked at does not matter for exactness: they only join connected
-// vertices, and every edge with an endpoint outside the sampled component is
-// linked afterwards.
+// holds. (Full unions here would be exact sooner, but on power-law graphs
+// thousands of them then meet at the root of the growing giant tree, one
+// compare-and-swap at a time.) Then the component most sampled vertices fall
+// into is found, and the remaining edges are linked (k_uf_link_rest).
+// Exactness does not depend on what the sweeps joined: they only join
+// connected vertices, and every edge whose endpoints were apart when the
+// sweeps ended is linked afterwards.
 constexpr int CONNECT_K = 8;   // entries per row the hooking sweeps look at
 
 __global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par) {
@@ -93,18 +91,36 @@ __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int
     if (threadIdx.x == 0) *mode = bestr[0];
 }
 
-__global__ __launch_bounds__(256) void k_uf_link_rest(DGraph g, int32_t* par, const int32_t* mode,
-                                                     unsigned long long* pb) {
+// After a compress: snap[v] = v's root, inbig[v] = 1 iff that root is the
+// root of the largest sampled component.
+__global__ void k_uf_snapshot(const int32_t* par, int32_t n, const int32_t* mode, uint8_t* inbig, int32_t* snap) {
     const int32_t big = *mode;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = par[v];
+        snap[v] = r;
+        inbig[v] = r == big;
+    }
+}
+
+// The edges still to link: those whose endpoints were in different trees
+// at the snapshot. Rows of the largest sampled component skip whole, so an
+// edge is linked from its smaller endpoint's row, or from the outside
+// endpoint's row when the other endpoint is in that component. The
+// snapshot is taken before any of these unions (roots move while they run).
+__global__ __launch_bounds__(256) void k_uf_link_rest(DGraph g, int32_t* par, const uint8_t* __restrict__ inbig,
+                                                     const int32_t* __restrict__ snap, unsigned long long* pb) {
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
-        if (sl == 0) bytes += 4;
-        if (ld_acq(&par[v]) == big) continue;
-        const int32_t o = g.off[v], l = g.len[v];
-        for (int32_t j = sl; j < l; j += SUB) uf_union(par, (int32_t)v, g.col[o + j]);
-        if (sl == 0) bytes += 8 + 8 * (int64_t)l;
+        if (sl == 0) bytes += 1;
+        if (inbig[v]) continue;
+        const int32_t o = g.off[v], l = g.len[v], rv = snap[v];
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = g.col[o + j];
+            if ((x > v || inbig[x]) && snap[x] != rv) uf_union(par, (int32_t)v, x);
+        }
+        if (sl == 0) bytes += 12 + 9 * (int64_t)l;
     }
     if (pb) prof_add(pb, bytes);
 }
@@ -132,7 +148,12 @@ __global__ void k_label(const int32_t* par, const int32_t* newid, int32_t n, int
 
 // Padberg-Rinaldi tests on the current graph with bound lam:
 //  test 1: an edge of weight >= lam joins two vertices whose connectivity is
-//          at least lam, so no cut below lam separates them;
+//          at least lam, so no cut below lam separates them; the test-1
+//          edges are joined as Afforest joins a graph: each row's first
+//          test-1 neighbour is unioned, then the component most sampled
+//          vertices fall into is found, and only rows outside it union all
+//          their test-1 entries (once the bound is small nearly every edge
+//          passes, and nearly every row then skips);
 //  test 2: if 2 c(v,p) >= c(v) for v's heaviest neighbour p (smallest id on
 //          ties), moving v to p's side of any cut does not increase it; one
 //          such pointer per vertex may be contracted together with all
@@ -146,7 +167,8 @@ constexpr int32_t PR_CHUNK = 4096;
 // (off, len, deg) of the rows this kernel tests.
 __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                              unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
-                                             int32_t* long_list, int32_t* long_cnt, unsigned long long* pb) {
+                                             int32_t* long_list, int32_t* long_cnt, int32_t* first, int32_t* heavy_cnt,
+                                             unsigned long long* pb) {
     const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
@@ -155,30 +177,40 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
         const int32_t o = g.off[v], l = g.len[v];
         if (l > PR_LONG) {
-            if (sl == 0) long_list[atomicAdd(long_cnt, 1)] = (int32_t)v;
+            if (sl == 0) {
+                long_list[atomicAdd(long_cnt, 1)] = (int32_t)v;
+                first[v] = -1;       // a long row unions its test-1 entries itself
+                heavy_cnt[v] = 0;
+            }
             continue;
         }
         if (sl == 0) bytes += 16 + 12 * (int64_t)l;
         const int64_t lam = vinst ? lamp[vinst[v]] : lam0;   // bound of v's instance
         int64_t bw = -1;
         int32_t bx = -1;
+        int32_t hj = INT32_MAX, hn = 0;    // first test-1 entry, test-1 entries
         for (int32_t j = sl; j < l; j += SUB) {
             const int32_t x = g.col[o + j];
             const int64_t c = g.w[o + j];
             const bool heavy = c >= lam;
             if (flag1) flag1[o + j] = heavy;
-            if (heavy && x > v && uf_union(par, (int32_t)v, x)) joined++;
+            if (heavy) { hn++; hj = j < hj ? j : hj; }
             if (c > bw || (c == bw && x < bx)) { bw = c; bx = x; }
         }
         for (int k = SUB / 2; k > 0; k >>= 1) {
             int64_t w2 = __shfl_xor(bw, k, SUB);
             int32_t x2 = __shfl_xor(bx, k, SUB);
             if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
+            const int32_t hj2 = __shfl_xor(hj, k, SUB);
+            hj = hj2 < hj ? hj2 : hj;
+            hn += __shfl_xor(hn, k, SUB);
         }
         const bool take = bx >= 0 && 2 * bw >= g.deg[v];
         if (sl == 0) {
             if (ptr2) ptr2[v] = take ? bx : -1;
             if (take && uf_union(par, (int32_t)v, bx)) joined++;
+            first[v] = hj != INT32_MAX ? g.col[o + hj] : -1;
+            heavy_cnt[v] = hn;
         }
     }
     // marks go to one of SPREAD partial counters (128 B apart): a single
@@ -189,6 +221,53 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
         atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
     }
     if (pb) prof_add(pb, bytes);
+}
+
+// each row's first test-1 neighbour (marks go to the partial counters)
+__global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ first, int32_t n, int32_t* par,
+                                                  unsigned long long* marks) {
+    unsigned long long joined = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = first[v];
+        if (x >= 0 && uf_union(par, (int32_t)v, x)) joined++;
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
+        atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
+    }
+}
+
+// rows with more test-1 entries than the first, outside the sampled
+// component: union all of them (an edge into that component from a row
+// inside it is seen from this side)
+__global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
+                                                 const int32_t* __restrict__ heavy_cnt,
+                                                 const uint8_t* __restrict__ inbig, const int32_t* __restrict__ snap,
+                                                 unsigned long long* marks) {
+    const int64_t lam0 = *lamp;
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    unsigned long long joined = 0;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        if (heavy_cnt[v] < 2 || inbig[v]) continue;
+        const int32_t o = g.off[v], l = g.len[v], rv = snap[v];
+        const int64_t lam = vinst ? lamp[vinst[v]] : lam0;
+        // as in k_uf_link_rest: edges between different snapshot trees,
+        // from the smaller endpoint or from outside into the sampled
+        // component (a long row links all of its test-1 entries itself, and
+        // a row whose only test-1 entry is its first one was linked by
+        // k_pr1_first)
+        for (int32_t j = sl; j < l; j += SUB) {
+            const int32_t x = g.col[o + j];
+            if (g.w[o + j] >= lam && (x > v || inbig[x]) && snap[x] != rv && uf_union(par, (int32_t)v, x)) joined++;
+        }
+    }
+    joined = (unsigned long long)wave_sum_i64((int64_t)joined);
+    if (lane_id() == 0 && joined) {
+        const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
+        atomicAdd(&marks[(size_t)slot * SPREAD_STRIDE], joined);
+    }
 }
 
 // fold the partial counters of k_pr12 into the round's mark count
@@ -238,6 +317,7 @@ __global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp
                                                   const int32_t* task_off, int64_t* part_w, int32_t* part_x) {
     __shared__ int64_t sw[4];
     __shared__ int32_t sx[4];
+    __shared__ int32_t s_rv;
     const int64_t lam0 = *lamp;
     const int32_t nl = *long_cnt;
     const int32_t ntask = task_off[nl];
@@ -249,6 +329,11 @@ __global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp
         const int64_t lam = vinst ? lamp[vinst[v]] : lam0;
         const int32_t j0 = (t - task_off[i]) * PR_CHUNK;
         const int32_t j1 = j0 + PR_CHUNK < l ? j0 + PR_CHUNK : l;
+        // every union of the piece involves v: find its root once, so the
+        // threads do not all walk (and shorten) v's path at the same time
+        if (threadIdx.x == 0) s_rv = uf_find(par, v);
+        __syncthreads();
+        const int32_t rv = s_rv;
         int64_t bw = -1;
         int32_t bx = -1;
         for (int32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -256,7 +341,7 @@ __global__ __launch_bounds__(256) void k_pr12_long(DGraph g, const int64_t* lamp
             const int64_t c = g.w[o + j];
             const bool heavy = c >= lam;
             if (flag1) flag1[o + j] = heavy;
-            if (heavy && x > v && uf_union(par, v, x)) joined++;
+            if (heavy && uf_union(par, rv, x)) joined++;
             if (c > bw || (c == bw && x < bx)) { bw = c; bx = x; }
         }
         int32_t aux = 0;
@@ -557,7 +642,7 @@ bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
     return true;
 }
 
-bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s) {
+bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, uint8_t* inbig, int32_t* snap, hipStream_t s) {
     const int rows = grid_for((int64_t)g.n * SUB, 256);
     for (int sweep = 0; sweep < 2; sweep++) {
         k_uf_root_min<<<grid_for(g.n, 256), 256, 0, s>>>(g, parent);
@@ -567,8 +652,10 @@ bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t
     }
     k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, tmp);
     MC_LAUNCHED("k_uf_sample_mode");
+    k_uf_snapshot<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, tmp, inbig, snap);
+    MC_LAUNCHED("k_uf_snapshot");
     prof_begin(PK_UF_LINK_REST, s);
-    k_uf_link_rest<<<rows, 256, 0, s>>>(g, parent, tmp, prof_dev_bytes(PK_UF_LINK_REST));
+    k_uf_link_rest<<<rows, 256, 0, s>>>(g, parent, inbig, snap, prof_dev_bytes(PK_UF_LINK_REST));
     MC_LAUNCHED("k_uf_link_rest");
     prof_end(PK_UF_LINK_REST, s);
     return true;
@@ -596,6 +683,11 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
     w.part_w = a.take<int64_t>(tasks);
     w.part_x = a.take<int32_t>(tasks);
     w.spread = a.take<unsigned long long>((size_t)SPREAD * SPREAD_STRIDE);
+    w.first = a.take<int32_t>((size_t)n + 1);
+    w.heavy = a.take<int32_t>((size_t)n + 1);
+    w.mode = a.take<int32_t>(4);
+    w.inbig = a.take<uint8_t>((size_t)n + 1);
+    w.snap = a.take<int32_t>((size_t)n + 1);
 }
 
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
@@ -604,9 +696,20 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
     if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s)) return false;
     prof_begin(PK_PR12, s);
     k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.spread, flag1, ptr2, w.long_list,
-                                                            w.counters, prof_dev_bytes(PK_PR12));
+                                                            w.counters, w.first, w.heavy, prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
+    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, g.n, parent, w.spread);
+    MC_LAUNCHED("k_pr1_first");
+    k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
+    MC_LAUNCHED("k_uf_compress");
+    k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, w.mode);
+    MC_LAUNCHED("k_uf_sample_mode");
+    k_uf_snapshot<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, w.mode, w.inbig, w.snap);
+    MC_LAUNCHED("k_uf_snapshot");
+    k_pr1_rest<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.heavy, w.inbig, w.snap,
+                                                                w.spread);
+    MC_LAUNCHED("k_pr1_rest");
     k_pr12_fold<<<1, SPREAD, 0, s>>>(w.spread, marks);
     MC_LAUNCHED("k_pr12_fold");
     k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);

@@ -330,6 +330,128 @@ __global__ void k_lp_long_final(const int32_t* __restrict__ lab_in, int32_t* __r
     }
 }
 
+// The round from singleton labels (lab_in[v] = v) on a normal graph (no
+// loop, no parallel entries, positive weights): every neighbour carries its
+// own label, so a label's weight is the weight of the one edge to it, the
+// own label weighs nothing, and the rule above picks the heaviest
+// neighbour, the smallest one on ties (v itself when the row is empty). One
+// streaming pass over the rows, 16 lanes per row; rows longer than LP_SMALL
+// are listed and take a workgroup each.
+__device__ __forceinline__ void lp_better(int64_t c, int32_t x, int64_t& bw, int32_t& bx) {
+    if (c > 0 && (c > bw || (c == bw && x < bx))) { bw = c; bx = x; }
+}
+
+constexpr int LP_FIRST_TASK = 4096;   // entries per piece of a long row
+
+__global__ __launch_bounds__(256) void k_lp_first(DGraph g, int32_t* __restrict__ lab_out,
+                                                 int32_t* __restrict__ long_list, int32_t* __restrict__ long_base,
+                                                 int32_t* __restrict__ counters, int32_t* __restrict__ task_row,
+                                                 int32_t* __restrict__ task_idx) {
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / LP_SUB);
+    const int sl = threadIdx.x % LP_SUB;
+    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / LP_SUB) + threadIdx.x / LP_SUB; v < g.n; v += nsub) {
+        const int32_t o = g.off[v], l = g.len[v];
+        if (l > LP_SMALL) {
+            // listed with its pieces; the 16 lanes write the task table
+            const int32_t nt = (l + LP_FIRST_TASK - 1) / LP_FIRST_TASK;
+            int32_t k = 0, t0 = 0;
+            if (sl == 0) {
+                k = atomicAdd(&counters[0], 1);
+                t0 = atomicAdd(&counters[2], nt);
+                long_list[k] = (int32_t)v;
+                long_base[k] = t0;
+            }
+            k = __shfl(k, 0, LP_SUB);
+            t0 = __shfl(t0, 0, LP_SUB);
+            for (int32_t t = sl; t < nt; t += LP_SUB) { task_row[t0 + t] = k; task_idx[t0 + t] = t; }
+            continue;
+        }
+        int64_t bw = 0;
+        int32_t bx = INT32_MAX;
+        int32_t j = sl;
+        for (; j + 3 * LP_SUB < l; j += 4 * LP_SUB) {   // four independent loads in flight
+            int32_t x[4];
+            int64_t c[4];
+            for (int u = 0; u < 4; u++) { x[u] = g.col[o + j + u * LP_SUB]; c[u] = g.w[o + j + u * LP_SUB]; }
+            for (int u = 0; u < 4; u++) if (x[u] != (int32_t)v) lp_better(c[u], x[u], bw, bx);
+        }
+        for (; j < l; j += LP_SUB) {
+            const int32_t x = g.col[o + j];
+            if (x != (int32_t)v) lp_better(g.w[o + j], x, bw, bx);
+        }
+        for (int k = LP_SUB / 2; k > 0; k >>= 1) {
+            const int64_t w2 = __shfl_xor(bw, k, LP_SUB);
+            const int32_t x2 = __shfl_xor(bx, k, LP_SUB);
+            if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
+        }
+        if (sl == 0) lab_out[v] = bx != INT32_MAX ? bx : (int32_t)v;
+    }
+}
+
+// one workgroup per piece of a long row: the piece's heaviest entry
+__global__ __launch_bounds__(256) void k_lp_first_long(DGraph g, const int32_t* __restrict__ long_list,
+                                                      const int32_t* __restrict__ counters,
+                                                      const int32_t* __restrict__ task_row,
+                                                      const int32_t* __restrict__ task_idx,
+                                                      int64_t* __restrict__ part_w, int32_t* __restrict__ part_x) {
+    __shared__ int64_t sw[256 / MC_WAVE];
+    __shared__ int32_t sx[256 / MC_WAVE];
+    const int32_t ntask = counters[2];
+    for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const int32_t v = long_list[task_row[i]];
+        const int32_t o = g.off[v], l = g.len[v];
+        const int32_t j0 = task_idx[i] * LP_FIRST_TASK;
+        const int32_t j1 = j0 + LP_FIRST_TASK < l ? j0 + LP_FIRST_TASK : l;
+        int64_t bw = 0;
+        int32_t bx = INT32_MAX;
+        for (int32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+            const int32_t x = g.col[o + j];
+            if (x != v) lp_better(g.w[o + j], x, bw, bx);
+        }
+        for (int k = MC_WAVE / 2; k > 0; k >>= 1) {
+            const int64_t w2 = __shfl_xor(bw, k, MC_WAVE);
+            const int32_t x2 = __shfl_xor(bx, k, MC_WAVE);
+            if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
+        }
+        __syncthreads();
+        if (lane_id() == 0) { sw[threadIdx.x / MC_WAVE] = bw; sx[threadIdx.x / MC_WAVE] = bx; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < 256 / MC_WAVE; k++)
+                if (sw[k] > bw || (sw[k] == bw && sx[k] < bx)) { bw = sw[k]; bx = sx[k]; }
+            part_w[i] = bw;
+            part_x[i] = bx;
+        }
+    }
+}
+
+// one wavefront per long row: fold its pieces
+__global__ __launch_bounds__(MC_WAVE) void k_lp_first_fold(DGraph g, int32_t* __restrict__ lab_out,
+                                                          const int32_t* __restrict__ long_list,
+                                                          const int32_t* __restrict__ long_base,
+                                                          const int32_t* __restrict__ counters,
+                                                          const int64_t* __restrict__ part_w,
+                                                          const int32_t* __restrict__ part_x) {
+    const int32_t nl = counters[0];
+    for (int32_t k = blockIdx.x; k < nl; k += gridDim.x) {
+        const int32_t v = long_list[k];
+        const int32_t nt = (g.len[v] + LP_FIRST_TASK - 1) / LP_FIRST_TASK;
+        int64_t bw = 0;
+        int32_t bx = INT32_MAX;
+        for (int32_t t = threadIdx.x; t < nt; t += MC_WAVE) {
+            const int64_t w2 = part_w[long_base[k] + t];
+            const int32_t x2 = part_x[long_base[k] + t];
+            if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
+        }
+        for (int d = MC_WAVE / 2; d > 0; d >>= 1) {
+            const int64_t w2 = __shfl_xor(bw, d, MC_WAVE);
+            const int32_t x2 = __shfl_xor(bx, d, MC_WAVE);
+            if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
+        }
+        if (threadIdx.x == 0) lab_out[v] = bx != INT32_MAX ? bx : v;
+    }
+}
+
 // flag[l] = 1 for every label in use (flag zeroed before)
 __global__ void k_label_used(const int32_t* __restrict__ lab, int32_t n, int32_t* __restrict__ flag) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -391,6 +513,20 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     k_lp_long_final<<<64, 256, 0, s>>>(lab_in, lab_out, w.long_list, w.counters, w.long_best, w.long_own,
                                        w.long_lab);
     MC_LAUNCHED("k_lp_long_final");
+    return true;
+}
+
+bool lp_first(const DGraph& g, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s) {
+    if (!fill_i32(w.counters, 0, 4, s)) return false;
+    k_lp_first<<<grid_for((int64_t)g.n * LP_SUB, 256), 256, 0, s>>>(g, lab_out, w.long_list, w.long_base, w.counters,
+                                                                   w.task_row, w.task_idx);
+    MC_LAUNCHED("k_lp_first");
+    // piece partials go to the large-group table arrays (>= 2.5 cap slots,
+    // more than the pieces)
+    k_lp_first_long<<<2048, 256, 0, s>>>(g, w.long_list, w.counters, w.task_row, w.task_idx, cw.tval, cw.tkey);
+    MC_LAUNCHED("k_lp_first_long");
+    k_lp_first_fold<<<1024, MC_WAVE, 0, s>>>(g, lab_out, w.long_list, w.long_base, w.counters, cw.tval, cw.tkey);
+    MC_LAUNCHED("k_lp_first_fold");
     return true;
 }
 

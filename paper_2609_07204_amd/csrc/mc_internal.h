@@ -79,15 +79,20 @@ struct ContractWS {
     int32_t* tkey;    // [4*cap+1024]
     int64_t* tval;    // [4*cap+1024]
     int32_t* dslot;   // [n+1]  dense accumulator of a giant group, or -1
-    int32_t* dinfo;   // [1+slots] count, then the group of each slot
-    int64_t* dense;   // [slots*(n+1)]
+    int32_t* dinfo;   // [1+DENSE_MAX] count, then the group of each slot
+    int64_t* dense;   // [dense_elems] accumulators, n2 each; all zero between contractions
+    int64_t dense_elems;
     int32_t* scan_tmp;
     int64_t* red_val; // [1024] per-block minima
     int32_t* red_id;  // [1024]
     int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
     int32_t* tinfo;   // [2*(cap/1024+2)] group and first member of every large-group tile
+    int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
 };
 void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
+// Zero the dense accumulators (once after carving; every contraction leaves
+// them zero again).
+bool contract_ws_reset(const ContractWS& ws, hipStream_t s);
 
 // Contract `src` by labels L (L == nullptr: identity, which only folds
 // loops, parallel and zero-weight entries) into `dst` with n2 vertices.
@@ -109,7 +114,9 @@ bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s);
 // (a normalised graph), with far fewer unions when there is a giant
 // component (hooking sweeps, then sampling-based linking); tmp holds one
 // int.
-bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, hipStream_t s);
+// lambda = 0 test: parent[] ends as a union-find of all edges of g. tmp: 4
+// ints; inbig: n bytes; snap: n ints (scratch).
+bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, uint8_t* inbig, int32_t* snap, hipStream_t s);
 // Compress parent[] and write canonical labels (components numbered by
 // their smallest vertex) to L; the count goes to sc->n2.
 bool uf_labels(int32_t* parent, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp,
@@ -126,6 +133,11 @@ struct Pr12WS {
     int64_t* part_w;
     int32_t* part_x;
     unsigned long long* spread;   // [SPREAD * SPREAD_STRIDE] partial mark counts
+    int32_t* first;       // [n] a test-1 neighbour of each row, or -1
+    int32_t* heavy;       // [n] test-1 entries of each row
+    int32_t* mode;        // [1] root of the largest sampled component
+    uint8_t* inbig;       // [n] 1 for the vertices of that component
+    int32_t* snap;        // [n] root of every vertex after the first unions
 };
 void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 // With vinst (per-vertex instance) the bound of vertex v is lam[vinst[v]]
@@ -168,6 +180,9 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w);
 // label is strictly heavier, smallest label on ties. Uses cw.mstart,
 // cw.scan_tmp, cw.tkey and cw.tval as scratch.
 bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s);
+// The same round from singleton labels (lab_in[v] = v) on a normal graph:
+// lab_out[v] = v's heaviest neighbour, the smallest on ties, v if isolated.
+bool lp_first(const DGraph& g, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s);
 // Canonical relabel of arbitrary labels in [0, n): L[v] = rank of lab[v]
 // among the labels in use; the count goes to sc->n2.
 bool lp_relabel(const int32_t* lab, int32_t n, int32_t* L, int32_t* flag_tmp, int32_t* scan_tmp, DevScalars* sc,

@@ -767,13 +767,17 @@ static mc_status heuristic(Solver& S) {
         const int32_t n = cur->n;
         int32_t* a = w.parent;   // labels ping-pong between parent[] and lab2[]
         int32_t* b = w.lab2;
-        if (!iota_i32(a, n, s)) return MC_E_DEVICE;
-        for (int it = 0; it < iters; it++) {
+        // the first round starts from singleton labels on a normal graph
+        if (!lp_first(*cur, b, w.lw, w.cw, s)) return MC_E_DEVICE;
+        std::swap(a, b);
+        for (int it = 1; it < iters; it++) {
             if (!lp_round(*cur, a, b, w.lw, w.cw, s)) return MC_E_DEVICE;
             std::swap(a, b);
         }
         if (!lp_relabel(a, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback()) return MC_E_DEVICE;
         const int32_t n2 = S.c->hsc->n2;
+        if (S.debug) fprintf(stderr, "[mc] heuristic level %d: n=%d clusters=%d lam=%lld\n", S.stats.heuristic_levels, n, n2,
+                             (long long)S.lam);
         if ((int64_t)n2 * 20 > (int64_t)n * 19) break;
         cur = contract_and_bound(S, cur, n2, &nxt_idx, &err);
         if (!cur) return err;
@@ -785,6 +789,8 @@ static mc_status heuristic(Solver& S) {
             return MC_E_DEVICE;
         S.tri_account(cur->n);
         const int32_t n3 = S.c->hsc->n2;
+        if (S.debug) fprintf(stderr, "[mc]   after cluster contraction n=%d lam=%lld, tests 1-4 leave %d\n", cur->n,
+                             (long long)S.lam, n3);
         if (n3 < cur->n) {
             S.stats.marks_pr += (int64_t)(S.c->hsc->marks_pr + S.c->hsc->marks_tri);
             cur = contract_and_bound(S, cur, n3, &nxt_idx, &err);
@@ -847,6 +853,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         wt = w.in_w;
     }
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
+    if (!contract_ws_reset(w.cw, s)) return MC_E_DEVICE;
     if (!host_input) {
         if (!validate_csr(rp, col, wt, n, (int32_t)nnz, w.sc, w.vpart, s) || !S.readback()) return MC_E_DEVICE;
         if (c->hsc->err != 0)
@@ -880,7 +887,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
     if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected
-    if (!uf_init(w.parent, n, s) || !uf_connectivity(w.g[0], w.parent, w.vpart_i32(), s) ||
+    if (!uf_init(w.parent, n, s) || !uf_connectivity(w.g[0], w.parent, w.vpart_i32(), w.flag8, w.L, s) ||
         !uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
         return MC_E_DEVICE;
     DevScalars h = *c->hsc;
@@ -988,6 +995,7 @@ mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws
     a.size = bytes;
     carve_step(a, n, cap, passes, w);
     if (a.used > bytes) return fail(MC_E_INVALID_ARG, "step: workspace too small");
+    if (!contract_ws_reset(w.cw, c->stream)) return fail(MC_E_DEVICE, "step: workspace reset failed");
     return MC_OK;
 }
 
@@ -1076,12 +1084,14 @@ extern "C" mc_status mc_step_pr34(mc_ctx* c, const mc_dgraph* g, int64_t lam, in
 
 extern "C" mc_status mc_step_lp(mc_ctx* c, const mc_dgraph* g, const int32_t* lab_in, int32_t* lab_out, void* ws,
                                 size_t bytes) {
-    if (!g || !lab_in || !lab_out) return fail(MC_E_INVALID_ARG, "mc_step_lp: NULL argument");
+    if (!g || !lab_out) return fail(MC_E_INVALID_ARG, "mc_step_lp: NULL argument");
     if (lab_in == lab_out) return fail(MC_E_INVALID_ARG, "mc_step_lp: lab_in and lab_out must differ");
     StepWS w;
     mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
     if (r != MC_OK) return r;
-    if (!lp_round(to_dgraph(g), lab_in, lab_out, w.lw, w.cw, c->stream)) return MC_E_DEVICE;
+    const bool ok = lab_in ? lp_round(to_dgraph(g), lab_in, lab_out, w.lw, w.cw, c->stream)
+                           : lp_first(to_dgraph(g), lab_out, w.lw, w.cw, c->stream);
+    if (!ok) return MC_E_DEVICE;
     return sync_read(c, w);
 }
 

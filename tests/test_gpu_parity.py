@@ -3,7 +3,11 @@ through the C ABI (include/mincut_steps.h), and the whole solver against
 the oracle's lambda. Integer work, so the bar is bit-exact; where several
 answers are correct (row order, the side of the cut) the unique part is
 compared and the rest checked for validity."""
+import json
+import os
 import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -493,6 +497,25 @@ def test_lp_round_matches_oracle(ctx, seed, nlab):
     assert np.array_equal(ctx.step_lp(dev, want), oracle.lp_round(g, want))
 
 
+@pytest.mark.parametrize("seed,whi", [(11, 1), (12, 3), (13, 1000)])
+def test_lp_first_round_from_singletons_matches_oracle(ctx, seed, whi):
+    # the heuristic's first round (singleton labels, normal graph) takes its
+    # own streaming kernels; it must equal the general rule bit for bit:
+    # rows of up to 1800 entries (listed long rows), many equal weights,
+    # and vertices with no edge at all (they keep their own label)
+    g = hub_graph(3000, 5, 1800, 6, seed, 1, whi)
+    rp, col, w = g.row_ptr, g.col, g.w
+    n = g.n + 7      # seven isolated vertices at the end
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    keep = rows < col
+    h = gen.from_edges(n, rows[keep], col[keep], w[keep])
+    dev = ctx.dgraph(h)
+    got = ctx.step_lp(dev, None)
+    want = oracle.lp_round(h, np.arange(h.n, dtype=np.int32))
+    say("lp first round", seed, whi, int(np.sum(got != np.arange(h.n))), "moved")
+    assert np.array_equal(got, want)
+
+
 def test_lp_round_ties_and_own_label(ctx):
     # star-like rows with equal weights: ties go to the smallest label, and a
     # vertex keeps its label unless another is strictly heavier
@@ -762,3 +785,56 @@ def test_single_solve_ignores_stale_workspace(ctx, fill):
         lam, side = ctx.mincut(g, workspace=ws)
         ref = oracle_lambda(g)
         assert lam == ref and oracle.cut_value(g, side) == ref
+
+
+# ------------------------------------------------ the configurations at full size
+GOLDEN = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lambda.json")))
+
+
+@pytest.mark.parametrize("name,make", [
+    ("chung_lu_2^22_core10_seed1", lambda: gen.config_chung_lu(22, 1)),
+    ("rhg_2^23_core32_seed1", lambda: gen.config_rhg(23, 1)),
+])
+def test_full_size_config_matches_oracle(ctx, name, make):
+    # the workload solved at its real size, input resident on the device as
+    # the benchmark times it, with the bound heuristic on (default) and off:
+    # lambda equals the oracle's stored value, the side recomputes to it
+    ref = GOLDEN[name]
+    t = time.time()
+    g = make()
+    say("full size", name, g.n, g.m, "generated in %.1fs" % (time.time() - t))
+    assert (g.n, g.m) == (ref["n"], ref["m"])
+    dev = ctx.upload(g)
+    try:
+        for hmin in (10000, 0):
+            ctx.set_options(heuristic_min_n=hmin)
+            lam, side = ctx.mincut(dev=dev)
+            say("  heuristic_min_n", hmin, "lambda", lam)
+            assert lam == ref["lambda"]
+            assert side[0] == 0 and 0 < int(side.sum()) < g.n
+            assert oracle.cut_value(g, side) == lam
+    finally:
+        ctx.set_options(heuristic_min_n=10000)
+
+
+def test_batch_full_config_matches_oracle(ctx):
+    # all 4096 graphs of the batched configuration in one call; every lambda
+    # against the oracle (run on host threads: the oracle releases the
+    # interpreter lock), every side recomputed
+    gen._L()
+    oracle._L()     # load both libraries before the threads use them
+    t = time.time()
+    with ThreadPoolExecutor(16) as ex:
+        gs = list(ex.map(gen.config_batch_graph, range(4096)))
+    say("batch config: %d graphs, %d entries, generated in %.1fs" % (len(gs), sum(g.nnz for g in gs), time.time() - t))
+    t = time.time()
+    lams, sides = ctx.mincut_batch(gs)
+    say("  solved in %.1fs (host input, sides)" % (time.time() - t))
+    t = time.time()
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(lambda g: oracle.noi(g)[0], gs))
+        cuts = list(ex.map(lambda a: oracle.cut_value(a[0], a[1]), zip(gs, sides)))
+    say("  oracle in %.1fs" % (time.time() - t))
+    bad = [(i, gs[i].name, int(lams[i]), refs[i], cuts[i]) for i in range(len(gs))
+           if lams[i] != refs[i] or cuts[i] != refs[i] or sides[i][0] != 0]
+    assert not bad, bad[:5]
