@@ -67,10 +67,21 @@ def batch_main(args, log):
     N = sum(g.n for g in gs)
     M = sum(g.nnz for g in gs)
     log("generated %d graphs: %d vertices, %d entries in %.1fs" % (len(gs), N, M, time.time() - t))
-    ctx = mc.Context(0)
+    ctx = mc.Context(0, pass_len_cap=args.len_cap, heuristic_min_n=args.heuristic_min_n)
     devs = [ctx.upload(g) for g in gs]
     ws = torch.empty(ctx.batch_workspace_bytes(devs=devs), dtype=torch.uint8, device=ctx.device)
     log("batch workspace %.2f GB" % (ws.numel() / 1e9))
+    tuning = None
+    if args.tune_sample > 0:
+        # untimed: the autotuner picks the pass workgroup size and whether to
+        # bound at admission, on a spread sample of this batch
+        t = time.time()
+        tuning = ctx.batch_autotune(devs=devs, workspace=ws, sample=args.tune_sample)
+        tuning["seconds"] = time.time() - t
+        log("autotune (%d graphs, %.1fs): pass threads %d, admission bound %s; %s" % (
+            tuning["sample"], tuning["seconds"], tuning["pass_threads"], "on" if tuning["lp"] == 1 else "off",
+            ", ".join("%d/%s %.1f ms" % (c["pass_threads"], "on" if c["lp"] == 1 else "off", c["ms"])
+                      for c in tuning["candidates"])))
     torch.cuda.synchronize()
     lams = None
     for i in range(args.warmup):
@@ -84,6 +95,10 @@ def batch_main(args, log):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     log("batched: %.2f ms per batch, %.1f solves/s" % (ms, len(gs) / (ms / 1000.0)))
+    if args.no_plain:
+        print(json.dumps({"batched_ms": ms, "solves_per_s": len(gs) / (ms / 1000.0), "len_cap": args.len_cap,
+                          "heuristic_min_n": args.heuristic_min_n, "tuning": tuning}))
+        return
     # plain: one mc_mincut per graph on the same stream, workspace reused
     wsp = torch.empty(max(ctx.workspace_bytes(g.n, g.nnz) for g in gs), dtype=torch.uint8, device=ctx.device)
     torch.cuda.synchronize()
@@ -124,7 +139,10 @@ def batch_main(args, log):
         "config": {"workload": "batch of %d graphs: planted / Erdos-Renyi / Chung-Lu, n log-uniform in "
                                "[64, 65536], mean degree 8-32, weights 1-100, seeds 1000+i" % len(gs),
                    "vertices": N, "entries": M, "plain_solves_per_s": len(gs) / (ms_plain / 1000.0),
-                   "batched_over_plain": ms_plain / ms},
+                   "batched_over_plain": ms_plain / ms,
+                   "tuning": None if tuning is None else {
+                       "sample": tuning["sample"], "seconds": round(tuning["seconds"], 2),
+                       "pass_threads": tuning["pass_threads"], "admission_bound": tuning["lp"] == 1}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -244,6 +262,9 @@ def main():
                          "the random hyperbolic graph; batch: the mixed batch, batched against plain per-graph "
                          "solves; served: Poisson requests to the server")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-plain", action="store_true", help="batch: time the batched call only (parameter sweeps)")
+    ap.add_argument("--tune-sample", type=int, default=512,
+                    help="batch: graphs the autotuner times before the run (0: no tuning)")
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--rates", default="50,200,1000")
     ap.add_argument("--requests", type=int, default=1000)

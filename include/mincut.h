@@ -91,6 +91,12 @@ typedef struct {
                                  at a time, smallest id first on ties; the
                                  whole solve then does not depend on timing */
     int32_t validate;         /* 1: check symmetry of host inputs */
+    int32_t batch_pass_threads; /* threads of each graph's CAPFOREST pass in
+                                 the batched and served forms: 64, 128, 256,
+                                 512 or 1024 (0 = 256) */
+    int32_t batch_lp;         /* label-propagation bound at admission in the
+                                 batched and served forms: 0 = when
+                                 heuristic_min_n > 0, 1 = always, 2 = never */
 } mc_options;
 
 typedef struct {
@@ -147,7 +153,7 @@ mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws
  * lambdas[i] (host, k values) is graph i's minimum cut; if sides != NULL and
  * sides[i] != NULL, sides[i] (host, n_i bytes) receives one side of it with
  * sides[i][0] = 0. per_graph (host, k values, may be NULL) receives MC_OK
- * for every graph. When heuristic_min_n > 0, every graph first goes
+ * for every graph. When batch_lp selects it, every graph first goes
  * through the label-propagation heuristic's coarsening (LP rounds and
  * cluster contraction while the graphs shrink; the smallest collapsed
  * degree of each level bounds lambda), all graphs in the same launches, but
@@ -155,6 +161,29 @@ mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws
 mc_status mc_batch_workspace_size(const mc_ctx* ctx, int32_t k, const mc_csr* graphs, size_t* bytes);
 mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
                           int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
+
+/* Autotuner of the batched form. Solves a sample of the batch (`sample`
+ * graphs spread evenly over the k given, all of them when sample <= 0 or
+ * >= k) once per candidate setting - every pass workgroup size of
+ * batch_pass_threads, with and without the admission bound of batch_lp -
+ * after one untimed run, times each (wall clock around the synchronised
+ * call), and stores the fastest setting in the context's options (the
+ * other options are left as they are). The results of the sample solves
+ * are discarded; a setting changes only the speed, never a result.
+ * dev_workspace must hold mc_batch_workspace_size of the whole batch (the
+ * sample needs less). On error the options are left unchanged. */
+#define MC_TUNE_MAX 16
+typedef struct {
+    int32_t pass_threads;      /* chosen batch_pass_threads */
+    int32_t lp;                /* chosen batch_lp (1 or 2) */
+    int32_t sample;            /* graphs in the timed sample */
+    int32_t candidates;        /* settings timed */
+    int32_t cand_threads[MC_TUNE_MAX];
+    int32_t cand_lp[MC_TUNE_MAX];
+    double cand_ms[MC_TUNE_MAX];  /* wall time of each setting on the sample */
+} mc_tuning;
+mc_status mc_batch_autotune(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
+                            int32_t sample, mc_tuning* out);
 
 /* Served form: a request loop with continuous batching. The server holds
  * one device allocation of hbm_bytes (made at create) for the graphs in

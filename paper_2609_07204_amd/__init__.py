@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("heuristic_min_n", ctypes.c_int32), ("lp_iters", ctypes.c_int32),
                 ("pr_tri_deg_cap", ctypes.c_int32), ("capforest_passes", ctypes.c_int32),
                 ("pass_len_cap", ctypes.c_int32), ("capforest_mode", ctypes.c_int32),
-                ("levels_min_n", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32)]
+                ("levels_min_n", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("batch_pass_threads", ctypes.c_int32), ("batch_lp", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -50,6 +51,15 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MC_TUNE_MAX = 16
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("pass_threads", ctypes.c_int32), ("lp", ctypes.c_int32), ("sample", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("cand_threads", ctypes.c_int32 * MC_TUNE_MAX),
+                ("cand_lp", ctypes.c_int32 * MC_TUNE_MAX), ("cand_ms", ctypes.c_double * MC_TUNE_MAX)]
 
 
 class KernelTime(ctypes.Structure):
@@ -90,6 +100,7 @@ SIGNATURES = {
     "mc_last_error": (ctypes.c_char_p, []),
     "mc_batch_workspace_size": (ctypes.c_int, [P, I32, P, P]),
     "mc_mincut_batch": (ctypes.c_int, [P, I32, P, P, SZ, P, P, P]),
+    "mc_batch_autotune": (ctypes.c_int, [P, I32, P, P, SZ, I32, P]),
     "mc_server_create": (ctypes.c_int, [P, P, P]),
     "mc_server_destroy": (ctypes.c_int, [P]),
     "mc_server_submit": (ctypes.c_int, [P, P, P]),
@@ -177,9 +188,12 @@ class Context:
             pass
 
     def set_options(self, **kw):
+        o = Options()
+        ctypes.pointer(o)[0] = self.options
         for k, v in kw.items():
-            setattr(self.options, k, v)
-        _check(lib().mc_ctx_set_options(self.h, ctypes.byref(self.options)))
+            setattr(o, k, v)
+        _check(lib().mc_ctx_set_options(self.h, ctypes.byref(o)))
+        self.options = o
 
     # ------------------------------------------------------------ solve
     def workspace_bytes(self, n, nnz):
@@ -273,6 +287,27 @@ class Context:
                                      lams.ctypes.data, sp, None))
         del keep
         return lams, sides
+
+    def batch_autotune(self, graphs=None, devs=None, workspace=None, sample=0):
+        """Time the batched form on a spread sample of the batch under every
+        pass workgroup size, with and without the admission bound, and keep
+        the fastest in this context (mc_batch_autotune). Returns the timings."""
+        torch = _torch()
+        arr, keep = self._csr_array(graphs, devs)
+        k = len(arr)
+        if workspace is None:
+            b = ctypes.c_size_t()
+            _check(lib().mc_batch_workspace_size(self.h, k, arr, ctypes.byref(b)))
+            workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        t = Tuning()
+        _check(lib().mc_batch_autotune(self.h, k, arr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                       int(sample), ctypes.byref(t)))
+        del keep
+        self.options.batch_pass_threads = t.pass_threads
+        self.options.batch_lp = t.lp
+        return {"pass_threads": t.pass_threads, "lp": t.lp, "sample": t.sample,
+                "candidates": [{"pass_threads": t.cand_threads[i], "lp": t.cand_lp[i], "ms": t.cand_ms[i]}
+                               for i in range(t.candidates)]}
 
     # ------------------------------------------------------------ timing
     def profile(self, on=True):

@@ -19,6 +19,7 @@
 // its lambda with the collapsed degrees it meets (the bound only changes the
 // work, not the result).
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 #include "mc_internal.h"
@@ -585,7 +586,7 @@ struct Engine {
         }
         // the label-propagation heuristic on the staged graphs (every graph
         // at once); its best bounds are applied after the minimum degrees
-        const bool lp = c->opt.heuristic_min_n > 0;
+        const bool lp = c->opt.batch_lp == 1 || (c->opt.batch_lp == 0 && c->opt.heuristic_min_n > 0);
         if (lp) EG_OK(heuristic_levels(S, k, NS, sv));
         DGraph& G = w.g[cur];
         k_eg_append<<<grid_for((int64_t)CS + NS, 256), 256, 0, s>>>(S, CS, G, n, used);
@@ -769,6 +770,7 @@ struct Engine {
         pa.plam = w.lam;
         pa.prun = w.prun;
         pa.pmarks = w.pmarks;
+        pa.threads = c->opt.batch_pass_threads;
         EG_OK(capforest_private(pa, s, cap.nmax));
         k_bg_alpha<<<grid_for(k, 256), 256, 0, s>>>(pa.alpha, w.done, k, w.lam, w.snap);
         EG_OK(labels(k));
@@ -939,6 +941,47 @@ extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, voi
     return MC_OK;
 }
 
+// The autotuner: time the batch engine on a spread sample of the batch
+// under every candidate setting and keep the fastest.
+extern "C" mc_status mc_batch_autotune(mc_ctx* c, int32_t k, const mc_csr* gs, void* dev_ws, size_t ws_bytes,
+                                       int32_t sample, mc_tuning* out) {
+    if (!c || !gs || k <= 0 || !dev_ws || !out) return mc_fail(MC_E_INVALID_ARG, "mc_batch_autotune: bad argument");
+    const int32_t m = sample <= 0 || sample >= k ? k : sample;
+    std::vector<mc_csr> sub((size_t)m);
+    for (int32_t i = 0; i < m; i++) sub[i] = gs[(int64_t)i * k / m];
+    std::vector<int64_t> lam((size_t)m);
+    const mc_options saved = c->opt;
+    static const int32_t threads[] = {64, 128, 256, 512, 1024};
+    mc_tuning t{};
+    t.sample = m;
+    // one untimed run first: first-touch costs are not any setting's
+    mc_status r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
+    if (r != MC_OK) { c->opt = saved; return r; }
+    double best = 0;
+    for (int32_t lp = 1; lp <= 2; lp++) {
+        for (int32_t th : threads) {
+            c->opt.batch_pass_threads = th;
+            c->opt.batch_lp = lp;
+            if (hipStreamSynchronize(c->stream) != hipSuccess) { c->opt = saved; return mc_fail(MC_E_DEVICE, "sync"); }
+            const auto t0 = std::chrono::steady_clock::now();
+            r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
+            if (r != MC_OK) { c->opt = saved; return r; }
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            const int32_t j = t.candidates++;
+            t.cand_threads[j] = th;
+            t.cand_lp[j] = lp;
+            t.cand_ms[j] = ms;
+            if (j == 0 || ms < best) { best = ms; t.pass_threads = th; t.lp = lp; }
+        }
+    }
+    c->opt = saved;
+    c->opt.batch_pass_threads = t.pass_threads;
+    c->opt.batch_lp = t.lp;
+    *out = t;
+    return MC_OK;
+}
+
 // ------------------------------------------------------------ the server
 // Continuous batching over the engine: requests are copied at submission
 // and queued; every mc_server_step admits queued requests in arrival order
@@ -949,7 +992,6 @@ extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, voi
 // way through their rounds join them in the same launches; a graph's rounds
 // do not depend on the others (its bound, passes and contractions touch
 // only its own range), so its result is the one it gets alone.
-#include <chrono>
 #include <deque>
 #include <unordered_map>
 

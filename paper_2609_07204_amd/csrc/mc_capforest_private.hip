@@ -17,7 +17,7 @@
 // Passes do not share a visited array (the private mode of the paper's
 // parallel session, item 1): a pass's traversal is never cut by another
 // pass, which on power-law graphs is what lets vertices reach lam at all.
-// Every pass is one 1024-thread workgroup with dense per-pass state in HBM
+// Every pass is one workgroup with dense per-pass state in HBM
 // (st, r, capped FIFO, touched list, queue list, scan order), which has no
 // capacity limit, so hubs are scanned like any other vertex. State is
 // cleared through the touched list at the end of the pass.
@@ -25,14 +25,20 @@
 
 namespace {
 
-constexpr int PT = 1024;
-constexpr int PW = PT / MC_WAVE;
+// Threads per pass: a single solve's few passes take 1024 threads each; in
+// instance mode (one pass per graph of a batch, most of them small) a pass
+// takes 256 by default, so four times as many passes are resident at once
+// (64 to 1024 on request).
+constexpr int PT_SOLVE = 1024;
+constexpr int PT_INST = 256;
 
 enum : int32_t { S_NEW = 0, S_QUEUED = 1, S_SCANNED = 2, S_BATCH = 3 };
 
 constexpr int L2_MAX = 8192;   // level-2 entries (n <= 32 M vertices)
 
+template <int PT>
 struct PassLds {
+    static constexpr int PW = PT / MC_WAVE;
     int32_t head, tail, tn, dn, single_x;
     int32_t bx[PT];
     int32_t boff[PT + 1];
@@ -50,7 +56,9 @@ __device__ __forceinline__ int64_t ld64(const int64_t* p) {
 }
 
 // exclusive scan over the block; every thread gets the total
-__device__ int32_t block_scan(int32_t v, int32_t& total, PassLds& L) {
+template <int PT>
+__device__ int32_t block_scan(int32_t v, int32_t& total, PassLds<PT>& L) {
+    constexpr int PW = PT / MC_WAVE;
     const int lane = lane_id(), wid = threadIdx.x / MC_WAVE;
     int32_t incl = v;
     for (int o = 1; o < MC_WAVE; o <<= 1) {
@@ -70,7 +78,9 @@ __device__ int32_t block_scan(int32_t v, int32_t& total, PassLds& L) {
     return pre + incl - v;
 }
 
-__device__ int64_t block_sum(int64_t v, PassLds& L) {
+template <int PT>
+__device__ int64_t block_sum(int64_t v, PassLds<PT>& L) {
+    constexpr int PW = PT / MC_WAVE;
     v = wave_sum_i64(v);
     __syncthreads();
     if (lane_id() == 0) L.red64[threadIdx.x / MC_WAVE] = v;
@@ -81,7 +91,9 @@ __device__ int64_t block_sum(int64_t v, PassLds& L) {
 }
 
 // (key desc, id asc) maximum over the block; id < 0 means empty
-__device__ void block_argmax(int64_t& key, int32_t& id, PassLds& L) {
+template <int PT>
+__device__ void block_argmax(int64_t& key, int32_t& id, PassLds<PT>& L) {
+    constexpr int PW = PT / MC_WAVE;
     int32_t aux = 0;
     wave_argmax(key, id, aux);
     __syncthreads();
@@ -105,7 +117,8 @@ __device__ __forceinline__ int32_t last_le_lds(const int32_t* a, int32_t n, int3
     return lo;
 }
 
-__device__ __forceinline__ void mark_dirty(uint32_t* dbits, int32_t* dlist, int32_t b, PassLds& L) {
+template <int PT>
+__device__ __forceinline__ void mark_dirty(uint32_t* dbits, int32_t* dlist, int32_t b, PassLds<PT>& L) {
     const uint32_t bit = 1u << (b & 31);
     if (!(atomicOr(&dbits[b >> 5], bit) & bit)) dlist[atomicAdd(&L.dn, 1)] = b;
 }
@@ -117,9 +130,11 @@ __device__ __forceinline__ void mark_dirty(uint32_t* dbits, int32_t* dlist, int3
 // FIFO, or scanned) marks its block dirty, and dirty blocks are recomputed
 // right before the next single pop, which is then exact: largest r, then
 // smallest block and id.
+template <int PT>
 __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
+    constexpr int PW = PT / MC_WAVE;
     extern __shared__ long long l2[];
-    __shared__ PassLds L;
+    __shared__ PassLds<PT> L;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / MC_WAVE;
     const int p = blockIdx.x;
     // the pass's vertices are [base, base + n); st and r are indexed by
@@ -394,7 +409,17 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
             mc_hip_ok(hipErrorInvalidValue, "capforest_private: instance too large for the pass index");
             return false;
         }
-        k_capforest_private<<<a.passes, PT, (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long), s>>>(a);
+        const size_t lds = (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long);
+        switch (a.threads > 0 ? a.threads : PT_INST) {
+            case 64: k_capforest_private<64><<<a.passes, 64, lds, s>>>(a); break;
+            case 128: k_capforest_private<128><<<a.passes, 128, lds, s>>>(a); break;
+            case 256: k_capforest_private<256><<<a.passes, 256, lds, s>>>(a); break;
+            case 512: k_capforest_private<512><<<a.passes, 512, lds, s>>>(a); break;
+            case 1024: k_capforest_private<1024><<<a.passes, 1024, lds, s>>>(a); break;
+            default:
+                mc_hip_ok(hipErrorInvalidValue, "capforest_private: unsupported pass workgroup size");
+                return false;
+        }
         MC_LAUNCHED("k_capforest_private");
         return true;
     }
@@ -407,7 +432,7 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: graph too large for the pass index");
         return false;
     }
-    k_capforest_private<<<a.passes, PT, (size_t)nb2 * sizeof(long long), s>>>(a);
+    k_capforest_private<PT_SOLVE><<<a.passes, PT_SOLVE, (size_t)nb2 * sizeof(long long), s>>>(a);
     MC_LAUNCHED("k_capforest_private");
     return true;
 }

@@ -273,6 +273,7 @@ struct PrivateArgs {
     const int64_t* plam = nullptr;
     const uint8_t* prun = nullptr;
     unsigned long long* pmarks = nullptr;
+    int32_t threads = 0;    // instance mode: workgroup size of a pass (64..1024; 0 = 256)
 };
 constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
 bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n = 0);

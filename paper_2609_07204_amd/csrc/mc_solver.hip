@@ -175,15 +175,31 @@ extern "C" void mc_default_options(mc_options* o) {
     o->levels_min_n = 0;
     o->deterministic = 0;
     o->validate = 0;
+    o->batch_pass_threads = 0;
+    o->batch_lp = 0;
 }
 
 extern "C" const char* mc_last_error(void) { return g_err.c_str(); }
+
+static bool options_ok(const mc_options* o) {
+    const int32_t t = o->batch_pass_threads;
+    if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512 && t != 1024) {
+        fail(MC_E_INVALID_ARG, "options: batch_pass_threads must be 0, 64, 128, 256, 512 or 1024");
+        return false;
+    }
+    if (o->batch_lp < 0 || o->batch_lp > 2) {
+        fail(MC_E_INVALID_ARG, "options: batch_lp must be 0, 1 or 2");
+        return false;
+    }
+    return true;
+}
 
 extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_options* opt, mc_ctx** out) {
     if (!out) return fail(MC_E_INVALID_ARG, "mc_ctx_create: out is NULL");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return fail(MC_E_DEVICE, "mc_ctx_create: no such HIP device");
+    if (opt && !options_ok(opt)) return MC_E_INVALID_ARG;
     mc_ctx* c = new (std::nothrow) mc_ctx();
     if (!c) return fail(MC_E_OOM, "mc_ctx_create: out of host memory");
     c->device = device;
@@ -261,6 +277,7 @@ extern "C" mc_status mc_profile_read(mc_ctx* c, int32_t kernel, mc_kernel_time* 
 
 extern "C" mc_status mc_ctx_set_options(mc_ctx* c, const mc_options* opt) {
     if (!c || !opt) return fail(MC_E_INVALID_ARG, "mc_ctx_set_options: NULL argument");
+    if (!options_ok(opt)) return MC_E_INVALID_ARG;
     c->opt = *opt;
     return MC_OK;
 }

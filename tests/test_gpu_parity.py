@@ -670,6 +670,40 @@ def test_batch_matches_oracle(ctx, seed, count):
     assert not bad
 
 
+@pytest.mark.parametrize("threads,lp", [(64, 2), (128, 1), (512, 2), (1024, 1)])
+def test_batch_pass_sizes_match_oracle(ctx, threads, lp):
+    # every pass workgroup size the autotuner may pick, with and without
+    # the admission bound, gives the oracle's lambdas and valid sides
+    gs = batch_mix(20 + threads, 150)
+    ctx.set_options(batch_pass_threads=threads, batch_lp=lp)
+    try:
+        lams, sides = ctx.mincut_batch(gs)
+    finally:
+        ctx.set_options(batch_pass_threads=0, batch_lp=0)
+    bad = [(i, gs[i].name) for i, g in enumerate(gs)
+           if lams[i] != oracle_lambda(g) or oracle.cut_value(g, sides[i]) != lams[i] or sides[i][0] != 0]
+    assert not bad, bad[:5]
+
+
+def test_batch_autotune_picks_a_setting_and_keeps_results(ctx):
+    import paper_2609_07204_amd as mc
+    gs = batch_mix(31, 200)
+    t = ctx.batch_autotune(gs, sample=80)
+    say("autotune", t["pass_threads"], t["lp"], [round(c["ms"], 2) for c in t["candidates"]])
+    assert t["sample"] == 80 and len(t["candidates"]) == 10
+    assert t["pass_threads"] in (64, 128, 256, 512, 1024) and t["lp"] in (1, 2)
+    assert all(c["ms"] > 0 for c in t["candidates"])
+    best = min(t["candidates"], key=lambda c: c["ms"])
+    assert (best["pass_threads"], best["lp"]) == (t["pass_threads"], t["lp"])
+    try:
+        lams, sides = ctx.mincut_batch(gs)
+        assert all(lams[i] == oracle_lambda(g) and oracle.cut_value(g, sides[i]) == lams[i] for i, g in enumerate(gs))
+        with pytest.raises(mc.MincutError):
+            ctx.set_options(batch_pass_threads=100)
+    finally:
+        ctx.set_options(batch_pass_threads=0, batch_lp=0)
+
+
 def test_batch_device_input_same_as_host(ctx):
     gs = batch_mix(9, 120)
     devs = [ctx.upload(g) for g in gs]
