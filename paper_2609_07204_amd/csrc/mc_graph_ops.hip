@@ -169,48 +169,78 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
                                              unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
                                              int32_t* long_list, int32_t* long_cnt, int32_t* first, int32_t* heavy_cnt,
                                              unsigned long long* pb) {
+    // 16 lanes take 16 consecutive rows: the rows' offsets, lengths,
+    // degrees and bounds come in one load, each lane then loads up to four
+    // entries of a row at once, and the rows' results (test-2 unions
+    // included) are written by one lane each, all 16 at the same time
     const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
     int64_t bytes = 0;
-    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
-        const int32_t o = g.off[v], l = g.len[v];
-        if (l > PR_LONG) {
-            if (sl == 0) {
-                long_list[atomicAdd(long_cnt, 1)] = (int32_t)v;
-                first[v] = -1;       // a long row unions its test-1 entries itself
-                heavy_cnt[v] = 0;
+    for (int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB) * SUB; v0 < g.n;
+         v0 += nsub * SUB) {
+        const int32_t rows = g.n - v0 < SUB ? (int32_t)(g.n - v0) : SUB;
+        const int32_t mv = (int32_t)v0 + sl;
+        int32_t my_o = 0, my_l = 0;
+        int64_t my_lam = lam0, my_deg = 0;
+        if (sl < rows) {
+            my_o = g.off[mv];
+            my_l = g.len[mv];
+            my_deg = g.deg[mv];
+            if (vinst) my_lam = lamp[vinst[mv]];   // bound of the row's instance
+            if (my_l > PR_LONG) {
+                long_list[atomicAdd(long_cnt, 1)] = mv;
+                first[mv] = -1;       // a long row unions its test-1 entries itself
+                heavy_cnt[mv] = 0;
             }
-            continue;
         }
-        if (sl == 0) bytes += 16 + 12 * (int64_t)l;
-        const int64_t lam = vinst ? lamp[vinst[v]] : lam0;   // bound of v's instance
-        int64_t bw = -1;
-        int32_t bx = -1;
-        int32_t hj = INT32_MAX, hn = 0;    // first test-1 entry, test-1 entries
-        for (int32_t j = sl; j < l; j += SUB) {
-            const int32_t x = g.col[o + j];
-            const int64_t c = g.w[o + j];
-            const bool heavy = c >= lam;
-            if (flag1) flag1[o + j] = heavy;
-            if (heavy) { hn++; hj = j < hj ? j : hj; }
-            if (c > bw || (c == bw && x < bx)) { bw = c; bx = x; }
+        int64_t my_bw = -1;
+        int32_t my_bx = -1, my_hj = INT32_MAX, my_hn = 0;
+        for (int32_t r = 0; r < rows; r++) {
+            const int32_t l = __shfl(my_l, r, SUB);
+            if (l > PR_LONG) continue;
+            const int32_t o = __shfl(my_o, r, SUB);
+            const int64_t lam = __shfl(my_lam, r, SUB);
+            int64_t bw = -1;
+            int32_t bx = -1;
+            int32_t hj = INT32_MAX, hn = 0;    // first test-1 entry, test-1 entries
+            for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
+                int32_t x[4];
+                int64_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t j = j0 + u * SUB + sl;
+                    x[u] = j < l ? g.col[o + j] : -1;
+                    c[u] = j < l ? g.w[o + j] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t j = j0 + u * SUB + sl;
+                    if (j >= l) continue;
+                    const bool heavy = c[u] >= lam;
+                    if (flag1) flag1[o + j] = heavy;
+                    if (heavy) { hn++; hj = j < hj ? j : hj; }
+                    if (c[u] > bw || (c[u] == bw && x[u] < bx)) { bw = c[u]; bx = x[u]; }
+                }
+            }
+            for (int k = SUB / 2; k > 0; k >>= 1) {
+                int64_t w2 = __shfl_xor(bw, k, SUB);
+                int32_t x2 = __shfl_xor(bx, k, SUB);
+                if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
+                const int32_t hj2 = __shfl_xor(hj, k, SUB);
+                hj = hj2 < hj ? hj2 : hj;
+                hn += __shfl_xor(hn, k, SUB);
+            }
+            if (sl == r) { my_bw = bw; my_bx = bx; my_hj = hj; my_hn = hn; }
+            if (sl == 0) bytes += 16 + 12 * (int64_t)l;
         }
-        for (int k = SUB / 2; k > 0; k >>= 1) {
-            int64_t w2 = __shfl_xor(bw, k, SUB);
-            int32_t x2 = __shfl_xor(bx, k, SUB);
-            if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
-            const int32_t hj2 = __shfl_xor(hj, k, SUB);
-            hj = hj2 < hj ? hj2 : hj;
-            hn += __shfl_xor(hn, k, SUB);
-        }
-        const bool take = bx >= 0 && 2 * bw >= g.deg[v];
-        if (sl == 0) {
-            if (ptr2) ptr2[v] = take ? bx : -1;
-            if (take && uf_union(par, (int32_t)v, bx)) joined++;
-            first[v] = hj != INT32_MAX ? g.col[o + hj] : -1;
-            heavy_cnt[v] = hn;
+        if (sl < rows && my_l <= PR_LONG) {
+            const bool take = my_bx >= 0 && 2 * my_bw >= my_deg;
+            if (ptr2) ptr2[mv] = take ? my_bx : -1;
+            first[mv] = my_hj != INT32_MAX ? g.col[my_o + my_hj] : -1;
+            heavy_cnt[mv] = my_hn;
+            if (take && uf_union(par, mv, my_bx)) joined++;
         }
     }
     // marks go to one of SPREAD partial counters (128 B apart): a single
@@ -604,28 +634,49 @@ __global__ __launch_bounds__(256) void k_validate_sum(const unsigned long long* 
 __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                               const int64_t* __restrict__ w, int32_t n, int32_t* __restrict__ len,
                                               int64_t* __restrict__ deg, int32_t* noncanon) {
+    // 16 lanes take 16 consecutive rows: their offsets come in one load,
+    // and each lane then loads up to four entries of a row at once
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
-    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < n; v += nsub) {
-        const int32_t o = rp[v], l = rp[v + 1] - o;
-        int64_t d = 0;
-        bool bad = false;
-        for (int32_t j = sl; j < l; j += SUB) {
-            const int32_t x = col[o + j];
-            const int64_t c = w[o + j];
-            d += c;
-            bad |= x == v || c <= 0 || (j > 0 && col[o + j - 1] >= x);
+    bool bad_any = false;
+    for (int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB) * SUB; v0 < n; v0 += nsub * SUB) {
+        const int32_t my_o = v0 + sl <= n ? rp[v0 + sl] : 0;
+        const int32_t my_e = v0 + sl < n ? rp[v0 + sl + 1] : my_o;
+        int64_t my_d = 0;
+        const int32_t rows = n - v0 < SUB ? (int32_t)(n - v0) : SUB;
+        for (int32_t r = 0; r < rows; r++) {
+            const int32_t v = (int32_t)v0 + r;
+            const int32_t o = __shfl(my_o, r, SUB), e = __shfl(my_e, r, SUB), l = e - o;
+            int64_t d = 0;
+            bool bad = false;
+            for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
+                int32_t x[4], xp[4];
+                int64_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t j = j0 + u * SUB + sl;
+                    x[u] = j < l ? col[o + j] : INT32_MAX;
+                    xp[u] = j > 0 && j < l ? col[o + j - 1] : -1;
+                    c[u] = j < l ? w[o + j] : 1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (j0 + u * SUB + sl < l) {
+                        d += c[u];
+                        bad |= x[u] == v || c[u] <= 0 || xp[u] >= x[u];
+                    }
+                }
+            }
+            for (int k = SUB / 2; k > 0; k >>= 1) d += __shfl_xor(d, k, SUB);
+            if (sl == r) my_d = d;
+            bad_any |= bad;
         }
-        for (int k = SUB / 2; k > 0; k >>= 1) {
-            d += __shfl_xor(d, k, SUB);
-            bad |= __shfl_xor((int)bad, k, SUB) != 0;
-        }
-        if (sl == 0) {
-            len[v] = l;
-            deg[v] = d;
-            if (bad && ld_acq(noncanon) == 0) st_rel(noncanon, 1);
+        if (v0 + sl < n) {
+            len[v0 + sl] = my_e - my_o;
+            deg[v0 + sl] = my_d;
         }
     }
+    if (__ballot(bad_any) && lane_id() == 0 && ld_acq(noncanon) == 0) st_rel(noncanon, 1);
 }
 
 }  // namespace
@@ -695,7 +746,7 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
     if (!fill_i32(w.counters, 0, 4, s)) return false;
     if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s)) return false;
     prof_begin(PK_PR12, s);
-    k_pr12<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.spread, flag1, ptr2, w.long_list,
+    k_pr12<<<grid_for(g.n, 256), 256, 0, s>>>(g, lam, vinst, parent, w.spread, flag1, ptr2, w.long_list,
                                                             w.counters, w.first, w.heavy, prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
@@ -785,7 +836,7 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
 bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t* len,
                  int64_t* deg, int32_t* noncanon, hipStream_t s) {
     if (!fill_i32(noncanon, 0, 1, s)) return false;
-    k_canon<<<grid_for((int64_t)n * SUB, 256), 256, 0, s>>>(row_ptr, col, w, n, len, deg, noncanon);
+    k_canon<<<grid_for(((int64_t)n + SUB - 1) / SUB * SUB, 256), 256, 0, s>>>(row_ptr, col, w, n, len, deg, noncanon);
     MC_LAUNCHED("k_canon");
     return true;
 }
