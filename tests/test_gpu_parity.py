@@ -516,6 +516,23 @@ def test_lp_first_round_from_singletons_matches_oracle(ctx, seed, whi):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("seed,nlab", [(5, 3), (6, 60), (7, 0)])
+def test_lp_round_all_row_classes_match_oracle(ctx, seed, nlab):
+    # a power-law graph with rows of every length class (register rows up
+    # to 128 entries, LDS-table rows up to 512, long rows beyond), weights
+    # 1..3 so that label weights tie often; bit-exact
+    g = gen.chung_lu(20000, 2.1, 24, seed, 1, 3, kcore=0, lcc=False)
+    d = np.diff(g.row_ptr)
+    say("lp rows", seed, nlab, "max row", int(d.max()), "rows >128:", int((d > 128).sum()), ">512:", int((d > 512).sum()))
+    assert d.max() > 512 and ((d > 128) & (d <= 512)).sum() > 0
+    r = np.random.default_rng(seed)
+    lab = np.arange(g.n, dtype=np.int32) if nlab == 0 else r.integers(0, nlab, g.n).astype(np.int32)
+    dev = ctx.dgraph(g)
+    want = oracle.lp_round(g, lab)
+    assert np.array_equal(ctx.step_lp(dev, lab), want)
+    assert np.array_equal(ctx.step_lp(dev, want), oracle.lp_round(g, want))
+
+
 def test_lp_round_ties_and_own_label(ctx):
     # star-like rows with equal weights: ties go to the smallest label, and a
     # vertex keeps its label unless another is strictly heavier
