@@ -331,8 +331,13 @@ def main():
     ms = (t1 - t0) * 1000.0 / args.steps
     log("timed %d steps: %.3f ms/step, lambda=%d, rounds=%d" % (args.steps, ms, lam, stats[-1]["rounds"]))
     roofline = None
+    rounds = None
     if not args.no_profile:
         ctx.profile(False)
+        rounds = [round_record(r) for r in ctx.profile_rounds()]
+        for r in rounds:
+            log("  round %-6s n %9d -> %9d  edges %10d -> %10d  %7.3f ms  %6.2f G edges/s  %7.1f GB/s algorithmic" % (
+                r["kind"], r["n"], r["n_out"], r["m"], r["m_out"], r["ms"], r["edges_per_s"] / 1e9, r["alg_gbps"]))
         kt = ctx.profile_read()
         for name, r in sorted(kt.items(), key=lambda kv: -kv[1]["ms"]):
             if r["launches"]:
@@ -390,9 +395,29 @@ def main():
         "config": {"workload": wname, "n": g.n, "m": g.m, "lambda": lam,
                    "rounds": stats[-1]["rounds"], "heuristic_levels": stats[-1]["heuristic_levels"]},
         "roofline": roofline,
+        "rounds": rounds,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def round_record(r):
+    """One round of the last timed solve: undirected edges in and out,
+    device time, edges contracted per second and algorithmic GB/s. A round of
+    Algorithm 2 moves about 40 B per entry in (reduction tests 12, CAPFOREST
+    12, contraction 16), 12 B per entry out and 40 B per vertex; a coarsening
+    level of the heuristic about 44 B per entry in (two LP rounds 28,
+    contraction 16), 24 B per entry out (written, then read by the tests)
+    and 60 B per vertex."""
+    m_in, m_out, n = r["m_in"], r["m_out"], r["n_in"]
+    if r["kind"] == "level":
+        alg = 44 * m_in + 24 * m_out + 60 * n
+    else:
+        alg = 40 * m_in + 12 * m_out + 40 * n
+    ms = r["ms"]
+    return {"kind": r["kind"], "n": n, "n_out": r["n_out"], "m": m_in // 2, "m_out": m_out // 2,
+            "ms": round(ms, 4), "edges_per_s": (m_in / 2) / (ms / 1000.0) if ms > 0 else 0.0,
+            "alg_gbps": alg / (ms * 1e6) if ms > 0 else 0.0}
 
 
 if __name__ == "__main__":

@@ -261,6 +261,25 @@ mc_status mc_profile(mc_ctx* ctx, int32_t on);
 /* Totals of one kernel (kernel in [0, MC_K_COUNT)); synchronous. */
 mc_status mc_profile_read(mc_ctx* ctx, int32_t kernel, mc_kernel_time* out);
 
+/* Rounds of the last mc_mincut made while timing was on, in order: kind 1
+ * for a coarsening level of the bound heuristic (LP rounds, cluster
+ * contraction, reduction tests and their contraction), kind 2 for a round
+ * of Algorithm 2 on the heuristic's coarse graph, kind 0 for a round of
+ * Algorithm 2 on the input graph. n/m are the vertices and CSR entries
+ * before and after the round; ms is the device time from the round's first
+ * launch to its last (HIP events on the context's stream, so the gaps
+ * between launches count). *count is always written; out only when
+ * 0 <= i < *count. Synchronous. */
+typedef struct {
+    int32_t kind;
+    int32_t n_in;
+    int64_t m_in;
+    int32_t n_out;
+    int64_t m_out;
+    double ms;
+} mc_round_time;
+mc_status mc_profile_round(mc_ctx* ctx, int32_t i, mc_round_time* out, int32_t* count);
+
 /* Thread-local description of the last error (never NULL). */
 const char* mc_last_error(void);
 

@@ -62,6 +62,11 @@ class Tuning(ctypes.Structure):
                 ("cand_lp", ctypes.c_int32 * MC_TUNE_MAX), ("cand_ms", ctypes.c_double * MC_TUNE_MAX)]
 
 
+class RoundTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_in", ctypes.c_int32), ("m_in", ctypes.c_int64),
+                ("n_out", ctypes.c_int32), ("m_out", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -111,6 +116,7 @@ SIGNATURES = {
     "mc_server_capacity": (ctypes.c_int, [P, P, P, P, P]),
     "mc_profile": (ctypes.c_int, [P, I32]),
     "mc_profile_read": (ctypes.c_int, [P, I32, P]),
+    "mc_profile_round": (ctypes.c_int, [P, I32, P, P]),
     "mc_step_ws_size": (ctypes.c_int, [I32, I64, I32, P]),
     "mc_step_contract": (ctypes.c_int, [P, P, P, I32, P, P, SZ, P, P]),
     "mc_step_components": (ctypes.c_int, [P, I32, I64, P, P, P, P, P, SZ]),
@@ -313,6 +319,20 @@ class Context:
     def profile(self, on=True):
         """Switch kernel timing on (zeroing the totals) or off."""
         _check(lib().mc_profile(self.h, int(bool(on))))
+
+    def profile_rounds(self):
+        """Rounds of the last solve made while timing was on (mc_profile_round):
+        [{"kind": "exact" | "level" | "coarse", "n_in", "m_in", "n_out", "m_out", "ms"}]."""
+        cnt = ctypes.c_int32()
+        _check(lib().mc_profile_round(self.h, 0, None, ctypes.byref(cnt)))
+        kinds = {0: "exact", 1: "level", 2: "coarse"}
+        out = []
+        for i in range(cnt.value):
+            r = RoundTime()
+            _check(lib().mc_profile_round(self.h, i, ctypes.byref(r), ctypes.byref(cnt)))
+            out.append({"kind": kinds.get(r.kind, str(r.kind)), "n_in": r.n_in, "m_in": r.m_in, "n_out": r.n_out,
+                        "m_out": r.m_out, "ms": r.ms})
+        return out
 
     def profile_read(self):
         """{kernel name: {"launches", "ms", "bytes"}} since profiling was switched on."""

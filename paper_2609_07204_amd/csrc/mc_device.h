@@ -30,6 +30,7 @@ struct DevScalars {
     unsigned long long marks_pr;
     unsigned long long marks_cf;
     unsigned long long marks_tri;   // of which reduction tests 3 and 4
+    int64_t m2;             // entries of the graph the last min_degree read
     int32_t dmin_arg;       // vertex of minimum degree (smallest id on ties)
     int32_t best_pass;      // pass that found best_alpha
     int32_t best_len;       // its scanned-prefix length

@@ -86,6 +86,9 @@ struct Prof {
     std::vector<hipEvent_t> pool;
     struct Pending { int k; hipEvent_t a, b; };
     std::vector<Pending> pending;
+    struct Round { int32_t kind, n_in, n_out; int64_t m_in, m_out; hipEvent_t a, b; };
+    std::vector<Round> rounds;   // of the last solve
+    bool round_open = false;
 
     hipEvent_t take() {
         hipEvent_t e = nullptr;
@@ -104,7 +107,17 @@ struct Prof {
         }
         pending.clear();
     }
+    // a new solve: the last solve's round events go back to the pool
+    void clear_rounds() {
+        for (const Round& r : rounds) {
+            if (r.a) pool.push_back(r.a);
+            if (r.b) pool.push_back(r.b);
+        }
+        rounds.clear();
+        round_open = false;
+    }
     ~Prof() {
+        clear_rounds();
         for (const Pending& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
         if (dbytes) (void)hipFree(dbytes);
@@ -160,6 +173,29 @@ unsigned long long* prof_dev_bytes(int k) {
 
 void prof_host_bytes(int k, double bytes) {
     if (g_prof) g_prof->hbytes[k] += bytes;
+}
+
+// round records: a round left open (no contraction followed) closes with
+// its input sizes when the next one begins
+void prof_round_end(int32_t n_out, int64_t m_out, hipStream_t s) {
+    Prof* p = g_prof;
+    if (!p || !p->round_open) return;
+    Prof::Round& r = p->rounds.back();
+    r.b = p->take();
+    if (r.b) (void)hipEventRecord(r.b, s);
+    r.n_out = n_out;
+    r.m_out = m_out;
+    p->round_open = false;
+}
+
+void prof_round_begin(int32_t kind, int32_t n, int64_t m, hipStream_t s) {
+    Prof* p = g_prof;
+    if (!p) return;
+    if (p->round_open) prof_round_end(p->rounds.back().n_in, p->rounds.back().m_in, s);
+    Prof::Round r{kind, n, n, m, m, p->take(), nullptr};
+    if (r.a) (void)hipEventRecord(r.a, s);
+    p->rounds.push_back(r);
+    p->round_open = true;
 }
 
 
@@ -272,6 +308,27 @@ extern "C" mc_status mc_profile_read(mc_ctx* c, int32_t kernel, mc_kernel_time* 
     out->launches = p->launches[kernel];
     out->ms = p->ms[kernel];
     out->bytes = dev_bytes + p->hbytes[kernel];
+    return MC_OK;
+}
+
+extern "C" mc_status mc_profile_round(mc_ctx* c, int32_t i, mc_round_time* out, int32_t* count) {
+    if (!c || !count) return fail(MC_E_INVALID_ARG, "mc_profile_round: NULL argument");
+    *count = 0;
+    if (!c->prof) return MC_OK;
+    Prof* p = static_cast<Prof*>(c->prof);
+    *count = (int32_t)p->rounds.size();
+    if (i < 0 || i >= *count || !out) return MC_OK;
+    const Prof::Round& r = p->rounds[(size_t)i];
+    std::memset(out, 0, sizeof(*out));
+    out->kind = r.kind;
+    out->n_in = r.n_in;
+    out->m_in = r.m_in;
+    out->n_out = r.n_out;
+    out->m_out = r.m_out;
+    float t = 0.f;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
+    if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess)
+        out->ms = t;
     return MC_OK;
 }
 
@@ -502,6 +559,8 @@ struct Solver {
     int64_t lam = 0;
     bool debug = false;
     bool tri_on = false;          // reduction tests 3 and 4 still pay off
+    bool in_heuristic = false;    // exact rounds on the heuristic's coarse graph
+    int64_t cur_m = 0;            // entries of the current graph
     mc_stats stats{};
 
     // Reduction tests of one round on g into parent (reset beforehand):
@@ -647,6 +706,7 @@ static mc_status exact_rounds(Solver& S, int src) {
     while (cur->n > 2) {
         DGraph* nxt = &w.g[nxt_idx];
         const int32_t n = cur->n;
+        prof_round_begin(S.in_heuristic ? 2 : 0, n, S.cur_m, s);
         k_reset_round<<<1, 1, 0, s>>>(w.sc);
         if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
         if (!S.reduction_tests(*cur)) return MC_E_DEVICE;
@@ -732,14 +792,17 @@ static mc_status exact_rounds(Solver& S, int src) {
         if (!map_update(w.map0, w.L, S.n0, s)) return MC_E_DEVICE;
         if (!S.readback()) return MC_E_DEVICE;
         h = *S.c->hsc;
+        S.cur_m = h.m2;
         if (n2 >= 2 && h.dmin < S.lam) {
             if (!side_from_vertex(w.side, w.map0, S.n0, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
             if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
         }
+        prof_round_end(n2, S.cur_m, s);
         nxt_idx = (nxt_idx == 1) ? 2 : 1;
         cur = nxt;
         round++;
     }
+    prof_round_end(cur->n, S.cur_m, s);   // a round that ended without contraction
     S.stats.rounds += round;
     return MC_OK;
 }
@@ -755,6 +818,7 @@ static DGraph* contract_and_bound(Solver& S, DGraph* cur, int32_t n2, int* nxt_i
     if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s) || !map_update(w.map0, w.L, S.n0, s) || !S.readback())
         return nullptr;
     const DevScalars h = *S.c->hsc;
+    S.cur_m = h.m2;
     if (n2 >= 2 && h.dmin < S.lam) {
         if (!side_from_vertex(w.side, w.map0, S.n0, &w.sc->dmin_arg, s) || !S.set_lam(h.dmin)) return nullptr;
     }
@@ -782,6 +846,7 @@ static mc_status heuristic(Solver& S) {
     mc_status err = MC_OK;
     while (cur->n > nh && cur->n > 2) {
         const int32_t n = cur->n;
+        prof_round_begin(1, n, S.cur_m, s);
         int32_t* a = w.parent;   // labels ping-pong between parent[] and lab2[]
         int32_t* b = w.lab2;
         // the first round starts from singleton labels on a normal graph
@@ -813,10 +878,14 @@ static mc_status heuristic(Solver& S) {
             cur = contract_and_bound(S, cur, n3, &nxt_idx, &err);
             if (!cur) return err;
         }
+        prof_round_end(cur->n, S.cur_m, s);
     }
+    prof_round_end(cur->n, S.cur_m, s);   // a level that stopped before contracting
     if (cur == &w.g[0]) return MC_OK;   // nothing coarsened: the exact rounds start from the min degree
     if (cur->n > 2) {
+        S.in_heuristic = true;
         mc_status r = exact_rounds(S, nxt_idx == 1 ? 2 : 1);
+        S.in_heuristic = false;
         if (r != MC_OK) return r;
     }
     S.stats.lambda_heuristic = S.lam;
@@ -840,6 +909,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     if (hipSetDevice(c->device) != hipSuccess) return fail(MC_E_DEVICE, "hipSetDevice failed");
 
     ProfScope prof_scope(static_cast<Prof*>(c->prof));
+    if (g_prof) g_prof->clear_rounds();
     Solver S;
     S.c = c;
     S.s = c->stream;
@@ -909,6 +979,8 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         return MC_E_DEVICE;
     DevScalars h = *c->hsc;
     S.stats.n_input = n;
+    const int64_t m_input = h.m2;   // entries of the normalised input (read by min_degree)
+    S.cur_m = m_input;
     int64_t result = 0;
     if (h.n2 > 1) {
         if (!side_from_components(w.side, w.parent, n, s)) return MC_E_DEVICE;
@@ -923,6 +995,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
             if ((r = heuristic(S)) != MC_OK) return r;
             // the exact rounds start again from the normalised input
             if (!iota_i32(w.map0, n, s)) return MC_E_DEVICE;
+            S.cur_m = m_input;
         }
         if ((r = exact_rounds(S, 0)) != MC_OK) return r;
         result = S.lam;

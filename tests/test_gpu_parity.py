@@ -889,3 +889,27 @@ def test_batch_full_config_matches_oracle(ctx):
     bad = [(i, gs[i].name, int(lams[i]), refs[i], cuts[i]) for i in range(len(gs))
            if lams[i] != refs[i] or cuts[i] != refs[i] or sides[i][0] != 0]
     assert not bad, bad[:5]
+
+
+def test_round_timing_records_the_solve(ctx):
+    # per-round records of a profiled solve: heuristic levels first, then
+    # the exact rounds; sizes shrink, the first round starts from the input
+    g = gen.config_chung_lu(16)
+    ctx.profile(True)
+    try:
+        lam, _ = ctx.mincut(g)
+        rounds = ctx.profile_rounds()
+    finally:
+        ctx.profile(False)
+    say("rounds", [(r["kind"], r["n_in"], r["m_in"], r["n_out"], round(r["ms"], 3)) for r in rounds])
+    assert lam == oracle.noi(g)[0]
+    assert rounds and all(r["ms"] > 0 for r in rounds)
+    assert rounds[0]["n_in"] == g.n and rounds[0]["m_in"] == g.nnz
+    kinds = [r["kind"] for r in rounds]
+    assert kinds == sorted(kinds, key=lambda k: {"level": 0, "coarse": 1, "exact": 2}[k])
+    for r in rounds:
+        assert r["n_out"] <= r["n_in"] and r["m_out"] <= r["m_in"]
+    ex = [r for r in rounds if r["kind"] == "exact"]
+    assert ex and ex[0]["n_in"] == g.n
+    for a, b in zip(ex, ex[1:]):
+        assert b["n_in"] == a["n_out"] and b["m_in"] == a["m_out"]
