@@ -273,6 +273,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the solves, one device-to-device copy of this many MiB (the known-size kernel "
                          "that scales hardware byte counters)")
+    ap.add_argument("--lp-iters", type=int, default=0, help="label-propagation rounds per level (0: default)")
+    ap.add_argument("--tri-cap", type=int, default=-1, help="row-length cap of reduction tests 3 and 4 (-1: default)")
     ap.add_argument("--heuristic-min-n", type=int, default=10000,
                     help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
     args = ap.parse_args()
@@ -305,8 +307,13 @@ def main():
         key = "chung_lu_2^%d_core10_seed%d" % (args.log2n, args.seed)
         wname = ("chung_lu n=2^%d beta=2.5 avg_deg=20 10-core LCC unit weights seed=%d" % (args.log2n, args.seed))
     log("generated %s: n=%d m=%d in %.1fs" % (g.name, g.n, g.m, time.time() - t))
+    extra = {}
+    if args.lp_iters > 0:
+        extra["lp_iters"] = args.lp_iters
+    if args.tri_cap >= 0:
+        extra["pr_tri_deg_cap"] = args.tri_cap
     ctx = mc.Context(0, capforest_passes=args.passes, pass_len_cap=args.len_cap,
-                     heuristic_min_n=args.heuristic_min_n)
+                     heuristic_min_n=args.heuristic_min_n, **extra)
     dev = ctx.upload(g)
     ws = torch.empty(ctx.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device=ctx.device)
     torch.cuda.synchronize()
