@@ -245,12 +245,18 @@ __global__ __launch_bounds__(T) void k_cfs_plan(StepArgs a) {
         single = true;
         B = 1;
     } else if (c.head < c.tail) {
+        // capped vertices may be scanned in any order, so a batch cut at
+        // the pass's remaining budget is a prefix of a valid pass
         B = c.tail - c.head;
         if (cap > 0 && B > cap - c.nscan) B = cap - c.nscan;
+        if (B > a.bcap) B = a.bcap;
     } else {
-        // the largest key, from the parts of k_cfs_popscan; a pass that has
-        // spent its single pops stops here (it ends at a valid prefix)
-        if (a.max_singles > 0 && c.singles >= a.max_singles) {
+        // the largest key, from the parts of k_cfs_popscan. A truncated pass
+        // stops here, at a valid prefix, after max_singles single pops in a
+        // row (each costs a whole-GPU step); single pops up to there are
+        // what lets a weighted graph's pass reach its first capped vertices
+        const int32_t streak = c.streak;
+        if (a.max_singles > 0 && streak >= a.max_singles) {
             __syncthreads();
             if (tid == 0) { c.done = 1; c.bcount = 0; c.E = 0; }
             return;
@@ -269,11 +275,12 @@ __global__ __launch_bounds__(T) void k_cfs_plan(StepArgs a) {
             if (tid == 0) { c.done = 1; c.bcount = 0; c.E = 0; }
             return;
         }
-        if (tid == 0) { *w.single = s_x; c.singles++; }
+        if (tid == 0) { *w.single = s_x; c.singles++; c.streak++; }
         single = true;
         B = 1;
     }
     __syncthreads();
+    if (tid == 0 && !single) c.streak = 0;
     // mark the batch, prefix of row lengths, sum of c(x) - 2 r(x)
     const int32_t* src = single ? w.single : w.fifo + c.head;
     int32_t run = 0;

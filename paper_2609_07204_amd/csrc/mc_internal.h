@@ -289,6 +289,7 @@ struct StepCtl {
     int32_t nscan, done, bcount, bsingle;
     int32_t E, single_pending, best_len, steps;
     int32_t singles, maxbatch;
+    int32_t streak, pad_;     // single pops since the last batch
     int64_t entries;
     int64_t alpha, best_alpha, lam, part, intra;
     unsigned long long marks;
@@ -303,7 +304,7 @@ struct StepArgs {
     int32_t* running;   // [1]
     int64_t* popk;      // [passes*512] parts of the single-pop maximum
     int32_t* popv;
-    int32_t max_singles;  // single pops per pass before it stops (0: none)
+    int32_t max_singles;  // single pops in a row after which a pass stops (0: no bound)
     unsigned long long* prof;  // algorithmic-byte counter (profiling) or nullptr
     // per pass, SPREAD partial sums 128 B apart of the step's intra-batch
     // weight ([0]) and marks ([1]), so the edge tiles do not all add to one

@@ -681,9 +681,9 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
         sa.pv = pa;
         int32_t running = 0;
         if (len_cap <= 0 || len_cap > sa.bcap) sa.bcap = g.n;   // unlimited pass: one pass, n+1 prefix slots
-        // a truncated pass that has run out of capped vertices continues one
-        // vertex per whole-GPU step; bound that tail (the complete fallback
-        // pass is never bounded)
+        // a truncated pass with no capped vertex queued continues one vertex
+        // per whole-GPU step; bound such runs (the complete fallback pass is
+        // never bounded)
         sa.max_singles = len_cap > 0 ? 256 : 0;
         if (!capforest_steps(sa, &running, S.s)) return false;
     } else if (!capforest_private(pa, S.s)) {
@@ -760,10 +760,17 @@ static mc_status exact_rounds(Solver& S, int src) {
         }
         S.stats.marks_pr += (int64_t)(h.marks_pr + h.marks_tri);
         S.stats.marks_capforest += (int64_t)h.marks_cf;
-        if (h.marks_pr + h.marks_tri + h.marks_cf == 0) {
-            // Algorithm 2: no contractible edge found, run CAPFOREST over the
-            // whole graph without a length limit; with a fixed bound it marks
-            // at least one edge, otherwise it lowered the bound
+        const unsigned long long marks0 = h.marks_pr + h.marks_tri + h.marks_cf;
+        // Algorithm 2: no contractible edge found, run CAPFOREST over the
+        // whole graph without a length limit; with a fixed bound it marks at
+        // least one edge, otherwise it lowered the bound. The same complete
+        // pass also follows truncated passes that found fewer than one
+        // contraction per 1024 vertices (on heavily weighted graphs a pass
+        // reaches capped vertices only after many single pops, and a
+        // truncated one stops first), so such graphs are not contracted a
+        // handful of edges per round.
+        const bool truncated = !det && !shared && !skip_cf && private_len_cap(S.c) > 0;
+        if (marks0 == 0 || (truncated && marks0 * 1024 < (unsigned long long)n)) {
             const int64_t lam_before = S.lam;
             if (det) {
                 if (!sequential_pass(S, *cur, round + 7777)) return MC_E_DEVICE;
@@ -771,16 +778,17 @@ static mc_status exact_rounds(Solver& S, int src) {
                 if (!private_passes(S, *cur, round + 7777, 1, 0)) return MC_E_DEVICE;
             }
             if (!S.readback()) return MC_E_DEVICE;
+            const unsigned long long cf0 = h.marks_cf;
             h = *S.c->hsc;
             S.stats.fallback_passes++;
-            S.stats.marks_capforest += (int64_t)h.marks_cf;
+            S.stats.marks_capforest += (int64_t)(h.marks_cf - cf0);
             if (h.best_pass >= 0 && h.best_alpha < S.lam) {
                 pref_order = det ? w.corder : w.pv.order;
                 if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, pref_order, &w.sc->best_len, s))
                     return MC_E_DEVICE;
                 if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
             }
-            if (h.marks_cf == 0) {
+            if (marks0 == 0 && h.marks_cf == 0) {
                 if (S.lam < lam_before) { round++; continue; }
                 return fail(MC_E_DEVICE, "sequential CAPFOREST marked no edge at a fixed bound");
             }
