@@ -29,7 +29,7 @@ namespace {
 
 constexpr int CHUNK = 512;          // chunk span in (entry offset + group index)
 constexpr int SMALL_MAX = 512;      // larger groups take the global-table path
-constexpr int HSLOTS = 1024;        // LDS hash slots per chunk (load <= 1/2)
+constexpr int HSLOTS = 1024;        // LDS hash slots per chunk (> the most entries a chunk holds)
 constexpr int TILE_SLOTS = 256;     // global-table allocation and extraction unit
 constexpr uint64_t EMPTY_KEY = ~0ULL;
 
