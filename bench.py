@@ -11,7 +11,7 @@ largest connected component of its 10-core, unit int64 weights, seed 1
 input edges / solve time (every input edge is contracted away or ends in the
 final cut during one solve).
 
-Prints one JSON line. --gpus > 1 is refused: this build runs on one GPU.
+Prints one JSON line. --gpus > 1 is refused: the solver runs on one GPU.
 """
 import argparse
 import json
@@ -279,7 +279,7 @@ def main():
                     help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
+        print("bench.py: the solver runs on one GPU only (it has no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
