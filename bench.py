@@ -265,9 +265,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="batch: time the batched call only (parameter sweeps)")
     ap.add_argument("--tune-sample", type=int, default=512,
                     help="batch: graphs the autotuner times before the run (0: no tuning)")
-    ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--rates", default="50,200,1000")
-    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--pool", type=int, default=256)
+    ap.add_argument("--rates", default="20,50,200,1000,2000",
+                    help="served: arrival rates per second (20/s is below the server's capacity)")
+    ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--hbm-gb", type=float, default=48.0)
     ap.add_argument("--max-inflight", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
