@@ -400,6 +400,21 @@ __global__ void k_private_reset(int32_t* st, int64_t* r, int64_t count) {
 
 }  // namespace
 
+static bool launch_private(const PrivateArgs& a, int32_t threads, size_t lds, hipStream_t s) {
+    switch (threads) {
+        case 64: k_capforest_private<64><<<a.passes, 64, lds, s>>>(a); break;
+        case 128: k_capforest_private<128><<<a.passes, 128, lds, s>>>(a); break;
+        case 256: k_capforest_private<256><<<a.passes, 256, lds, s>>>(a); break;
+        case 512: k_capforest_private<512><<<a.passes, 512, lds, s>>>(a); break;
+        case 1024: k_capforest_private<1024><<<a.passes, 1024, lds, s>>>(a); break;
+        default:
+            mc_hip_ok(hipErrorInvalidValue, "capforest_private: unsupported pass workgroup size");
+            return false;
+    }
+    MC_LAUNCHED("k_capforest_private");
+    return true;
+}
+
 bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) {
     if (a.passes <= 0) return true;
     if (a.pvoff) {
@@ -409,19 +424,7 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
             mc_hip_ok(hipErrorInvalidValue, "capforest_private: instance too large for the pass index");
             return false;
         }
-        const size_t lds = (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long);
-        switch (a.threads > 0 ? a.threads : PT_INST) {
-            case 64: k_capforest_private<64><<<a.passes, 64, lds, s>>>(a); break;
-            case 128: k_capforest_private<128><<<a.passes, 128, lds, s>>>(a); break;
-            case 256: k_capforest_private<256><<<a.passes, 256, lds, s>>>(a); break;
-            case 512: k_capforest_private<512><<<a.passes, 512, lds, s>>>(a); break;
-            case 1024: k_capforest_private<1024><<<a.passes, 1024, lds, s>>>(a); break;
-            default:
-                mc_hip_ok(hipErrorInvalidValue, "capforest_private: unsupported pass workgroup size");
-                return false;
-        }
-        MC_LAUNCHED("k_capforest_private");
-        return true;
+        return launch_private(a, a.threads > 0 ? a.threads : PT_INST, (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long), s);
     }
     if (a.g.n > a.stride) {
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: per-pass stride smaller than n");
@@ -432,9 +435,7 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: graph too large for the pass index");
         return false;
     }
-    k_capforest_private<PT_SOLVE><<<a.passes, PT_SOLVE, (size_t)nb2 * sizeof(long long), s>>>(a);
-    MC_LAUNCHED("k_capforest_private");
-    return true;
+    return launch_private(a, a.threads > 0 ? a.threads : PT_SOLVE, (size_t)nb2 * sizeof(long long), s);
 }
 
 bool capforest_private_reset(const PrivateArgs& a, hipStream_t s) {

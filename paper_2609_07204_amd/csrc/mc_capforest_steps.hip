@@ -33,6 +33,8 @@
 // The host issues steps and reads the running-pass count every few steps.
 #include <algorithm>
 
+#include <vector>
+
 #include "mc_internal.h"
 
 namespace {
@@ -595,7 +597,9 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
     k_cfs_init<<<P, T, 0, s>>>(a);
     MC_LAUNCHED("k_cfs_init");
     const int poll = 4;
+    a.steps_run = 0;
     for (int32_t step = 0;; step++) {
+        a.steps_run = step + 1;
         k_cfs_popscan<<<POP_BLOCKS, POP_T, 0, s>>>(a);
         MC_LAUNCHED("k_cfs_popscan");
         k_cfs_plan<<<P, T, 0, s>>>(a);
@@ -622,7 +626,13 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
             return false;
         }
     }
+    // the passes' scan counts, for the caller's choice of a complete pass
+    std::vector<StepCtl> ctl((size_t)P);
+    MC_HIP(hipMemcpyAsync(ctl.data(), a.ctl, sizeof(StepCtl) * (size_t)P, hipMemcpyDeviceToHost, s));
     k_cfs_end<<<P * END_SPLIT, T, 0, s>>>(a);
     MC_LAUNCHED("k_cfs_end");
+    MC_HIP(hipStreamSynchronize(s));
+    a.scans_run = 0;
+    for (const StepCtl& c : ctl) a.scans_run += c.nscan;
     return true;
 }

@@ -274,7 +274,7 @@ struct PrivateArgs {
     const int64_t* plam = nullptr;
     const uint8_t* prun = nullptr;
     unsigned long long* pmarks = nullptr;
-    int32_t threads = 0;    // instance mode: workgroup size of a pass (64..1024; 0 = 256)
+    int32_t threads = 0;    // workgroup size of a pass (64..1024; 0 = 256 in instance mode, else 1024)
 };
 constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
 bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n = 0);
@@ -305,6 +305,8 @@ struct StepArgs {
     int64_t* popk;      // [passes*512] parts of the single-pop maximum
     int32_t* popv;
     int32_t max_singles;  // single pops in a row after which a pass stops (0: no bound)
+    int32_t steps_run;    // out (host): whole-GPU steps the last call took
+    int64_t scans_run;    // out (host): vertices its passes scanned
     unsigned long long* prof;  // algorithmic-byte counter (profiling) or nullptr
     // per pass, SPREAD partial sums 128 B apart of the step's intra-batch
     // weight ([0]) and marks ([1]), so the edge tiles do not all add to one

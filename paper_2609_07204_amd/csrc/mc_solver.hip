@@ -561,6 +561,8 @@ struct Solver {
     bool tri_on = false;          // reduction tests 3 and 4 still pay off
     bool in_heuristic = false;    // exact rounds on the heuristic's coarse graph
     int64_t cur_m = 0;            // entries of the current graph
+    int32_t last_cf_steps = 0;    // whole-GPU steps of the round's last CAPFOREST launch
+    int64_t last_cf_scans = 0;    // and the vertices it scanned
     mc_stats stats{};
 
     // Reduction tests of one round on g into parent (reset beforehand):
@@ -661,6 +663,7 @@ static bool sequential_pass(Solver& S, const DGraph& g, int32_t round) {
 // `passes` private batched passes over g (len_cap 0: complete), results in sc.
 static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t passes, int32_t len_cap) {
     SolveWS& w = S.w;
+    if (len_cap > 0) S.last_cf_steps = 0, S.last_cf_scans = 0;
     PrivateArgs pa = w.pv;
     pa.g = g;
     pa.lam = &w.sc->lam;
@@ -672,11 +675,18 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     pa.start = -1;
     pa.marks = &w.sc->marks_cf;
     pa.steps = w.psteps;
-    // a complete pass (len_cap 0) of a sparse graph can be mostly single
-    // pops, one whole-GPU step each; below 4x the level threshold it runs in
-    // one workgroup, which pops a vertex in microseconds
+    // A complete pass (len_cap 0, the fallback of Algorithm 2) of a graph
+    // whose truncated passes were mostly single pops (many whole-GPU steps
+    // of fewer than 8 vertices on average: heavy weights, a bound far above
+    // most edge weights) runs in one workgroup of 256 threads, which takes a
+    // single pop from its two-level index in about a microsecond, where a
+    // whole-GPU step rescans every vertex. Below 4x the level threshold it
+    // always does; above, a complete pass of large batches stays on the
+    // whole GPU.
     const int64_t lmin = levels_min_n(S.c);
-    if (g.n >= lmin && (len_cap > 0 || g.n >= 4 * lmin)) {
+    const bool singles_heavy = len_cap <= 0 && S.last_cf_steps > 200 && S.last_cf_scans < 8 * (int64_t)S.last_cf_steps;
+    if (len_cap <= 0 && (singles_heavy || g.n < 4 * lmin)) pa.threads = 256;
+    if (g.n >= lmin && (len_cap > 0 || (g.n >= 4 * lmin && !singles_heavy))) {
         StepArgs sa = w.sa;
         sa.pv = pa;
         int32_t running = 0;
@@ -686,6 +696,8 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
         // never bounded)
         sa.max_singles = len_cap > 0 ? 256 : 0;
         if (!capforest_steps(sa, &running, S.s)) return false;
+        S.last_cf_steps = sa.steps_run;
+        S.last_cf_scans = sa.scans_run;
     } else if (!capforest_private(pa, S.s)) {
         return false;
     }
@@ -772,6 +784,9 @@ static mc_status exact_rounds(Solver& S, int src) {
         const bool truncated = !det && !shared && !skip_cf && private_len_cap(S.c) > 0;
         if (marks0 == 0 || (truncated && marks0 * 1024 < (unsigned long long)n)) {
             const int64_t lam_before = S.lam;
+            if (S.debug)
+                fprintf(stderr, "[mc] round %d complete pass: n=%d marks so far %llu, last truncated launch %d steps %lld scans\n",
+                        round, n, marks0, S.last_cf_steps, (long long)S.last_cf_scans);
             if (det) {
                 if (!sequential_pass(S, *cur, round + 7777)) return MC_E_DEVICE;
             } else {
