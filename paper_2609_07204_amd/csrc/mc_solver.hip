@@ -678,14 +678,14 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     // A complete pass (len_cap 0, the fallback of Algorithm 2) of a graph
     // whose truncated passes were mostly single pops (many whole-GPU steps
     // of fewer than 8 vertices on average: heavy weights, a bound far above
-    // most edge weights) runs in one workgroup of 256 threads, which takes a
-    // single pop from its two-level index in about a microsecond, where a
-    // whole-GPU step rescans every vertex. Below 4x the level threshold it
-    // always does; above, a complete pass of large batches stays on the
-    // whole GPU.
+    // most edge weights) runs in one workgroup of 512 threads (the best of
+    // 64..1024 measured), which takes a single pop from its two-level index
+    // in about a microsecond, where a whole-GPU step rescans every vertex.
+    // Below 4x the level threshold it always does; above, a complete pass
+    // of large batches stays on the whole GPU.
     const int64_t lmin = levels_min_n(S.c);
     const bool singles_heavy = len_cap <= 0 && S.last_cf_steps > 200 && S.last_cf_scans < 8 * (int64_t)S.last_cf_steps;
-    if (len_cap <= 0 && (singles_heavy || g.n < 4 * lmin)) pa.threads = 256;
+    if (len_cap <= 0 && (singles_heavy || g.n < 4 * lmin)) pa.threads = 512;
     if (g.n >= lmin && (len_cap > 0 || (g.n >= 4 * lmin && !singles_heavy))) {
         StepArgs sa = w.sa;
         sa.pv = pa;
