@@ -228,24 +228,35 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
             const int32_t u = perm ? perm[m] : m;
             const int32_t o = src.off[u], l = src.len[u];
             if (sl == 0) nin += l;
-            for (int32_t j = sl; j < l; j += SUB) {
-                const int32_t x = src.col[o + j];
-                const int64_t c = src.w[o + j];
-                if (c <= 0) continue;
-                const int32_t t = L ? L[x] : x;
-                if (t == g) continue;
-                const unsigned long long key = ((unsigned long long)gl << 32) | (uint32_t)t;
-                uint32_t h = hash32((uint32_t)t ^ ((uint32_t)gl * 0x9E3779B1u)) & (HSLOTS - 1);
-                for (;;) {
-                    unsigned long long k = hkey[h];
-                    if (k == key) break;
-                    if (k == EMPTY_KEY) {
-                        unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
-                        if (old == EMPTY_KEY || old == key) break;
-                    }
-                    h = (h + 1) & (HSLOTS - 1);
+            // four entries per lane at a time: their loads, then the labels
+            // of their targets, are in flight together
+            for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
+                int32_t x[4], t[4];
+                int64_t c[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int32_t j = j0 + q * SUB + sl;
+                    x[q] = j < l ? src.col[o + j] : 0;
+                    c[q] = j < l ? src.w[o + j] : 0;
                 }
-                atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c);
+#pragma unroll
+                for (int q = 0; q < 4; q++) t[q] = c[q] > 0 ? (L ? L[x[q]] : x[q]) : g;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (t[q] == g) continue;   // a loop, zero weight or no entry
+                    const unsigned long long key = ((unsigned long long)gl << 32) | (uint32_t)t[q];
+                    uint32_t h = hash32((uint32_t)t[q] ^ ((uint32_t)gl * 0x9E3779B1u)) & (HSLOTS - 1);
+                    for (;;) {
+                        unsigned long long k = hkey[h];
+                        if (k == key) break;
+                        if (k == EMPTY_KEY) {
+                            unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
+                            if (old == EMPTY_KEY || old == key) break;
+                        }
+                        h = (h + 1) & (HSLOTS - 1);
+                    }
+                    atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c[q]);
+                }
             }
         }
     }

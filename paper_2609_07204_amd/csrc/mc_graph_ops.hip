@@ -58,9 +58,14 @@ __global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t o = g.off[v], l = g.len[v] < CONNECT_K ? g.len[v] : CONNECT_K;
         const int32_t r = ld_acq(&par[v]);
+        // all targets, then all their parents, in flight at once
+        int32_t x[CONNECT_K];
+#pragma unroll
+        for (int j = 0; j < CONNECT_K; j++) x[j] = j < l ? g.col[o + j] : (int32_t)v;
         int32_t m = r;
-        for (int32_t j = 0; j < l; j++) {
-            const int32_t px = ld_acq(&par[g.col[o + j]]);
+#pragma unroll
+        for (int j = 0; j < CONNECT_K; j++) {
+            const int32_t px = j < l ? ld_acq(&par[x[j]]) : r;
             m = px < m ? px : m;
         }
         if (m < r && m < ld_acq(&par[r])) atomicMin(&par[r], m);

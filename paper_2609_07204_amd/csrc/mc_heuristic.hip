@@ -105,23 +105,36 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
         const int32_t v = g_lo + gl;
         const int32_t o = g.off[v], l = g.len[v];
         if (l > LP_SMALL) continue;
-        for (int32_t j = sl; j < l; j += LP_SUB) {
-            const int32_t x = g.col[o + j];
-            if (x == v) continue;
-            const unsigned long long c = (unsigned long long)g.w[o + j];
-            const uint32_t lbl = (uint32_t)lab_in[x];
-            const unsigned long long key = ((unsigned long long)gl << 32) | lbl;
-            uint32_t h = lp_hash((uint32_t)gl, lbl) & (LP_HSLOTS - 1);
-            for (;;) {
-                const unsigned long long k = hkey[h];
-                if (k == key) break;
-                if (k == LP_EMPTY) {
-                    const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, key);
-                    if (old == LP_EMPTY || old == key) break;
-                }
-                h = (h + 1) & (LP_HSLOTS - 1);
+        // four entries per lane at a time: their loads, then their labels'
+        // loads, are in flight together
+        for (int32_t j0 = 0; j0 < l; j0 += 4 * LP_SUB) {
+            int32_t x[4];
+            unsigned long long c[4];
+            uint32_t lb[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int32_t j = j0 + u * LP_SUB + sl;
+                x[u] = j < l ? g.col[o + j] : v;
+                c[u] = j < l ? (unsigned long long)g.w[o + j] : 0;
             }
-            atomicAdd(&hval[h], c);
+#pragma unroll
+            for (int u = 0; u < 4; u++) lb[u] = x[u] != v ? (uint32_t)lab_in[x[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (x[u] == v) continue;   // a loop, or no entry
+                const unsigned long long key = ((unsigned long long)gl << 32) | lb[u];
+                uint32_t h = lp_hash((uint32_t)gl, lb[u]) & (LP_HSLOTS - 1);
+                for (;;) {
+                    const unsigned long long k = hkey[h];
+                    if (k == key) break;
+                    if (k == LP_EMPTY) {
+                        const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, key);
+                        if (old == LP_EMPTY || old == key) break;
+                    }
+                    h = (h + 1) & (LP_HSLOTS - 1);
+                }
+                atomicAdd(&hval[h], c[u]);
+            }
         }
     }
     __syncthreads();
@@ -206,10 +219,24 @@ __global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t
         for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) { hkey[k] = LP_EMPTY; hval[k] = 0; }
         __syncthreads();
         const int32_t j1 = (x.t + 1) * LP_TASK < x.l ? (x.t + 1) * LP_TASK : x.l;
-        for (int32_t j = x.t * LP_TASK + threadIdx.x; j < j1; j += LP_T) {
-            const int32_t y = g.col[x.o + j];
-            if (y == x.v) continue;
-            const uint32_t lbl = (uint32_t)lab_in[y];
+        // the task's LP_TASK / LP_T entries per thread: loads, then label
+        // loads, all in flight together
+        constexpr int PER = LP_TASK / LP_T;
+        int32_t y[PER];
+        unsigned long long c[PER];
+        uint32_t lb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int32_t j = x.t * LP_TASK + u * LP_T + threadIdx.x;
+            y[u] = j < j1 ? g.col[x.o + j] : x.v;
+            c[u] = j < j1 ? (unsigned long long)g.w[x.o + j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) lb[u] = y[u] != x.v ? (uint32_t)lab_in[y[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            if (y[u] == x.v) continue;   // a loop, or no entry
+            const uint32_t lbl = lb[u];
             uint32_t h = hash32(lbl) & (LP_TSLOTS - 1);
             for (;;) {
                 const unsigned long long kk = hkey[h];
@@ -220,7 +247,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t
                 }
                 h = (h + 1) & (LP_TSLOTS - 1);
             }
-            atomicAdd(&hval[h], (unsigned long long)g.w[x.o + j]);
+            atomicAdd(&hval[h], c[u]);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) {
