@@ -131,16 +131,30 @@ __global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t*
 // number of dense groups is at most budget / n2 (and DENSE_MAX).
 constexpr int DENSE_MAX = 1024;
 
+// Groups of (SMALL_MAX, MID_MAX] entries and at most MID_MEM members are
+// merged by one workgroup each, entirely in LDS: no global atomics, and the
+// row is written in place. Larger groups take the tile path below.
+constexpr int MID_MAX = 2048;
+constexpr int MID_MEM = 1024;
+constexpr int MID_SLOTS = 4096;    // LDS table (load <= 1/2)
+constexpr int MID_T = 256;
+constexpr int MID_GRID = 512;
+
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
                            int32_t nd_max, int32_t* __restrict__ tsize, int32_t* __restrict__ bigm,
                            int32_t* __restrict__ bcur, int32_t* __restrict__ dslot, int32_t* __restrict__ dinfo,
-                           DGraph dst) {
+                           int32_t* __restrict__ mlist, int32_t* __restrict__ mcnt, DGraph dst) {
     const int64_t dense_min = n2 / 4;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x) {
         int32_t s = gstart[g + 1] - gstart[g];
         dst.off[g] = gstart[g];
         dslot[g] = -1;
-        if (s > SMALL_MAX) {
+        const int32_t members = vstart ? vstart[g + 1] - vstart[g] : 1;
+        if (s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM) {
+            mlist[atomicAdd(mcnt, 1)] = (int32_t)g;
+            tsize[g] = 0;
+            bigm[g] = 0;
+        } else if (s > SMALL_MAX) {
             int32_t d = -1;
             if (s >= dense_min && nd_max > 0) {
                 d = atomicAdd(&dinfo[0], 1);
@@ -281,6 +295,79 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
         ngrp++;
     }
     if (pb) prof_add(pb, nin * (L ? 16 : 12) + nout * 12 + ngrp * 12);
+}
+
+__global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* __restrict__ L,
+                                                    const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ vstart,
+                                                    const int32_t* __restrict__ mstart,
+                                                    const int32_t* __restrict__ gstart,
+                                                    const int32_t* __restrict__ mlist,
+                                                    const int32_t* __restrict__ mcnt, DGraph dst) {
+    __shared__ int32_t tk[MID_SLOTS];
+    __shared__ long long tv[MID_SLOTS];
+    __shared__ int32_t wm[MID_MEM + 1];   // group-relative entry offset of each member
+    __shared__ int32_t wo[MID_MEM];       // row offset of each member
+    __shared__ int32_t s_cnt;
+    __shared__ long long s_deg;
+    const int32_t cnt = *mcnt;
+    const int tid = threadIdx.x;
+    for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int32_t g = mlist[i];
+        const int32_t m0 = vstart ? vstart[g] : g;
+        const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
+        const int32_t gs = gstart[g], s = gstart[g + 1] - gs;
+        __syncthreads();
+        for (int k = tid; k < MID_SLOTS; k += MID_T) { tk[k] = -1; tv[k] = 0; }
+        for (int k = tid; k < mc; k += MID_T) {
+            wm[k] = mstart[m0 + k] - gs;
+            wo[k] = src.off[perm ? perm[m0 + k] : m0 + k];
+        }
+        if (tid == 0) { wm[mc] = s; s_cnt = 0; s_deg = 0; }
+        __syncthreads();
+        for (int32_t e0 = 0; e0 < s; e0 += 4 * MID_T) {
+            int32_t x[4], t[4];
+            int64_t c[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int32_t e = e0 + q * MID_T + tid;
+                x[q] = 0;
+                c[q] = 0;
+                if (e >= s) continue;
+                int32_t lo = 0, hi = mc;   // the member holding entry e
+                while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (wm[mid] <= e) lo = mid; else hi = mid; }
+                x[q] = src.col[wo[lo] + (e - wm[lo])];
+                c[q] = src.w[wo[lo] + (e - wm[lo])];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) t[q] = c[q] > 0 ? (L ? L[x[q]] : x[q]) : g;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (t[q] == g) continue;   // a loop, zero weight or no entry
+                uint32_t h = hash32((uint32_t)t[q]) & (MID_SLOTS - 1);
+                for (;;) {
+                    const int32_t k = tk[h];
+                    if (k == t[q]) break;
+                    if (k == -1) {
+                        const int32_t old = atomicCAS(&tk[h], -1, t[q]);
+                        if (old == -1 || old == t[q]) break;
+                    }
+                    h = (h + 1) & (MID_SLOTS - 1);
+                }
+                atomicAdd((unsigned long long*)&tv[h], (unsigned long long)c[q]);
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < MID_SLOTS; k += MID_T) {
+            if (tk[k] < 0) continue;
+            const int32_t pos = atomicAdd(&s_cnt, 1);
+            dst.col[gs + pos] = tk[k];
+            dst.w[gs + pos] = tv[k];
+            atomicAdd((unsigned long long*)&s_deg, (unsigned long long)tv[k]);
+        }
+        __syncthreads();
+        if (tid == 0) { dst.len[g] = s_cnt; dst.deg[g] = s_deg; }
+    }
 }
 
 __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __restrict__ tkey,
@@ -658,6 +745,8 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
     ws.cg = a.take<int32_t>((size_t)((cap + n) / CHUNK) + 4);
     ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
     ws.xg = a.take<int32_t>(slots / TILE_SLOTS + 8);
+    ws.mlist = a.take<int32_t>((size_t)n + 1);
+    ws.mcnt = a.take<int32_t>(4);
 }
 
 bool contract_ws_reset(const ContractWS& ws, hipStream_t s) { return fill_i64(ws.dense, 0, ws.dense_elems, s); }
@@ -708,9 +797,9 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     // extraction clears what it read)
     const int64_t ndm = ws.dense_elems / (n2 > 0 ? n2 : 1);
     const int32_t nd_max = (int32_t)(ndm < DENSE_MAX ? ndm : DENSE_MAX);
-    if (!fill_i32(ws.dinfo, 0, 1, s)) return false;
+    if (!fill_i32(ws.dinfo, 0, 1, s) || !fill_i32(ws.mcnt, 0, 1, s)) return false;
     k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, nd_max, ws.tsize, ws.bigm, ws.bcur, ws.dslot,
-                                                 ws.dinfo, dst);
+                                                 ws.dinfo, ws.mlist, ws.mcnt, dst);
     MC_LAUNCHED("k_classify");
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
     if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
@@ -722,6 +811,8 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
                                                              prof_dev_bytes(PK_MERGE_SMALL));
     MC_LAUNCHED("k_merge_small");
     prof_end(PK_MERGE_SMALL, s);
+    k_mid_merge<<<MID_GRID, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt, dst);
+    MC_LAUNCHED("k_mid_merge");
     k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);
     MC_LAUNCHED("k_big_clear");
     k_big_tiles<<<grid_for(src.cap / BIG_TILE + 1, 256), 256, 0, s>>>(vstart, ws.mstart, gstart, ws.bigm, n2,

@@ -89,6 +89,8 @@ struct ContractWS {
     int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
     int32_t* tinfo;   // [2*(cap/1024+2)] group and first member of every large-group tile
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
+    int32_t* mlist;   // [n+1] groups merged by one workgroup each in LDS
+    int32_t* mcnt;    // [4] their count
 };
 void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
 // Zero the dense accumulators (once after carving; every contraction leaves

@@ -123,6 +123,30 @@ def test_contract_mixed_group_sizes(ctx):
     assert_same_csr(dst, rp, col, w)
 
 
+def test_contract_groups_around_workgroup_limits(ctx):
+    # groups of 150..1300 members at about three entries each: below, inside
+    # and above the range merged by one workgroup per group (by entries, and
+    # by members on both sides of 1024)
+    say("contract groups around workgroup limits")
+    g = gen.erdos_renyi(30000, 3 / 29999, 11, 1, 40, lcc=False)
+    sizes = [150, 200, 400, 700, 1024, 1025, 1300, 90]
+    lab = np.empty(g.n, np.int32)
+    pos, k = 0, 0
+    while pos < g.n:
+        c = sizes[k % len(sizes)]
+        lab[pos:pos + c] = k
+        pos += c
+        k += 1
+    n2 = k
+    import torch
+    src, _, _ = canon_dev(ctx, g)
+    dst, dmin, darg = ctx.step_contract(src, torch.as_tensor(lab).cuda(), n2)
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert_same_csr(dst, rp, col, w)
+    odeg = np.array([w[rp[x]:rp[x + 1]].sum() for x in range(n2)])
+    assert dmin == odeg.min() and darg == int(np.argmin(odeg))
+
+
 # ---------------------------------------------------------- union-find
 @pytest.mark.parametrize("n,k,seed", [(1, 0, 1), (10, 5, 2), (5000, 3000, 3), (200000, 150000, 4)])
 def test_components(ctx, n, k, seed):
