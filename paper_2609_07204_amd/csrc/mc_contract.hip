@@ -384,8 +384,10 @@ __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __rest
 // BIG_TILE entries, combines equal (group, target) pairs in an LDS hash, and
 // adds each distinct pair once to the group's global table, so a target hit
 // by many members costs one global atomic per tile rather than per entry.
-constexpr int BIG_TILE = 1024;
-constexpr int BIG_HSLOTS = 2048;
+constexpr int BIG_TILE = 4096;
+constexpr int BIG_HSLOTS = 2 * BIG_TILE;
+constexpr int BIG_T = BIG_TILE / 4;      // threads: four entries each per segment pass
+constexpr int BIG_WIN = 1024;            // members whose row offsets a segment stages in LDS
 
 // group and first member of every tile's first entry, searched for all
 // tiles at once so the searches' latencies overlap
@@ -403,7 +405,7 @@ __global__ void k_big_tiles(const int32_t* __restrict__ vstart, const int32_t* _
     }
 }
 
-__global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* __restrict__ L,
+__global__ __launch_bounds__(BIG_T) void k_big_insert(DGraph src, const int32_t* __restrict__ L,
                                                    const int32_t* __restrict__ perm,
                                                    const int32_t* __restrict__ vstart,
                                                    const int32_t* __restrict__ mstart,
@@ -414,12 +416,12 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
                                                    const int32_t* __restrict__ dslot, int64_t* __restrict__ dense,
                                                    const int32_t* __restrict__ tinfo, DGraph dst,
                                                    unsigned long long* pb) {
-    constexpr int PER = BIG_TILE / 256;     // entries per thread and segment pass
-    constexpr int FL = BIG_HSLOTS / 256;    // table slots per thread in the flush
+    constexpr int PER = BIG_TILE / BIG_T;   // entries per thread and segment pass
+    constexpr int FL = BIG_HSLOTS / BIG_T;  // table slots per thread in the flush
     __shared__ unsigned long long hkey[BIG_HSLOTS];
     __shared__ long long hval[BIG_HSLOTS];
-    __shared__ int32_t wm[BIG_TILE + 2];     // member-space start of each member in the window
-    __shared__ int32_t wo[BIG_TILE + 1];     // row offset of each member in the window
+    __shared__ int32_t wm[BIG_WIN + 2];      // member-space start of each member in the window
+    __shared__ int32_t wo[BIG_WIN + 1];      // row offset of each member in the window
     __shared__ int32_t info[4];              // g, first member, member count in window, g's group end
     const int64_t total = bebase[n2];
     const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
             __syncthreads();
             const int32_t g = info[0], mf = info[1];
             gprev = g;
-            const int32_t wc = info[2] < BIG_TILE + 1 ? info[2] : BIG_TILE + 1;
+            const int32_t wc = info[2] < BIG_WIN + 1 ? info[2] : BIG_WIN + 1;
             const int64_t seg_end = (int64_t)info[3] < e1 ? (int64_t)info[3] : e1;
             for (int i = threadIdx.x; i <= wc; i += blockDim.x) {
                 wm[i] = mstart[mf + i];
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
             int64_t c[PER];
 #pragma unroll
             for (int q = 0; q < PER; q++) {
-                const int64_t f = e + threadIdx.x + q * 256;
+                const int64_t f = e + threadIdx.x + q * BIG_T;
                 c[q] = 0;
                 x[q] = 0;
                 if (f >= seg_end) continue;
@@ -533,11 +535,11 @@ __global__ __launch_bounds__(256) void k_big_insert(DGraph src, const int32_t* _
         bool pend[FL];
 #pragma unroll
         for (int q = 0; q < FL; q++) {
-            const unsigned long long k = hkey[threadIdx.x + q * 256];
+            const unsigned long long k = hkey[threadIdx.x + q * BIG_T];
             pend[q] = k != EMPTY_KEY;
             fg[q] = (int32_t)(k >> 32);
             ft[q] = (int32_t)(k & 0xFFFFFFFFu);
-            fv[q] = hval[threadIdx.x + q * 256];
+            fv[q] = hval[threadIdx.x + q * BIG_T];
         }
 #pragma unroll
         for (int q = 0; q < FL; q++) {
@@ -819,7 +821,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
                                                                       ws.tinfo);
     MC_LAUNCHED("k_big_tiles");
     prof_begin(PK_BIG_INSERT, s);
-    k_big_insert<<<4096, 256, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.bigm, ws.tsize, n2, ws.tkey,
+    k_big_insert<<<4096 * 256 / BIG_T, BIG_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.bigm, ws.tsize, n2, ws.tkey,
                                       ws.tval, ws.dslot, ws.dense, ws.tinfo, dst, prof_dev_bytes(PK_BIG_INSERT));
     MC_LAUNCHED("k_big_insert");
     prof_end(PK_BIG_INSERT, s);
