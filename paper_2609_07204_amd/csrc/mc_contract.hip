@@ -581,27 +581,6 @@ __global__ __launch_bounds__(BIG_T) void k_big_insert(DGraph src, const int32_t*
     if (pb) prof_add(pb, nin * (L ? 16 : 12));
 }
 
-// Block-level allocation of output slots: one atomic per block for `take`
-// items; returns this thread's slot (valid where take) and the block sum of v.
-__device__ __forceinline__ int32_t block_alloc(int32_t* ctr, bool take, int64_t v, int64_t* deg,
-                                               int32_t* s_cnt, long long* s_sum, int32_t* s_base) {
-    const int lane = lane_id(), wid = threadIdx.x / MC_WAVE;
-    const unsigned long long m = __ballot(take);
-    const int32_t rank = __popcll(m & ((1ULL << lane) - 1));
-    const int64_t ws = wave_sum_i64(take ? v : 0);
-    if (lane == 0) { s_cnt[wid] = __popcll(m); s_sum[wid] = ws; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t tot = 0;
-        long long sum = 0;
-        for (int k = 0; k < (int)(blockDim.x / MC_WAVE); k++) { int32_t c = s_cnt[k]; s_cnt[k] = tot; tot += c; sum += s_sum[k]; }
-        s_base[0] = tot ? atomicAdd(ctr, tot) : 0;
-        if (sum) atomic_add_i64(deg, sum);
-    }
-    __syncthreads();
-    return s_base[0] + s_cnt[wid] + rank;
-}
-
 // group of every 256-slot table tile (tables are whole tiles), searched for
 // all tiles at once so the searches' latencies overlap
 __global__ void k_big_xtiles(const int32_t* __restrict__ tbase, int32_t n2, int32_t* __restrict__ xg) {
@@ -610,55 +589,99 @@ __global__ void k_big_xtiles(const int32_t* __restrict__ tbase, int32_t n2, int3
         xg[t] = last_le(tbase, n2, t * TILE_SLOTS);
 }
 
-__global__ __launch_bounds__(TILE_SLOTS) void k_big_extract(const int32_t* __restrict__ tbase,
-                                                            const int32_t* __restrict__ gstart, int32_t n2,
-                                                            const int32_t* __restrict__ xg,
-                                                            const int32_t* __restrict__ tkey,
-                                                            const int64_t* __restrict__ tval,
-                                                            int32_t* __restrict__ bcur, DGraph dst) {
-    __shared__ int32_t s_cnt[TILE_SLOTS / MC_WAVE], s_base[1];
-    __shared__ long long s_sum[TILE_SLOTS / MC_WAVE];
+// One wavefront emits the valid slots of a 256-slot unit of group g (four
+// slots per lane): a wave prefix sum places them, and one atomic per unit
+// reserves their room in the row (one more adds their weight to the degree).
+// Units are independent, so a wave's only round trip is that reservation.
+__device__ __forceinline__ void wave_emit(int32_t g, const bool (&take)[4], const int32_t (&key)[4],
+                                          const int64_t (&val)[4], int32_t gs, int32_t* __restrict__ bcur,
+                                          DGraph& dst) {
+    const int lane = lane_id();
+    int32_t cnt = 0;
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) { cnt += take[q] ? 1 : 0; sum += take[q] ? val[q] : 0; }
+    int32_t incl = cnt;
+    for (int d = 1; d < MC_WAVE; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d, MC_WAVE);
+        if (lane >= d) incl += y;
+    }
+    const int32_t total = __shfl(incl, MC_WAVE - 1, MC_WAVE);
+    if (total == 0) return;
+    const int64_t wsum = wave_sum_i64(sum);
+    int32_t base = 0;
+    if (lane == 0) {
+        base = atomicAdd(&bcur[g], total);
+        atomic_add_i64(&dst.deg[g], wsum);
+    }
+    int32_t pos = gs + __shfl(base, 0, MC_WAVE) + incl - cnt;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (!take[q]) continue;
+        dst.col[pos] = key[q];
+        dst.w[pos] = val[q];
+        pos++;
+    }
+}
+
+constexpr int EX_T = 256;   // threads of the extraction kernels: four waves, one unit each
+static_assert(TILE_SLOTS == 4 * MC_WAVE, "a table tile is one wave's unit");
+
+__global__ __launch_bounds__(EX_T) void k_big_extract(const int32_t* __restrict__ tbase,
+                                                      const int32_t* __restrict__ gstart, int32_t n2,
+                                                      const int32_t* __restrict__ xg,
+                                                      const int32_t* __restrict__ tkey,
+                                                      const int64_t* __restrict__ tval,
+                                                      int32_t* __restrict__ bcur, DGraph dst) {
     const int64_t ntiles = tbase[n2] / TILE_SLOTS;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t base = t * TILE_SLOTS;
+    const int64_t wid = (int64_t)blockIdx.x * (EX_T / MC_WAVE) + threadIdx.x / MC_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (EX_T / MC_WAVE);
+    for (int64_t t = wid; t < ntiles; t += nw) {
+        const int64_t base = t * TILE_SLOTS + lane_id();
         const int32_t g = xg[t];
-        const int64_t k = base + threadIdx.x;
-        __syncthreads();   // the previous tile's block_alloc results are read
-        const int32_t key = tkey[k];
-        const int64_t v = key >= 0 ? tval[k] : 0;
-        const int32_t pos = block_alloc(&bcur[g], key >= 0, v, &dst.deg[g], s_cnt, s_sum, s_base);
-        if (key >= 0) {
-            dst.col[gstart[g] + pos] = key;
-            dst.w[gstart[g] + pos] = v;
+        bool take[4];
+        int32_t key[4];
+        int64_t val[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) key[q] = tkey[base + q * MC_WAVE];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            take[q] = key[q] >= 0;
+            val[q] = take[q] ? tval[base + q * MC_WAVE] : 0;
         }
+        wave_emit(g, take, key, val, gstart[g], bcur, dst);
     }
 }
 
 // dense accumulators of the giant groups: stream over n2 targets, emit the
 // non-zero ones, and leave the array zero for the next contraction
-__global__ __launch_bounds__(256) void k_dense_extract(const int32_t* __restrict__ dinfo, int32_t nd_max,
-                                                       const int32_t* __restrict__ gstart, int32_t n2,
-                                                       int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
-                                                       DGraph dst) {
-    __shared__ int32_t s_cnt[4], s_base[1];
-    __shared__ long long s_sum[4];
+__global__ __launch_bounds__(EX_T) void k_dense_extract(const int32_t* __restrict__ dinfo, int32_t nd_max,
+                                                        const int32_t* __restrict__ gstart, int32_t n2,
+                                                        int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
+                                                        DGraph dst) {
     const int32_t nd = dinfo[0] < nd_max ? dinfo[0] : nd_max;
-    const int64_t per = ((int64_t)n2 + 255) / 256 * 256;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nd * per;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t d = (int32_t)(i / per);
-        const int32_t t = (int32_t)(i % per);
+    const int64_t per = ((int64_t)n2 + 255) / 256;   // units per accumulator
+    const int64_t wid = (int64_t)blockIdx.x * (EX_T / MC_WAVE) + threadIdx.x / MC_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (EX_T / MC_WAVE);
+    for (int64_t u = wid; u < (int64_t)nd * per; u += nw) {
+        const int32_t d = (int32_t)(u / per);
+        const int32_t t0 = (int32_t)(u % per) * 256 + lane_id();
         const int32_t g = dinfo[1 + d];
-        int64_t v = 0;
-        if (t < n2) {
-            v = dense[(int64_t)d * n2 + t];
-            if (v) dense[(int64_t)d * n2 + t] = 0;
+        int64_t* acc = dense + (int64_t)d * n2;
+        bool take[4];
+        int32_t key[4];
+        int64_t val[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            key[q] = t0 + q * MC_WAVE;
+            val[q] = key[q] < n2 ? acc[key[q]] : 0;
         }
-        const int32_t pos = block_alloc(&bcur[g], v != 0, v, &dst.deg[g], s_cnt, s_sum, s_base);
-        if (v != 0) {
-            dst.col[gstart[g] + pos] = t;
-            dst.w[gstart[g] + pos] = v;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            take[q] = val[q] != 0;
+            if (take[q]) acc[key[q]] = 0;
         }
+        wave_emit(g, take, key, val, gstart[g], bcur, dst);
     }
 }
 
@@ -827,9 +850,9 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     prof_end(PK_BIG_INSERT, s);
     k_big_xtiles<<<grid_for((src.cap * 5 / 2) / TILE_SLOTS + 8, 256), 256, 0, s>>>(ws.tsize, n2, ws.xg);
     MC_LAUNCHED("k_big_xtiles");
-    k_big_extract<<<4096, TILE_SLOTS, 0, s>>>(ws.tsize, gstart, n2, ws.xg, ws.tkey, ws.tval, ws.bcur, dst);
+    k_big_extract<<<4096, EX_T, 0, s>>>(ws.tsize, gstart, n2, ws.xg, ws.tkey, ws.tval, ws.bcur, dst);
     MC_LAUNCHED("k_big_extract");
-    k_dense_extract<<<grid_for((int64_t)nd_max * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, nd_max, gstart, n2, ws.dense,
+    k_dense_extract<<<grid_for((int64_t)nd_max * n2, 4 * EX_T, 4096), EX_T, 0, s>>>(ws.dinfo, nd_max, gstart, n2, ws.dense,
                                                                               ws.bcur, dst);
     MC_LAUNCHED("k_dense_extract");
     k_big_finalize<<<grid_for(n2, 256), 256, 0, s>>>(ws.bigm, n2, ws.bcur, dst);

@@ -31,7 +31,8 @@ constexpr int LP_T = 256;
 constexpr int LP_SUB = 16;
 constexpr int LP_NSUB = LP_T / LP_SUB;
 constexpr int LP_TASK = 1024;     // entries per task of a long row (multiple of 128)
-constexpr int LP_TSLOTS = 2048;   // LDS slots of a task's pre-merge
+constexpr int LP_TSLOTS = 2 * LP_TASK;   // LDS slots of a task's pre-merge
+constexpr int LP_IT = LP_TASK / 4;       // threads of the pre-merge: four entries each
 constexpr unsigned long long LP_EMPTY = ~0ULL;
 
 inline int grid_for(int64_t count, int threads, int cap = 8192) {
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_long_clear(DGraph g, const int32_t*
 }
 
 // each task merges its entries in LDS, then adds the sums to the row's table
-__global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t* __restrict__ lab_in,
+__global__ __launch_bounds__(LP_IT) void k_lp_long_insert(DGraph g, const int32_t* __restrict__ lab_in,
                                                         const int32_t* __restrict__ long_list,
                                                         const int32_t* __restrict__ long_base,
                                                         const int32_t* __restrict__ counters,
@@ -216,18 +217,18 @@ __global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t
     for (int32_t i = blockIdx.x; i < ntask; i += gridDim.x) {
         const LongTask x = long_task(g, long_list, long_base, task_row, task_idx, i);
         __syncthreads();
-        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) { hkey[k] = LP_EMPTY; hval[k] = 0; }
+        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_IT) { hkey[k] = LP_EMPTY; hval[k] = 0; }
         __syncthreads();
         const int32_t j1 = (x.t + 1) * LP_TASK < x.l ? (x.t + 1) * LP_TASK : x.l;
-        // the task's LP_TASK / LP_T entries per thread: loads, then label
+        // the task's LP_TASK / LP_IT entries per thread: loads, then label
         // loads, all in flight together
-        constexpr int PER = LP_TASK / LP_T;
+        constexpr int PER = LP_TASK / LP_IT;
         int32_t y[PER];
         unsigned long long c[PER];
         uint32_t lb[PER];
 #pragma unroll
         for (int u = 0; u < PER; u++) {
-            const int32_t j = x.t * LP_TASK + u * LP_T + threadIdx.x;
+            const int32_t j = x.t * LP_TASK + u * LP_IT + threadIdx.x;
             y[u] = j < j1 ? g.col[x.o + j] : x.v;
             c[u] = j < j1 ? (unsigned long long)g.w[x.o + j] : 0;
         }
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_long_insert(DGraph g, const int32_t
             atomicAdd(&hval[h], c[u]);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_T) {
+        for (int k = threadIdx.x; k < LP_TSLOTS; k += LP_IT) {
             const unsigned long long kk = hkey[k];
             if (kk == LP_EMPTY) continue;
             const int32_t lbl = (int32_t)kk;
@@ -528,7 +529,7 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     k_lp_long_clear<<<tb, LP_T, 0, s>>>(g, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx, cw.tkey,
                                         cw.tval);
     MC_LAUNCHED("k_lp_long_clear");
-    k_lp_long_insert<<<tb, LP_T, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
+    k_lp_long_insert<<<tb, LP_IT, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
                                          cw.tkey, cw.tval);
     MC_LAUNCHED("k_lp_long_insert");
     k_lp_long_max<<<tb, LP_T, 0, s>>>(g, lab_in, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx,
