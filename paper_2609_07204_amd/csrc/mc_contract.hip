@@ -589,18 +589,20 @@ __global__ void k_big_xtiles(const int32_t* __restrict__ tbase, int32_t n2, int3
         xg[t] = last_le(tbase, n2, t * TILE_SLOTS);
 }
 
-// One wavefront emits the valid slots of a 256-slot unit of group g (four
-// slots per lane): a wave prefix sum places them, and one atomic per unit
-// reserves their room in the row (one more adds their weight to the degree).
-// Units are independent, so a wave's only round trip is that reservation.
-__device__ __forceinline__ void wave_emit(int32_t g, const bool (&take)[4], const int32_t (&key)[4],
-                                          const int64_t (&val)[4], int32_t gs, int32_t* __restrict__ bcur,
+// One wavefront emits the valid slots of a unit of group g (PERL slots per
+// lane): a wave prefix sum places them, and one atomic per unit reserves
+// their room in the row (one more adds their weight to the degree). The
+// callers spread the units of one group over time, since atomics on one
+// address serialise.
+template <int PERL>
+__device__ __forceinline__ void wave_emit(int32_t g, const bool (&take)[PERL], const int32_t (&key)[PERL],
+                                          const int64_t (&val)[PERL], int32_t gs, int32_t* __restrict__ bcur,
                                           DGraph& dst) {
     const int lane = lane_id();
     int32_t cnt = 0;
     int64_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < 4; q++) { cnt += take[q] ? 1 : 0; sum += take[q] ? val[q] : 0; }
+    for (int q = 0; q < PERL; q++) { cnt += take[q] ? 1 : 0; sum += take[q] ? val[q] : 0; }
     int32_t incl = cnt;
     for (int d = 1; d < MC_WAVE; d <<= 1) {
         const int32_t y = __shfl_up(incl, d, MC_WAVE);
@@ -616,7 +618,7 @@ __device__ __forceinline__ void wave_emit(int32_t g, const bool (&take)[4], cons
     }
     int32_t pos = gs + __shfl(base, 0, MC_WAVE) + incl - cnt;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < PERL; q++) {
         if (!take[q]) continue;
         dst.col[pos] = key[q];
         dst.w[pos] = val[q];
@@ -636,7 +638,11 @@ __global__ __launch_bounds__(EX_T) void k_big_extract(const int32_t* __restrict_
     const int64_t ntiles = tbase[n2] / TILE_SLOTS;
     const int64_t wid = (int64_t)blockIdx.x * (EX_T / MC_WAVE) + threadIdx.x / MC_WAVE;
     const int64_t nw = (int64_t)gridDim.x * (EX_T / MC_WAVE);
-    for (int64_t t = wid; t < ntiles; t += nw) {
+    // tiles in the order u K mod ntiles (a permutation when K and ntiles
+    // are coprime), so that waves running together serve different groups
+    const int64_t K = ntiles % 1000003 ? 1000003 : 1;
+    for (int64_t u = wid; u < ntiles; u += nw) {
+        const int64_t t = (u * K) % ntiles;
         const int64_t base = t * TILE_SLOTS + lane_id();
         const int32_t g = xg[t];
         bool take[4];
@@ -649,7 +655,7 @@ __global__ __launch_bounds__(EX_T) void k_big_extract(const int32_t* __restrict_
             take[q] = key[q] >= 0;
             val[q] = take[q] ? tval[base + q * MC_WAVE] : 0;
         }
-        wave_emit(g, take, key, val, gstart[g], bcur, dst);
+        wave_emit<4>(g, take, key, val, gstart[g], bcur, dst);
     }
 }
 
@@ -659,29 +665,33 @@ __global__ __launch_bounds__(EX_T) void k_dense_extract(const int32_t* __restric
                                                         const int32_t* __restrict__ gstart, int32_t n2,
                                                         int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
                                                         DGraph dst) {
+    constexpr int PERL = 16;                       // a unit is 1024 targets
+    constexpr int UNIT = PERL * MC_WAVE;
     const int32_t nd = dinfo[0] < nd_max ? dinfo[0] : nd_max;
-    const int64_t per = ((int64_t)n2 + 255) / 256;   // units per accumulator
+    const int64_t per = ((int64_t)n2 + UNIT - 1) / UNIT;   // units per accumulator
     const int64_t wid = (int64_t)blockIdx.x * (EX_T / MC_WAVE) + threadIdx.x / MC_WAVE;
     const int64_t nw = (int64_t)gridDim.x * (EX_T / MC_WAVE);
+    // unit u belongs to accumulator u mod nd: waves running together serve
+    // different groups
     for (int64_t u = wid; u < (int64_t)nd * per; u += nw) {
-        const int32_t d = (int32_t)(u / per);
-        const int32_t t0 = (int32_t)(u % per) * 256 + lane_id();
+        const int32_t d = (int32_t)(u % nd);
+        const int32_t t0 = (int32_t)(u / nd) * UNIT + lane_id();
         const int32_t g = dinfo[1 + d];
         int64_t* acc = dense + (int64_t)d * n2;
-        bool take[4];
-        int32_t key[4];
-        int64_t val[4];
+        bool take[PERL];
+        int32_t key[PERL];
+        int64_t val[PERL];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < PERL; q++) {
             key[q] = t0 + q * MC_WAVE;
             val[q] = key[q] < n2 ? acc[key[q]] : 0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < PERL; q++) {
             take[q] = val[q] != 0;
             if (take[q]) acc[key[q]] = 0;
         }
-        wave_emit(g, take, key, val, gstart[g], bcur, dst);
+        wave_emit<PERL>(g, take, key, val, gstart[g], bcur, dst);
     }
 }
 
@@ -852,7 +862,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     MC_LAUNCHED("k_big_xtiles");
     k_big_extract<<<4096, EX_T, 0, s>>>(ws.tsize, gstart, n2, ws.xg, ws.tkey, ws.tval, ws.bcur, dst);
     MC_LAUNCHED("k_big_extract");
-    k_dense_extract<<<grid_for((int64_t)nd_max * n2, 4 * EX_T, 4096), EX_T, 0, s>>>(ws.dinfo, nd_max, gstart, n2, ws.dense,
+    k_dense_extract<<<grid_for((int64_t)nd_max * n2, 16 * EX_T, 4096), EX_T, 0, s>>>(ws.dinfo, nd_max, gstart, n2, ws.dense,
                                                                               ws.bcur, dst);
     MC_LAUNCHED("k_dense_extract");
     k_big_finalize<<<grid_for(n2, 256), 256, 0, s>>>(ws.bigm, n2, ws.bcur, dst);
