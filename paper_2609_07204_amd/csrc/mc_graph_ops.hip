@@ -172,8 +172,8 @@ constexpr int32_t PR_CHUNK = 4096;
 // (off, len, deg) of the rows this kernel tests.
 __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                              unsigned long long* marks, uint8_t* flag1, int32_t* ptr2,
-                                             int32_t* long_list, int32_t* long_cnt, int32_t* first, int32_t* heavy_cnt,
-                                             unsigned long long* pb) {
+                                             int32_t* long_list, int32_t* long_cnt, int32_t* first, int32_t* second,
+                                             int32_t* heavy_cnt, unsigned long long* pb) {
     // 16 lanes take 16 consecutive rows: the rows' offsets, lengths,
     // degrees and bounds come in one load, each lane then loads up to four
     // entries of a row at once, and the rows' results (test-2 unions
@@ -197,11 +197,12 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
             if (my_l > PR_LONG) {
                 long_list[atomicAdd(long_cnt, 1)] = mv;
                 first[mv] = -1;       // a long row unions its test-1 entries itself
+                second[mv] = -1;
                 heavy_cnt[mv] = 0;
             }
         }
         int64_t my_bw = -1;
-        int32_t my_bx = -1, my_hj = INT32_MAX, my_hn = 0;
+        int32_t my_bx = -1, my_hj = INT32_MAX, my_hj2 = INT32_MAX, my_hn = 0;
         for (int32_t r = 0; r < rows; r++) {
             const int32_t l = __shfl(my_l, r, SUB);
             if (l > PR_LONG) continue;
@@ -209,7 +210,8 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
             const int64_t lam = __shfl(my_lam, r, SUB);
             int64_t bw = -1;
             int32_t bx = -1;
-            int32_t hj = INT32_MAX, hn = 0;    // first test-1 entry, test-1 entries
+            // first and second test-1 entries, test-1 entries
+            int32_t hj = INT32_MAX, hj2 = INT32_MAX, hn = 0;
             for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
                 int32_t x[4];
                 int64_t c[4];
@@ -225,7 +227,12 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
                     if (j >= l) continue;
                     const bool heavy = c[u] >= lam;
                     if (flag1) flag1[o + j] = heavy;
-                    if (heavy) { hn++; hj = j < hj ? j : hj; }
+                    // a lane meets its entries in increasing j
+                    if (heavy) {
+                        hn++;
+                        if (hj == INT32_MAX) hj = j;
+                        else if (hj2 == INT32_MAX) hj2 = j;
+                    }
                     if (c[u] > bw || (c[u] == bw && x[u] < bx)) { bw = c[u]; bx = x[u]; }
                 }
             }
@@ -233,17 +240,24 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
                 int64_t w2 = __shfl_xor(bw, k, SUB);
                 int32_t x2 = __shfl_xor(bx, k, SUB);
                 if (x2 >= 0 && (bx < 0 || w2 > bw || (w2 == bw && x2 < bx))) { bw = w2; bx = x2; }
-                const int32_t hj2 = __shfl_xor(hj, k, SUB);
-                hj = hj2 < hj ? hj2 : hj;
+                // the two smallest of two sorted pairs
+                const int32_t oj = __shfl_xor(hj, k, SUB), oj2 = __shfl_xor(hj2, k, SUB);
+                if (oj < hj) {
+                    hj2 = hj < oj2 ? hj : oj2;
+                    hj = oj;
+                } else {
+                    hj2 = hj2 < oj ? hj2 : oj;
+                }
                 hn += __shfl_xor(hn, k, SUB);
             }
-            if (sl == r) { my_bw = bw; my_bx = bx; my_hj = hj; my_hn = hn; }
+            if (sl == r) { my_bw = bw; my_bx = bx; my_hj = hj; my_hj2 = hj2; my_hn = hn; }
             if (sl == 0) bytes += 16 + 12 * (int64_t)l;
         }
         if (sl < rows && my_l <= PR_LONG) {
             const bool take = my_bx >= 0 && 2 * my_bw >= my_deg;
             if (ptr2) ptr2[mv] = take ? my_bx : -1;
             first[mv] = my_hj != INT32_MAX ? g.col[my_o + my_hj] : -1;
+            second[mv] = my_hj2 != INT32_MAX ? g.col[my_o + my_hj2] : -1;
             heavy_cnt[mv] = my_hn;
             if (take && uf_union(par, mv, my_bx)) joined++;
         }
@@ -258,13 +272,18 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
     if (pb) prof_add(pb, bytes);
 }
 
-// each row's first test-1 neighbour (marks go to the partial counters)
-__global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ first, int32_t n, int32_t* par,
+// each row's first two test-1 neighbours (marks go to the partial
+// counters). Two per row, not one: on geometric graphs the first neighbours
+// alone leave many small trees and no large component, and almost every
+// remaining test-1 edge would then need a union of its own.
+__global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ second, int32_t n, int32_t* par,
                                                   unsigned long long* marks) {
     unsigned long long joined = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t x = first[v];
+        const int32_t x = first[v], y = second[v];
         if (x >= 0 && uf_union(par, (int32_t)v, x)) joined++;
+        if (y >= 0 && uf_union(par, (int32_t)v, y)) joined++;
     }
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
     if (lane_id() == 0 && joined) {
@@ -273,7 +292,7 @@ __global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ f
     }
 }
 
-// rows with more test-1 entries than the first, outside the sampled
+// rows with more than two test-1 entries, outside the sampled
 // component: union all of them (an edge into that component from a row
 // inside it is seen from this side)
 __global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
@@ -285,14 +304,13 @@ __global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp,
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
-        if (heavy_cnt[v] < 2 || inbig[v]) continue;
+        if (heavy_cnt[v] <= 2 || inbig[v]) continue;
         const int32_t o = g.off[v], l = g.len[v], rv = snap[v];
         const int64_t lam = vinst ? lamp[vinst[v]] : lam0;
         // as in k_uf_link_rest: edges between different snapshot trees,
         // from the smaller endpoint or from outside into the sampled
         // component (a long row links all of its test-1 entries itself, and
-        // a row whose only test-1 entry is its first one was linked by
-        // k_pr1_first)
+        // a row with at most two test-1 entries was linked by k_pr1_first)
         for (int32_t j = sl; j < l; j += SUB) {
             const int32_t x = g.col[o + j];
             if (g.w[o + j] >= lam && (x > v || inbig[x]) && snap[x] != rv && uf_union(par, (int32_t)v, x)) joined++;
@@ -740,6 +758,7 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
     w.part_x = a.take<int32_t>(tasks);
     w.spread = a.take<unsigned long long>((size_t)SPREAD * SPREAD_STRIDE);
     w.first = a.take<int32_t>((size_t)n + 1);
+    w.second = a.take<int32_t>((size_t)n + 1);
     w.heavy = a.take<int32_t>((size_t)n + 1);
     w.mode = a.take<int32_t>(4);
     w.inbig = a.take<uint8_t>((size_t)n + 1);
@@ -752,10 +771,11 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
     if (!fill_i64((int64_t*)w.spread, 0, (int64_t)SPREAD * SPREAD_STRIDE, s)) return false;
     prof_begin(PK_PR12, s);
     k_pr12<<<grid_for(g.n, 256), 256, 0, s>>>(g, lam, vinst, parent, w.spread, flag1, ptr2, w.long_list,
-                                                            w.counters, w.first, w.heavy, prof_dev_bytes(PK_PR12));
+                                                            w.counters, w.first, w.second, w.heavy,
+                                                            prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
-    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, g.n, parent, w.spread);
+    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, w.second, g.n, parent, w.spread);
     MC_LAUNCHED("k_pr1_first");
     k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
     MC_LAUNCHED("k_uf_compress");

@@ -87,7 +87,7 @@ struct ContractWS {
     int32_t* red_id;  // [1024]
     int64_t* red_m;   // [1024] per-block entry counts
     int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
-    int32_t* tinfo;   // [2*(cap/1024+2)] group and first member of every large-group tile
+    int32_t* tinfo;   // [2*(cap/4096+2)] group and first member of every large-group tile
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
     int32_t* mlist;   // [n+1] groups merged by one workgroup each in LDS
     int32_t* mcnt;    // [4] their count
@@ -137,10 +137,11 @@ struct Pr12WS {
     int32_t* part_x;
     unsigned long long* spread;   // [SPREAD * SPREAD_STRIDE] partial mark counts
     int32_t* first;       // [n] a test-1 neighbour of each row, or -1
+    int32_t* second;      // [n] a second test-1 neighbour of each row, or -1
     int32_t* heavy;       // [n] test-1 entries of each row
     int32_t* mode;        // [1] root of the largest sampled component
     uint8_t* inbig;       // [n] 1 for the vertices of that component
-    int32_t* snap;        // [n] root of every vertex after the first unions
+    int32_t* snap;        // [n] root of every vertex after the first two unions of each row
 };
 void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 // With vinst (per-vertex instance) the bound of vertex v is lam[vinst[v]]
