@@ -26,15 +26,19 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size),
-    or None when there is none or its kernel source has changed since."""
+    or None when there is none, it was measured on another workload, or its
+    kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(kernel)
+    tab = json.load(open(path))
+    if tab.get("_calibration", {}).get("workload", "chung_lu") != workload:
+        return None
+    rec = tab.get(kernel)
     if not rec:
         return None
     src = os.path.join(ROOT, rec["source"])
@@ -355,7 +359,7 @@ def main():
         name, r = max(kt.items(), key=lambda kv: kv[1]["ms"])
         achieved = r["bytes"] / (r["ms"] * 1e6)          # GB/s = bytes per launch / avg launch time
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name),
+                    "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(name, args.workload),
                     "kernel": name, "launches_per_step": r["launches"] / args.steps,
                     "avg_launch_us": 1000.0 * r["ms"] / r["launches"],
                     "bytes_per_launch": r["bytes"] / r["launches"],

@@ -40,8 +40,8 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
 
 // Connectivity in the manner of Afforest (Sutton, Ben-Nun and Barak, IPDPS
 // 2018), on a graph whose entries all have positive weight (a normalised
-// graph). Two hooking sweeps over the first CONNECT_K entries of every row
-// first join much of the graph: in each, a row lowers the root of its own
+// graph). CONNECT_SWEEPS hooking sweeps over the first CONNECT_K entries of
+// every row first join much of the graph: in each, a row lowers the root of its own
 // tree to the smallest root among those neighbours (parent[] is compressed
 // before each sweep, so par[v] is a root); pointers only ever decrease, so
 // the forest stays acyclic and the union-find invariant parent[x] <= x
@@ -53,6 +53,10 @@ __global__ __launch_bounds__(256) void k_uf_all_edges(DGraph g, int32_t* par) {
 // connected vertices, and every edge whose endpoints were apart when the
 // sweeps ended is linked afterwards.
 constexpr int CONNECT_K = 8;   // entries per row the hooking sweeps look at
+// Three sweeps, not two: on geometric graphs (hyperbolic, 32-core) two
+// leave thousands of trees and the linking pass then runs millions of
+// unions; the third costs about 0.2 ms and saves about 0.4 ms there.
+constexpr int CONNECT_SWEEPS = 3;
 
 __global__ __launch_bounds__(256) void k_uf_root_min(DGraph g, int32_t* par) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -718,7 +722,7 @@ bool uf_all_edges(const DGraph& g, int32_t* parent, hipStream_t s) {
 
 bool uf_connectivity(const DGraph& g, int32_t* parent, int32_t* tmp, uint8_t* inbig, int32_t* snap, hipStream_t s) {
     const int rows = grid_for((int64_t)g.n * SUB, 256);
-    for (int sweep = 0; sweep < 2; sweep++) {
+    for (int sweep = 0; sweep < CONNECT_SWEEPS; sweep++) {
         k_uf_root_min<<<grid_for(g.n, 256), 256, 0, s>>>(g, parent);
         MC_LAUNCHED("k_uf_root_min");
         k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);

@@ -8,7 +8,10 @@ average bytes per launch, the factors, and the SHA-256 of the source file
 that holds the kernel (bench.py reports the figure only while that file is
 unchanged).
 
-    python -m paper_2609_07204_amd.traffic FETCH_DIR WRITE_DIR MIB
+    python -m paper_2609_07204_amd.traffic FETCH_DIR WRITE_DIR MIB [WORKLOAD]
+
+WORKLOAD (default chung_lu) is the bench.py workload the counter runs
+measured; bench.py reports the figure for that workload only.
 """
 import csv
 import glob
@@ -47,7 +50,7 @@ def per_kernel(d, counter):
     return out
 
 
-def main(fetch_dir, write_dir, mib):
+def main(fetch_dir, write_dir, mib, workload="chung_lu"):
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
@@ -58,7 +61,7 @@ def main(fetch_dir, write_dir, mib):
     f_fetch = nbytes / max(fetch[ck])             # bytes per counter unit
     f_write = nbytes / max(write.get(ck, [0.0]) or [1.0])
     res = {"_calibration": {"copy_kernel": ck, "copy_bytes": nbytes, "fetch_factor": f_fetch,
-                            "write_factor": f_write}}
+                            "write_factor": f_write, "workload": workload}}
     for k, src in KERNEL_SOURCE.items():
         if k not in fetch or k not in write:
             continue
@@ -73,4 +76,4 @@ def main(fetch_dir, write_dir, mib):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2], sys.argv[3])
+    main(*sys.argv[1:5])
