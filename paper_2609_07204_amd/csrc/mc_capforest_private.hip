@@ -39,7 +39,8 @@ constexpr int L2_MAX = 8192;   // level-2 entries (n <= 32 M vertices)
 template <int PT>
 struct PassLds {
     static constexpr int PW = PT / MC_WAVE;
-    int32_t head, tail, tn, dn, single_x;
+    int32_t head, tail, tn, dn, single_x, one_valid;
+    int64_t one_part, one_intra;
     int32_t bx[PT];
     int32_t boff[PT + 1];
     int64_t red64[PW];
@@ -292,6 +293,74 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
         d_maxb = B > d_maxb ? B : d_maxb;
         for (int32_t c0 = 0; c0 < B; c0 += PT) {
             const int32_t cnt = (B - c0) < PT ? (B - c0) : PT;
+            if (cnt == 1) {
+                // one vertex (a single pop, or a batch of one): thread 0 sets
+                // it up, with two barriers in place of the scans and sums a
+                // batch needs; most pops of a sparse, lightly weighted graph
+                // take this path
+                int32_t x1 = -1;
+                if (tid == 0) {
+                    x1 = from_lds ? L.single_x : src[c0];
+                    int32_t e1 = 0;
+                    int64_t p1 = 0;
+                    if (ld32(&st[x1]) == S_QUEUED) {
+                        st[x1] = S_BATCH;
+                        e1 = a.g.len[x1];
+                        p1 = a.g.deg[x1] - 2 * ld64(&r[x1]);
+                        order[nscan] = x1;
+                        mark_dirty(dbits, dlist, (x1 - base) >> 6, L);
+                    } else {
+                        x1 = -1;
+                    }
+                    L.bx[0] = x1 < 0 ? 0 : x1;
+                    L.boff[0] = 0;
+                    L.boff[1] = e1;
+                    L.one_valid = x1 >= 0 ? 1 : 0;
+                    L.one_part = p1;
+                    L.one_intra = 0;
+                }
+                __syncthreads();
+                __threadfence_block();
+                const int32_t E = L.boff[1];
+                const int32_t xs = L.bx[0];
+                int64_t intra = 0;
+                if (E > 0) {
+                    const int32_t o = a.g.off[xs];
+                    for (int32_t j = tid; j < E; j += PT) {
+                        const int32_t y = a.g.col[o + j];
+                        const int64_t c = a.g.w[o + j];
+                        const int32_t sy = ld32(&st[y]);
+                        if (sy == S_BATCH) { intra += c; continue; }
+                        if (sy == S_SCANNED) continue;
+                        if (sy == S_NEW) {
+                            if (atomicCAS(&st[y], S_NEW, S_QUEUED) == S_NEW) tl[atomicAdd(&L.tn, 1)] = y;
+                        }
+                        const int64_t old = atomic_add_i64(&r[y], c);
+                        const int64_t nw = old + c;
+                        if (old < lam && lam <= nw) {
+                            if (uf_union(a.parent, xs, y)) marks++;
+                            fifo[atomicAdd(&L.tail, 1)] = y;
+                            mark_dirty(dbits, dlist, (y - base) >> 6, L);
+                        } else if (nw < lam) {
+                            atomicMax((long long*)&l1[(y - base) >> 6], (long long)nw);
+                            atomicMax(&l2[(y - base) >> 12], (long long)nw);
+                        }
+                    }
+                }
+                if (intra) atomicAdd((unsigned long long*)&L.one_intra, (unsigned long long)intra);
+                d_entries += E;
+                __syncthreads();
+                if (x1 >= 0) st[x1] = S_SCANNED;
+                __threadfence_block();
+                const int32_t nvalid = L.one_valid;
+                nscan += nvalid;
+                alpha += L.one_part - L.one_intra;
+                if (nscan < n) {
+                    if (alpha < best_alpha) { best_alpha = alpha; best_len = nscan; }
+                    if (alpha < lam) lam = alpha;
+                }
+                continue;
+            }
             int32_t dl = 0;
             int64_t part = 0;
             int32_t x = -1;
