@@ -679,8 +679,9 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     // whose truncated passes were mostly single pops (many whole-GPU steps
     // of fewer than 8 vertices on average: heavy weights, a bound far above
     // most edge weights) runs in one workgroup of 512 threads (the best of
-    // 64..1024 measured), which takes a single pop from its two-level index
-    // in about a microsecond, where a whole-GPU step rescans every vertex.
+    // 64..1024 measured), which selects a single pop from its two-level
+    // index and scans it in a few microseconds, where a whole-GPU step costs
+    // about seven launches per pop.
     // Below 4x the level threshold it always does; above, a complete pass
     // of large batches stays on the whole GPU.
     const int64_t lmin = levels_min_n(S.c);
