@@ -35,6 +35,24 @@ constexpr int PT_INST = 256;
 enum : int32_t { S_NEW = 0, S_QUEUED = 1, S_SCANNED = 2, S_BATCH = 3 };
 
 constexpr int L2_MAX = 8192;   // level-2 entries (n <= 32 M vertices)
+// passes of at most L1_LDS * 64 vertices keep their level-1 index in LDS
+// (16 KB), which takes a global round trip off the refresh and the
+// selection of every single pop
+constexpr int L1_LDS = 2048;
+
+// level-1 entry b of the pass: in LDS (ls) or in HBM (lg)
+__device__ __forceinline__ int64_t l1_get(const int64_t* lg, const long long* ls, int32_t b) {
+    if (ls) return ls[b];
+    return __hip_atomic_load(&lg[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void l1_set(int64_t* lg, long long* ls, int32_t b, int64_t v) {
+    if (ls) ls[b] = v;
+    else __hip_atomic_store(&lg[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void l1_max(int64_t* lg, long long* ls, int32_t b, int64_t v) {
+    if (ls) atomicMax(&ls[b], (long long)v);
+    else atomicMax((long long*)&lg[b], (long long)v);
+}
 
 template <int PT>
 struct PassLds {
@@ -178,8 +196,9 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
     }
     const int32_t nb1 = (n + 63) / 64;
     const int32_t nb2 = (nb1 + 63) / 64;
+    long long* l1s = a.l1_at > 0 ? l2 + a.l1_at : nullptr;   // uniform
 
-    for (int32_t b = tid; b < nb1; b += PT) l1[b] = -1;
+    for (int32_t b = tid; b < nb1; b += PT) l1_set(l1, l1s, b, -1);
     for (int32_t b = tid; b <= nb1 / 32; b += PT) dbits[b] = 0;
     for (int32_t g = tid; g < nb2; g += PT) l2[g] = -1;
     for (int32_t g = tid; g < L2_MAX / 32; g += PT) L.l2dirty[g] = 0;
@@ -237,7 +256,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                 if (lv < n && ld32(&st[base + lv]) == S_QUEUED) val = ld64(&r[base + lv]);
                 for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(val, o, MC_WAVE); val = t > val ? t : val; }
                 if (lane == 0) {
-                    __hip_atomic_store(&l1[b], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    l1_set(l1, l1s, b, val);
                     atomicAnd(&dbits[b >> 5], ~(1u << (b & 31)));
                     atomicOr(&L.l2dirty[b >> 11], 1u << ((b >> 6) & 31));
                 }
@@ -248,7 +267,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
             for (int32_t g = wid; g < nb2; g += PW) {
                 if (!(L.l2dirty[g >> 5] & (1u << (g & 31)))) continue;
                 const int32_t b = g * 64 + lane;
-                int64_t val = b < nb1 ? ld64(&l1[b]) : -1;
+                int64_t val = b < nb1 ? l1_get(l1, l1s, b) : -1;
                 for (int o = 32; o > 0; o >>= 1) { int64_t t = __shfl_xor(val, o, MC_WAVE); val = t > val ? t : val; }
                 if (lane == 0) l2[g] = val;
             }
@@ -266,7 +285,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
             if (bg < 0) break;          // queue empty (uniform)
             if (wid == 0) {
                 const int32_t b = bg * 64 + lane;
-                int64_t v1 = b < nb1 ? ld64(&l1[b]) : -1;
+                int64_t v1 = b < nb1 ? l1_get(l1, l1s, b) : -1;
                 int32_t bb = v1 >= 0 ? b : -1;
                 int32_t aux = 0;
                 wave_argmax(v1, bb, aux);
@@ -342,7 +361,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                             fifo[atomicAdd(&L.tail, 1)] = y;
                             mark_dirty(dbits, dlist, (y - base) >> 6, L);
                         } else if (nw < lam) {
-                            atomicMax((long long*)&l1[(y - base) >> 6], (long long)nw);
+                            l1_max(l1, l1s, (y - base) >> 6, nw);
                             atomicMax(&l2[(y - base) >> 12], (long long)nw);
                         }
                     }
@@ -410,7 +429,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                     fifo[atomicAdd(&L.tail, 1)] = y;
                     mark_dirty(dbits, dlist, (y - base) >> 6, L);
                 } else if (nw < lam) {
-                    atomicMax((long long*)&l1[(y - base) >> 6], (long long)nw);
+                    l1_max(l1, l1s, (y - base) >> 6, nw);
                     atomicMax(&l2[(y - base) >> 12], (long long)nw);
                 }
             }
@@ -493,7 +512,11 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
             mc_hip_ok(hipErrorInvalidValue, "capforest_private: instance too large for the pass index");
             return false;
         }
-        return launch_private(a, a.threads > 0 ? a.threads : PT_INST, (size_t)(nb2 > 0 ? nb2 : 1) * sizeof(long long), s);
+        const int32_t nb1 = (max_pass_n + 63) / 64;
+        PrivateArgs b = a;
+        b.l1_at = nb1 <= L1_LDS ? (nb2 > 0 ? nb2 : 1) : 0;
+        const size_t lds = (size_t)((nb2 > 0 ? nb2 : 1) + (b.l1_at ? nb1 : 0)) * sizeof(long long);
+        return launch_private(b, a.threads > 0 ? a.threads : PT_INST, lds, s);
     }
     if (a.g.n > a.stride) {
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: per-pass stride smaller than n");
@@ -504,7 +527,10 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
         mc_hip_ok(hipErrorInvalidValue, "capforest_private: graph too large for the pass index");
         return false;
     }
-    return launch_private(a, a.threads > 0 ? a.threads : PT_SOLVE, (size_t)nb2 * sizeof(long long), s);
+    const int32_t nb1 = (a.g.n + 63) / 64;
+    PrivateArgs b = a;
+    b.l1_at = nb1 <= L1_LDS ? nb2 : 0;
+    return launch_private(b, a.threads > 0 ? a.threads : PT_SOLVE, (size_t)(nb2 + (b.l1_at ? nb1 : 0)) * sizeof(long long), s);
 }
 
 bool capforest_private_reset(const PrivateArgs& a, hipStream_t s) {

@@ -278,6 +278,9 @@ struct PrivateArgs {
     const uint8_t* prun = nullptr;
     unsigned long long* pmarks = nullptr;
     int32_t threads = 0;    // workgroup size of a pass (64..1024; 0 = 256 in instance mode, else 1024)
+    // set by capforest_private: the level-1 index lives in LDS after the
+    // l1_at level-2 entries (0: in HBM at l1)
+    int32_t l1_at = 0;
 };
 constexpr size_t PRIV_BYTES_PER_VERTEX = 4 + 8 + 4 + 4 + 4 + 1;
 bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n = 0);
