@@ -39,6 +39,7 @@ constexpr int L2_MAX = 8192;   // level-2 entries (n <= 32 M vertices)
 // (16 KB), which takes a global round trip off the refresh and the
 // selection of every single pop
 constexpr int L1_LDS = 2048;
+constexpr int DL_LDS = 128;    // dirty blocks whose ids are also kept in LDS
 
 // level-1 entry b of the pass: in LDS (ls) or in HBM (lg)
 __device__ __forceinline__ int64_t l1_get(const int64_t* lg, const long long* ls, int32_t b) {
@@ -65,6 +66,7 @@ struct PassLds {
     int32_t redi[PW];
     int32_t scan32[PW];
     uint32_t l2dirty[L2_MAX / 32];
+    int32_t dl[DL_LDS];
 };
 
 __device__ __forceinline__ int32_t ld32(const int32_t* p) {
@@ -139,7 +141,11 @@ __device__ __forceinline__ int32_t last_le_lds(const int32_t* a, int32_t n, int3
 template <int PT>
 __device__ __forceinline__ void mark_dirty(uint32_t* dbits, int32_t* dlist, int32_t b, PassLds<PT>& L) {
     const uint32_t bit = 1u << (b & 31);
-    if (!(atomicOr(&dbits[b >> 5], bit) & bit)) dlist[atomicAdd(&L.dn, 1)] = b;
+    if (!(atomicOr(&dbits[b >> 5], bit) & bit)) {
+        const int32_t k = atomicAdd(&L.dn, 1);
+        dlist[k] = b;
+        if (k < DL_LDS) L.dl[k] = b;   // the refresh reads these from LDS
+    }
 }
 
 // Per-pass priority index over the queued vertices outside the capped FIFO:
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
             // refresh dirty blocks (one wavefront per block)
             const int32_t dn = L.dn;
             for (int32_t i = wid; i < dn; i += PW) {
-                const int32_t b = dlist[i];
+                const int32_t b = i < DL_LDS ? L.dl[i] : dlist[i];
                 const int32_t lv = b * 64 + lane;
                 // every queued vertex counts: one whose r reached a lowered
                 // bound has the largest key and must stay findable
@@ -304,7 +310,8 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
             from_lds = true;
             d_single++;
         }
-        __syncthreads();
+        // a single pop has passed a barrier since head and tail were read
+        if (!from_lds) __syncthreads();
         if (tid == 0 && !from_lds) L.head = head + B;
         steps++;
         const int64_t t_b0 = wall_clock64();
@@ -320,16 +327,18 @@ __global__ __launch_bounds__(PT) void k_capforest_private(PrivateArgs a) {
                 int32_t x1 = -1;
                 if (tid == 0) {
                     x1 = from_lds ? L.single_x : src[c0];
-                    int32_t e1 = 0;
-                    int64_t p1 = 0;
-                    if (ld32(&st[x1]) == S_QUEUED) {
+                    // the vertex's state, length, degree and r in one round trip
+                    const int32_t s1 = ld32(&st[x1]);
+                    int32_t e1 = a.g.len[x1];
+                    int64_t p1 = a.g.deg[x1] - 2 * ld64(&r[x1]);
+                    if (s1 == S_QUEUED) {
                         st[x1] = S_BATCH;
-                        e1 = a.g.len[x1];
-                        p1 = a.g.deg[x1] - 2 * ld64(&r[x1]);
                         order[nscan] = x1;
                         mark_dirty(dbits, dlist, (x1 - base) >> 6, L);
                     } else {
                         x1 = -1;
+                        e1 = 0;
+                        p1 = 0;
                     }
                     L.bx[0] = x1 < 0 ? 0 : x1;
                     L.boff[0] = 0;
