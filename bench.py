@@ -78,7 +78,7 @@ def batch_main(args, log):
     tuning = None
     if args.tune_sample > 0:
         # untimed: the autotuner picks the pass workgroup size and whether to
-        # bound at admission, on a spread sample of this batch
+        # bound at admission, on a sample of this batch (its largest graphs and a spread of the rest)
         t = time.time()
         tuning = ctx.batch_autotune(devs=devs, workspace=ws, sample=args.tune_sample)
         tuning["seconds"] = time.time() - t

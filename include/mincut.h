@@ -163,11 +163,13 @@ mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* de
                           int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
 
 /* Autotuner of the batched form. Solves a sample of the batch (`sample`
- * graphs spread evenly over the k given, all of them when sample <= 0 or
- * >= k) once per candidate setting - every pass workgroup size of
- * batch_pass_threads, with and without the admission bound of batch_lp -
- * after one untimed run, times each (wall clock around the synchronised
- * call), and stores the fastest setting in the context's options (the
+ * graphs: the sample/8 largest by entries, since a batch takes as long as
+ * its largest graphs' passes, and the rest spread evenly over the k given;
+ * all of them when sample <= 0 or >= k) twice per candidate setting - every
+ * pass workgroup size of batch_pass_threads, with and without the admission
+ * bound of batch_lp - after one untimed run, times each (wall clock around
+ * the synchronised call, the faster of the two), and stores the fastest
+ * setting in the context's options (the
  * other options are left as they are). The results of the sample solves
  * are discarded; a setting changes only the speed, never a result.
  * dev_workspace must hold mc_batch_workspace_size of the whole batch (the

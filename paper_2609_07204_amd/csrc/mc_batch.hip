@@ -941,14 +941,33 @@ extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, voi
     return MC_OK;
 }
 
-// The autotuner: time the batch engine on a spread sample of the batch
-// under every candidate setting and keep the fastest.
+// The autotuner: time the batch engine on a sample of the batch under every
+// candidate setting (best of two runs each) and keep the fastest. A batch
+// takes as long as the passes of its largest graphs, so the sample holds the
+// batch's largest graphs (an eighth of it, by entries) and a spread of the
+// rest.
 extern "C" mc_status mc_batch_autotune(mc_ctx* c, int32_t k, const mc_csr* gs, void* dev_ws, size_t ws_bytes,
                                        int32_t sample, mc_tuning* out) {
     if (!c || !gs || k <= 0 || !dev_ws || !out) return mc_fail(MC_E_INVALID_ARG, "mc_batch_autotune: bad argument");
     const int32_t m = sample <= 0 || sample >= k ? k : sample;
-    std::vector<mc_csr> sub((size_t)m);
-    for (int32_t i = 0; i < m; i++) sub[i] = gs[(int64_t)i * k / m];
+    std::vector<mc_csr> sub;
+    sub.reserve((size_t)m);
+    {
+        std::vector<int32_t> idx((size_t)k);
+        for (int32_t i = 0; i < k; i++) idx[i] = i;
+        const int32_t big = m < k ? m / 8 : 0;
+        std::partial_sort(idx.begin(), idx.begin() + big, idx.end(),
+                          [&](int32_t a, int32_t b) { return gs[a].nnz > gs[b].nnz || (gs[a].nnz == gs[b].nnz && a < b); });
+        std::vector<char> taken((size_t)k, 0);
+        for (int32_t i = 0; i < big; i++) { taken[idx[i]] = 1; sub.push_back(gs[idx[i]]); }
+        const int32_t rest = m - big;
+        for (int32_t i = 0; i < rest; i++) {
+            int64_t j = (int64_t)i * k / rest;
+            while (taken[j]) j = (j + 1) % k;   // k > m, so a free one exists
+            taken[j] = 1;
+            sub.push_back(gs[j]);
+        }
+    }
     std::vector<int64_t> lam((size_t)m);
     const mc_options saved = c->opt;
     static const int32_t threads[] = {64, 128, 256, 512, 1024};
@@ -962,12 +981,16 @@ extern "C" mc_status mc_batch_autotune(mc_ctx* c, int32_t k, const mc_csr* gs, v
         for (int32_t th : threads) {
             c->opt.batch_pass_threads = th;
             c->opt.batch_lp = lp;
-            if (hipStreamSynchronize(c->stream) != hipSuccess) { c->opt = saved; return mc_fail(MC_E_DEVICE, "sync"); }
-            const auto t0 = std::chrono::steady_clock::now();
-            r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
-            if (r != MC_OK) { c->opt = saved; return r; }
-            const double ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            double ms = 0;
+            for (int rep = 0; rep < 2; rep++) {
+                if (hipStreamSynchronize(c->stream) != hipSuccess) { c->opt = saved; return mc_fail(MC_E_DEVICE, "sync"); }
+                const auto t0 = std::chrono::steady_clock::now();
+                r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
+                if (r != MC_OK) { c->opt = saved; return r; }
+                const double t1 =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                ms = rep == 0 || t1 < ms ? t1 : ms;
+            }
             const int32_t j = t.candidates++;
             t.cand_threads[j] = th;
             t.cand_lp[j] = lp;
