@@ -159,10 +159,11 @@ __global__ void k_label(const int32_t* par, const int32_t* newid, int32_t n, int
 //  test 1: an edge of weight >= lam joins two vertices whose connectivity is
 //          at least lam, so no cut below lam separates them; the test-1
 //          edges are joined as Afforest joins a graph: each row's first
-//          test-1 neighbour is unioned, then the component most sampled
-//          vertices fall into is found, and only rows outside it union all
-//          their test-1 entries (once the bound is small nearly every edge
-//          passes, and nearly every row then skips);
+//          two test-1 neighbours are unioned, then the component most
+//          sampled vertices fall into is found, and only rows outside it
+//          union their test-1 entries to other trees of that snapshot (once
+//          the bound is small nearly every edge passes, and nearly every
+//          row or entry then skips);
 //  test 2: if 2 c(v,p) >= c(v) for v's heaviest neighbour p (smallest id on
 //          ties), moving v to p's side of any cut does not increase it; one
 //          such pointer per vertex may be contracted together with all
