@@ -50,7 +50,7 @@ def per_kernel(d, counter):
     return out
 
 
-def main(fetch_dir, write_dir, mib, workload="chung_lu"):
+def main(fetch_dir, write_dir, mib, workload="chung_lu", path=None):
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
@@ -70,9 +70,10 @@ def main(fetch_dir, write_dir, mib, workload="chung_lu"):
         res[k] = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                   "launches": len(fetch[k]), "source": src,
                   "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     json.dump(res, open(path, "w"), indent=1, sort_keys=True)
     print(json.dumps(res, indent=1, sort_keys=True))
+    return res
 
 
 if __name__ == "__main__":
