@@ -76,9 +76,17 @@ def batch_main(args, log):
     ws = torch.empty(ctx.batch_workspace_bytes(devs=devs), dtype=torch.uint8, device=ctx.device)
     log("batch workspace %.2f GB" % (ws.numel() / 1e9))
     tuning = None
-    if args.tune_sample > 0:
+    if args.batch_threads or args.batch_lp:
+        # a fixed setting (for comparisons): no autotuning
+        ctx.set_options(batch_pass_threads=args.batch_threads, batch_lp=args.batch_lp)
+        tuning = {"fixed": True, "pass_threads": args.batch_threads or 256, "lp": args.batch_lp}
+        log("fixed batch setting: pass threads %d, batch_lp %d" % (tuning["pass_threads"], args.batch_lp))
+    elif args.tune_sample > 0:
         # untimed: the autotuner picks the pass workgroup size and whether to
-        # bound at admission, on a sample of this batch (its largest graphs and a spread of the rest)
+        # bound at admission, by default on the whole batch: a sample of 512
+        # or even 2048 of its graphs loads the GPU with fewer passes at once
+        # and favoured 512-thread passes, which run the whole batch 12 %
+        # slower than 256-thread ones
         t = time.time()
         tuning = ctx.batch_autotune(devs=devs, workspace=ws, sample=args.tune_sample)
         tuning["seconds"] = time.time() - t
@@ -267,8 +275,13 @@ def main():
                          "solves; served: Poisson requests to the server")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-plain", action="store_true", help="batch: time the batched call only (parameter sweeps)")
-    ap.add_argument("--tune-sample", type=int, default=512,
-                    help="batch: graphs the autotuner times before the run (0: no tuning)")
+    ap.add_argument("--tune-sample", type=int, default=4096,
+                    help="batch: graphs the autotuner times before the run (at least --batch-count: the whole "
+                         "batch; 0: no tuning)")
+    ap.add_argument("--batch-threads", type=int, default=0, choices=[0, 64, 128, 256, 512, 1024],
+                    help="batch: fixed pass workgroup size instead of autotuning (0: autotune)")
+    ap.add_argument("--batch-lp", type=int, default=0, choices=[0, 1, 2],
+                    help="batch: fixed admission bound (1 on, 2 off) instead of autotuning (0: autotune)")
     ap.add_argument("--pool", type=int, default=256)
     ap.add_argument("--rates", default="20,50,200,1000,2000",
                     help="served: arrival rates per second (20/s is below the server's capacity)")
