@@ -487,3 +487,61 @@ def test_pr3_needs_the_matching(seed):
     if matched:
         h, nc = _contract_marks(g, matched)
         assert nc >= 2 and oracle.brute(h)[0] == lam
+
+
+# ------------------------------------------- hand-worked label-propagation round
+def test_lp_round_hand_example():
+    # Worked by hand from the synchronous rule (own label kept unless another
+    # label is strictly heavier; ties among other labels to the smallest):
+    #   v0: 7 -> 3 (own), 9 -> 2+1 = 3, not heavier     -> keeps 7
+    #   v1: 7 -> 3 (own), 9 -> 4                        -> 9
+    #   v2: 9 -> 5 (own), 7 -> 2+4 = 6                  -> 7
+    #   v3: 9 -> 5 (own), 7 -> 1, 5 -> 2, 3 -> 2; loop ignored -> keeps 9
+    #   v4: 5 -> 0 (own), 9 -> 2, 3 -> 2 (tie)          -> 3
+    #   v5: 3 -> 0 (own), 9 -> 2, 5 -> 2 (tie)          -> 5
+    #   v6: isolated                                    -> keeps 4
+    u = [0, 0, 0, 1, 2, 3, 3, 4, 3]
+    v = [1, 2, 3, 2, 3, 4, 5, 5, 3]
+    w = [3, 2, 1, 4, 5, 2, 2, 2, 100]
+    g = gen.raw_csr(7, u, v, w)
+    lab = np.array([7, 7, 9, 9, 5, 3, 4], np.int32)
+    assert list(oracle.lp_round(g, lab)) == [7, 9, 7, 9, 3, 5, 4]
+    # splitting an edge into parallel entries of the same total changes nothing
+    g2 = gen.raw_csr(7, u + [1], v + [2], w[:3] + [1] + w[4:] + [3])
+    assert list(oracle.lp_round(g2, lab)) == [7, 9, 7, 9, 3, 5, 4]
+
+
+# ------------------------------------------------------- s-t cut enumeration
+def test_brute_st_hand_example():
+    # triangle 0-1 (3), 1-2 (5), 0-2 (1):
+    #   lambda(0,2) = min({0}: 3+1, {0,1}: 5+1) = 4
+    #   lambda(1,2) = min({1}: 3+5, {0,1}: 5+1) = 6
+    #   lambda(0,1) = min({0}: 3+1, {0,2}: 3+5) = 4
+    g = gen.from_edges(3, [0, 1, 0], [1, 2, 2], [3, 5, 1])
+    assert oracle.brute_st(g, 0, 2) == 4
+    assert oracle.brute_st(g, 2, 0) == 4
+    assert oracle.brute_st(g, 1, 2) == 6
+    assert oracle.brute_st(g, 0, 1) == 4
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_st_equals_max_flow(seed):
+    # max-flow min-cut theorem: the smallest s-t cut equals the maximum s-t
+    # flow, computed here by scipy's own routine on the symmetric capacities
+    from scipy.sparse.csgraph import maximum_flow
+    g = gen.random_small(6 + seed % 7, 0.5, 9100 + seed, 0, 9)
+    cap = sp.csr_matrix((g.w.astype(np.int32), g.col, g.row_ptr), shape=(g.n, g.n))
+    r = gen.SplitMix64(seed)
+    for _ in range(4):
+        s = r.below(g.n)
+        t = (s + 1 + r.below(g.n - 1)) % g.n
+        assert oracle.brute_st(g, s, t) == maximum_flow(cap, s, t).flow_value
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_st_minimum_over_t_is_lambda(seed):
+    # every cut separates vertex 0 from some t, so the global minimum is the
+    # smallest s-t cut from vertex 0
+    g = gen.random_small(5 + seed % 8, 0.5, 9200 + seed, 0, 9)
+    lam, _ = oracle.brute(g)
+    assert min(oracle.brute_st(g, 0, t) for t in range(1, g.n)) == lam
