@@ -131,6 +131,29 @@ static int regular_into(gen_edges* e, int32_t base, int32_t n, int32_t d, uint64
         if (ok) { free(pts); free(adj); free(deg); return 0; }
     }
     free(pts); free(adj); free(deg);
+    /* Dense blocks (d close to n - 1), where the pairing rarely completes: a
+     * d-regular graph is the complement of an (n-1-d)-regular one, which the
+     * pairing finds easily. Taken only after the pairing failed, so every
+     * graph the pairing produces stays as it was. */
+    if (2 * d > n - 1 && n <= 4096) {
+        gen_edges c;
+        memset(&c, 0, sizeof(c));
+        int rc = regular_into(&c, 0, n, n - 1 - d, s);
+        if (rc) { gen_free(&c); return rc; }
+        uint8_t* mat = (uint8_t*)calloc((size_t)n * n, 1);
+        if (!mat) { gen_free(&c); return -1; }
+        for (int64_t k = 0; k < c.m; k++) {
+            mat[(int64_t)c.u[k] * n + c.v[k]] = 1;
+            mat[(int64_t)c.v[k] * n + c.u[k]] = 1;
+        }
+        gen_free(&c);
+        e->m = m0;
+        for (int32_t a = 0; a < n; a++)
+            for (int32_t b = a + 1; b < n; b++)
+                if (!mat[(int64_t)a * n + b] && edges_push(e, base + a, base + b)) { free(mat); return -1; }
+        free(mat);
+        return 0;
+    }
     return -3;
 }
 

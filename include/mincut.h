@@ -146,18 +146,29 @@ mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws
                     int64_t* lambda, uint8_t* side, mc_stats* st);
 
 /* Batched solves: k graphs (all in host memory or all in device memory,
- * each n >= 2, together fewer than 2^30 vertices and 2^30 entries) solved
- * in one call, with one set of launches per round of Algorithm 2 for all of
- * them (the graphs are laid side by side as one union graph; each keeps its
- * own bound, CAPFOREST pass and side). Results are those of mc_mincut:
+ * together fewer than 2^30 vertices and 2^30 entries) solved in one call,
+ * with one set of launches per round of Algorithm 2 for all of them (the
+ * graphs are laid side by side as one union graph; each keeps its own
+ * bound, CAPFOREST pass and side). Results are those of mc_mincut:
  * lambdas[i] (host, k values) is graph i's minimum cut; if sides != NULL and
  * sides[i] != NULL, sides[i] (host, n_i bytes) receives one side of it with
- * sides[i][0] = 0. per_graph (host, k values, may be NULL) receives MC_OK
- * for every graph. When batch_lp selects it, every graph first goes
- * through the label-propagation heuristic's coarsening (LP rounds and
- * cluster contraction while the graphs shrink; the smallest collapsed
- * degree of each level bounds lambda), all graphs in the same launches, but
- * without its reduction tests and exact finish. Synchronises the stream. */
+ * sides[i][0] = 0.
+ * Every graph is checked on its own before anything is solved: host graphs
+ * as mc_check_graph does (with symmetry when the context's validate option
+ * is 1), device graphs on the device (the same checks without symmetry);
+ * the 2^62 weight bound applies to each graph's own total.
+ *  - per_graph != NULL (host, k values): per_graph[i] receives graph i's
+ *    status; graphs that fail their checks are skipped (their lambdas[i]
+ *    and sides[i] stay untouched) and the others are solved; the call
+ *    returns MC_OK unless the call itself fails.
+ *  - per_graph == NULL: the first graph that fails its checks fails the
+ *    whole call with its status, before anything is solved.
+ * On a failing call every output is left untouched. When batch_lp selects
+ * it, every graph first goes through the label-propagation heuristic's
+ * coarsening (LP rounds and cluster contraction while the graphs shrink;
+ * the smallest collapsed degree of each level bounds lambda), all graphs in
+ * the same launches, but without its reduction tests and exact finish.
+ * Synchronises the stream. */
 mc_status mc_batch_workspace_size(const mc_ctx* ctx, int32_t k, const mc_csr* graphs, size_t* bytes);
 mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
                           int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph);
@@ -189,45 +200,72 @@ mc_status mc_batch_autotune(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* 
 
 /* Served form: a request loop with continuous batching. The server holds
  * one device allocation of hbm_bytes (made at create) for the graphs in
- * flight. mc_server_submit copies a host graph into a queue. Each
- * mc_server_step admits queued requests in arrival order while they fit
- * (graphs in flight <= max_inflight, vertices and entries within what the
- * budget holds), runs one round of Algorithm 2 for every graph in flight
- * (admitted graphs join graphs already half way through their rounds, in
- * the same launches), and collects finished graphs. A graph's result does
- * not depend on the others in flight. Calls on one server must not overlap
- * (one thread at a time). */
+ * flight. mc_server_submit checks a host graph (as mc_check_graph, with
+ * symmetry when the context's validate option is 1) and copies it into a
+ * queue. Each mc_server_step
+ *  - collects large requests whose solve ended and drops requests that
+ *    were cancelled or passed their deadline;
+ *  - admits queued requests in arrival order: requests with n >=
+ *    solo_min_n start on a free solo slot (mc_mincut on a worker thread
+ *    with its own context and non-blocking stream, so its kernels overlap
+ *    the engine's on the device and no other request waits for it); the
+ *    others join the engine while they fit (graphs in flight <=
+ *    max_inflight, vertices and entries within what the budget holds);
+ *  - runs one round of Algorithm 2 for every graph in the engine (admitted
+ *    graphs join graphs already half way through their rounds, in the same
+ *    launches) and collects finished graphs.
+ * A graph's result does not depend on the others in flight. Calls on one
+ * server must not overlap (one thread at a time). */
 typedef struct {
     size_t hbm_bytes;          /* device memory of the server (>= 64 MiB) */
     int32_t max_inflight;      /* graphs in the rounds at once (0: 1024) */
     int32_t max_request_n;     /* largest request, vertices (0: 2^20) */
     int64_t max_request_nnz;   /* largest request, entries (0: 2^25) */
     int32_t solo_min_n;        /* requests with at least this many vertices
-                                  are solved one per step by mc_mincut (whole
-                                  GPU, full heuristic) from a workspace set
-                                  aside in the budget (0: 65536) */
+                                  are solved by mc_mincut (whole GPU, full
+                                  heuristic) on a solo slot, from a
+                                  workspace set aside in the budget
+                                  (0: 65536) */
+    int32_t solo_slots;        /* large requests solved at once, each with a
+                                  workspace of its own (0: 1; at most 8) */
+    double deadline_ms;        /* a request not done this long after its
+                                  submission is answered with MC_E_TIMEOUT;
+                                  checked at every step (a queued request is
+                                  never admitted, one in the engine leaves
+                                  it at the next round, a solo solve is
+                                  reported as timed out when it ends late);
+                                  0: no deadline */
 } mc_server_opts;
 typedef struct {
     double t_submit_ms, t_admit_ms, t_done_ms;   /* since the server was created */
-    int32_t rounds;                              /* rounds the graph took part in */
+    int32_t rounds;                              /* engine rounds the graph took
+                                                    part in (0 for a solo solve) */
 } mc_req_stats;
 typedef struct mc_server mc_server;
 mc_status mc_server_create(mc_ctx* ctx, const mc_server_opts* opts, mc_server** out);
 mc_status mc_server_destroy(mc_server* srv);
-/* Queue a copy of host graph g; *ticket identifies it. MC_E_OOM when the
- * graph alone exceeds what the server can ever admit. */
+/* Check and queue a copy of host graph g; *ticket identifies it. The
+ * checks' error (MC_E_INVALID_ARG, MC_E_BAD_GRAPH, MC_E_OVERFLOW) is
+ * returned at once and nothing is queued; MC_E_OOM when the graph alone
+ * exceeds what the server can ever admit. */
 mc_status mc_server_submit(mc_server* srv, const mc_csr* g, uint64_t* ticket);
-/* Admit, run one round, collect. *in_flight / *queued (may be NULL): graphs
- * in the rounds and waiting after the step. Synchronises the stream. */
+/* Collect, admit, run one round, collect. *in_flight / *queued (may be
+ * NULL): requests running (engine and solo slots) and waiting after the
+ * step. Synchronises the engine's stream. A device failure of an admission
+ * or a round fails the requests it touched (their poll returns the error)
+ * and is returned; the other requests go on. */
 mc_status mc_server_step(mc_server* srv, int32_t* in_flight, int32_t* queued);
 /* MC_OK with lambda, side (host, n bytes, side[0] = 0; may be NULL) and
  * timing once done (the ticket is then released); MC_E_NOT_READY before;
- * MC_E_CANCELLED for a cancelled request (released). */
+ * MC_E_CANCELLED for a cancelled request, MC_E_TIMEOUT for one past its
+ * deadline and the failure's status for a failed one (each released). */
 mc_status mc_server_poll(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_req_stats* st);
-/* *state: 0 queued, 1 in flight, 2 done (poll returns it), 3 cancelled. */
+/* *state: 0 queued, 1 in flight, 2 done (poll returns it), 3 cancelled,
+ * 4 failed, 5 timed out. */
 mc_status mc_server_state(const mc_server* srv, uint64_t ticket, int32_t* state);
-/* Cancel a request: a queued one is never admitted, one in flight is
- * dropped when its rounds end. */
+/* Cancel a request: a queued one is never admitted, one in the engine
+ * leaves it at the next step, a solo solve is reported as cancelled when it
+ * ends. */
 mc_status mc_server_cancel(mc_server* srv, uint64_t ticket);
 /* Capacity the budget gives (entries, vertices, graphs in flight, bytes). */
 mc_status mc_server_capacity(const mc_server* srv, int64_t* entries, int32_t* vertices, int32_t* graphs,
@@ -247,7 +285,12 @@ enum {
     MC_K_GROUP_SCATTER = 4,    /* k_group_scatter: members grouped by label */
     MC_K_PR12 = 5,             /* k_pr12: reduction tests 1 and 2 */
     MC_K_CONNECT_LINK = 6,     /* k_uf_link_rest: connectivity unions */
-    MC_K_COUNT = 7
+    MC_K_LP_SMALL = 7,         /* k_lp_small: label-propagation round, rows of <= 512 entries */
+    MC_K_LP_FIRST = 8,         /* k_lp_first: first label-propagation round (from singletons) */
+    MC_K_MID_MERGE = 9,        /* k_mid_merge: contraction of groups of 513..2048 entries */
+    MC_K_PR1_FIRST = 10,       /* k_pr1_first: unions of every row's first two test-1 entries */
+    MC_K_PR1_REST = 11,        /* k_pr1_rest: unions of the remaining test-1 entries */
+    MC_K_COUNT = 12
 };
 typedef struct {
     char name[32];      /* kernel symbol name */
@@ -257,7 +300,7 @@ typedef struct {
 } mc_kernel_time;
 
 /* on != 0: switch timing on and zero the totals (the first call allocates
- * 56 KiB of device counters, kept until mc_ctx_destroy); on = 0:
+ * 96 KiB of device counters, kept until mc_ctx_destroy); on = 0:
  * switch it off and keep the totals. */
 mc_status mc_profile(mc_ctx* ctx, int32_t on);
 /* Totals of one kernel (kernel in [0, MC_K_COUNT)); synchronous. */
@@ -281,6 +324,17 @@ typedef struct {
     double ms;
 } mc_round_time;
 mc_status mc_profile_round(mc_ctx* ctx, int32_t i, mc_round_time* out, int32_t* count);
+
+/* Check a host graph (location MC_HOST) exactly as mc_mincut does before it
+ * touches the device: MC_E_INVALID_ARG for a NULL graph or pointer, n < 2 or
+ * nnz < 0; MC_E_BAD_GRAPH for row_ptr[0] != 0, row_ptr[n] != nnz, a
+ * decreasing row_ptr, a target outside [0, n) or a negative weight;
+ * MC_E_OVERFLOW for a total weight of 2^62 or more; with symmetric != 0,
+ * MC_E_BAD_GRAPH when some folded pair (u, v, s) (loops dropped, parallel
+ * entries summed) has no matching (v, u, s). The input definition is that of
+ * Section 2 "Basic Concepts" (undirected, non-negative integer weights).
+ * Reads the arrays only; needs no GPU and no context. */
+mc_status mc_check_graph(const mc_csr* g, int32_t symmetric);
 
 /* Thread-local description of the last error (never NULL). */
 const char* mc_last_error(void);

@@ -72,12 +72,13 @@ class KernelTime(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
-MC_K_COUNT = 7  # kernels mc_profile times (MC_K_* in include/mincut.h)
+MC_K_COUNT = 12  # kernels mc_profile times (MC_K_* in include/mincut.h)
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("max_request_n", ctypes.c_int32),
-                ("max_request_nnz", ctypes.c_int64), ("solo_min_n", ctypes.c_int32)]
+                ("max_request_nnz", ctypes.c_int64), ("solo_min_n", ctypes.c_int32), ("solo_slots", ctypes.c_int32),
+                ("deadline_ms", ctypes.c_double)]
 
 
 class ReqStats(ctypes.Structure):
@@ -103,6 +104,7 @@ SIGNATURES = {
     "mc_workspace_size": (ctypes.c_int, [P, I32, I32, P]),
     "mc_mincut": (ctypes.c_int, [P, P, P, SZ, P, P, P]),
     "mc_last_error": (ctypes.c_char_p, []),
+    "mc_check_graph": (ctypes.c_int, [P, I32]),
     "mc_batch_workspace_size": (ctypes.c_int, [P, I32, P, P]),
     "mc_mincut_batch": (ctypes.c_int, [P, I32, P, P, SZ, P, P, P]),
     "mc_batch_autotune": (ctypes.c_int, [P, I32, P, P, SZ, I32, P]),
@@ -276,9 +278,11 @@ class Context:
         _check(lib().mc_batch_workspace_size(self.h, len(arr), arr, ctypes.byref(b)))
         return b.value
 
-    def mincut_batch(self, graphs=None, devs=None, workspace=None, want_sides=True):
+    def mincut_batch(self, graphs=None, devs=None, workspace=None, want_sides=True, per_graph=False):
         """Minimum cuts of many graphs in one call (mc_mincut_batch): host
-        graphs or device (rp, col, w) tuples. Returns (lambdas, sides)."""
+        graphs or device (rp, col, w) tuples. Returns (lambdas, sides), or
+        (lambdas, sides, statuses) with per_graph=True, where a graph that
+        fails its own checks gets its status and is skipped."""
         torch = _torch()
         arr, keep = self._csr_array(graphs, devs)
         k = len(arr)
@@ -287,12 +291,13 @@ class Context:
             _check(lib().mc_batch_workspace_size(self.h, k, arr, ctypes.byref(b)))
             workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
         lams = np.zeros(k, np.int64)
-        sides = [np.zeros(arr[i].n, np.uint8) for i in range(k)] if want_sides else None
+        sides = [np.zeros(max(int(arr[i].n), 0), np.uint8) for i in range(k)] if want_sides else None
         sp = (ctypes.c_void_p * k)(*[s.ctypes.data for s in sides]) if want_sides else None
+        st = np.zeros(k, np.int32) if per_graph else None
         _check(lib().mc_mincut_batch(self.h, k, arr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                     lams.ctypes.data, sp, None))
+                                     lams.ctypes.data, sp, st.ctypes.data if per_graph else None))
         del keep
-        return lams, sides
+        return (lams, sides, st) if per_graph else (lams, sides)
 
     def batch_autotune(self, graphs=None, devs=None, workspace=None, sample=0):
         """Time the batched form on a spread sample of the batch under every
@@ -436,12 +441,26 @@ class Context:
                 "best_alpha": ba.value, "best_len": bl.value, "lam": lo.value}
 
 
+def check_graph(g, symmetric=False):
+    """Host-side checks of a graph (mc_check_graph; no GPU needed): the
+    status code, 0 for a valid graph."""
+    rp = np.ascontiguousarray(g.row_ptr, np.int32)
+    col = np.ascontiguousarray(g.col, np.int32)
+    w = np.ascontiguousarray(g.w, np.int64)
+    nnz = int(getattr(g, "nnz", rp[-1] if rp.size else 0))
+    csr = CSR(int(g.n), nnz, rp.ctypes.data if rp.size else 0, col.ctypes.data if col.size else 0,
+              w.ctypes.data if w.size else 0, MC_HOST)
+    return int(lib().mc_check_graph(ctypes.byref(csr), 1 if symmetric else 0))
+
+
 class Server:
     """Continuous-batching request server (mc_server_*) on a context."""
 
-    def __init__(self, ctx, hbm_bytes, max_inflight=0, max_request_n=0, max_request_nnz=0, solo_min_n=0):
+    def __init__(self, ctx, hbm_bytes, max_inflight=0, max_request_n=0, max_request_nnz=0, solo_min_n=0,
+                 solo_slots=0, deadline_ms=0.0):
         self.ctx = ctx
-        self.opts = ServerOpts(hbm_bytes, max_inflight, max_request_n, max_request_nnz, solo_min_n)
+        self.opts = ServerOpts(hbm_bytes, max_inflight, max_request_n, max_request_nnz, solo_min_n, solo_slots,
+                               deadline_ms)
         h = ctypes.c_void_p()
         _check(lib().mc_server_create(ctx.h, ctypes.byref(self.opts), ctypes.byref(h)))
         self.h = h

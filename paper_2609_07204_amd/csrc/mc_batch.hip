@@ -80,6 +80,49 @@ __global__ void k_bg_gather(const BatchGraph* tab, int32_t k, const int32_t* vof
     }
 }
 
+// Per-graph checks of device inputs (what check_host_csr does on the host,
+// without the symmetry check), one workgroup per graph at a time:
+// row_ptr[0] = 0, row_ptr[n] = nnz and non-decreasing, every target in
+// [0, n) and every weight >= 0 (MC_E_BAD_GRAPH), then the graph's own total
+// weight below 2^62 (MC_E_OVERFLOW). gerr[i] receives graph i's status.
+constexpr unsigned long long BG_WCAP = 1ULL << 62;
+__global__ __launch_bounds__(256) void k_bg_check(const BatchGraph* tab, int32_t k, int32_t* gerr) {
+    __shared__ unsigned long long ssum[256];
+    __shared__ int32_t sbad;
+    for (int32_t i = blockIdx.x; i < k; i += gridDim.x) {
+        const BatchGraph g = tab[i];
+        if (threadIdx.x == 0) sbad = 0;
+        __syncthreads();
+        bool bad = threadIdx.x == 0 && (g.rp[0] != 0 || g.rp[g.n] != g.nnz);
+        for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x)
+            if (g.rp[v + 1] < g.rp[v]) bad = true;
+        unsigned long long sum = 0;
+        for (int32_t j = threadIdx.x; j < g.nnz; j += blockDim.x) {
+            const int32_t x = g.col[j];
+            const int64_t c = g.w[j];
+            if (x < 0 || x >= g.n || c < 0) {
+                bad = true;
+            } else {
+                // sum < 2^62 and c < 2^63 before the add: no wrap
+                sum += (unsigned long long)c;
+                if (sum >= BG_WCAP) sum = BG_WCAP;
+            }
+        }
+        if (bad) sbad = 1;
+        ssum[threadIdx.x] = sum;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                const unsigned long long t = ssum[threadIdx.x] + ssum[threadIdx.x + o];
+                ssum[threadIdx.x] = t >= BG_WCAP ? BG_WCAP : t;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) gerr[i] = sbad ? MC_E_BAD_GRAPH : (ssum[0] >= BG_WCAP ? MC_E_OVERFLOW : MC_OK);
+        __syncthreads();
+    }
+}
+
 // host inputs were copied as they are: shift row offsets and targets
 __global__ void k_bg_shift(int32_t k, const int32_t* voff, const int32_t* eoff, int32_t N, int32_t C, int32_t* rp,
                            int32_t* col) {
@@ -333,6 +376,7 @@ struct EngineWS {
     uint8_t *done, *snap, *prun, *dead;
     int32_t* gstart_total;
     BatchGraph* tab;
+    int32_t* gerr;            // [K] per-graph status of device-input checks
     int32_t *in_rp, *in_col;
     int64_t* in_w;
     DGraph g[3];
@@ -376,6 +420,7 @@ void carve_engine(Arena& a, const Caps& cp, EngineWS& w) {
     w.dead = a.take<uint8_t>((size_t)K + 1);
     w.gstart_total = a.take<int32_t>(1);
     w.tab = a.take<BatchGraph>((size_t)K);
+    w.gerr = a.take<int32_t>((size_t)K);
     w.in_rp = a.take<int32_t>((size_t)Ns + 1);
     w.in_col = a.take<int32_t>((size_t)Cs + 1);
     w.in_w = a.take<int64_t>((size_t)Cs + 1);
@@ -506,7 +551,10 @@ struct Engine {
                ne <= cap.Cs && live0 + nv <= cap.N0;
     }
 
-    // Append graphs (normalised on the way) behind the current graph.
+    // Append graphs (normalised on the way) behind the current graph. Every
+    // graph must already have passed its own checks (check_host_csr for
+    // host graphs, check_device for device graphs): admission relies on
+    // them and checks only sizes and capacity.
     mc_status admit(const mc_csr* gs, int32_t k, const uint64_t* ids) {
         if (k <= 0) return MC_OK;
         const int32_t loc = gs[0].location;
@@ -546,11 +594,6 @@ struct Engine {
         } else {
             for (int32_t i = 0; i < k; i++) {
                 const mc_csr& g = gs[i];
-                if (g.row_ptr[0] != 0 || g.row_ptr[g.n] != g.nnz) return mc_fail(MC_E_BAD_GRAPH, "malformed row_ptr");
-                for (int32_t v = 0; v < g.n; v++)
-                    if (g.row_ptr[v + 1] < g.row_ptr[v]) return mc_fail(MC_E_BAD_GRAPH, "row_ptr not monotone");
-                for (int32_t j = 0; j < g.nnz; j++)
-                    if (g.col[j] < 0 || g.col[j] >= g.n || g.w[j] < 0) return mc_fail(MC_E_BAD_GRAPH, "bad entry");
                 EG_HIP(hipMemcpyAsync(w.in_rp + sv[i], g.row_ptr, sizeof(int32_t) * g.n, hipMemcpyHostToDevice, s));
                 if (g.nnz > 0) {
                     EG_HIP(hipMemcpyAsync(w.in_col + se[i], g.col, sizeof(int32_t) * g.nnz, hipMemcpyHostToDevice, s));
@@ -561,9 +604,13 @@ struct Engine {
                                                                           w.in_col);
             EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_shift"));
         }
-        EG_OK(validate_csr(w.in_rp, w.in_col, w.in_w, NS, CS, w.sc, w.vpart, s));
-        if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
-        if (c->hsc->err) return mc_fail((mc_status)c->hsc->err, "malformed graph");
+        if (loc == MC_DEVICE) {
+            // the gather repeats the structural checks of k_bg_check; the
+            // graphs were checked before admission, so this only catches
+            // inputs changed in between
+            if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
+            if (c->hsc->err) return mc_fail((mc_status)c->hsc->err, "malformed graph");
+        }
         // normal form: in place when already normal, else contraction by
         // the identity into the staging graph
         DGraph S = w.stage;
@@ -681,6 +728,24 @@ struct Engine {
             if (!more) break;
         }
         return true;
+    }
+
+    // Per-graph checks of k device graphs (check_host_csr's checks without
+    // symmetry, on the device): st[i] receives graph i's status. Pointers and
+    // n were checked on the host.
+    mc_status check_device(const mc_csr* gs, int32_t k, mc_status* st) {
+        if (k <= 0) return MC_OK;
+        if (k > cap.K) return mc_fail(MC_E_INVALID_ARG, "engine: too many graphs to check");
+        std::vector<BatchGraph> tab(k);
+        for (int32_t i = 0; i < k; i++) tab[i] = {gs[i].row_ptr, gs[i].col, gs[i].w, gs[i].n, gs[i].nnz};
+        std::vector<int32_t> e(k);
+        EG_HIP(hipMemcpyAsync(w.tab, tab.data(), sizeof(BatchGraph) * k, hipMemcpyHostToDevice, s));
+        k_bg_check<<<std::min(k, 4096), 256, 0, s>>>(w.tab, k, w.gerr);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_check"));
+        EG_HIP(hipMemcpyAsync(e.data(), w.gerr, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+        EG_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < k; i++) st[i] = (mc_status)e[i];
+        return MC_OK;
     }
 
     // Move the input-vertex ranges of live graphs to the front.
@@ -878,19 +943,21 @@ struct Engine {
 namespace {
 
 Caps batch_caps(int32_t k, const mc_csr* gs, bool& ok) {
+    // graphs that can never be admitted (n < 2, nnz < 0) take no room
     Caps cp;
     int64_t n = 0, e = 0;
     int32_t nmax = 0;
     for (int32_t i = 0; i < k; i++) {
+        if (gs[i].n < 2 || gs[i].nnz < 0) continue;
         n += gs[i].n;
         e += gs[i].nnz;
         nmax = std::max(nmax, gs[i].n);
     }
     ok = n < INT32_MAX / 2 && e < INT32_MAX / 2;
-    cp.N = cp.N0 = cp.Ns = (int32_t)n;
+    cp.N = cp.N0 = cp.Ns = (int32_t)std::max<int64_t>(n, 2);
     cp.C = cp.Cs = e;
     cp.K = k;
-    cp.nmax = nmax;
+    cp.nmax = std::max(nmax, 2);
     return cp;
 }
 
@@ -911,32 +978,87 @@ extern "C" mc_status mc_batch_workspace_size(const mc_ctx* c, int32_t k, const m
 extern "C" mc_status mc_mincut_batch(mc_ctx* c, int32_t k, const mc_csr* gs, void* dev_ws, size_t ws_bytes,
                                      int64_t* lambdas, uint8_t* const* sides, mc_status* per_graph) {
     if (!c || !gs || !lambdas || k <= 0 || !dev_ws) return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: bad argument");
+    const int32_t loc = gs[0].location;
+    for (int32_t i = 0; i < k; i++)
+        if (gs[i].location != loc || (loc != MC_HOST && loc != MC_DEVICE))
+            return mc_fail(MC_E_INVALID_ARG, "mc_mincut_batch: all graphs of one call must share one location");
     bool ok;
     Caps cp = batch_caps(k, gs, ok);
     if (!ok) return mc_fail(MC_E_OVERFLOW, "batch too large (vertices or entries >= 2^30)");
+    // every graph is checked on its own: one bad graph does not stop the
+    // others when per_graph is given
+    std::vector<mc_status> st((size_t)k, MC_OK);
+    std::vector<std::string> why((size_t)k);
+    std::vector<int32_t> dev_idx;
+    for (int32_t i = 0; i < k; i++) {
+        const mc_csr& g = gs[i];
+        if (loc == MC_HOST) {
+            st[i] = check_host_csr(&g, c->opt.validate != 0);
+        } else if (g.n < 2) {
+            st[i] = mc_fail(MC_E_INVALID_ARG, "need n >= 2");
+        } else if (g.nnz < 0 || !g.row_ptr || (g.nnz > 0 && (!g.col || !g.w))) {
+            st[i] = mc_fail(MC_E_INVALID_ARG, "bad CSR pointers");
+        } else {
+            dev_idx.push_back(i);
+        }
+        if (st[i] != MC_OK) why[i] = mc_error_slot();
+    }
     Engine E;
     mc_status r = E.init(c, cp, dev_ws, ws_bytes);
     if (r != MC_OK) return r;
-    std::vector<uint64_t> ids(k);
-    for (int32_t i = 0; i < k; i++) ids[i] = (uint64_t)i;
-    if ((r = E.admit(gs, k, ids.data())) != MC_OK) return r;
+    if (!dev_idx.empty()) {
+        std::vector<mc_csr> dg;
+        for (int32_t i : dev_idx) dg.push_back(gs[i]);
+        std::vector<mc_status> ds(dg.size());
+        if ((r = E.check_device(dg.data(), (int32_t)dg.size(), ds.data())) != MC_OK) return r;
+        for (size_t q = 0; q < dg.size(); q++) {
+            st[dev_idx[q]] = ds[q];
+            if (ds[q] == MC_E_BAD_GRAPH) why[dev_idx[q]] = "malformed CSR (row_ptr, col or w)";
+            if (ds[q] == MC_E_OVERFLOW) why[dev_idx[q]] = "total weight must be below 2^62";
+        }
+    }
+    std::vector<mc_csr> good;
+    std::vector<uint64_t> ids;
+    for (int32_t i = 0; i < k; i++) {
+        if (st[i] == MC_OK) {
+            good.push_back(gs[i]);
+            ids.push_back((uint64_t)i);
+        } else if (!per_graph) {
+            return mc_fail(st[i], "mc_mincut_batch: graph " + std::to_string(i) + ": " + why[i]);
+        }
+    }
+    if (!good.empty() && (r = E.admit(good.data(), (int32_t)good.size(), ids.data())) != MC_OK) return r;
     std::vector<EngineInst> fin;
     // graphs final at admission (two vertices, or lambda 0)
     for (EngineInst& x : E.insts)
         if (x.done) fin.push_back(x);
     for (EngineInst& x : E.insts)
         if (x.done) x.dead = true;
+    // results are staged and written only once every graph is done, so a
+    // failing call leaves the outputs untouched
+    std::vector<int64_t> lam_out((size_t)k, 0);
+    std::vector<std::vector<uint8_t>> side_out(sides ? (size_t)k : 0);
     size_t got = 0;
     for (int32_t rounds = 0;; rounds++) {
         for (; got < fin.size(); got++) {
             const EngineInst& x = fin[got];
-            lambdas[x.id] = x.lam;
-            if ((r = E.side_of(x, sides ? sides[x.id] : nullptr)) != MC_OK) return r;
-            if (per_graph) per_graph[x.id] = MC_OK;
+            lam_out[x.id] = x.lam;
+            uint8_t* so = nullptr;
+            if (sides && sides[x.id]) {
+                side_out[x.id].resize((size_t)x.n0);
+                so = side_out[x.id].data();
+            }
+            if ((r = E.side_of(x, so)) != MC_OK) return r;
         }
         if (E.live() == 0) break;
         if (rounds > cp.N + 64) return mc_fail(MC_E_DEVICE, "mc_mincut_batch: no progress");
         if ((r = E.step(fin)) != MC_OK) return r;
+    }
+    for (int32_t i = 0; i < k; i++) {
+        if (per_graph) per_graph[i] = st[i];
+        if (st[i] != MC_OK) continue;
+        lambdas[i] = lam_out[i];
+        if (sides && sides[i]) std::copy(side_out[i].begin(), side_out[i].end(), sides[i]);
     }
     return MC_OK;
 }
@@ -1006,43 +1128,68 @@ extern "C" mc_status mc_batch_autotune(mc_ctx* c, int32_t k, const mc_csr* gs, v
 }
 
 // ------------------------------------------------------------ the server
-// Continuous batching over the engine: requests are copied at submission
-// and queued; every mc_server_step admits queued requests in arrival order
-// while they fit the engine's capacity (graphs in flight, vertices,
-// entries; all carved from one device allocation of the configured HBM
-// budget), runs one round for every graph in flight, and collects the
-// graphs whose result became final. Graphs admitted while others are half
-// way through their rounds join them in the same launches; a graph's rounds
-// do not depend on the others (its bound, passes and contractions touch
-// only its own range), so its result is the one it gets alone.
+// Continuous batching over the engine: requests are checked and copied at
+// submission and queued; every mc_server_step admits queued requests in
+// arrival order while they fit the engine's capacity (graphs in flight,
+// vertices, entries; all carved from one device allocation of the
+// configured HBM budget), runs one round for every graph in flight, and
+// collects the graphs whose result became final. Graphs admitted while
+// others are half way through their rounds join them in the same launches;
+// a graph's rounds do not depend on the others (its bound, passes and
+// contractions touch only its own range), so its result is the one it gets
+// alone. Large requests (n >= solo_min_n) are solved by mc_mincut on a
+// worker thread with a context and non-blocking stream of their own, from a
+// workspace set aside in the budget, so their kernels overlap the engine's
+// rounds on the device and nothing waits for them.
+#include <atomic>
 #include <deque>
+#include <memory>
+#include <thread>
 #include <unordered_map>
 
 struct mc_server {
     mc_ctx* c = nullptr;
     void* mem = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;             // engine part of mem
+    size_t solo_bytes = 0;        // workspace of each solo slot
     Engine E;
-    void* solo_ws = nullptr;      // workspace of one large request solved on its own
-    size_t solo_bytes = 0;
     int32_t solo_min_n = 0;
+    double deadline_ms = 0;
     std::chrono::steady_clock::time_point t0;
     struct Req {
         std::vector<int32_t> rp, col;
         std::vector<int64_t> w;
         int32_t n = 0, nnz = 0;
-        int state = 0;             // 0 queued, 1 in flight, 2 done, 3 cancelled
+        int state = 0;             // 0 queued, 1 in flight, 2 done, 3 cancelled, 4 failed, 5 timed out
         bool cancel = false;
+        bool solo = false;
+        mc_status status = MC_OK;  // of a failed request
+        std::string err;
         int64_t lam = 0;
         std::vector<uint8_t> side;
         mc_req_stats st{};
     };
+    // one large request at a time per slot, on its own context and stream
+    struct Slot {
+        mc_ctx* ctx = nullptr;
+        hipStream_t stream = nullptr;
+        void* ws = nullptr;
+        std::thread th;
+        std::atomic<int> busy{0};  // 0 free, 1 running, 2 result ready
+        uint64_t id = 0;
+        mc_status st = MC_OK;
+        std::string err;
+        int64_t lam = 0;
+        std::vector<uint8_t> side;
+    };
+    std::vector<std::unique_ptr<Slot>> slots;
     std::unordered_map<uint64_t, Req> reqs;
     std::deque<uint64_t> queue;
     uint64_t next = 1;
     double now() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+    bool late(const Req& r, double t) const { return deadline_ms > 0 && t - r.st.t_submit_ms > deadline_ms; }
 };
 
 namespace {
@@ -1075,9 +1222,84 @@ mc_status finish(mc_server* S, const EngineInst& x) {
     mc_status st = S->E.side_of(x, r.side.data());
     if (st != MC_OK) return st;
     r.lam = x.lam;
-    r.state = r.cancel ? 3 : 2;
     r.st.t_done_ms = S->now();
     r.st.rounds = x.rounds;
+    r.state = r.cancel ? 3 : (S->late(r, r.st.t_done_ms) ? 5 : 2);
+    return MC_OK;
+}
+
+void fail_req(mc_server::Req& r, mc_status st, const std::string& why, double t) {
+    r.state = 4;
+    r.status = st;
+    r.err = why;
+    r.st.t_done_ms = t;
+}
+
+mc_csr host_csr(const mc_server::Req& r) {
+    mc_csr g;
+    g.n = r.n;
+    g.nnz = r.nnz;
+    g.row_ptr = r.rp.data();
+    g.col = r.col.data();
+    g.w = r.w.data();
+    g.location = MC_HOST;
+    return g;
+}
+
+// collect the results of solo slots whose solve ended
+void collect_solo(mc_server* S) {
+    for (auto& sp : S->slots) {
+        mc_server::Slot& sl = *sp;
+        if (sl.busy.load(std::memory_order_acquire) != 2) continue;
+        sl.th.join();
+        mc_server::Req& r = S->reqs[sl.id];
+        const double t = S->now();
+        if (sl.st != MC_OK) {
+            fail_req(r, sl.st, sl.err, t);
+        } else {
+            r.lam = sl.lam;
+            r.side.swap(sl.side);
+            r.st.t_done_ms = t;
+            r.st.rounds = 0;
+            r.state = r.cancel ? 3 : (S->late(r, t) ? 5 : 2);
+        }
+        sl.busy.store(0, std::memory_order_relaxed);
+    }
+}
+
+bool start_solo(mc_server* S, uint64_t id) {
+    for (auto& sp : S->slots) {
+        mc_server::Slot& sl = *sp;
+        if (sl.busy.load(std::memory_order_acquire) != 0) continue;
+        mc_server::Req& r = S->reqs[id];
+        r.state = 1;
+        r.solo = true;
+        r.st.t_admit_ms = S->now();
+        sl.id = id;
+        sl.side.assign((size_t)r.n, 0);
+        sl.busy.store(1, std::memory_order_relaxed);
+        const mc_csr g = host_csr(r);
+        mc_server::Slot* p = &sl;
+        const size_t wsb = S->solo_bytes;
+        sl.th = std::thread([p, g, wsb]() {
+            p->st = mc_mincut(p->ctx, &g, p->ws, wsb, &p->lam, p->side.data(), nullptr);
+            if (p->st != MC_OK) p->err = mc_last_error();
+            p->busy.store(2, std::memory_order_release);
+        });
+        return true;
+    }
+    return false;
+}
+
+// drop an engine request in flight (cancelled or past its deadline): its
+// vertices leave the union graph in the next contraction
+mc_status drop_inflight(mc_server* S, uint64_t id) {
+    for (EngineInst& x : S->E.insts) {
+        if (x.id != id || x.dead) continue;
+        x.done = true;
+        x.dead = true;
+        return S->E.side_of(x, nullptr);   // stops tracking its input vertices
+    }
     return MC_OK;
 }
 
@@ -1086,20 +1308,23 @@ mc_status finish(mc_server* S, const EngineInst& x) {
 extern "C" mc_status mc_server_create(mc_ctx* c, const mc_server_opts* opts, mc_server** out) {
     if (!c || !opts || !out) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: NULL argument");
     if (opts->hbm_bytes < ((size_t)64 << 20)) return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget below 64 MiB");
-    // requests of at least solo_min_n vertices are solved one at a time by
+    if (opts->solo_slots < 0 || opts->solo_slots > 8 || opts->deadline_ms < 0)
+        return mc_fail(MC_E_INVALID_ARG, "mc_server_create: solo_slots must be in [0, 8] and deadline_ms >= 0");
+    // requests of at least solo_min_n vertices are solved on solo slots by
     // the single-graph solver (whole-GPU CAPFOREST steps, the full
     // heuristic); the rest of the budget holds the engine
     const int32_t rn = opts->max_request_n > 0 ? opts->max_request_n : (1 << 20);
     const int64_t re = opts->max_request_nnz > 0 ? opts->max_request_nnz : ((int64_t)1 << 25);
     const int32_t solo_min_n = opts->solo_min_n > 0 ? opts->solo_min_n : (1 << 16);
+    const int32_t nslots = rn >= solo_min_n ? (opts->solo_slots > 0 ? opts->solo_slots : 1) : 0;
     size_t solo = 0;
-    if (rn >= solo_min_n) {
+    if (nslots > 0) {
         if (mc_workspace_size(c, rn, (int32_t)std::min<int64_t>(re, INT32_MAX / 2), &solo) != MC_OK) return MC_E_INVALID_ARG;
         solo = (solo + 4095) & ~(size_t)4095;
     }
-    if (solo + ((size_t)64 << 20) > opts->hbm_bytes)
+    if (solo * nslots + ((size_t)64 << 20) > opts->hbm_bytes)
         return mc_fail(MC_E_INVALID_ARG, "mc_server_create: budget too small for the largest request");
-    const size_t engine_budget = opts->hbm_bytes - solo;
+    const size_t engine_budget = opts->hbm_bytes - solo * nslots;
     // the largest entry capacity whose engine fits the budget
     mc_server_opts eo = *opts;
     if (rn >= solo_min_n) eo.max_request_n = solo_min_n - 1;
@@ -1111,30 +1336,50 @@ extern "C" mc_status mc_server_create(mc_ctx* c, const mc_server_opts* opts, mc_
         if (engine_bytes(server_caps(eo, mid)) <= engine_budget) lo = mid; else hi = mid;
     }
     const Caps cp = server_caps(eo, lo);
-    mc_server* S = new (std::nothrow) mc_server();
+    std::unique_ptr<mc_server> S(new (std::nothrow) mc_server());
     if (!S) return mc_fail(MC_E_OOM, "mc_server_create: out of host memory");
     S->c = c;
     S->bytes = (engine_bytes(cp) + 4095) & ~(size_t)4095;
     S->solo_bytes = solo;
     S->solo_min_n = solo_min_n;
-    if (hipSetDevice(c->device) != hipSuccess || hipMalloc(&S->mem, S->bytes + solo) != hipSuccess) {
-        delete S;
+    S->deadline_ms = opts->deadline_ms;
+    if (hipSetDevice(c->device) != hipSuccess || hipMalloc(&S->mem, S->bytes + solo * nslots) != hipSuccess)
         return mc_fail(MC_E_OOM, "mc_server_create: device allocation of the budget failed");
-    }
-    if (solo) S->solo_ws = (char*)S->mem + S->bytes;
-    mc_status r = S->E.init(c, cp, S->mem, S->bytes);
-    if (r != MC_OK) {
+    auto cleanup = [&]() {
+        for (auto& sl : S->slots) {
+            if (sl->ctx) mc_ctx_destroy(sl->ctx);
+            if (sl->stream) (void)hipStreamDestroy(sl->stream);
+        }
         (void)hipFree(S->mem);
-        delete S;
-        return r;
+    };
+    for (int32_t q = 0; q < nslots; q++) {
+        std::unique_ptr<mc_server::Slot> sl(new mc_server::Slot());
+        sl->ws = (char*)S->mem + S->bytes + solo * q;
+        // default priority, non-blocking: it must not wait for work on the
+        // legacy default stream the engine may use
+        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess) {
+            S->slots.push_back(std::move(sl));
+            cleanup();
+            return mc_fail(MC_E_DEVICE, "mc_server_create: stream creation failed");
+        }
+        mc_status r = mc_ctx_create(c->device, sl->stream, &c->opt, &sl->ctx);
+        S->slots.push_back(std::move(sl));
+        if (r != MC_OK) { cleanup(); return r; }
     }
+    mc_status r = S->E.init(c, cp, S->mem, S->bytes);
+    if (r != MC_OK) { cleanup(); return r; }
     S->t0 = std::chrono::steady_clock::now();
-    *out = S;
+    *out = S.release();
     return MC_OK;
 }
 
 extern "C" mc_status mc_server_destroy(mc_server* S) {
     if (!S) return MC_OK;
+    for (auto& sl : S->slots) {
+        if (sl->th.joinable()) sl->th.join();   // a running solve ends first
+        if (sl->ctx) mc_ctx_destroy(sl->ctx);
+        if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    }
     if (S->mem) (void)hipFree(S->mem);
     delete S;
     return MC_OK;
@@ -1143,12 +1388,14 @@ extern "C" mc_status mc_server_destroy(mc_server* S) {
 extern "C" mc_status mc_server_submit(mc_server* S, const mc_csr* g, uint64_t* ticket) {
     if (!S || !g || !ticket) return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: NULL argument");
     if (g->location != MC_HOST) return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: host graphs only");
-    if (g->n < 2 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
-        return mc_fail(MC_E_INVALID_ARG, "mc_server_submit: bad graph");
+    // the request's contents are checked here, so admission never fails on
+    // data
+    mc_status v = check_host_csr(g, S->c->opt.validate != 0);
+    if (v != MC_OK) return v;
     const Caps& cp = S->E.cap;
     if (g->n >= S->solo_min_n) {
         size_t need = 0;
-        if (!S->solo_ws || mc_workspace_size(S->c, g->n, g->nnz, &need) != MC_OK || need > S->solo_bytes)
+        if (S->slots.empty() || mc_workspace_size(S->c, g->n, g->nnz, &need) != MC_OK || need > S->solo_bytes)
             return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
     } else if (g->n > cp.nmax || g->n > cp.Ns || g->nnz > cp.Cs || g->n > cp.N || g->nnz > cp.C) {
         return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
@@ -1171,60 +1418,66 @@ extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* q
     if (!S) return mc_fail(MC_E_INVALID_ARG, "mc_server_step: NULL server");
     Engine& E = S->E;
     mc_status st;
-    auto host_csr = [](const mc_server::Req& r) {
-        mc_csr g;
-        g.n = r.n;
-        g.nnz = r.nnz;
-        g.row_ptr = r.rp.data();
-        g.col = r.col.data();
-        g.w = r.w.data();
-        g.location = MC_HOST;
-        return g;
-    };
-    // a large request at the head of the queue is solved on its own now
-    while (!S->queue.empty() && S->reqs[S->queue.front()].cancel) {
-        S->reqs[S->queue.front()].state = 3;
-        S->queue.pop_front();
+    collect_solo(S);
+    double t = S->now();
+    // requests in the engine that were cancelled or passed their deadline
+    // leave it now
+    for (size_t i = 0; i < E.insts.size(); i++) {
+        const EngineInst x = E.insts[i];
+        if (x.dead || x.done) continue;
+        mc_server::Req& r = S->reqs[x.id];
+        if (!r.cancel && !S->late(r, t)) continue;
+        if ((st = drop_inflight(S, x.id)) != MC_OK) return st;
+        r.state = r.cancel ? 3 : 5;
+        r.st.t_done_ms = t;
     }
-    if (!S->queue.empty() && S->reqs[S->queue.front()].n >= S->solo_min_n) {
-        const uint64_t id = S->queue.front();
-        S->queue.pop_front();
-        mc_server::Req& r = S->reqs[id];
-        r.st.t_admit_ms = S->now();
-        r.side.assign((size_t)r.n, 0);
-        const mc_csr g = host_csr(r);
-        if ((st = mc_mincut(S->c, &g, S->solo_ws, S->solo_bytes, &r.lam, r.side.data(), nullptr)) != MC_OK) return st;
-        r.state = r.cancel ? 3 : 2;
-        r.st.t_done_ms = S->now();
-        r.st.rounds = 0;
-    }
-    // admission in arrival order while the graphs fit
+    // admission in arrival order: large requests to free solo slots, the
+    // others into the engine while they fit (the first that does not fit
+    // stops the engine's admission, so small requests keep their order)
     std::vector<mc_csr> adm;
     std::vector<uint64_t> ids;
+    std::deque<uint64_t> rest;
     int64_t nv = 0, ne = 0;
-    while (!S->queue.empty()) {
-        const uint64_t id = S->queue.front();
+    bool engine_full = false;
+    for (uint64_t id : S->queue) {
         mc_server::Req& r = S->reqs[id];
-        if (r.cancel) { S->queue.pop_front(); r.state = 3; continue; }
-        if (r.n >= S->solo_min_n) break;          // waits for its own step
+        if (r.cancel) { r.state = 3; continue; }
+        if (S->late(r, t)) { r.state = 5; r.st.t_done_ms = t; continue; }
+        if (r.n >= S->solo_min_n) {
+            if (!start_solo(S, id)) rest.push_back(id);
+            continue;
+        }
+        if (engine_full) { rest.push_back(id); continue; }
         if (!E.fits((int32_t)adm.size() + 1, nv + r.n, ne + r.nnz)) {
-            if (adm.empty() && E.live() == 0) {
-                E.compact_n0();
-                if (!E.fits(1, r.n, r.nnz)) return mc_fail(MC_E_OOM, "mc_server_step: request does not fit");
+            if (adm.empty() && E.live() == 0 && E.insts.empty()) {
+                if (!E.compact_n0()) return MC_E_DEVICE;
+                if (!E.fits(1, r.n, r.nnz)) {
+                    fail_req(r, MC_E_OOM, "request does not fit the server's engine", t);
+                    continue;
+                }
             } else {
-                break;
+                engine_full = true;
+                rest.push_back(id);
+                continue;
             }
         }
         adm.push_back(host_csr(r));
         ids.push_back(id);
         nv += r.n;
         ne += r.nnz;
-        S->queue.pop_front();
     }
+    S->queue.swap(rest);
     if (!adm.empty()) {
         const size_t before = E.insts.size();
-        if ((st = E.admit(adm.data(), (int32_t)adm.size(), ids.data())) != MC_OK) return st;
-        const double t = S->now();
+        if ((st = E.admit(adm.data(), (int32_t)adm.size(), ids.data())) != MC_OK) {
+            // each request of the failed admission gets the error as its own
+            // result; the engine keeps the graphs already in flight
+            const std::string why = mc_error_slot();
+            E.insts.resize(before);
+            for (uint64_t id : ids) fail_req(S->reqs[id], st, why, S->now());
+            return mc_fail(st, why);
+        }
+        t = S->now();
         for (uint64_t id : ids) { S->reqs[id].state = 1; S->reqs[id].st.t_admit_ms = t; }
         for (size_t i = before; i < E.insts.size(); i++)
             if (E.insts[i].done) {
@@ -1232,17 +1485,32 @@ extern "C" mc_status mc_server_step(mc_server* S, int32_t* in_flight, int32_t* q
                 E.insts[i].dead = true;
             }
     }
-    if (E.live() > 0) {
+    if (!E.insts.empty()) {
+        // one round; with only finished graphs left it drops them from the
+        // union graph
         std::vector<EngineInst> fin;
-        if ((st = E.step(fin)) != MC_OK) return st;
+        if ((st = E.step(fin)) != MC_OK) {
+            const std::string why = mc_error_slot();
+            for (const EngineInst& x : E.insts)
+                if (!x.dead) fail_req(S->reqs[x.id], st, why, S->now());
+            (void)E.init(S->c, E.cap, S->mem, S->bytes);   // an empty engine for what follows
+            return mc_fail(st, why);
+        }
         for (const EngineInst& x : fin)
             if ((st = finish(S, x)) != MC_OK) return st;
-    } else if (!E.insts.empty()) {
-        // only finished graphs left: one round drops them from the union graph
-        std::vector<EngineInst> fin;
-        if ((st = E.step(fin)) != MC_OK) return st;
+    } else {
+        // nothing on the engine: give a running solo solve a moment instead
+        // of returning at once to a caller that polls in a loop
+        for (auto& sl : S->slots)
+            if (sl->busy.load(std::memory_order_acquire) == 1) {
+                std::this_thread::sleep_for(std::chrono::microseconds(200));
+                break;
+            }
+        collect_solo(S);
     }
-    if (in_flight) *in_flight = E.live();
+    int32_t solo_running = 0;
+    for (auto& sl : S->slots) solo_running += sl->busy.load(std::memory_order_acquire) != 0;
+    if (in_flight) *in_flight = E.live() + solo_running;
     if (queued) *queued = (int32_t)S->queue.size();
     return MC_OK;
 }
@@ -1255,6 +1523,16 @@ extern "C" mc_status mc_server_poll(mc_server* S, uint64_t ticket, int64_t* lamb
     if (r.state == 3) {
         S->reqs.erase(it);
         return mc_fail(MC_E_CANCELLED, "mc_server_poll: request cancelled");
+    }
+    if (r.state == 4) {
+        const mc_status code = r.status;
+        const std::string why = r.err;
+        S->reqs.erase(it);
+        return mc_fail(code, "mc_server_poll: request failed: " + why);
+    }
+    if (r.state == 5) {
+        S->reqs.erase(it);
+        return mc_fail(MC_E_TIMEOUT, "mc_server_poll: request passed its deadline");
     }
     if (r.state != 2) return MC_E_NOT_READY;
     if (lambda) *lambda = r.lam;
@@ -1287,6 +1565,6 @@ extern "C" mc_status mc_server_capacity(const mc_server* S, int64_t* entries, in
     if (entries) *entries = S->E.cap.C;
     if (vertices) *vertices = S->E.cap.N;
     if (graphs) *graphs = S->E.cap.K;
-    if (bytes) *bytes = S->bytes + S->solo_bytes;
+    if (bytes) *bytes = S->bytes + S->solo_bytes * S->slots.size();
     return MC_OK;
 }

@@ -303,7 +303,8 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
                                                     const int32_t* __restrict__ mstart,
                                                     const int32_t* __restrict__ gstart,
                                                     const int32_t* __restrict__ mlist,
-                                                    const int32_t* __restrict__ mcnt, DGraph dst) {
+                                                    const int32_t* __restrict__ mcnt, DGraph dst,
+                                                    unsigned long long* pb) {
     __shared__ int32_t tk[MID_SLOTS];
     __shared__ long long tv[MID_SLOTS];
     __shared__ int32_t wm[MID_MEM + 1];   // group-relative entry offset of each member
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
     __shared__ long long s_deg;
     const int32_t cnt = *mcnt;
     const int tid = threadIdx.x;
+    int64_t bytes = 0;
     for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int32_t g = mlist[i];
         const int32_t m0 = vstart ? vstart[g] : g;
@@ -366,8 +368,14 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
             atomicAdd((unsigned long long*)&s_deg, (unsigned long long)tv[k]);
         }
         __syncthreads();
-        if (tid == 0) { dst.len[g] = s_cnt; dst.deg[g] = s_deg; }
+        if (tid == 0) {
+            dst.len[g] = s_cnt;
+            dst.deg[g] = s_deg;
+            // col, w (and the label of each target) in; col, w out; off, len, deg
+            bytes += (int64_t)s * (L ? 16 : 12) + (int64_t)s_cnt * 12 + 12 * mc;
+        }
     }
+    if (pb) prof_add(pb, bytes);
 }
 
 __global__ void k_big_clear(const int32_t* __restrict__ total_p, int32_t* __restrict__ tkey,
@@ -846,8 +854,11 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
                                                              prof_dev_bytes(PK_MERGE_SMALL));
     MC_LAUNCHED("k_merge_small");
     prof_end(PK_MERGE_SMALL, s);
-    k_mid_merge<<<MID_GRID, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt, dst);
+    prof_begin(PK_MID_MERGE, s);
+    k_mid_merge<<<MID_GRID, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt, dst,
+                                           prof_dev_bytes(PK_MID_MERGE));
     MC_LAUNCHED("k_mid_merge");
+    prof_end(PK_MID_MERGE, s);
     k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);
     MC_LAUNCHED("k_big_clear");
     k_big_tiles<<<grid_for(src.cap / BIG_TILE + 1, 256), 256, 0, s>>>(vstart, ws.mstart, gstart, ws.bigm, n2,

@@ -283,13 +283,16 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
 // remaining test-1 edge would then need a union of its own.
 __global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ first,
                                                   const int32_t* __restrict__ second, int32_t n, int32_t* par,
-                                                  unsigned long long* marks) {
+                                                  unsigned long long* marks, unsigned long long* pb) {
     unsigned long long joined = 0;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = first[v], y = second[v];
         if (x >= 0 && uf_union(par, (int32_t)v, x)) joined++;
         if (y >= 0 && uf_union(par, (int32_t)v, y)) joined++;
+        bytes += 8 + 4 * ((x >= 0) + (y >= 0));   // first, second; the parent word of each union
     }
+    if (pb) prof_add(pb, bytes);
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
     if (lane_id() == 0 && joined) {
         const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
@@ -303,13 +306,17 @@ __global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ f
 __global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                                  const int32_t* __restrict__ heavy_cnt,
                                                  const uint8_t* __restrict__ inbig, const int32_t* __restrict__ snap,
-                                                 unsigned long long* marks) {
+                                                 unsigned long long* marks, unsigned long long* pb) {
     const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     unsigned long long joined = 0;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB; v < g.n; v += nsub) {
+        if (sl == 0) bytes += 5;   // test-1 count and component flag of every row
         if (heavy_cnt[v] <= 2 || inbig[v]) continue;
+        // off, len, snapshot root of the row; col, w, flag and root of each target
+        if (sl == 0) bytes += 12 + 17 * (int64_t)g.len[v];
         const int32_t o = g.off[v], l = g.len[v], rv = snap[v];
         const int64_t lam = vinst ? lamp[vinst[v]] : lam0;
         // as in k_uf_link_rest: edges between different snapshot trees,
@@ -321,6 +328,7 @@ __global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp,
             if (g.w[o + j] >= lam && (x > v || inbig[x]) && snap[x] != rv && uf_union(par, (int32_t)v, x)) joined++;
         }
     }
+    if (pb) prof_add(pb, bytes);
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
     if (lane_id() == 0 && joined) {
         const unsigned slot = (blockIdx.x * (blockDim.x / MC_WAVE) + threadIdx.x / MC_WAVE) % SPREAD;
@@ -780,17 +788,22 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
                                                             prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
-    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, w.second, g.n, parent, w.spread);
+    prof_begin(PK_PR1_FIRST, s);
+    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, w.second, g.n, parent, w.spread,
+                                                  prof_dev_bytes(PK_PR1_FIRST));
     MC_LAUNCHED("k_pr1_first");
+    prof_end(PK_PR1_FIRST, s);
     k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
     MC_LAUNCHED("k_uf_compress");
     k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, w.mode);
     MC_LAUNCHED("k_uf_sample_mode");
     k_uf_snapshot<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, w.mode, w.inbig, w.snap);
     MC_LAUNCHED("k_uf_snapshot");
+    prof_begin(PK_PR1_REST, s);
     k_pr1_rest<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.heavy, w.inbig, w.snap,
-                                                                w.spread);
+                                                                w.spread, prof_dev_bytes(PK_PR1_REST));
     MC_LAUNCHED("k_pr1_rest");
+    prof_end(PK_PR1_REST, s);
     k_pr12_fold<<<1, SPREAD, 0, s>>>(w.spread, marks);
     MC_LAUNCHED("k_pr12_fold");
     k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
                                                   unsigned long long* __restrict__ long_best,
                                                   unsigned long long* __restrict__ long_own,
                                                   int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
-                                                  int32_t* __restrict__ task_idx) {
+                                                  int32_t* __restrict__ task_idx, unsigned long long* pb) {
     __shared__ unsigned long long hkey[LP_HSLOTS];
     __shared__ unsigned long long hval[LP_HSLOTS];
     __shared__ int32_t own[LP_CHUNK];
@@ -158,11 +158,15 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
         if (lbl != own[gl] && hval[i] == best_w[gl]) atomicMin(&best_l[gl], lbl);
     }
     __syncthreads();
+    int64_t bytes = 0;
     for (int i = tid; i < ng; i += LP_T) {
         const int32_t v = g_lo + i;
-        if (g.len[v] > LP_SMALL) continue;
+        const int32_t l = g.len[v];
+        if (l > LP_SMALL) continue;
         lab_out[v] = best_l[i] != INT32_MAX && best_w[i] > own_w[i] ? best_l[i] : own[i];
+        bytes += 16 + 16 * (int64_t)l;   // off, len, own label, new label; col, w, label of each target
     }
+    if (pb) prof_add(pb, bytes);
 }
 
 // Long rows are cut into tasks of LP_TASK entries; task t of row k owns the
@@ -374,9 +378,10 @@ constexpr int LP_FIRST_TASK = 4096;   // entries per piece of a long row
 __global__ __launch_bounds__(256) void k_lp_first(DGraph g, int32_t* __restrict__ lab_out,
                                                  int32_t* __restrict__ long_list, int32_t* __restrict__ long_base,
                                                  int32_t* __restrict__ counters, int32_t* __restrict__ task_row,
-                                                 int32_t* __restrict__ task_idx) {
+                                                 int32_t* __restrict__ task_idx, unsigned long long* pb) {
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / LP_SUB);
     const int sl = threadIdx.x % LP_SUB;
+    int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / LP_SUB) + threadIdx.x / LP_SUB; v < g.n; v += nsub) {
         const int32_t o = g.off[v], l = g.len[v];
         if (l > LP_SMALL) {
@@ -412,8 +417,12 @@ __global__ __launch_bounds__(256) void k_lp_first(DGraph g, int32_t* __restrict_
             const int32_t x2 = __shfl_xor(bx, k, LP_SUB);
             if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
         }
-        if (sl == 0) lab_out[v] = bx != INT32_MAX ? bx : (int32_t)v;
+        if (sl == 0) {
+            lab_out[v] = bx != INT32_MAX ? bx : (int32_t)v;
+            bytes += 12 + 12 * (int64_t)l;   // off, len, label; col and w of each entry
+        }
     }
+    if (pb) prof_add(pb, bytes);
 }
 
 // one workgroup per piece of a long row: the piece's heaviest entry
@@ -521,10 +530,12 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     k_lp_chunks<<<grid_for(nchunks + 1, 256), 256, 0, s>>>(cw.mstart, n, nchunks, w.cg);
     MC_LAUNCHED("k_lp_chunks");
     if (!fill_i32(w.counters, 0, 4, s)) return false;
+    prof_begin(PK_LP_SMALL, s);
     k_lp_small<<<(unsigned)nchunks, LP_T, 0, s>>>(g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base,
                                                   w.counters, w.long_best, w.long_own, w.long_lab, w.task_row,
-                                                  w.task_idx);
+                                                  w.task_idx, prof_dev_bytes(PK_LP_SMALL));
     MC_LAUNCHED("k_lp_small");
+    prof_end(PK_LP_SMALL, s);
     const int tb = 2048;
     k_lp_long_clear<<<tb, LP_T, 0, s>>>(g, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx, cw.tkey,
                                         cw.tval);
@@ -546,9 +557,11 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
 
 bool lp_first(const DGraph& g, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s) {
     if (!fill_i32(w.counters, 0, 4, s)) return false;
+    prof_begin(PK_LP_FIRST, s);
     k_lp_first<<<grid_for((int64_t)g.n * LP_SUB, 256), 256, 0, s>>>(g, lab_out, w.long_list, w.long_base, w.counters,
-                                                                   w.task_row, w.task_idx);
+                                                                   w.task_row, w.task_idx, prof_dev_bytes(PK_LP_FIRST));
     MC_LAUNCHED("k_lp_first");
+    prof_end(PK_LP_FIRST, s);
     // piece partials go to the large-group table arrays (>= 2.5 cap slots,
     // more than the pieces)
     k_lp_first_long<<<2048, 256, 0, s>>>(g, w.long_list, w.counters, w.task_row, w.task_idx, cw.tval, cw.tkey);

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "mc_device.h"
+#include "mc_host.h"
 #include "mincut.h"
 
 // Records the first HIP failure of a call; launchers return false on error.
@@ -24,6 +25,7 @@ bool mc_hip_ok(hipError_t e, const char* what);
 // returns nullptr and the kernels skip the count.
 enum ProfKernel {
     PK_CFS_EDGES = 0, PK_MERGE_SMALL, PK_BIG_INSERT, PK_GROUP_COUNT, PK_GROUP_SCATTER, PK_PR12, PK_UF_LINK_REST,
+    PK_LP_SMALL, PK_LP_FIRST, PK_MID_MERGE, PK_PR1_FIRST, PK_PR1_REST,
     PK_COUNT
 };
 void prof_begin(int k, hipStream_t s);
@@ -356,10 +358,6 @@ bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, i
 // Device-side validation of a user CSR: sets sc->err to an mc_status code.
 bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
                   DevScalars* sc, unsigned long long* part, hipStream_t s);
-
-std::string& mc_error_slot();
-// Sets the thread-local error message and returns code.
-mc_status mc_fail(mc_status code, const std::string& msg);
 
 // The library context (opaque to callers).
 struct mc_ctx {

@@ -26,8 +26,6 @@
 
 namespace {
 
-thread_local std::string g_err;
-
 inline int grid_for(int64_t count, int threads, int cap = 8192) {
     int64_t b = (count + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -56,20 +54,13 @@ uint64_t splitmix_host(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-mc_status fail(mc_status code, const std::string& msg) {
-    g_err = msg;
-    return code;
-}
+mc_status fail(mc_status code, const std::string& msg) { return mc_fail(code, msg); }
 
 }  // namespace
 
-mc_status mc_fail(mc_status code, const std::string& msg) { return fail(code, msg); }
-
-std::string& mc_error_slot() { return g_err; }
-
 bool mc_hip_ok(hipError_t e, const char* what) {
     if (e == hipSuccess) return true;
-    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    mc_error_slot() = std::string(what) + ": " + hipGetErrorString(e);
     return false;
 }
 
@@ -126,8 +117,9 @@ struct Prof {
 thread_local Prof* g_prof = nullptr;   // the profiler of the solve running on this thread
 constexpr size_t kProfCounterBytes = sizeof(unsigned long long) * PK_COUNT * PROF_LANES * PROF_STRIDE;
 
-const char* const kProfNames[PK_COUNT] = {"k_cfs_edges",     "k_merge_small", "k_big_insert",  "k_group_count",
-                                          "k_group_scatter", "k_pr12",        "k_uf_link_rest"};
+const char* const kProfNames[PK_COUNT] = {"k_cfs_edges",    "k_merge_small", "k_big_insert", "k_group_count",
+                                          "k_group_scatter", "k_pr12",       "k_uf_link_rest", "k_lp_small",
+                                          "k_lp_first",     "k_mid_merge",   "k_pr1_first",  "k_pr1_rest"};
 
 // sets g_prof for the duration of one call and resolves its events at the end
 struct ProfScope {
@@ -199,43 +191,12 @@ void prof_round_begin(int32_t kind, int32_t n, int64_t m, hipStream_t s) {
 }
 
 
-extern "C" void mc_default_options(mc_options* o) {
-    std::memset(o, 0, sizeof(*o));
-    o->seed = 1;
-    o->heuristic_min_n = 10000;
-    o->lp_iters = 2;
-    o->pr_tri_deg_cap = 16;
-    o->capforest_passes = 0;
-    o->pass_len_cap = 0;
-    o->capforest_mode = MC_CF_PRIVATE;
-    o->levels_min_n = 0;
-    o->deterministic = 0;
-    o->validate = 0;
-    o->batch_pass_threads = 0;
-    o->batch_lp = 0;
-}
-
-extern "C" const char* mc_last_error(void) { return g_err.c_str(); }
-
-static bool options_ok(const mc_options* o) {
-    const int32_t t = o->batch_pass_threads;
-    if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512 && t != 1024) {
-        fail(MC_E_INVALID_ARG, "options: batch_pass_threads must be 0, 64, 128, 256, 512 or 1024");
-        return false;
-    }
-    if (o->batch_lp < 0 || o->batch_lp > 2) {
-        fail(MC_E_INVALID_ARG, "options: batch_lp must be 0, 1 or 2");
-        return false;
-    }
-    return true;
-}
-
 extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_options* opt, mc_ctx** out) {
     if (!out) return fail(MC_E_INVALID_ARG, "mc_ctx_create: out is NULL");
+    if (opt && mc_options_check(opt) != MC_OK) return MC_E_INVALID_ARG;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return fail(MC_E_DEVICE, "mc_ctx_create: no such HIP device");
-    if (opt && !options_ok(opt)) return MC_E_INVALID_ARG;
     mc_ctx* c = new (std::nothrow) mc_ctx();
     if (!c) return fail(MC_E_OOM, "mc_ctx_create: out of host memory");
     c->device = device;
@@ -334,7 +295,7 @@ extern "C" mc_status mc_profile_round(mc_ctx* c, int32_t i, mc_round_time* out, 
 
 extern "C" mc_status mc_ctx_set_options(mc_ctx* c, const mc_options* opt) {
     if (!c || !opt) return fail(MC_E_INVALID_ARG, "mc_ctx_set_options: NULL argument");
-    if (!options_ok(opt)) return MC_E_INVALID_ARG;
+    if (mc_options_check(opt) != MC_OK) return MC_E_INVALID_ARG;
     c->opt = *opt;
     return MC_OK;
 }
@@ -509,46 +470,6 @@ int32_t private_len_cap(const mc_ctx* c) {
     if (c->opt.pass_len_cap < 0) return 0;
     if (c->opt.pass_len_cap > 0) return c->opt.pass_len_cap;
     return 32768;
-}
-
-// Host-side checks of a host CSR (exact, including symmetry when asked).
-mc_status check_host_csr(const mc_csr* g, bool symmetric) {
-    const int32_t n = g->n, nnz = g->nnz;
-    if (g->row_ptr[0] != 0 || g->row_ptr[n] != nnz) return fail(MC_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
-    for (int32_t v = 0; v < n; v++)
-        if (g->row_ptr[v + 1] < g->row_ptr[v]) return fail(MC_E_BAD_GRAPH, "row_ptr is not non-decreasing");
-    const unsigned long long cap = 1ULL << 62;
-    unsigned long long s = 0;
-    for (int32_t j = 0; j < nnz; j++) {
-        if (g->col[j] < 0 || g->col[j] >= n) return fail(MC_E_BAD_GRAPH, "col out of range");
-        if (g->w[j] < 0) return fail(MC_E_BAD_GRAPH, "negative weight");
-        s += (unsigned long long)g->w[j];
-        if (s >= cap || (unsigned long long)g->w[j] >= cap) return fail(MC_E_OVERFLOW, "total weight must be below 2^62");
-    }
-    if (symmetric) {
-        // fold each row, then every (u,v,s) must have a matching (v,u,s)
-        std::vector<std::pair<int64_t, int64_t>> e;  // key u*n+v -> weight
-        e.reserve((size_t)nnz);
-        for (int32_t u = 0; u < n; u++)
-            for (int32_t j = g->row_ptr[u]; j < g->row_ptr[u + 1]; j++)
-                if (g->col[j] != u) e.push_back({(int64_t)u * n + g->col[j], g->w[j]});
-        std::sort(e.begin(), e.end());
-        std::vector<std::pair<int64_t, int64_t>> f;
-        for (size_t i = 0; i < e.size();) {
-            size_t k = i;
-            int64_t t = 0;
-            while (k < e.size() && e[k].first == e[i].first) t += e[k++].second;
-            f.push_back({e[i].first, t});
-            i = k;
-        }
-        for (auto& p : f) {
-            int64_t u = p.first / n, v = p.first % n;
-            auto it = std::lower_bound(f.begin(), f.end(), std::make_pair(v * n + u, (int64_t)INT64_MIN));
-            if (it == f.end() || it->first != v * n + u || it->second != p.second)
-                return fail(MC_E_BAD_GRAPH, "edge list is not symmetric");
-        }
-    }
-    return MC_OK;
 }
 
 struct Solver {

@@ -50,7 +50,7 @@ def per_kernel(d, counter):
     return out
 
 
-def main(fetch_dir, write_dir, mib, workload="chung_lu", path=None):
+def main(fetch_dir, write_dir, mib, workload="rhg", path=None):
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()]
@@ -71,7 +71,9 @@ def main(fetch_dir, write_dir, mib, workload="chung_lu", path=None):
                   "launches": len(fetch[k]), "source": src,
                   "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()}
     path = path or os.path.join(ROOT, "profiles", "traffic.json")
-    json.dump(res, open(path, "w"), indent=1, sort_keys=True)
+    tab = json.load(open(path)) if os.path.exists(path) else {}
+    tab[workload] = res
+    json.dump(tab, open(path, "w"), indent=1, sort_keys=True)
     print(json.dumps(res, indent=1, sort_keys=True))
     return res
 

@@ -19,6 +19,12 @@ WORKLOADS = {
     "rhg_2^20_core32_seed1": lambda: gen.config_rhg(20, 1),
     "rhg_2^23_core32_seed1": lambda: gen.config_rhg(23, 1),
 }
+# graphs of the served pool (m log-uniform in [1e3, 1e7], weights 1-1000):
+# the three heaviest Erdos-Renyi ones, four with n >= 65536, small ones of
+# each family and mid-size ones
+SERVED_POOL = [13, 145, 178, 66, 22, 248, 150, 147, 226, 131, 211, 104]
+for _j in SERVED_POOL:
+    WORKLOADS["served_pool_%d" % _j] = (lambda j: lambda: gen.config_served_graph(j))(_j)
 
 
 def main(names):

@@ -76,3 +76,17 @@ def test_batch_params_ranges():
         ns.append(n)
     med = np.median(ns)
     assert 800 < med < 5000  # log-uniform over [64, 65536]: median 2048
+
+
+def test_dense_regular_blocks_by_complement():
+    # d close to n - 1: the pairing model gives up and the generator takes
+    # the complement of an (n-1-d)-regular graph; the result is still a
+    # simple d-regular graph
+    for n, d, seed in [(33, 30, 5), (20, 18, 1), (9, 8, 3)]:
+        g = gen.regular(n, d, seed)
+        deg = np.diff(g.row_ptr)
+        assert (deg == d).all(), (n, d, set(deg))
+        assert all(len(set(g.col[g.row_ptr[v]:g.row_ptr[v + 1]])) == d for v in range(n))
+        assert not any(v in g.col[g.row_ptr[v]:g.row_ptr[v + 1]] for v in range(n))
+    g = gen.config_batch_graph(747, 5000)   # halves of 33 vertices, 30-regular
+    assert g.n == 66

@@ -54,7 +54,10 @@ def test_traffic_scales_by_the_copy_and_averages_per_launch(tmp_path):
     src = os.path.join(ROOT, k["source"])
     assert k["source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
     assert "k_other" not in res           # only the timed kernels are kept
-    assert json.load(open(out)) == json.loads(json.dumps(res))
+    assert json.load(open(out)) == {"rhg": json.loads(json.dumps(res))}
+    # a run of another workload adds its own section and keeps this one
+    traffic.main(str(tmp_path / "f"), str(tmp_path / "w"), str(mib), "chung_lu", out)
+    assert set(json.load(open(out))) == {"rhg", "chung_lu"}
 
 
 def test_bench_reports_traffic_only_for_its_workload_and_source():
@@ -62,17 +65,19 @@ def test_bench_reports_traffic_only_for_its_workload_and_source():
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         pytest.skip("no committed traffic summary")
-    tab = json.load(open(path))
-    measured = tab.get("_calibration", {}).get("workload", "chung_lu")
-    others = [w for w in ("chung_lu", "rhg", "batch", "served") if w != measured]
-    for kernel in [k for k in tab if not k.startswith("_")]:
-        for w in others:
-            assert bench.traffic_for(kernel, w) is None
-        rec = tab[kernel]
-        same = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest() == rec["source_sha256"]
-        got = bench.traffic_for(kernel, measured)
-        assert (got == rec["bytes_per_launch"]) if same else got is None
-    assert bench.traffic_for("k_no_such_kernel", measured) is None
+    full = json.load(open(path))
+    for measured, tab in full.items():
+        assert tab["_calibration"]["workload"] == measured
+        others = [w for w in ("chung_lu", "rhg", "batch", "served") if w not in full]
+        for kernel in [k for k in tab if not k.startswith("_")]:
+            for w in others:
+                assert bench.traffic_for(kernel, w) is None
+            rec = tab[kernel]
+            same = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest() == \
+                rec["source_sha256"]
+            got = bench.traffic_for(kernel, measured)
+            assert (got == rec["bytes_per_launch"]) if same else got is None
+        assert bench.traffic_for("k_no_such_kernel", measured) is None
 
 
 def test_bench_refuses_more_than_one_gpu():
