@@ -145,6 +145,21 @@ mc_status mc_workspace_size(const mc_ctx* ctx, int32_t n, int32_t nnz, size_t* b
 mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws_bytes,
                     int64_t* lambda, uint8_t* side, mc_stats* st);
 
+/* mc_mincut without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The call runs
+ * exactly mc_mincut (same options, results and error behaviour) on a
+ * static scratch array of 64 MiB that the library keeps on each GPU until
+ * the process ends (its address is fetched when the first context on the
+ * device is created); it calls no hipMalloc, hipFree or other allocating
+ * routine, and kernel timing (mc_profile) is suspended for the call. Graphs
+ * whose mc_workspace_size exceeds 64 MiB get MC_E_INVALID_ARG before any
+ * device work. Every call on one GPU uses that GPU's one array, which keeps
+ * the last call's contents (the solve initialises all it reads): calls that
+ * overlap on one GPU, from any thread or context, race and must not be
+ * made. */
+mc_status mc_mincut_static(mc_ctx* ctx, const mc_csr* g, int64_t* lambda, uint8_t* side, mc_stats* st);
+
 /* Batched solves: k graphs (all in host memory or all in device memory,
  * together fewer than 2^30 vertices and 2^30 entries) solved in one call,
  * with one set of launches per round of Algorithm 2 for all of them (the

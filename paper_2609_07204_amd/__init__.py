@@ -103,6 +103,7 @@ SIGNATURES = {
     "mc_ctx_set_options": (ctypes.c_int, [P, P]),
     "mc_workspace_size": (ctypes.c_int, [P, I32, I32, P]),
     "mc_mincut": (ctypes.c_int, [P, P, P, SZ, P, P, P]),
+    "mc_mincut_static": (ctypes.c_int, [P, P, P, P, P]),
     "mc_last_error": (ctypes.c_char_p, []),
     "mc_check_graph": (ctypes.c_int, [P, I32]),
     "mc_batch_workspace_size": (ctypes.c_int, [P, I32, P, P]),

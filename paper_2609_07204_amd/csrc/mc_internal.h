@@ -368,4 +368,5 @@ struct mc_ctx {
     DevScalars* hsc = nullptr;   // pinned readback slot
     int32_t tag = 0;             // round tag for visited arrays (never reset)
     void* prof = nullptr;        // kernel timing (mc_profile), owned by the solver file
+    void* scratch = nullptr;     // device address of this GPU's static scratch (mc_mincut_static)
 };

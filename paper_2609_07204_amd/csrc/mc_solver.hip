@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -191,6 +192,42 @@ void prof_round_begin(int32_t kind, int32_t n, int64_t m, hipStream_t s) {
 }
 
 
+// ------------------------------------------ static scratch (no allocation)
+// Workspace of mc_mincut_static: a file-scope device array, one copy on each
+// GPU the library runs on, held until the process ends. In host code its
+// name is only a host-side stand-in, never a device address: the address
+// comes from hipGetSymbolAddress, taken once per device (with that device
+// current) when the first context on the device is created, and only that
+// address is handed to kernels and copies.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's copy (device current); nullptr and
+// the error set on failure
+void* scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) {
+        fail(MC_E_DEVICE, "static scratch: device index out of range");
+        return nullptr;
+    }
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fail(MC_E_DEVICE, std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
 extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_options* opt, mc_ctx** out) {
     if (!out) return fail(MC_E_INVALID_ARG, "mc_ctx_create: out is NULL");
     if (opt && mc_options_check(opt) != MC_OK) return MC_E_INVALID_ARG;
@@ -205,6 +242,8 @@ extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_option
     if (hipSetDevice(device) != hipSuccess) { delete c; return fail(MC_E_DEVICE, "hipSetDevice failed"); }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cus = prop.multiProcessorCount;
+    c->scratch = scratch_address(device);
+    if (!c->scratch) { delete c; return MC_E_DEVICE; }
     if (hipHostMalloc((void**)&c->hsc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(MC_E_DEVICE, "hipHostMalloc failed");
@@ -960,6 +999,25 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         *st = S.stats;
     }
     return MC_OK;
+}
+
+extern "C" mc_status mc_mincut_static(mc_ctx* c, const mc_csr* g, int64_t* lambda, uint8_t* side_out, mc_stats* st) {
+    if (!c || !g || !lambda) return fail(MC_E_INVALID_ARG, "mc_mincut_static: NULL argument");
+    if (!c->scratch) return fail(MC_E_DEVICE, "mc_mincut_static: no static scratch on this device");
+    if (g->n < 2 || g->nnz < 0) return fail(MC_E_INVALID_ARG, "mc_mincut_static: need n >= 2 and nnz >= 0");
+    size_t need = 0;
+    mc_status r = mc_workspace_size(c, g->n, g->nnz, &need);
+    if (r != MC_OK) return r;
+    if (need > kStaticScratchBytes)
+        return fail(MC_E_INVALID_ARG, "mc_mincut_static: the graph needs " + std::to_string(need) +
+                                          " bytes of scratch, more than the static " +
+                                          std::to_string(kStaticScratchBytes) + " (use mc_mincut with a workspace)");
+    // kernel timing is suspended for the call: its event pool could allocate
+    void* prof = c->prof;
+    c->prof = nullptr;
+    r = mc_mincut(c, g, c->scratch, kStaticScratchBytes, lambda, side_out, st);
+    c->prof = prof;
+    return r;
 }
 
 // ------------------------------------------------------------ step ABI

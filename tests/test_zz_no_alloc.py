@@ -1,0 +1,69 @@
+"""mc_mincut_static (no allocation, static scratch) against mc_mincut (caller
+workspace) through the C ABI: the same lambda, valid sides, on two calls in
+a row with the second input smaller, host and device inputs; graphs whose
+scratch would exceed the static array are refused before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def static_solve(ctx, g=None, dev=None):
+    import paper_2609_07204_amd as mc
+    if dev is not None:
+        rp, col, w = dev
+        n, nnz = int(rp.numel() - 1), int(col.numel())
+        csr = mc.CSR(n, nnz, rp.data_ptr(), col.data_ptr(), w.data_ptr(), mc.MC_DEVICE)
+    else:
+        rp = np.ascontiguousarray(g.row_ptr, np.int32)
+        col = np.ascontiguousarray(g.col, np.int32)
+        w = np.ascontiguousarray(g.w, np.int64)
+        n, nnz = int(g.n), int(rp[-1])
+        csr = mc.CSR(n, nnz, rp.ctypes.data, col.ctypes.data, w.ctypes.data, mc.MC_HOST)
+    lam = ctypes.c_int64(-1)
+    side = np.full(n, 7, np.uint8)
+    st = mc.Stats()
+    rc = mc.lib().mc_mincut_static(ctx.h, ctypes.byref(csr), ctypes.byref(lam), side.ctypes.data, ctypes.byref(st))
+    return rc, lam.value, side, st.as_dict()
+
+
+def test_static_scratch_matches_workspace_solves():
+    import paper_2609_07204_amd as mc
+    ctx = mc.Context(0)
+    big = gen.mixed_graph(12000, 10, 2, 11, 1, 100)        # heuristic levels and exact rounds
+    small = gen.planted(300, 420, 8, 3, 1, 9, 5)             # smaller than the first
+    assert small.nnz < big.nnz and small.n < big.n and big.n >= 10000
+    assert ctx.workspace_bytes(big.n, big.nnz) <= 64 << 20
+    for rep in range(2):
+        for g in (big, small):
+            ref, ref_side = ctx.mincut(g)
+            rc, lam, side, st = static_solve(ctx, g)
+            assert rc == 0, mc.lib().mc_last_error()
+            assert lam == ref, (g.name, lam, ref)
+            assert side[0] == 0 and 0 < int(side.sum()) < g.n
+            assert oracle.cut_value(g, side) == lam
+            dev = ctx.upload(g)
+            rc, lam_d, side_d, _ = static_solve(ctx, dev=dev)
+            assert rc == 0 and lam_d == ref and oracle.cut_value(g, side_d) == ref
+    ctx.close()
+
+
+def test_static_scratch_refuses_graphs_beyond_its_size():
+    import paper_2609_07204_amd as mc
+    ctx = mc.Context(0)
+    g = gen.mixed_graph(1 << 19, 24, 1, 3, 1, 100)
+    need = ctx.workspace_bytes(g.n, g.nnz)
+    assert need > 64 << 20
+    rc, lam, side, _ = static_solve(ctx, g)
+    assert rc == -1 and lam == -1 and (side == 7).all()
+    assert b"static" in mc.lib().mc_last_error()
+    # a small solve right after still works
+    h = gen.wheel(30)
+    rc, lam, side, _ = static_solve(ctx, h)
+    assert rc == 0 and lam == oracle.stoer_wagner(h)[0] and oracle.cut_value(h, side) == lam
+    ctx.close()
