@@ -476,8 +476,9 @@ def main():
     log2n = args.log2n or (23 if which == "rhg" else 22)
     context = not args.no_context and which == "rhg" and args.log2n is None
     t = time.time()
-    pool = mp.get_context("fork").Pool(worker_count())
-    # the context graphs are generated in worker processes meanwhile
+    # the context graphs are generated in worker processes meanwhile (no
+    # pool at all without context, so profiler runs see one process)
+    pool = mp.get_context("fork").Pool(worker_count()) if context else None
     cl_job = pool.apply_async(_gen_config, ("chung_lu", 22, args.seed)) if context else None
     batch_job = pool.map_async(_batch_graph, [(i, 1000) for i in range(args.batch_count)], chunksize=8) \
         if context else None
@@ -544,7 +545,7 @@ def main():
         ctxinfo["batch"] = res
         del gs, tune
         torch.cuda.empty_cache()
-    pool.close()
+        pool.close()
 
     if args.calibrate_copy > 0:
         src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device=ctx.device)
