@@ -97,6 +97,16 @@ typedef struct {
     int32_t batch_lp;         /* label-propagation bound at admission in the
                                  batched and served forms: 0 = when
                                  heuristic_min_n > 0, 1 = always, 2 = never */
+    int32_t finish_max_n;     /* current graphs with at most this many
+                                 vertices (<= 1024) finish all their remaining
+                                 rounds in one launch, one workgroup per graph
+                                 (0 = 1024; < 0 = never) */
+    int32_t queue;            /* priority queue of the finisher's CAPFOREST
+                                 passes (Section 2.1 "Bounded priority
+                                 queues"): 0 = buckets while the bound is
+                                 below 2048, else a binary heap; 1 = buckets;
+                                 2 = heap (the largest key, then the
+                                 smallest id, as the sequential pass) */
 } mc_options;
 
 typedef struct {
@@ -116,6 +126,8 @@ typedef struct {
     int32_t input_normal;        /* 1: the input was already a simple graph
                                     with sorted rows and was used in place */
     int64_t marks_tri;           /* of marks_pr: edges unioned by tests 3, 4 */
+    int32_t finish_rounds;       /* of rounds: rounds run inside the finisher
+                                    (one launch for all of them) */
 } mc_stats;
 
 typedef struct mc_ctx mc_ctx;

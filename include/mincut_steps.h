@@ -95,12 +95,18 @@ mc_status mc_step_lp(mc_ctx* ctx, const mc_dgraph* g, const int32_t* lab_in, int
  *  MC_STEP_CF_PRIVATE (2): `passes` passes, one workgroup each, private
  *     visited state in HBM, capped vertices scanned in batches;
  *  MC_STEP_CF_LEVELS (3): the same passes advanced in steps, each step's
- *     edges processed by all compute units.
+ *     edges processed by all compute units;
+ *  MC_STEP_CF_BUCKET (4) / MC_STEP_CF_HEAP (5): one complete pass from
+ *     `start` of the small-graph finisher (n <= 1024), its priority queue
+ *     in LDS (Section 2.1 "Bounded priority queues"): one LIFO bucket per
+ *     attainable key, or a binary heap ordered by the largest key and then
+ *     the smallest id (the order of MC_STEP_CF_SEQUENTIAL).
  * Each pass stops after len_cap scans (0: none). Outputs: canonical labels
  * of the marked edges (labels[n], *n2), the scan order of pass 0 (order[n],
  * *nscan), the smallest alpha over the passes with its prefix length
  * (*best_alpha = INT64_MAX if none), and the bound after pass 0 (*lam_out). */
-enum { MC_STEP_CF_SHARED = 0, MC_STEP_CF_SEQUENTIAL = 1, MC_STEP_CF_PRIVATE = 2, MC_STEP_CF_LEVELS = 3 };
+enum { MC_STEP_CF_SHARED = 0, MC_STEP_CF_SEQUENTIAL = 1, MC_STEP_CF_PRIVATE = 2, MC_STEP_CF_LEVELS = 3,
+       MC_STEP_CF_BUCKET = 4, MC_STEP_CF_HEAP = 5 };
 mc_status mc_step_capforest(mc_ctx* ctx, const mc_dgraph* g, int64_t lam, int32_t start, int32_t mode,
                             int32_t passes, int32_t shared, int32_t len_cap, int32_t* labels, int32_t* n2,
                             int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,

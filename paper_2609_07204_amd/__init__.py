@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("pr_tri_deg_cap", ctypes.c_int32), ("capforest_passes", ctypes.c_int32),
                 ("pass_len_cap", ctypes.c_int32), ("capforest_mode", ctypes.c_int32),
                 ("levels_min_n", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("batch_pass_threads", ctypes.c_int32), ("batch_lp", ctypes.c_int32)]
+                ("batch_pass_threads", ctypes.c_int32), ("batch_lp", ctypes.c_int32),
+                ("finish_max_n", ctypes.c_int32), ("queue", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -47,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("marks_pr", ctypes.c_int64), ("marks_capforest", ctypes.c_int64),
                 ("fallback_passes", ctypes.c_int32), ("n_input", ctypes.c_int32), ("m_input", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("rounds_pr_only", ctypes.c_int32), ("input_normal", ctypes.c_int32),
-                ("marks_tri", ctypes.c_int64)]
+                ("marks_tri", ctypes.c_int64), ("finish_rounds", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

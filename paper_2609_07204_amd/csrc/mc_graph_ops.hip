@@ -848,6 +848,12 @@ bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s) {
     return true;
 }
 
+bool side_from_flag(uint8_t* side, const int32_t* map0, int32_t n0, const uint8_t* flag, hipStream_t s) {
+    k_side_flag<<<grid_for(n0, 256), 256, 0, s>>>(side, map0, n0, flag);
+    MC_LAUNCHED("k_side_flag");
+    return true;
+}
+
 bool side_from_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int32_t* target_dev, hipStream_t s) {
     k_side_vertex<<<grid_for(n0, 256), 256, 0, s>>>(side, map0, n0, target_dev);
     MC_LAUNCHED("k_side_vertex");

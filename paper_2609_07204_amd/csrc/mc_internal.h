@@ -335,6 +335,36 @@ constexpr int HUB_SLOTS = 16;
 
 bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s);
 
+// ------------------------------------------------------------ finisher
+// Device-resident exact rounds for graphs of at most FIN_N vertices: one
+// workgroup per graph runs every remaining round of Algorithm 2 (complete
+// CAPFOREST pass with an LDS bucket queue or heap, union-find, contraction,
+// collapsed-degree bounds) in one launch.
+constexpr int FIN_N = 1024;
+struct FinishArgs {
+    DGraph g;                 // current graph (rows of every graph to finish)
+    const int32_t* gvoff;     // [K+1] vertex ranges of the graphs (nullptr: one graph, all of g)
+    const int32_t* glist;     // [count] ranges to finish (nullptr: 0..count-1)
+    const int64_t* lam_in;    // [K] bound of each range at entry
+    int64_t* lam_out;         // [K] bound at the end: lambda of the graph (may alias lam_in)
+    int32_t* dropped;         // [K] 1 when the finisher lowered the bound
+    uint8_t* fside;           // [g.n] side over the current vertices of dropped graphs
+    int32_t* xcol[2];         // two scratch buffers for the contracted graphs
+    int64_t* xw[2];
+    int32_t xwindow;          // 1: a graph writes the scratch at its own window in g
+                              // (buffers with g's capacity); 0: from position 0
+                              // (buffers of at least FIN_N * (FIN_N - 1) entries,
+                              // or g's entry count if smaller)
+    uint64_t seed;
+    int32_t* rounds;          // [K] rounds taken (may be nullptr)
+    int32_t* err;             // [1] 0, or why a graph could not finish
+    int32_t qmode;            // 0 buckets while lam < 2048 else heap, 1 buckets, 2 heap
+};
+bool finish_graphs(const FinishArgs& a, int32_t count, hipStream_t s);
+// one pass of the finisher's CAPFOREST (step ABI): see k_fin_pass
+bool finish_pass(const DGraph& g, int32_t start, int32_t qmode, int64_t* lam_io, int64_t* best_alpha,
+                 int32_t* parent, int32_t* order, int32_t* nscan, int32_t* best_len, hipStream_t s);
+
 // -------------------------------------------------------- side tracking
 bool map_update(int32_t* map0, const int32_t* L, int32_t n0, hipStream_t s);
 // side[v0] = (map0[v0] == target)
@@ -344,6 +374,8 @@ bool side_from_vertex(uint8_t* side, const int32_t* map0, int32_t n0, const int3
 // has n entries); then side[v0] = flag[map0[v0]]
 bool side_from_prefix(uint8_t* side, const int32_t* map0, int32_t n0, uint8_t* flag, int32_t n,
                       const int32_t* order, const int32_t* len_dev, hipStream_t s);
+// side[v0] = flag[map0[v0]] (every input vertex tracked)
+bool side_from_flag(uint8_t* side, const int32_t* map0, int32_t n0, const uint8_t* flag, hipStream_t s);
 // side[v0] = (root(map0[v0]) != root(0)) over a compressed parent array
 bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipStream_t s);
 

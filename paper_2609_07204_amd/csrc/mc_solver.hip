@@ -379,6 +379,10 @@ struct SolveWS {
     DevScalars* sc = nullptr;
     unsigned long long* vpart = nullptr;
     int32_t* vpart_i32() { return reinterpret_cast<int32_t*>(vpart); }
+    int64_t* fin64 = nullptr;     // [2] finisher: bound in, bound out
+    int32_t* fin32 = nullptr;     // [4] finisher: dropped, rounds, error
+    int32_t* fx_col[2] = {nullptr, nullptr};   // finisher scratch graphs
+    int64_t* fx_w[2] = {nullptr, nullptr};
 };
 
 void carve_graph(Arena& a, int32_t n, int64_t cap, DGraph& g) {
@@ -469,6 +473,15 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     w.calen = a.take<int32_t>(1);
     w.clamout = a.take<int64_t>(1);
     w.vpart = a.take<unsigned long long>(1024);
+    w.fin64 = a.take<int64_t>(2);
+    w.fin32 = a.take<int32_t>(4);
+    // a simple graph of at most FIN_N vertices has at most FIN_N (FIN_N - 1)
+    // entries, and never more than the input
+    const int64_t fx = std::min<int64_t>(cap, (int64_t)FIN_N * (FIN_N - 1)) + 1;
+    for (int q = 0; q < 2; q++) {
+        w.fx_col[q] = a.take<int32_t>((size_t)fx);
+        w.fx_w[q] = a.take<int64_t>((size_t)fx);
+    }
     lp_ws_carve(a, n, cap, w.lw);
     pr34_ws_carve(a, n, w.tw);
     w.lab2 = a.take<int32_t>((size_t)n + 1);
@@ -669,6 +682,51 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     return capforest_reduce(ra, w.sc, S.s);
 }
 
+// vertices at or below which the remaining rounds run in the finisher
+static int32_t finish_max_n(const mc_ctx* c) {
+    if (c->opt.finish_max_n < 0) return 0;
+    return c->opt.finish_max_n > 0 ? std::min(c->opt.finish_max_n, FIN_N) : FIN_N;
+}
+
+// All remaining rounds of a small current graph in one launch (one
+// workgroup): the bound and, if it dropped, the side come back at once.
+static mc_status finish(Solver& S, DGraph* cur, int32_t round) {
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    FinishArgs fa{};
+    fa.g = *cur;
+    fa.gvoff = nullptr;
+    fa.glist = nullptr;
+    fa.lam_in = &w.sc->lam;
+    fa.lam_out = w.fin64;
+    fa.dropped = w.fin32;
+    fa.rounds = w.fin32 + 1;
+    fa.err = w.fin32 + 2;
+    fa.fside = w.flag8;
+    for (int q = 0; q < 2; q++) {
+        fa.xcol[q] = w.fx_col[q];
+        fa.xw[q] = w.fx_w[q];
+    }
+    fa.xwindow = 0;
+    fa.seed = S.c->opt.seed ^ ((uint64_t)(uint32_t)round << 20);
+    fa.qmode = S.c->opt.deterministic ? 2 : S.c->opt.queue;
+    if (!fill_i32(w.fin32, 0, 4, s) || !finish_graphs(fa, 1, s)) return MC_E_DEVICE;
+    int64_t lam_out = 0;
+    int32_t r32[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(&lam_out, w.fin64, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(r32, w.fin32, sizeof(r32), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MC_E_DEVICE, "finisher: readback failed");
+    if (r32[2] != 0) return fail(MC_E_DEVICE, "finisher: a graph could not finish (code " + std::to_string(r32[2]) + ")");
+    if (r32[0] && lam_out < S.lam) {
+        if (!side_from_flag(w.side, w.map0, S.n0, w.flag8, s)) return MC_E_DEVICE;
+        if (!S.set_lam(lam_out)) return MC_E_DEVICE;
+    }
+    S.stats.rounds += r32[1];
+    S.stats.finish_rounds += r32[1];
+    return MC_OK;
+}
+
 // Exact rounds of Algorithm 2 on w.g[src] until at most two vertices remain.
 static mc_status exact_rounds(Solver& S, int src) {
     SolveWS& w = S.w;
@@ -677,6 +735,12 @@ static mc_status exact_rounds(Solver& S, int src) {
     int nxt_idx = src == 1 ? 2 : 1;
     int32_t round = 0;
     while (cur->n > 2) {
+        if (cur->n <= finish_max_n(S.c)) {
+            // a small graph finishes every remaining round in one launch
+            mc_status r = finish(S, cur, round);
+            if (r != MC_OK) return r;
+            break;
+        }
         DGraph* nxt = &w.g[nxt_idx];
         const int32_t n = cur->n;
         prof_round_begin(S.in_heuristic ? 2 : 0, n, S.cur_m, s);
@@ -1193,7 +1257,35 @@ extern "C" mc_status mc_step_capforest(mc_ctx* c, const mc_dgraph* g, int64_t la
                                        int32_t* order, int32_t* nscan, int64_t* best_alpha, int32_t* best_len,
                                        int64_t* lam_out, void* ws, size_t bytes) {
     if (!g || !labels || !order) return fail(MC_E_INVALID_ARG, "mc_step_capforest: NULL argument");
-    if (mode < MC_STEP_CF_SHARED || mode > MC_STEP_CF_LEVELS) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad mode");
+    if (mode < MC_STEP_CF_SHARED || mode > MC_STEP_CF_HEAP) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad mode");
+    if (mode == MC_STEP_CF_BUCKET || mode == MC_STEP_CF_HEAP) {
+        // one pass of the finisher's CAPFOREST, queue in LDS
+        if (g->n > FIN_N) return fail(MC_E_INVALID_ARG, "mc_step_capforest: the LDS-queue pass takes n <= 1024");
+        if (start < 0 || start >= g->n) return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
+        StepWS w;
+        mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
+        if (r != MC_OK) return r;
+        hipStream_t s = c->stream;
+        if (!fill_i64(w.lamout, lam, 1, s)) return MC_E_DEVICE;
+        if (!finish_pass(to_dgraph(g), start, mode == MC_STEP_CF_HEAP ? 2 : 1, w.lamout, w.alpha, w.parent, order,
+                         w.nscan, w.alen, s))
+            return fail(MC_E_DEVICE, "mc_step_capforest: finisher pass launch failed");
+        if (!uf_labels(w.parent, g->n, labels, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
+        int64_t lo[2] = {0, 0};
+        int32_t cnt[2] = {0, 0};
+        if (hipMemcpyAsync(&lo[0], w.lamout, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&lo[1], w.alpha, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&cnt[0], w.nscan, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&cnt[1], w.alen, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return fail(MC_E_DEVICE, "step: readback failed");
+        if ((r = sync_read(c, w)) != MC_OK) return r;
+        if (n2) *n2 = c->hsc->n2;
+        if (nscan) *nscan = cnt[0];
+        if (best_alpha) *best_alpha = lo[1];
+        if (best_len) *best_len = lo[1] == INT64_MAX ? 0 : cnt[1];
+        if (lam_out) *lam_out = lo[0];
+        return MC_OK;
+    }
     if ((mode == MC_STEP_CF_SEQUENTIAL && start < 0) || start >= g->n)
         return fail(MC_E_INVALID_ARG, "mc_step_capforest: bad start");
     if (mode != MC_STEP_CF_SEQUENTIAL && passes < 1) return fail(MC_E_INVALID_ARG, "mc_step_capforest: passes must be >= 1");
