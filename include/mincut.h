@@ -52,7 +52,7 @@ typedef enum {
 } mc_status;
 
 enum { MC_HOST = 0, MC_DEVICE = 1 };
-enum { MC_CF_PRIVATE = 0, MC_CF_SHARED = 1 };
+enum { MC_CF_PRIVATE = 0, MC_CF_SHARED = 1, MC_CF_AUTO = 2 };
 
 typedef struct {
     int32_t n;             /* vertices, >= 2 */
@@ -79,10 +79,20 @@ typedef struct {
                                  (0 = automatic) */
     int32_t pass_len_cap;     /* scans per pass (0 = automatic; < 0 = until
                                  the pass's queue empties) */
-    int32_t capforest_mode;   /* MC_CF_PRIVATE (default): passes with private
-                                 visited state that scan capped vertices in
-                                 batches; MC_CF_SHARED: passes that share one
-                                 visited array (Algorithm 1 as printed) */
+    int32_t capforest_mode;   /* visited-array policy (Section 4, parallel
+                                 session (1)). MC_CF_PRIVATE: passes with
+                                 private visited state that scan capped
+                                 vertices in batches; MC_CF_SHARED: passes
+                                 that share one visited array (Algorithm 1 as
+                                 printed); MC_CF_AUTO (default): on the first
+                                 round of each size regime (at least / below
+                                 levels_min_n vertices) that runs CAPFOREST,
+                                 a short probe of shared passes (one per
+                                 compute unit, 128 pops each) runs first;
+                                 shared passes are kept for the regime if it
+                                 contracts at least one vertex in 1024,
+                                 otherwise private passes run in the same
+                                 round and are kept */
     int32_t levels_min_n;     /* current graphs with at least this many
                                  vertices advance all private passes in
                                  whole-GPU steps; smaller ones run one

@@ -15,7 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmincut.so")
 
 MC_HOST, MC_DEVICE = 0, 1
-MC_CF_PRIVATE, MC_CF_SHARED = 0, 1
+MC_CF_PRIVATE, MC_CF_SHARED, MC_CF_AUTO = 0, 1, 2
 CF_SHARED, CF_SEQUENTIAL, CF_PRIVATE, CF_LEVELS = 0, 1, 2, 3  # step modes
 STATUS = {0: "MC_OK", -1: "MC_E_INVALID_ARG", -2: "MC_E_BAD_GRAPH", -3: "MC_E_OVERFLOW", -4: "MC_E_OOM",
           -5: "MC_E_DEVICE", -6: "MC_E_NOT_READY", -7: "MC_E_CANCELLED", -8: "MC_E_TIMEOUT"}

@@ -76,9 +76,13 @@ __global__ __launch_bounds__(MC_WAVE) void k_capforest_passes(CapforestArgs a) {
     unsigned long long marks = 0;
     int32_t* order = a.order + (int64_t)p * CF_HC;
 
+    int32_t pops = 0;
     for (;;) {
         const int32_t qn = s_qn;
         if (qn == 0 || (a.len_cap > 0 && nscan >= a.len_cap)) break;
+        // a vertex another pass scanned, or whose row no longer fits, is
+        // blacklisted without a scan; pop_cap bounds those pops too
+        if (a.pop_cap > 0 && pops++ >= a.pop_cap) break;
         // pop: largest min(r, lam), then smallest vertex id
         int64_t bk = -1;
         int32_t bv = -1, bq = -1;

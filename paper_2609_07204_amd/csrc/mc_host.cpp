@@ -31,7 +31,7 @@ extern "C" void mc_default_options(mc_options* o) {
     o->pr_tri_deg_cap = 16;
     o->capforest_passes = 0;
     o->pass_len_cap = 0;
-    o->capforest_mode = MC_CF_PRIVATE;
+    o->capforest_mode = MC_CF_AUTO;
     o->levels_min_n = 0;
     o->deterministic = 0;
     o->validate = 0;
@@ -49,8 +49,8 @@ mc_status mc_options_check(const mc_options* o) {
         return mc_fail(MC_E_INVALID_ARG, "options: pr_tri_deg_cap must be in [0, 64]");
     if (o->lp_iters < 0) return mc_fail(MC_E_INVALID_ARG, "options: lp_iters must be >= 0");
     if (o->capforest_passes < 0) return mc_fail(MC_E_INVALID_ARG, "options: capforest_passes must be >= 0");
-    if (o->capforest_mode != MC_CF_PRIVATE && o->capforest_mode != MC_CF_SHARED)
-        return mc_fail(MC_E_INVALID_ARG, "options: capforest_mode must be MC_CF_PRIVATE or MC_CF_SHARED");
+    if (o->capforest_mode != MC_CF_PRIVATE && o->capforest_mode != MC_CF_SHARED && o->capforest_mode != MC_CF_AUTO)
+        return mc_fail(MC_E_INVALID_ARG, "options: capforest_mode must be MC_CF_PRIVATE, MC_CF_SHARED or MC_CF_AUTO");
     if (o->levels_min_n < 0) return mc_fail(MC_E_INVALID_ARG, "options: levels_min_n must be >= 0");
     if (o->deterministic != 0 && o->deterministic != 1)
         return mc_fail(MC_E_INVALID_ARG, "options: deterministic must be 0 or 1");

@@ -204,6 +204,7 @@ struct CapforestArgs {
     int32_t shared;         // 1: passes share the visited array
     int32_t passes;
     int32_t len_cap;        // scans per pass, 0 = unlimited
+    int32_t pop_cap = 0;    // pops per pass, scanned or blacklisted (0 = unlimited)
     uint64_t seed;
     int32_t start;          // >= 0: every pass starts here (parity runs)
     int32_t* order;         // [passes * CF_HC] scanned vertices per pass

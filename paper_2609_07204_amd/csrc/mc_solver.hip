@@ -491,7 +491,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
 
 // passes of the shared-visited-array form (one wavefront each)
 int32_t pass_count(const mc_ctx* c) {
-    if (c->opt.capforest_mode != MC_CF_SHARED) return 1;
+    if (c->opt.capforest_mode == MC_CF_PRIVATE || c->opt.deterministic) return 1;
     int32_t p = c->opt.capforest_passes;
     if (p <= 0) p = 4 * c->cus;
     return p;
@@ -524,10 +524,14 @@ int32_t private_len_cap(const mc_ctx* c) {
     return 32768;
 }
 
+// CAPFOREST form a round ran (whose pass orders hold its best prefix)
+enum { CF_RUN_NONE = 0, CF_RUN_SEQ, CF_RUN_SHARED, CF_RUN_PRIVATE };
+
 struct Solver {
     mc_ctx* c;
     hipStream_t s;
     SolveWS w;
+    int cf_choice[2] = {CF_RUN_NONE, CF_RUN_NONE};   // automatic mode: kept form per size regime
     int32_t n0 = 0;
     int64_t lam = 0;
     bool debug = false;
@@ -564,6 +568,17 @@ struct Solver {
         MC_HIP(hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
         return true;
+    }
+    // After a readback: the best proper-prefix alpha of the form that ran
+    // last, if below the bound, becomes the bound and its prefix the side.
+    bool apply_alpha(int used, int32_t n) {
+        const DevScalars& h = *c->hsc;
+        if (used == CF_RUN_NONE || h.best_pass < 0 || h.best_alpha >= lam) return true;
+        const int32_t* pref = used == CF_RUN_SEQ      ? w.corder
+                              : used == CF_RUN_SHARED ? w.order + (int64_t)h.best_pass * CF_HC
+                                                      : w.pv.order + (int64_t)h.best_pass * w.pv.stride;
+        if (!side_from_prefix(w.side, w.map0, n0, w.flag8, n, pref, &w.sc->best_len, s)) return false;
+        return set_lam(h.best_alpha);
     }
     bool set_lam(int64_t v) {
         lam = v;
@@ -605,6 +620,35 @@ static void debug_round(Solver& S, const DGraph& g, int32_t round, int32_t passe
             round, g.n, (long long)nnz, (long long)S.lam, h.marks_pr, h.marks_cf, passes, (long long)mx[0],
             (long long)mx[1], (long long)mx[2], (long long)sum[3], (long long)mx[3], mx[4] / (double)clk,
             mx[5] / (double)clk, (long long)mx[6], (long long)mx[7]);
+}
+
+// The shared-visited-array passes of Algorithm 1 as printed: many passes,
+// one wavefront each, that blacklist vertices another pass scanned. A probe
+// runs one pass per compute unit of at most 128 pops (scans or blacklistings)
+// each.
+constexpr int32_t kProbeScans = 128;
+static bool shared_passes(Solver& S, const DGraph& g, bool probe) {
+    SolveWS& w = S.w;
+    CapforestArgs ca{};
+    ca.g = g;
+    ca.lam = &w.sc->lam;
+    ca.parent = w.parent;
+    ca.claim = w.claim;
+    ca.tag = ++S.c->tag;
+    ca.shared = 1;
+    ca.passes = probe ? std::min(w.passes, S.c->cus) : w.passes;
+    ca.len_cap = S.c->opt.pass_len_cap > 0 ? S.c->opt.pass_len_cap : 0;
+    if (probe && (ca.len_cap <= 0 || ca.len_cap > kProbeScans)) ca.len_cap = kProbeScans;
+    ca.pop_cap = probe ? kProbeScans : 0;
+    ca.seed = S.c->opt.seed;
+    ca.start = -1;
+    ca.order = w.order;
+    ca.nscan = w.nscan;
+    ca.alpha = w.alpha;
+    ca.alpha_len = w.alen;
+    ca.lam_out = w.lamout;
+    ca.marks = &w.sc->marks_cf;
+    return capforest_passes(ca, S.s) && capforest_reduce(ca, w.sc, S.s);
 }
 
 // One sequential single-pop pass over g (deterministic), results in sc.
@@ -748,53 +792,57 @@ static mc_status exact_rounds(Solver& S, int src) {
         if (!uf_init(w.parent, n, s)) return MC_E_DEVICE;
         if (!S.reduction_tests(*cur)) return MC_E_DEVICE;
         const bool det = S.c->opt.deterministic != 0;
-        const bool shared = S.c->opt.capforest_mode == MC_CF_SHARED && !det;
-        const int32_t* pref_order = nullptr;   // scan order of the pass with the best alpha
         // when the reduction tests alone at least halve the graph, contract
         // now and leave CAPFOREST to the smaller graph of the next round
         // (any set of contractible edges is a valid round)
         if (!S.readback()) return MC_E_DEVICE;
         S.tri_account(n);
         const bool skip_cf = 2 * (int64_t)(S.c->hsc->marks_pr + S.c->hsc->marks_tri) >= n;
+        int used = CF_RUN_NONE;   // the CAPFOREST form whose results the round keeps last
         if (skip_cf) {
             S.stats.rounds_pr_only++;
         } else if (det) {
             if (!sequential_pass(S, *cur, round)) return MC_E_DEVICE;
-        } else if (shared) {
-            CapforestArgs ca{};
-            ca.g = *cur;
-            ca.lam = &w.sc->lam;
-            ca.parent = w.parent;
-            ca.claim = w.claim;
-            ca.tag = ++S.c->tag;
-            ca.shared = 1;
-            ca.passes = w.passes;
-            ca.len_cap = S.c->opt.pass_len_cap > 0 ? S.c->opt.pass_len_cap : 0;
-            ca.seed = S.c->opt.seed;
-            ca.start = -1;
-            ca.order = w.order;
-            ca.nscan = w.nscan;
-            ca.alpha = w.alpha;
-            ca.alpha_len = w.alen;
-            ca.lam_out = w.lamout;
-            ca.marks = &w.sc->marks_cf;
-            if (!capforest_passes(ca, s) || !capforest_reduce(ca, w.sc, s)) return MC_E_DEVICE;
+            used = CF_RUN_SEQ;
         } else {
-            if (!private_passes(S, *cur, round, std::min(w.pv.passes, private_pass_count(S.c, n)), private_len_cap(S.c)))
-                return MC_E_DEVICE;
+            // visited-array policy (Section 4, parallel session (1)): shared
+            // or private visited state, fixed by the options or, in the
+            // automatic mode, chosen on the first round of each size regime
+            // that runs CAPFOREST: a short probe of shared passes (one per
+            // compute unit, 128 pops each) runs first, and shared passes are
+            // kept if it contracts at least one vertex in 1024; otherwise
+            // private passes run in the same round and are kept. The
+            // probe's marks are contracted either way.
+            const int reg = n >= levels_min_n(S.c) ? 0 : 1;
+            int form = S.c->opt.capforest_mode == MC_CF_SHARED ? CF_RUN_SHARED
+                       : S.c->opt.capforest_mode == MC_CF_PRIVATE ? CF_RUN_PRIVATE : S.cf_choice[reg];
+            const bool probe = form == CF_RUN_NONE;
+            if (probe || form == CF_RUN_SHARED) {
+                if (!shared_passes(S, *cur, probe)) return MC_E_DEVICE;
+                used = CF_RUN_SHARED;
+            }
+            if (probe) {
+                if (!S.readback()) return MC_E_DEVICE;
+                const unsigned long long marks_s = S.c->hsc->marks_cf;
+                if (!S.apply_alpha(CF_RUN_SHARED, n)) return MC_E_DEVICE;
+                form = marks_s * 1024 >= (unsigned long long)n ? CF_RUN_SHARED : CF_RUN_PRIVATE;
+                S.cf_choice[reg] = form;
+                if (S.debug)
+                    fprintf(stderr, "[mc] round %d visited-array probe: shared passes marked %llu of n=%d -> %s\n",
+                            round, marks_s, n, form == CF_RUN_SHARED ? "shared" : "private");
+            }
+            if (form == CF_RUN_PRIVATE) {
+                if (!private_passes(S, *cur, round, std::min(w.pv.passes, private_pass_count(S.c, n)),
+                                    private_len_cap(S.c)))
+                    return MC_E_DEVICE;
+                used = CF_RUN_PRIVATE;
+            }
         }
         if (!S.readback()) return MC_E_DEVICE;
+        if (S.debug) debug_round(S, *cur, round, used == CF_RUN_PRIVATE ? std::min(w.pv.passes, private_pass_count(S.c, n)) : 0);
+        if (!S.apply_alpha(used, n)) return MC_E_DEVICE;
+        if (!S.readback()) return MC_E_DEVICE;
         DevScalars h = *S.c->hsc;
-        if (S.debug)
-            debug_round(S, *cur, round, det || shared || skip_cf ? 0 : std::min(w.pv.passes, private_pass_count(S.c, n)));
-        if (h.best_pass >= 0 && h.best_alpha < S.lam) {
-            if (det) pref_order = w.corder;
-            else if (shared) pref_order = w.order + (int64_t)h.best_pass * CF_HC;
-            else pref_order = w.pv.order + (int64_t)h.best_pass * w.pv.stride;
-            if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, pref_order, &w.sc->best_len, s))
-                return MC_E_DEVICE;
-            if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
-        }
         S.stats.marks_pr += (int64_t)(h.marks_pr + h.marks_tri);
         S.stats.marks_capforest += (int64_t)h.marks_cf;
         const unsigned long long marks0 = h.marks_pr + h.marks_tri + h.marks_cf;
@@ -806,7 +854,7 @@ static mc_status exact_rounds(Solver& S, int src) {
         // reaches capped vertices only after many single pops, and a
         // truncated one stops first), so such graphs are not contracted a
         // handful of edges per round.
-        const bool truncated = !det && !shared && !skip_cf && private_len_cap(S.c) > 0;
+        const bool truncated = used == CF_RUN_PRIVATE && private_len_cap(S.c) > 0;
         if (marks0 == 0 || (truncated && marks0 * 1024 < (unsigned long long)n)) {
             const int64_t lam_before = S.lam;
             if (S.debug)
@@ -823,7 +871,7 @@ static mc_status exact_rounds(Solver& S, int src) {
             S.stats.fallback_passes++;
             S.stats.marks_capforest += (int64_t)(h.marks_cf - cf0);
             if (h.best_pass >= 0 && h.best_alpha < S.lam) {
-                pref_order = det ? w.corder : w.pv.order;
+                const int32_t* pref_order = det ? w.corder : w.pv.order;
                 if (!side_from_prefix(w.side, w.map0, S.n0, w.flag8, n, pref_order, &w.sc->best_len, s))
                     return MC_E_DEVICE;
                 if (!S.set_lam(h.best_alpha)) return MC_E_DEVICE;
