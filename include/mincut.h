@@ -88,11 +88,12 @@ typedef struct {
                                  round of each size regime (at least / below
                                  levels_min_n vertices) that runs CAPFOREST,
                                  a short probe of shared passes (one per
-                                 compute unit, 128 pops each) runs first;
-                                 shared passes are kept for the regime if it
-                                 contracts at least one vertex in 1024,
-                                 otherwise private passes run in the same
-                                 round and are kept */
+                                 compute unit, 128 pops each) runs first; if
+                                 it contracts fewer than one vertex in 1024
+                                 private passes are kept, otherwise private
+                                 passes of at most 4096 scans run in the same
+                                 round and the form with more marks per
+                                 millisecond is kept */
     int32_t levels_min_n;     /* current graphs with at least this many
                                  vertices advance all private passes in
                                  whole-GPU steps; smaller ones run one

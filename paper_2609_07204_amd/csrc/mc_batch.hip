@@ -192,9 +192,10 @@ __global__ void k_bg_prefix(const int32_t* order, const int32_t* voff, const int
 }
 
 // snapshot the side of graphs whose bound dropped this round: snap = 1:
-// the vertex darg[i]; snap = 2: the marked prefix
+// the vertex darg[i]; snap = 2: the marked prefix; snap = 3: the cut the
+// finisher found (fside over the current vertices)
 __global__ void k_bg_side(uint8_t* side, const int32_t* map0, const int32_t* inst0, int32_t N0, const uint8_t* snap,
-                          const int32_t* darg, const uint8_t* inpref) {
+                          const int32_t* darg, const uint8_t* inpref, const uint8_t* fside) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N0; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t m = map0[v];
         if (m < 0) continue;                      // input vertex no longer tracked
@@ -202,6 +203,15 @@ __global__ void k_bg_side(uint8_t* side, const int32_t* map0, const int32_t* ins
         const uint8_t s = snap[i];
         if (s == 1) side[v] = m == darg[i];
         else if (s == 2) side[v] = inpref[m];
+        else if (s == 3) side[v] = fside[m];      // the finisher's best cut
+    }
+}
+
+// graphs the finisher completed with a lower bound take its cut as side
+__global__ void k_bg_fin_snap(const int32_t* flist, int32_t cnt, const int32_t* fdrop, uint8_t* snap) {
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+        const int32_t i = flist[q];
+        if (fdrop[i]) snap[i] = 3;
     }
 }
 
@@ -398,6 +408,8 @@ struct EngineWS {
     PrivateArgs pv;
     unsigned long long* pmarks;
     unsigned long long* vpart;
+    int32_t *flist, *fdrop, *frounds, *ferr;   // finisher: graphs, lowered bound, rounds, error
+    uint8_t* fside;           // [N] the finisher's side over the current vertices
 };
 
 void carve_engine(Arena& a, const Caps& cp, EngineWS& w) {
@@ -477,6 +489,11 @@ void carve_engine(Arena& a, const Caps& cp, EngineWS& w) {
     pv.lam_out = a.take<int64_t>((size_t)K);
     w.pmarks = a.take<unsigned long long>((size_t)K);
     w.vpart = a.take<unsigned long long>(1024);
+    w.flist = a.take<int32_t>((size_t)K + 1);
+    w.fdrop = a.take<int32_t>((size_t)K + 1);
+    w.frounds = a.take<int32_t>((size_t)K + 1);
+    w.ferr = a.take<int32_t>(4);
+    w.fside = a.take<uint8_t>((size_t)N + 1);
 }
 
 #define EG_HIP(x) do { if ((x) != hipSuccess) return mc_fail(MC_E_DEVICE, #x); } while (0)
@@ -651,7 +668,7 @@ struct Engine {
         k_bg_vinst<<<grid_for(NS, 256), 256, 0, s>>>(w.s_voff, k, NS, w.inst0 + n0_used);
         EG_OK(mc_hip_ok(hipGetLastError(), "admit bounds"));
         k_bg_side<<<grid_for(NS, 256), 256, 0, s>>>(w.side + n0_used, w.map0 + n0_used, w.inst0 + n0_used, NS, w.snap,
-                                                    w.darg, w.inpref);
+                                                    w.darg, w.inpref, w.fside);
         k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
         if (lp) {
             k_eg_apply_heuristic<<<grid_for(k, 256), 256, 0, s>>>(w.best, k, w.lam, w.h_hit);
@@ -791,12 +808,22 @@ struct Engine {
         std::vector<int32_t> vo(k + 1), io(k + 1);
         std::vector<int64_t> lam(k);
         std::vector<uint8_t> done(k), dead(k);
+        // graphs of at most finish_max_n vertices finish every remaining
+        // round in the finisher (one workgroup each, before this round's
+        // launches); they take no part in the round and leave the union
+        // graph in its contraction
+        const int32_t fmax = c->opt.finish_max_n < 0 ? 0
+                             : (c->opt.finish_max_n > 0 ? std::min(c->opt.finish_max_n, FIN_N) : FIN_N);
+        std::vector<int32_t> flist;
         for (int32_t i = 0; i < k; i++) {
             vo[i] = insts[i].voff;
             io[i] = insts[i].ioff;
             lam[i] = insts[i].lam;
-            done[i] = insts[i].done || insts[i].dead;
-            dead[i] = insts[i].dead;
+            const bool fin = !insts[i].done && !insts[i].dead && insts[i].nv > 2 && insts[i].nv <= fmax &&
+                             insts[i].lam > 0;
+            if (fin) flist.push_back(i);
+            done[i] = insts[i].done || insts[i].dead || fin;
+            dead[i] = insts[i].dead || fin;
         }
         vo[k] = n;
         io[k] = n0_used;
@@ -811,6 +838,31 @@ struct Engine {
         k_bg_vinst<<<grid_for(n, 256), 256, 0, s>>>(w.voff, k, n, w.vinst);
         k_bg_vinst<<<grid_for(n0_used, 256), 256, 0, s>>>(w.ioff, k, n0_used, w.inst0);
         EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_vinst"));
+        const int32_t nf = (int32_t)flist.size();
+        if (nf > 0) {
+            EG_HIP(hipMemcpyAsync(w.flist, flist.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s));
+            EG_OK(fill_i32(w.ferr, 0, 1, s));
+            FinishArgs fa{};
+            fa.g = G;
+            fa.gvoff = w.voff;
+            fa.glist = w.flist;
+            fa.lam_in = w.lam;
+            fa.lam_out = w.lam;
+            fa.dropped = w.fdrop;
+            fa.fside = w.fside;
+            fa.xcol[0] = w.g[(cur + 1) % 3].col;
+            fa.xw[0] = w.g[(cur + 1) % 3].w;
+            fa.xcol[1] = w.g[(cur + 2) % 3].col;
+            fa.xw[1] = w.g[(cur + 2) % 3].w;
+            fa.xwindow = 1;
+            fa.seed = c->opt.seed ^ ((uint64_t)(uint32_t)round << 20);
+            fa.rounds = w.frounds;
+            fa.err = w.ferr;
+            fa.qmode = c->opt.queue;
+            EG_OK(finish_graphs(fa, nf, s));
+            k_bg_fin_snap<<<grid_for(nf, 256), 256, 0, s>>>(w.flist, nf, w.fdrop, w.snap);
+            EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_fin_snap"));
+        }
         EG_OK(uf_init(w.parent, n, s));
         // reduction tests with each graph's own bound
         EG_OK(pr12(G, w.lam, w.parent, &w.sc->marks_pr, nullptr, tri_on ? w.tw.ptr2 : nullptr, w.prw, s, w.vinst));
@@ -867,7 +919,8 @@ struct Engine {
         EG_OK(map_update(w.map0, w.L, n0_used, s));
         k_bg_segmin<<<std::min(k, 8192), 256, 0, s>>>(Nx.deg, w.voff2, k, w.dmin, w.darg);
         k_bg_bound<<<grid_for(k, 256), 256, 0, s>>>(w.voff2, w.dmin, k, w.lam, w.done, w.snap, w.cnt);
-        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref);
+        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref,
+                                                          w.fside);
         EG_OK(mc_hip_ok(hipGetLastError(), "bound"));
         // new ranges, bounds and states; the entries in use of the new graph
         std::vector<int32_t> v2(k + 1);
@@ -876,11 +929,31 @@ struct Engine {
         EG_HIP(hipMemcpyAsync(done.data(), w.done, k, hipMemcpyDeviceToHost, s));
         int32_t total = 0;
         EG_HIP(hipMemcpyAsync(&total, w.cw.gstart + n2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        std::vector<int32_t> frounds(k, 0);
+        int32_t ferr = 0;
+        if (nf > 0) {
+            EG_HIP(hipMemcpyAsync(frounds.data(), w.frounds, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+            EG_HIP(hipMemcpyAsync(&ferr, w.ferr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        }
         EG_HIP(hipStreamSynchronize(s));
+        if (ferr != 0) return mc_fail(MC_E_DEVICE, "engine: a graph could not finish (code " + std::to_string(ferr) + ")");
+        std::vector<uint8_t> finished_now(k, 0);
+        for (int32_t i : flist) finished_now[i] = 1;
         std::vector<EngineInst> keep;
         keep.reserve(k);
         for (int32_t i = 0; i < k; i++) {
             EngineInst x = insts[i];
+            if (finished_now[i]) {
+                // the finisher completed it: its bound is lambda, its side is
+                // in place; its vertices left in this contraction
+                x.lam = lam[i];
+                x.rounds += 1 + frounds[i];
+                x.done = true;
+                x.dead = true;
+                x.nv = 0;
+                finished.push_back(x);
+                continue;
+            }
             if (x.dead) continue;                 // left the union graph in this contraction
             x.voff = v2[i];
             x.nv = v2[i + 1] - v2[i];
@@ -918,7 +991,8 @@ struct Engine {
     // sides of graphs whose bound dropped to a pass's prefix this round
     bool prefix_sides(const PrivateArgs& pa, int32_t k) {
         k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, w.voff, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 1);
-        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref);
+        k_bg_side<<<grid_for(n0_used, 256), 256, 0, s>>>(w.side, w.map0, w.inst0, n0_used, w.snap, w.darg, w.inpref,
+                                                          w.fside);
         k_bg_prefix<<<grid_for(n, 256), 256, 0, s>>>(pa.order, w.voff, w.vinst, pa.alpha_len, w.snap, n, w.inpref, 0);
         k_bg_clear_snap<<<grid_for(k, 256), 256, 0, s>>>(w.snap, k);
         return mc_hip_ok(hipGetLastError(), "prefix sides");

@@ -627,6 +627,7 @@ static void debug_round(Solver& S, const DGraph& g, int32_t round, int32_t passe
 // runs one pass per compute unit of at most 128 pops (scans or blacklistings)
 // each.
 constexpr int32_t kProbeScans = 128;
+constexpr int32_t kProbePrivate = 4096;   // scans per private pass in a probe round
 static bool shared_passes(Solver& S, const DGraph& g, bool probe) {
     SolveWS& w = S.w;
     CapforestArgs ca{};
@@ -808,33 +809,52 @@ static mc_status exact_rounds(Solver& S, int src) {
             // visited-array policy (Section 4, parallel session (1)): shared
             // or private visited state, fixed by the options or, in the
             // automatic mode, chosen on the first round of each size regime
-            // that runs CAPFOREST: a short probe of shared passes (one per
-            // compute unit, 128 pops each) runs first, and shared passes are
-            // kept if it contracts at least one vertex in 1024; otherwise
-            // private passes run in the same round and are kept. The
-            // probe's marks are contracted either way.
+            // that runs CAPFOREST. A short probe of shared passes (one per
+            // compute unit, 128 pops each) runs first: if it contracts fewer
+            // than one vertex in 1024, private passes are kept; otherwise a
+            // private run of at most kProbePrivate scans per pass follows in
+            // the same round, and the form with more marks per millisecond
+            // is kept. Every mark of both runs is contracted.
             const int reg = n >= levels_min_n(S.c) ? 0 : 1;
             int form = S.c->opt.capforest_mode == MC_CF_SHARED ? CF_RUN_SHARED
                        : S.c->opt.capforest_mode == MC_CF_PRIVATE ? CF_RUN_PRIVATE : S.cf_choice[reg];
-            const bool probe = form == CF_RUN_NONE;
-            if (probe || form == CF_RUN_SHARED) {
-                if (!shared_passes(S, *cur, probe)) return MC_E_DEVICE;
-                used = CF_RUN_SHARED;
-            }
-            if (probe) {
-                if (!S.readback()) return MC_E_DEVICE;
+            const int32_t npriv = std::min(w.pv.passes, private_pass_count(S.c, n));
+            bool private_done = false;
+            if (form == CF_RUN_NONE) {
+                using clk = std::chrono::steady_clock;
+                const auto t0 = clk::now();
+                if (!shared_passes(S, *cur, true) || !S.readback()) return MC_E_DEVICE;
+                const double ms_s = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
                 const unsigned long long marks_s = S.c->hsc->marks_cf;
                 if (!S.apply_alpha(CF_RUN_SHARED, n)) return MC_E_DEVICE;
-                form = marks_s * 1024 >= (unsigned long long)n ? CF_RUN_SHARED : CF_RUN_PRIVATE;
+                used = CF_RUN_SHARED;
+                form = CF_RUN_PRIVATE;
+                double ms_p = 0;
+                unsigned long long marks_p = 0;
+                if (marks_s * 1024 >= (unsigned long long)n) {
+                    const int32_t cap = private_len_cap(S.c);
+                    const auto t1 = clk::now();
+                    if (!private_passes(S, *cur, round, npriv, cap > 0 && cap < kProbePrivate ? cap : kProbePrivate) ||
+                        !S.readback())
+                        return MC_E_DEVICE;
+                    ms_p = std::chrono::duration<double, std::milli>(clk::now() - t1).count();
+                    marks_p = S.c->hsc->marks_cf - marks_s;
+                    used = CF_RUN_PRIVATE;
+                    private_done = true;
+                    if ((double)marks_s * ms_p > (double)marks_p * ms_s) form = CF_RUN_SHARED;
+                }
                 S.cf_choice[reg] = form;
                 if (S.debug)
-                    fprintf(stderr, "[mc] round %d visited-array probe: shared passes marked %llu of n=%d -> %s\n",
-                            round, marks_s, n, form == CF_RUN_SHARED ? "shared" : "private");
+                    fprintf(stderr,
+                            "[mc] round %d visited-array probe: shared %llu marks in %.3f ms, private %llu in %.3f ms, "
+                            "n=%d -> %s\n",
+                            round, marks_s, ms_s, marks_p, ms_p, n, form == CF_RUN_SHARED ? "shared" : "private");
+            } else if (form == CF_RUN_SHARED) {
+                if (!shared_passes(S, *cur, false)) return MC_E_DEVICE;
+                used = CF_RUN_SHARED;
             }
-            if (form == CF_RUN_PRIVATE) {
-                if (!private_passes(S, *cur, round, std::min(w.pv.passes, private_pass_count(S.c, n)),
-                                    private_len_cap(S.c)))
-                    return MC_E_DEVICE;
+            if (form == CF_RUN_PRIVATE && !private_done) {
+                if (!private_passes(S, *cur, round, npriv, private_len_cap(S.c))) return MC_E_DEVICE;
                 used = CF_RUN_PRIVATE;
             }
         }
