@@ -904,6 +904,15 @@ static mc_status exact_rounds(Solver& S, int src) {
         if (!uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s)) return MC_E_DEVICE;
         if (!S.readback()) return MC_E_DEVICE;
         const int32_t n2 = S.c->hsc->n2;
+        if (n2 == 1) {
+            // everything joins one vertex: the solve ends with this round
+            // and no later bound needs the contracted graph or the map
+            prof_round_end(1, 0, s);
+            S.cur_m = 0;
+            round++;
+            cur->n = 1;
+            break;
+        }
         if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s)) return MC_E_DEVICE;
         if (!map_update(w.map0, w.L, S.n0, s)) return MC_E_DEVICE;
         if (!S.readback()) return MC_E_DEVICE;
@@ -918,7 +927,7 @@ static mc_status exact_rounds(Solver& S, int src) {
         cur = nxt;
         round++;
     }
-    prof_round_end(cur->n, S.cur_m, s);   // a round that ended without contraction
+    if (cur->n > 1) prof_round_end(cur->n, S.cur_m, s);   // a round that ended without contraction
     S.stats.rounds += round;
     return MC_OK;
 }

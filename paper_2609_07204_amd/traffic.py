@@ -18,20 +18,22 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 
-KERNEL_SOURCE = {
-    "k_cfs_edges": "paper_2609_07204_amd/csrc/mc_capforest_steps.hip",
-    "k_merge_small": "paper_2609_07204_amd/csrc/mc_contract.hip",
-    "k_big_insert": "paper_2609_07204_amd/csrc/mc_contract.hip",
-    "k_group_count": "paper_2609_07204_amd/csrc/mc_contract.hip",
-    "k_group_scatter": "paper_2609_07204_amd/csrc/mc_contract.hip",
-    "k_pr12": "paper_2609_07204_amd/csrc/mc_graph_ops.hip",
-    "k_uf_link_rest": "paper_2609_07204_amd/csrc/mc_graph_ops.hip",
-}
+def kernel_sources():
+    """{kernel name: source file relative to the repository root} for every
+    __global__ function under csrc/."""
+    out = {}
+    d = os.path.join(PKG, "csrc")
+    for f in sorted(glob.glob(os.path.join(d, "*.hip"))):
+        rel = os.path.relpath(f, ROOT)
+        for m in re.finditer(r"__global__\s+(?:__launch_bounds__\([^)]*\)\s+)?void\s+(k_\w+)\s*\(", open(f).read()):
+            out.setdefault(m.group(1), rel)
+    return out
 
 
 def per_kernel(d, counter):
@@ -62,7 +64,7 @@ def main(fetch_dir, write_dir, mib, workload="rhg", path=None):
     f_write = nbytes / max(write.get(ck, [0.0]) or [1.0])
     res = {"_calibration": {"copy_kernel": ck, "copy_bytes": nbytes, "fetch_factor": f_fetch,
                             "write_factor": f_write, "workload": workload}}
-    for k, src in KERNEL_SOURCE.items():
+    for k, src in kernel_sources().items():
         if k not in fetch or k not in write:
             continue
         fb = sum(fetch[k]) / len(fetch[k]) * f_fetch
