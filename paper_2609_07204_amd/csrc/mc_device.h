@@ -137,6 +137,12 @@ __device__ __forceinline__ void wave_argmin(int64_t& val, int32_t& id) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (MC_WAVE - 1); }
 
+// order and visibility of LDS accesses between the lanes of one wavefront
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ------------------------------------------------- profiling counters
 // Algorithmic-byte counters of the profiled kernels: PROF_LANES counters per
 // kernel, 128 B apart, so the once-per-wave adds of a large launch spread

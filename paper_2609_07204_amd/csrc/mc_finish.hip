@@ -65,12 +65,6 @@ struct FinLds {
     int32_t n2;
 };
 
-// order and visibility of LDS accesses between the lanes of one wavefront
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // ------------------------------------------------------------ union-find
 __device__ __forceinline__ int32_t lf_find(int32_t* par, int32_t x) {
     int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);

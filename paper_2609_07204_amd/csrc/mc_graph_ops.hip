@@ -20,6 +20,10 @@ inline int grid_for(int64_t count, int threads, int cap = 8192) {
 }
 
 constexpr int SUB = 16;  // lanes per row for row-wise kernels
+// test-1 trees that the byte-label linking handles (k_pr1_trees) and
+// the words of its tree-pair bit matrix
+constexpr int PR1_TREES = 255;
+constexpr int PR1_WORDS = 256 * 256 / 32;
 
 __global__ void k_uf_init(int32_t* par, int32_t n) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -102,7 +106,9 @@ __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int
 
 // After a compress: snap[v] = v's root, inbig[v] = 1 iff that root is the
 // root of the largest sampled component.
-__global__ void k_uf_snapshot(const int32_t* par, int32_t n, const int32_t* mode, uint8_t* inbig, int32_t* snap) {
+__global__ void k_uf_snapshot(const int32_t* par, int32_t n, const int32_t* mode, uint8_t* inbig, int32_t* snap,
+                              const int32_t* ntree = nullptr) {
+    if (ntree && *ntree <= PR1_TREES) return;   // the trees are linked by k_pr1_trees
     const int32_t big = *mode;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = par[v];
@@ -277,20 +283,35 @@ __global__ __launch_bounds__(256) void k_pr12(DGraph g, const int64_t* lamp, con
     if (pb) prof_add(pb, bytes);
 }
 
-// each row's first two test-1 neighbours (marks go to the partial
-// counters). Two per row, not one: on geometric graphs the first neighbours
-// alone leave many small trees and no large component, and almost every
-// remaining test-1 edge would then need a union of its own.
-__global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ first,
-                                                  const int32_t* __restrict__ second, int32_t n, int32_t* par,
+// Joins u and v as Afforest's link does: climb from their parents and
+// hang the larger root under the smaller with a CAS. Finds write nothing
+// here (a compress pass follows), so many threads climbing one tree do not
+// contend on its nodes. True if this call joined two trees.
+__device__ __forceinline__ bool uf_link(int32_t* par, int32_t u, int32_t v) {
+    int32_t p1 = ld_acq(&par[u]), p2 = ld_acq(&par[v]);
+    while (p1 != p2) {
+        const int32_t high = p1 > p2 ? p1 : p2, low = p1 + p2 - high;
+        const int32_t ph = ld_acq(&par[high]);
+        if (ph == low) return false;
+        if (ph == high && atomicCAS(&par[high], high, low) == high) return true;
+        p1 = ld_acq(&par[ph]);
+        p2 = ld_acq(&par[low]);
+    }
+    return false;
+}
+
+// each row's first (round 0) or second (round 1) test-1 neighbour, with a
+// compress between the rounds (marks go to the partial counters). Two per
+// row, not one: on geometric graphs the first neighbours alone leave many
+// small trees, and the linking of the trees then has far more to do.
+__global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ nb, int32_t n, int32_t* par,
                                                   unsigned long long* marks, unsigned long long* pb) {
     unsigned long long joined = 0;
     int64_t bytes = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t x = first[v], y = second[v];
-        if (x >= 0 && uf_union(par, (int32_t)v, x)) joined++;
-        if (y >= 0 && uf_union(par, (int32_t)v, y)) joined++;
-        bytes += 8 + 4 * ((x >= 0) + (y >= 0));   // first, second; the parent word of each union
+        const int32_t x = nb[v];
+        if (x >= 0 && uf_link(par, (int32_t)v, x)) joined++;
+        bytes += 4 + 4 * (x >= 0);   // the neighbour; the parent word of the union
     }
     if (pb) prof_add(pb, bytes);
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
@@ -300,13 +321,154 @@ __global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ f
     }
 }
 
+// Linking the test-1 trees through a small tree graph. On geometric graphs
+// the first two unions of every row leave a few hundred trees of similar
+// size and no giant one (hyperbolic n = 2^23 at bound 2: 135 trees, the
+// largest with 3 % of the vertices), so skipping the rows of the sampled
+// tree saves nothing and every remaining test-1 entry would gather a 32-bit
+// root from a 6.6 MB array and try a union. When at most PR1_TREES trees
+// remain, each vertex instead gets its tree's number in one byte (1.6 MB,
+// which stays in L2), the entries between two trees only set a bit of a
+// 256 x 256 matrix, and one workgroup joins the trees along the set bits
+// and repoints every vertex at its component's root.
+
+// tree number of every vertex (trees numbered by root, so in the order of
+// their smallest vertex) and the root of every tree; tscan holds the
+// exclusive prefix count of the roots
+__global__ void k_tree_label(const int32_t* __restrict__ par, const int32_t* __restrict__ tscan, int32_t n,
+                             uint8_t* lab8, int32_t* troot) {
+    if (tscan[n] > PR1_TREES) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = par[v];
+        lab8[v] = (uint8_t)tscan[r];
+        if (r == v) troot[tscan[v]] = (int32_t)v;
+    }
+}
+
+// the test-1 entries of rows with more than two of them (a row with at
+// most two was joined by k_pr1_first) that join two trees, from the
+// smaller endpoint or from outside into the sampled tree, as bits (a < b).
+// As in k_pr12, 16 lanes take 16 consecutive rows, whose metadata comes in
+// one load, and each lane keeps four entries and their trees in flight.
+__global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp, const int32_t* vinst,
+                                                  const int32_t* __restrict__ heavy_cnt,
+                                                  const uint8_t* __restrict__ lab8,
+                                                  const int32_t* __restrict__ tscan, const int32_t* mode,
+                                                  uint32_t* bits, unsigned long long* pb) {
+    if (tscan[g.n] > PR1_TREES) return;
+    __shared__ uint32_t sb[PR1_WORDS];
+    for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x) sb[i] = 0;
+    __syncthreads();
+    const int32_t big = tscan[*mode];
+    const int64_t lam0 = *lamp;
+    const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
+    const int sl = threadIdx.x % SUB;
+    int64_t bytes = 0;
+    for (int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB) * SUB; v0 < g.n;
+         v0 += nsub * SUB) {
+        const int32_t rows = g.n - v0 < SUB ? (int32_t)(g.n - v0) : SUB;
+        const int32_t mv = (int32_t)v0 + sl;
+        int32_t my_o = 0, my_l = 0, my_lv = 0;
+        int64_t my_lam = lam0;
+        if (sl < rows) {
+            my_lv = lab8[mv];
+            if (heavy_cnt[mv] > 2 && my_lv != big) {
+                my_o = g.off[mv];
+                my_l = g.len[mv];
+                if (vinst) my_lam = lamp[vinst[mv]];   // bound of the row's instance
+            }
+        }
+        if (sl == 0) bytes += 5 * (int64_t)rows;   // test-1 count and tree of every row
+        for (int32_t r = 0; r < rows; r++) {
+            const int32_t l = __shfl(my_l, r, SUB);
+            if (l == 0) continue;
+            const int32_t o = __shfl(my_o, r, SUB), lv = __shfl(my_lv, r, SUB);
+            const int64_t lam = __shfl(my_lam, r, SUB);
+            const int32_t v = (int32_t)v0 + r;
+            if (sl == 0) bytes += 8 + 13 * (int64_t)l;   // off, len; col, w and tree of each target
+            for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
+                int32_t x[4], lx[4];
+                int64_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t j = j0 + u * SUB + sl;
+                    x[u] = j < l ? g.col[o + j] : -1;
+                    c[u] = j < l ? g.w[o + j] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) lx[u] = x[u] >= 0 && c[u] >= lam ? lab8[x[u]] : lv;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (lx[u] == lv || (x[u] < v && lx[u] != big)) continue;
+                    const int32_t a = lv < lx[u] ? lv : lx[u], b = lv < lx[u] ? lx[u] : lv;
+                    const int32_t bit = a * 256 + b;
+                    atomicOr(&sb[bit >> 5], 1u << (bit & 31));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x)
+        if (sb[i]) atomicOr(&bits[i], sb[i]);
+    if (pb) prof_add(pb, bytes);
+}
+
+// one workgroup: components of the tree graph (union-find on the tree
+// numbers, the smaller number as root, joined by one thread from the bit
+// matrix in LDS), then the root vertex of each tree's component; counts the
+// joins as marks
+__global__ __launch_bounds__(256) void k_tree_join(const int32_t* __restrict__ tscan, int32_t n,
+                                                  const uint32_t* __restrict__ bits, const int32_t* __restrict__ troot,
+                                                  int32_t* tmap, unsigned long long* marks) {
+    const int32_t T = tscan[n];
+    if (T > PR1_TREES) return;
+    __shared__ uint32_t sb[PR1_WORDS];
+    __shared__ int32_t tp[256];
+    for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x) sb[i] = bits[i];
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) tp[t] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long joined = 0;
+        for (int i = 0; i < PR1_WORDS; i++) {
+            for (uint32_t m = sb[i]; m; m &= m - 1) {
+                const int bit = i * 32 + __ffs(m) - 1;
+                int32_t x = bit >> 8, y = bit & 255;
+                while (tp[x] != x) { tp[x] = tp[tp[x]]; x = tp[x]; }
+                while (tp[y] != y) { tp[y] = tp[tp[y]]; y = tp[y]; }
+                if (x == y) continue;
+                if (x < y) tp[y] = x; else tp[x] = y;
+                joined++;
+            }
+        }
+        if (joined) atomicAdd(marks, joined);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        int32_t x = t;
+        while (tp[x] != x) x = tp[x];
+        tmap[t] = troot[x];
+    }
+}
+
+// every vertex points at the root of its tree's component
+__global__ void k_tree_apply(const int32_t* __restrict__ tscan, const uint8_t* __restrict__ lab8,
+                             const int32_t* __restrict__ tmap, int32_t n, int32_t* par) {
+    if (tscan[n] > PR1_TREES) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = tmap[lab8[v]];
+        if (par[v] != r) par[v] = r;
+    }
+}
+
 // rows with more than two test-1 entries, outside the sampled
 // component: union all of them (an edge into that component from a row
 // inside it is seen from this side)
 __global__ __launch_bounds__(256) void k_pr1_rest(DGraph g, const int64_t* lamp, const int32_t* vinst, int32_t* par,
                                                  const int32_t* __restrict__ heavy_cnt,
                                                  const uint8_t* __restrict__ inbig, const int32_t* __restrict__ snap,
-                                                 unsigned long long* marks, unsigned long long* pb) {
+                                                 const int32_t* ntree, unsigned long long* marks,
+                                                 unsigned long long* pb) {
+    if (*ntree <= PR1_TREES) return;   // the trees are linked by k_pr1_trees
     const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
@@ -492,14 +654,14 @@ __global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, c
         const bool live = v0 < g.n && g.len[v] <= D && g.len[v] > 0;
         const int32_t o = live ? g.off[v] : 0, l = live ? g.len[v] : 0;
         for (int k = sl; k < TRI_SLOTS; k += TRI_SUB) K[k] = -1;
-        __syncwarp();
+        wave_sync();
         for (int32_t j = sl; j < l; j += TRI_SUB) {
             const int32_t x = g.col[o + j];
             uint32_t h = hash32((uint32_t)x) & (TRI_SLOTS - 1);
             while (atomicCAS(&K[h], -1, x) != -1) h = (h + 1) & (TRI_SLOTS - 1);
             W[h] = g.w[o + j];
         }
-        __syncwarp();
+        wave_sync();
         const int64_t cv = live ? g.deg[v] : 0;
         const int64_t lam = live && vinst ? lamp[vinst[v]] : lam0;   // bound of v's instance
         for (int32_t j = 0; j < l; j++) {
@@ -544,7 +706,7 @@ __global__ __launch_bounds__(TRI_T) void k_pr34(DGraph g, const int64_t* lamp, c
                 }
             }
         }
-        __syncwarp();
+        wave_sync();
     }
     joined = (unsigned long long)wave_sum_i64((int64_t)joined);
     if (lane_id() == 0 && joined) {
@@ -601,10 +763,13 @@ __global__ void k_side_flag(uint8_t* side, const int32_t* map0, int32_t n0, cons
         side[v] = flag[map0[v]];
 }
 
-__global__ void k_side_comp(uint8_t* side, const int32_t* par, int32_t n0) {
-    const int32_t r0 = par[0];
+// side[v] = 1 iff input vertex v lies outside the component of vertex 0;
+// map (may be null: the identity) takes input vertices to the vertices of
+// the graph whose compressed forest par is
+__global__ void k_side_comp(uint8_t* side, const int32_t* par, const int32_t* map, int32_t n0) {
+    const int32_t r0 = par[map ? map[0] : 0];
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n0; v += (int64_t)gridDim.x * blockDim.x)
-        side[v] = par[v] != r0;
+        side[v] = par[map ? map[v] : (int32_t)v] != r0;
 }
 
 __global__ void k_csr_to_padded(const int32_t* rp, int32_t n, int32_t* off, int32_t* len) {
@@ -776,6 +941,11 @@ void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w) {
     w.mode = a.take<int32_t>(4);
     w.inbig = a.take<uint8_t>((size_t)n + 1);
     w.snap = a.take<int32_t>((size_t)n + 1);
+    w.tscan = a.take<int32_t>((size_t)n + 1);
+    w.scan_tmp = a.take<int32_t>(scan_tmp_elems((int64_t)n) + 1);
+    w.tbits = a.take<uint32_t>(PR1_WORDS);
+    w.troot = a.take<int32_t>(256);
+    w.tmap = a.take<int32_t>(256);
 }
 
 bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long long* marks, uint8_t* flag1,
@@ -788,22 +958,42 @@ bool pr12(const DGraph& g, const int64_t* lam, int32_t* parent, unsigned long lo
                                                             prof_dev_bytes(PK_PR12));
     MC_LAUNCHED("k_pr12");
     prof_end(PK_PR12, s);
-    prof_begin(PK_PR1_FIRST, s);
-    k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(w.first, w.second, g.n, parent, w.spread,
-                                                  prof_dev_bytes(PK_PR1_FIRST));
-    MC_LAUNCHED("k_pr1_first");
-    prof_end(PK_PR1_FIRST, s);
-    k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
-    MC_LAUNCHED("k_uf_compress");
+    for (int round = 0; round < 2; round++) {
+        prof_begin(PK_PR1_FIRST, s);
+        k_pr1_first<<<grid_for(g.n, 256), 256, 0, s>>>(round ? w.second : w.first, g.n, parent, w.spread,
+                                                      prof_dev_bytes(PK_PR1_FIRST));
+        MC_LAUNCHED("k_pr1_first");
+        prof_end(PK_PR1_FIRST, s);
+        k_uf_compress<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n);
+        MC_LAUNCHED("k_uf_compress");
+    }
+    // trees numbered by root: with at most PR1_TREES of them the byte-label
+    // path links them (k_pr1_trees ... k_tree_apply), otherwise the
+    // snapshot path (k_uf_snapshot, k_pr1_rest); each kernel of the path
+    // not taken returns at once
+    k_root_flag<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, w.tscan);
+    MC_LAUNCHED("k_root_flag");
+    if (!scan_i32(w.tscan, w.tscan, g.n, w.scan_tmp, s)) return false;
+    if (!fill_i32((int32_t*)w.tbits, 0, PR1_WORDS, s)) return false;
     k_uf_sample_mode<<<1, 1024, 0, s>>>(parent, g.n, w.mode);
     MC_LAUNCHED("k_uf_sample_mode");
-    k_uf_snapshot<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, w.mode, w.inbig, w.snap);
+    k_tree_label<<<grid_for(g.n, 256), 256, 0, s>>>(parent, w.tscan, g.n, w.inbig, w.troot);
+    MC_LAUNCHED("k_tree_label");
+    k_uf_snapshot<<<grid_for(g.n, 256), 256, 0, s>>>(parent, g.n, w.mode, w.inbig, w.snap, w.tscan + g.n);
     MC_LAUNCHED("k_uf_snapshot");
     prof_begin(PK_PR1_REST, s);
+    k_pr1_trees<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, w.heavy, w.inbig, w.tscan, w.mode,
+                                                                 w.tbits, prof_dev_bytes(PK_PR1_REST));
+    MC_LAUNCHED("k_pr1_trees");
     k_pr1_rest<<<grid_for((int64_t)g.n * SUB, 256), 256, 0, s>>>(g, lam, vinst, parent, w.heavy, w.inbig, w.snap,
-                                                                w.spread, prof_dev_bytes(PK_PR1_REST));
+                                                                w.tscan + g.n, w.spread,
+                                                                prof_dev_bytes(PK_PR1_REST));
     MC_LAUNCHED("k_pr1_rest");
     prof_end(PK_PR1_REST, s);
+    k_tree_join<<<1, 256, 0, s>>>(w.tscan, g.n, w.tbits, w.troot, w.tmap, marks);
+    MC_LAUNCHED("k_tree_join");
+    k_tree_apply<<<grid_for(g.n, 256), 256, 0, s>>>(w.tscan, w.inbig, w.tmap, g.n, parent);
+    MC_LAUNCHED("k_tree_apply");
     k_pr12_fold<<<1, SPREAD, 0, s>>>(w.spread, marks);
     MC_LAUNCHED("k_pr12_fold");
     k_pr12_long_scan<<<1, 1024, 0, s>>>(g, w.long_list, w.counters, w.task_off);
@@ -870,8 +1060,8 @@ bool side_from_prefix(uint8_t* side, const int32_t* map0, int32_t n0, uint8_t* f
     return true;
 }
 
-bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipStream_t s) {
-    k_side_comp<<<grid_for(n0, 256), 256, 0, s>>>(side, parent, n0);
+bool side_from_components(uint8_t* side, const int32_t* parent, const int32_t* map, int32_t n0, hipStream_t s) {
+    k_side_comp<<<grid_for(n0, 256), 256, 0, s>>>(side, parent, map, n0);
     MC_LAUNCHED("k_side_comp");
     return true;
 }

@@ -144,6 +144,11 @@ struct Pr12WS {
     int32_t* mode;        // [1] root of the largest sampled component
     uint8_t* inbig;       // [n] 1 for the vertices of that component
     int32_t* snap;        // [n] root of every vertex after the first two unions of each row
+    int32_t* tscan;       // [n + 1] exclusive prefix count of the roots (tree numbers; [n] = trees)
+    int32_t* scan_tmp;    // scratch of the prefix count
+    uint32_t* tbits;      // [256 * 256 / 32] pairs of trees joined by a test-1 entry
+    int32_t* troot;       // [256] root vertex of each tree
+    int32_t* tmap;        // [256] root vertex of each tree's component
 };
 void pr12_ws_carve(Arena& a, int32_t n, int64_t cap, Pr12WS& w);
 // With vinst (per-vertex instance) the bound of vertex v is lam[vinst[v]]
@@ -378,7 +383,7 @@ bool side_from_prefix(uint8_t* side, const int32_t* map0, int32_t n0, uint8_t* f
 // side[v0] = flag[map0[v0]] (every input vertex tracked)
 bool side_from_flag(uint8_t* side, const int32_t* map0, int32_t n0, const uint8_t* flag, hipStream_t s);
 // side[v0] = (root(map0[v0]) != root(0)) over a compressed parent array
-bool side_from_components(uint8_t* side, const int32_t* parent, int32_t n0, hipStream_t s);
+bool side_from_components(uint8_t* side, const int32_t* parent, const int32_t* map, int32_t n0, hipStream_t s);
 
 // ------------------------------------------------------- input handling
 // Turn a user CSR (row_ptr) into padded form (off = row_ptr, len = diff).

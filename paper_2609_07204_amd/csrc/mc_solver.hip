@@ -537,6 +537,8 @@ struct Solver {
     bool debug = false;
     bool tri_on = false;          // reduction tests 3 and 4 still pay off
     bool in_heuristic = false;    // exact rounds on the heuristic's coarse graph
+    bool conn_pending = false;    // connectivity not decided yet (the heuristic's coarse graph decides it)
+    bool disconnected = false;    // lambda = 0; the side is set
     int64_t cur_m = 0;            // entries of the current graph
     int32_t last_cf_steps = 0;    // whole-GPU steps of the round's last CAPFOREST launch
     int64_t last_cf_scans = 0;    // and the vertices it scanned
@@ -935,6 +937,26 @@ static mc_status exact_rounds(Solver& S, int src) {
 // Contract cur by labels L (n2 groups) into g[*nxt_idx]; the collapsed
 // degrees of the result bound lambda (Section 2.1 "Overall algorithm"; only
 // while at least two vertices remain). Returns the new current graph.
+// lambda = 0 iff the input is disconnected. g is the input or a contraction
+// of it that merged vertices of one component only (map0 takes input
+// vertices to g's vertices): such a contraction keeps every component
+// connected and joins no two, so g has exactly the input's components. On a
+// disconnected input the side becomes the complement of vertex 0's
+// component.
+static bool check_connected(Solver& S, const DGraph& g) {
+    SolveWS& w = S.w;
+    hipStream_t s = S.s;
+    if (!uf_init(w.parent, g.n, s) || !uf_connectivity(g, w.parent, w.vpart_i32(), w.flag8, w.L, s) ||
+        !uf_labels(w.parent, g.n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
+        return false;
+    S.conn_pending = false;
+    if (S.c->hsc->n2 > 1) {
+        S.disconnected = true;
+        if (!side_from_components(w.side, w.parent, &g == &w.g[0] ? nullptr : w.map0, S.n0, s)) return false;
+    }
+    return true;
+}
+
 static DGraph* contract_and_bound(Solver& S, DGraph* cur, int32_t n2, int* nxt_idx, mc_status* err) {
     SolveWS& w = S.w;
     hipStream_t s = S.s;
@@ -1006,6 +1028,15 @@ static mc_status heuristic(Solver& S) {
         prof_round_end(cur->n, S.cur_m, s);
     }
     prof_round_end(cur->n, S.cur_m, s);   // a level that stopped before contracting
+    // Every contraction above merged vertices inside a label cluster or
+    // along an edge. A label is the id of a vertex joined to its holder by a
+    // path (labels only move along edges), so a cluster lies inside one
+    // component: the coarse graph has the input's components, and deciding
+    // connectivity there costs next to nothing.
+    if (S.conn_pending) {
+        if (!check_connected(S, *cur)) return MC_E_DEVICE;
+        if (S.disconnected) return MC_OK;
+    }
     if (cur == &w.g[0]) return MC_OK;   // nothing coarsened: the exact rounds start from the min degree
     if (cur->n > 2) {
         S.in_heuristic = true;
@@ -1098,32 +1129,42 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     S.stats.input_normal = c->hsc->noncanon == 0;
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
     if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
-    // connectivity: lambda = 0 iff the positive-weight graph is disconnected
-    if (!uf_init(w.parent, n, s) || !uf_connectivity(w.g[0], w.parent, w.vpart_i32(), w.flag8, w.L, s) ||
-        !uf_labels(w.parent, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback())
+    // connectivity: lambda = 0 iff the positive-weight graph is disconnected.
+    // When the heuristic runs, its coarse graph has the same components and
+    // decides it at a fraction of the cost (a vertex of degree 0 decides it
+    // here).
+    const bool run_heuristic = c->opt.heuristic_min_n > 0 && n >= c->opt.heuristic_min_n;
+    if (!S.readback()) return MC_E_DEVICE;
+    if (run_heuristic && c->hsc->dmin > 0) {
+        S.conn_pending = true;
+    } else if (!check_connected(S, w.g[0])) {
         return MC_E_DEVICE;
+    }
     DevScalars h = *c->hsc;
     S.stats.n_input = n;
     const int64_t m_input = h.m2;   // entries of the normalised input (read by min_degree)
     S.cur_m = m_input;
     int64_t result = 0;
-    if (h.n2 > 1) {
-        if (!side_from_components(w.side, w.parent, n, s)) return MC_E_DEVICE;
-        result = 0;
+    if (S.disconnected) {
+        result = 0;   // check_connected set the side
     } else {
         // minimum degree is the first bound; its vertex is the first side
         if (!side_from_vertex(w.side, w.map0, n, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
         if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
         S.stats.lambda_min_degree = h.dmin;
         mc_status r = MC_OK;
-        if (c->opt.heuristic_min_n > 0 && n >= c->opt.heuristic_min_n) {
+        if (run_heuristic) {
             if ((r = heuristic(S)) != MC_OK) return r;
             // the exact rounds start again from the normalised input
             if (!iota_i32(w.map0, n, s)) return MC_E_DEVICE;
             S.cur_m = m_input;
         }
-        if ((r = exact_rounds(S, 0)) != MC_OK) return r;
-        result = S.lam;
+        if (S.disconnected) {
+            result = 0;
+        } else {
+            if ((r = exact_rounds(S, 0)) != MC_OK) return r;
+            result = S.lam;
+        }
     }
     if (side_out) {
         if (hipMemcpyAsync(side_out, w.side, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -167,6 +167,39 @@ def test_pr12(ctx, seed):
     g = gen.erdos_renyi(3000, 6 / 2999, seed, 1, 40, lcc=True) if seed % 2 else \
         gen.chung_lu(5000, 2.5, 8.0, seed, 1, 30, lcc=True)
     lam = int(oracle.degrees(g).min()) + seed * 3
+    check_pr12(ctx, g, lam)
+
+
+def _cycles(k, length=4, weight=5):
+    """k disjoint cycles of `length` vertices, each joined into one tree by
+    the first two unions of its rows."""
+    base = np.arange(k)[:, None] * length
+    u = (base + np.arange(length)).ravel()
+    v = (base + (np.arange(length) + 1) % length).ravel()
+    return gen.from_edges(k * length, u, v, np.full(u.size, weight), "cycles%d" % k)
+
+
+# The test-1 trees left by the first two unions of every row are linked
+# through byte labels and a bit matrix of tree pairs when there are at most
+# 255 of them, else through root snapshots: both sides of that limit, a
+# geometric graph whose few dozen trees share many test-1 entries, and a
+# power-law graph with hundreds of trees.
+@pytest.mark.parametrize("case,lam", [("rhg", 2), ("rhg", 30), ("cycles255", 2), ("cycles256", 2),
+                                      ("cl", 20), ("rhg_many", 2)])
+def test_pr12_tree_linking(ctx, case, lam):
+    say("pr12 tree linking", case, lam)
+    if case == "rhg":
+        g = gen.rhg(20000, 16, 3.0, 5, 1, 100, kcore=0, lcc=True)
+    elif case == "rhg_many":
+        g = gen.rhg(60000, 12, 3.0, 8, 1, 100, kcore=0, lcc=False)
+    elif case.startswith("cycles"):
+        g = _cycles(int(case[6:]))
+    else:
+        g = gen.chung_lu(5000, 2.5, 8.0, 0, 1, 30, lcc=True)
+    check_pr12(ctx, g, lam)
+
+
+def check_pr12(ctx, g, lam):
     dev, _, _ = canon_dev(ctx, g)
     flag, ptr, lab, n2 = ctx.step_pr12(dev, lam)
     oflag, optr = oracle.pr12(g, lam)
@@ -286,6 +319,38 @@ def test_disconnected_side_is_component_of_zero(ctx):
     g = gen.disjoint_union(gen.cycle([2, 2, 2, 2]), gen.complete(3))
     lam, side = ctx.mincut(g)
     assert lam == 0 and list(side) == [0, 0, 0, 0, 1, 1, 1]
+
+
+def _component_side(g):
+    """side[v] = 1 iff v lies outside the component of vertex 0 (scipy)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    _, comp = connected_components(sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n)))
+    return (comp != comp[0]).astype(np.uint8)
+
+
+@pytest.mark.parametrize("case", ["two_large", "large_and_triangle", "isolated_vertex", "many_small"])
+def test_disconnected_large_with_heuristic(ctx, case):
+    # graphs above the heuristic's size threshold: connectivity is then
+    # decided on the first coarse graph (or at once for a vertex of degree 0)
+    big = gen.chung_lu(30000, 2.5, 12.0, 77, 1, 50, kcore=3, lcc=True)
+    if case == "two_large":
+        g = gen.disjoint_union(big, gen.erdos_renyi(12000, 10 / 11999, 78, 1, 50, lcc=True))
+    elif case == "large_and_triangle":
+        g = gen.disjoint_union(big, gen.complete(3, weight=5))
+    elif case == "isolated_vertex":
+        g = gen.disjoint_union(big, gen.complete(1))
+    else:
+        g = big
+        for k in range(40):
+            g = gen.disjoint_union(g, gen.cycle([1 + (k + i) % 7 for i in range(5 + k % 9)]))
+    for seed in (3, 4):
+        h = gen.permute(g, seed)[0]
+        say("disconnected with heuristic", case, h.n, seed)
+        assert h.n >= 10000
+        ref = _component_side(h)
+        for lam, side in (ctx.mincut(h), ctx.mincut(dev=ctx.upload(h))):
+            assert lam == 0 and np.array_equal(side, ref)
 
 
 @pytest.mark.parametrize("seed", range(120))
