@@ -101,7 +101,10 @@ __global__ __launch_bounds__(1024) void k_uf_sample_mode(const int32_t* par, int
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *mode = bestr[0];
+    if (threadIdx.x == 0) {
+        mode[0] = bestr[0];
+        mode[1] = bestc[0];   // samples (of 1024) in that component
+    }
 }
 
 // After a compress: snap[v] = v's root, inbig[v] = 1 iff that root is the
@@ -330,14 +333,21 @@ __global__ __launch_bounds__(256) void k_pr1_first(const int32_t* __restrict__ n
 // remain, each vertex instead gets its tree's number in one byte (1.6 MB,
 // which stays in L2), the entries between two trees only set a bit of a
 // 256 x 256 matrix, and one workgroup joins the trees along the set bits
-// and repoints every vertex at its component's root.
+// and repoints every vertex at its component's root. When the tree most
+// sampled vertices fall into holds at least half of them, its rows are
+// skipped (an edge into it is seen from the other side); otherwise every
+// edge is looked at once, from its smaller endpoint, and only there are
+// its weight and the target's tree loaded. (Sampling the first entries of
+// each row, or the longest rows, before the full pass joins little on
+// these graphs: the trees are angular sectors, and the entries between
+// them are few and spread over all rows.)
 
 // tree number of every vertex (trees numbered by root, so in the order of
 // their smallest vertex) and the root of every tree; tscan holds the
 // exclusive prefix count of the roots
 __global__ void k_tree_label(const int32_t* __restrict__ par, const int32_t* __restrict__ tscan, int32_t n,
                              uint8_t* lab8, int32_t* troot) {
-    if (tscan[n] > PR1_TREES) return;
+    if (tscan[n] <= 1 || tscan[n] > PR1_TREES) return;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = par[v];
         lab8[v] = (uint8_t)tscan[r];
@@ -346,8 +356,8 @@ __global__ void k_tree_label(const int32_t* __restrict__ par, const int32_t* __r
 }
 
 // the test-1 entries of rows with more than two of them (a row with at
-// most two was joined by k_pr1_first) that join two trees, from the
-// smaller endpoint or from outside into the sampled tree, as bits (a < b).
+// most two was joined by k_pr1_first) that join two trees, as bits (a < b),
+// from the smaller endpoint or from outside into the sampled tree.
 // As in k_pr12, 16 lanes take 16 consecutive rows, whose metadata comes in
 // one load, and each lane keeps four entries and their trees in flight.
 __global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp, const int32_t* vinst,
@@ -355,11 +365,14 @@ __global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp
                                                   const uint8_t* __restrict__ lab8,
                                                   const int32_t* __restrict__ tscan, const int32_t* mode,
                                                   uint32_t* bits, unsigned long long* pb) {
-    if (tscan[g.n] > PR1_TREES) return;
+    if (tscan[g.n] <= 1 || tscan[g.n] > PR1_TREES) return;
     __shared__ uint32_t sb[PR1_WORDS];
     for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x) sb[i] = 0;
     __syncthreads();
-    const int32_t big = tscan[*mode];
+    // the sampled tree's rows are skipped only when it holds at least half
+    // of the samples; else big = -1 and every edge is taken from its
+    // smaller endpoint
+    const int32_t big = 2 * mode[1] >= 1024 ? tscan[mode[0]] : -1;
     const int64_t lam0 = *lamp;
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp
             const int32_t o = __shfl(my_o, r, SUB), lv = __shfl(my_lv, r, SUB);
             const int64_t lam = __shfl(my_lam, r, SUB);
             const int32_t v = (int32_t)v0 + r;
-            if (sl == 0) bytes += 8 + 13 * (int64_t)l;   // off, len; col, w and tree of each target
+            if (sl == 0) bytes += 8 + 4 * (int64_t)l;   // off, len; col of each entry
             for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
                 int32_t x[4], lx[4];
                 int64_t c[4];
@@ -393,10 +406,17 @@ __global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp
                 for (int u = 0; u < 4; u++) {
                     const int32_t j = j0 + u * SUB + sl;
                     x[u] = j < l ? g.col[o + j] : -1;
-                    c[u] = j < l ? g.w[o + j] : -1;
+                }
+                // without a skipped tree only x > v is needed: the weight
+                // and the target's tree are loaded for those alone
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const bool want = x[u] >= 0 && (big >= 0 || x[u] > v);
+                    c[u] = want ? g.w[o + j0 + u * SUB + sl] : -1;
+                    bytes += want ? 9 : 0;   // w and the target's tree
                 }
 #pragma unroll
-                for (int u = 0; u < 4; u++) lx[u] = x[u] >= 0 && c[u] >= lam ? lab8[x[u]] : lv;
+                for (int u = 0; u < 4; u++) lx[u] = c[u] >= lam ? lab8[x[u]] : lv;
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     if (lx[u] == lv || (x[u] < v && lx[u] != big)) continue;
@@ -413,47 +433,51 @@ __global__ __launch_bounds__(256) void k_pr1_trees(DGraph g, const int64_t* lamp
     if (pb) prof_add(pb, bytes);
 }
 
-// one workgroup: components of the tree graph (union-find on the tree
-// numbers, the smaller number as root, joined by one thread from the bit
-// matrix in LDS), then the root vertex of each tree's component; counts the
-// joins as marks
+// one workgroup: components of the tree graph by a lock-free union-find
+// on the tree numbers in LDS (the smaller number as root), one thread per
+// word of the bit matrix; then the root vertex of each tree's component.
+// Counts the joins as marks.
+__device__ __forceinline__ int32_t lds_ld(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __global__ __launch_bounds__(256) void k_tree_join(const int32_t* __restrict__ tscan, int32_t n,
                                                   const uint32_t* __restrict__ bits, const int32_t* __restrict__ troot,
                                                   int32_t* tmap, unsigned long long* marks) {
     const int32_t T = tscan[n];
-    if (T > PR1_TREES) return;
-    __shared__ uint32_t sb[PR1_WORDS];
+    if (T <= 1 || T > PR1_TREES) return;
     __shared__ int32_t tp[256];
-    for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x) sb[i] = bits[i];
+    __shared__ unsigned long long sj;
     for (int t = threadIdx.x; t < 256; t += blockDim.x) tp[t] = t;
+    if (threadIdx.x == 0) sj = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long joined = 0;
-        for (int i = 0; i < PR1_WORDS; i++) {
-            for (uint32_t m = sb[i]; m; m &= m - 1) {
-                const int bit = i * 32 + __ffs(m) - 1;
-                int32_t x = bit >> 8, y = bit & 255;
-                while (tp[x] != x) { tp[x] = tp[tp[x]]; x = tp[x]; }
-                while (tp[y] != y) { tp[y] = tp[tp[y]]; y = tp[y]; }
-                if (x == y) continue;
-                if (x < y) tp[y] = x; else tp[x] = y;
-                joined++;
+    unsigned long long joined = 0;
+    for (int i = threadIdx.x; i < PR1_WORDS; i += blockDim.x) {
+        for (uint32_t m = bits[i]; m; m &= m - 1) {
+            const int bit = i * 32 + __ffs(m) - 1;
+            int32_t x = bit >> 8, y = bit & 255;
+            for (;;) {
+                for (int32_t p = lds_ld(&tp[x]); p != x; p = lds_ld(&tp[x])) x = p;
+                for (int32_t p = lds_ld(&tp[y]); p != y; p = lds_ld(&tp[y])) y = p;
+                if (x == y) break;
+                if (x > y) { const int32_t t = x; x = y; y = t; }
+                if (atomicCAS(&tp[y], y, x) == y) { joined++; break; }
             }
         }
-        if (joined) atomicAdd(marks, joined);
     }
+    if (joined) atomicAdd(&sj, joined);
     __syncthreads();
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
         int32_t x = t;
         while (tp[x] != x) x = tp[x];
         tmap[t] = troot[x];
     }
+    if (threadIdx.x == 0 && sj) atomicAdd(marks, sj);
 }
 
 // every vertex points at the root of its tree's component
 __global__ void k_tree_apply(const int32_t* __restrict__ tscan, const uint8_t* __restrict__ lab8,
                              const int32_t* __restrict__ tmap, int32_t n, int32_t* par) {
-    if (tscan[n] > PR1_TREES) return;
+    if (tscan[n] <= 1 || tscan[n] > PR1_TREES) return;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = tmap[lab8[v]];
         if (par[v] != r) par[v] = r;
@@ -783,33 +807,6 @@ constexpr unsigned long long WCAP = 1ULL << 62;
 
 __device__ void set_err(DevScalars* sc, int32_t code) { atomicCAS(&sc->err, 0, code); }
 
-__global__ __launch_bounds__(256) void k_validate(const int32_t* rp, const int32_t* col, const int64_t* w, int32_t n,
-                                                 int32_t nnz, DevScalars* sc, unsigned long long* part) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    if (tid == 0 && (rp[0] != 0 || rp[n] != nnz)) set_err(sc, MC_E_BAD_GRAPH);
-    for (int64_t v = tid; v < n; v += nth)
-        if (rp[v + 1] < rp[v]) set_err(sc, MC_E_BAD_GRAPH);
-    unsigned long long s = 0;
-    for (int64_t j = tid; j < nnz; j += nth) {
-        const int32_t x = col[j];
-        const int64_t c = w[j];
-        if (x < 0 || x >= n || c < 0) set_err(sc, MC_E_BAD_GRAPH);
-        if (c > 0) {
-            s += (unsigned long long)c;
-            if (s >= WCAP || (unsigned long long)c >= WCAP) s = WCAP;
-        }
-    }
-    __shared__ unsigned long long bs[256];
-    bs[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int k = 0; k < 256; k++) { t += bs[k]; if (t >= WCAP) t = WCAP; }
-        part[blockIdx.x] = t;
-    }
-}
-
 // saturating sum of the block partials (each at most WCAP, so a pairwise
 // sum fits in 64 bits before it saturates)
 __global__ __launch_bounds__(256) void k_validate_sum(const unsigned long long* part, int nb, DevScalars* sc) {
@@ -831,18 +828,29 @@ __global__ __launch_bounds__(256) void k_validate_sum(const unsigned long long* 
 // Normalisation fast path: a row whose targets strictly increase, with no
 // loop and only positive weights, is already in normal form (a simple
 // graph, nothing to merge). Writes len and the degrees of every row, and
-// sets *noncanon when some row is not normal.
+// sets *noncanon when some row is not normal. With sc (a device input) the
+// same pass checks the input: row bounds within
+// [0, nnz] and non-decreasing (a row that fails is not read), targets in
+// range, weights non-negative, and the weights' sum, saturated at WCAP, into
+// part[blockIdx.x] for k_validate_sum.
 __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                              const int64_t* __restrict__ w, int32_t n, int32_t* __restrict__ len,
-                                              int64_t* __restrict__ deg, int32_t* noncanon) {
+                                              const int64_t* __restrict__ w, int32_t n, int32_t nnz,
+                                              int32_t* __restrict__ len, int64_t* __restrict__ deg,
+                                              int32_t* noncanon, DevScalars* sc, unsigned long long* part) {
     // 16 lanes take 16 consecutive rows: their offsets come in one load,
     // and each lane then loads up to four entries of a row at once
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
     const int sl = threadIdx.x % SUB;
     bool bad_any = false;
+    unsigned long long wsum = 0;
+    if (sc && blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || rp[n] != nnz)) set_err(sc, MC_E_BAD_GRAPH);
     for (int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x / SUB) + threadIdx.x / SUB) * SUB; v0 < n; v0 += nsub * SUB) {
-        const int32_t my_o = v0 + sl <= n ? rp[v0 + sl] : 0;
-        const int32_t my_e = v0 + sl < n ? rp[v0 + sl + 1] : my_o;
+        int32_t my_o = v0 + sl <= n ? rp[v0 + sl] : 0;
+        int32_t my_e = v0 + sl < n ? rp[v0 + sl + 1] : my_o;
+        if (sc && v0 + sl < n && (my_o < 0 || my_e < my_o || my_e > nnz)) {
+            set_err(sc, MC_E_BAD_GRAPH);
+            my_e = my_o = 0;
+        }
         int64_t my_d = 0;
         const int32_t rows = n - v0 < SUB ? (int32_t)(n - v0) : SUB;
         for (int32_t r = 0; r < rows; r++) {
@@ -865,6 +873,13 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, c
                     if (j0 + u * SUB + sl < l) {
                         d += c[u];
                         bad |= x[u] == v || c[u] <= 0 || xp[u] >= x[u];
+                        if (sc) {
+                            if (x[u] < 0 || x[u] >= n || c[u] < 0) set_err(sc, MC_E_BAD_GRAPH);
+                            if (c[u] > 0) {
+                                wsum += (unsigned long long)c[u];
+                                if (wsum >= WCAP || (unsigned long long)c[u] >= WCAP) wsum = WCAP;
+                            }
+                        }
                     }
                 }
             }
@@ -878,6 +893,16 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, c
         }
     }
     if (__ballot(bad_any) && lane_id() == 0 && ld_acq(noncanon) == 0) st_rel(noncanon, 1);
+    if (sc) {
+        __shared__ unsigned long long bs[256];
+        bs[threadIdx.x] = wsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int k = 0; k < 256; k++) { t += bs[k]; if (t >= WCAP) t = WCAP; }
+            part[blockIdx.x] = t;
+        }
+    }
 }
 
 }  // namespace
@@ -1072,20 +1097,17 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
     return true;
 }
 
-bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t* len,
-                 int64_t* deg, int32_t* noncanon, hipStream_t s) {
+bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
+                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, hipStream_t s) {
     if (!fill_i32(noncanon, 0, 1, s)) return false;
-    k_canon<<<grid_for(((int64_t)n + SUB - 1) / SUB * SUB, 256), 256, 0, s>>>(row_ptr, col, w, n, len, deg, noncanon);
+    // with checks, at most 1024 blocks (the partial sums of the weights)
+    const int nb = grid_for(((int64_t)n + SUB - 1) / SUB * SUB, 256, sc ? 1024 : 8192);
+    k_canon<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, len, deg, noncanon, sc, part);
     MC_LAUNCHED("k_canon");
+    if (sc) {
+        k_validate_sum<<<1, 256, 0, s>>>(part, nb, sc);
+        MC_LAUNCHED("k_validate_sum");
+    }
     return true;
 }
 
-bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
-                  DevScalars* sc, unsigned long long* part, hipStream_t s) {
-    const int nb = grid_for(nnz > n ? nnz : n, 256, 1024);
-    k_validate<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, sc, part);
-    MC_LAUNCHED("k_validate");
-    k_validate_sum<<<1, 256, 0, s>>>(part, nb, sc);
-    MC_LAUNCHED("k_validate_sum");
-    return true;
-}

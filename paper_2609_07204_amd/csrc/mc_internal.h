@@ -390,12 +390,14 @@ bool side_from_components(uint8_t* side, const int32_t* parent, const int32_t* m
 bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len, hipStream_t s);
 // Normalisation fast path: len[v] and deg[v] of every row of a user CSR,
 // and *noncanon = 1 if some row is not already normal (targets strictly
-// increasing, no loop, positive weights).
-bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t* len,
-                 int64_t* deg, int32_t* noncanon, hipStream_t s);
-// Device-side validation of a user CSR: sets sc->err to an mc_status code.
-bool validate_csr(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz,
-                  DevScalars* sc, unsigned long long* part, hipStream_t s);
+// increasing, no loop, positive weights). With sc (device inputs) the same
+// pass checks the input into sc->err as an mc_status code: row bounds in
+// [0, nnz] and non-decreasing (a row that fails is not read), targets in
+// range, non-negative weights, total weight below 2^62 (part: 1024 partial
+// sums).
+bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
+                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, hipStream_t s);
+
 
 // The library context (opaque to callers).
 struct mc_ctx {

@@ -539,6 +539,7 @@ struct Solver {
     bool in_heuristic = false;    // exact rounds on the heuristic's coarse graph
     bool conn_pending = false;    // connectivity not decided yet (the heuristic's coarse graph decides it)
     bool disconnected = false;    // lambda = 0; the side is set
+    bool pv_clean = false;        // private pass state cleared (once per solve, before the first private pass)
     int64_t cur_m = 0;            // entries of the current graph
     int32_t last_cf_steps = 0;    // whole-GPU steps of the round's last CAPFOREST launch
     int64_t last_cf_scans = 0;    // and the vertices it scanned
@@ -683,6 +684,12 @@ static bool sequential_pass(Solver& S, const DGraph& g, int32_t round) {
 // `passes` private batched passes over g (len_cap 0: complete), results in sc.
 static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t passes, int32_t len_cap) {
     SolveWS& w = S.w;
+    // every pass leaves its state cleared, so one clear per solve suffices,
+    // and a solve whose rounds never run a private pass needs none
+    if (!S.pv_clean) {
+        if (!capforest_private_reset(w.pv, S.s)) return false;
+        S.pv_clean = true;
+    }
     if (len_cap > 0) S.last_cf_steps = 0, S.last_cf_scans = 0;
     PrivateArgs pa = w.pv;
     pa.g = g;
@@ -1097,19 +1104,20 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     }
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
     if (!contract_ws_reset(w.cw, s)) return MC_E_DEVICE;
-    if (!host_input) {
-        if (!validate_csr(rp, col, wt, n, (int32_t)nnz, w.sc, w.vpart, s) || !S.readback()) return MC_E_DEVICE;
-        if (c->hsc->err != 0)
-            return fail((mc_status)c->hsc->err, c->hsc->err == MC_E_OVERFLOW ? "total weight must be below 2^62"
-                                                                              : "malformed CSR (row_ptr, col or w)");
-    }
     // normalise. An input already in normal form (rows strictly increasing,
     // no loops, positive weights) is used in place as the first graph: no
     // kernel writes the current graph's off/col/w. Otherwise contraction by
     // the identity folds loops, parallel entries and zero weights; the
-    // padded view of the input reuses g[1]'s arrays.
-    if (!canon_check(rp, col, wt, n, w.g[0].len, w.g[0].deg, &w.sc->noncanon, s) || !S.readback())
+    // padded view of the input reuses g[1]'s arrays. A device input is
+    // checked in the same pass (host inputs were checked on the host), and
+    // nothing else reads it before the check's result is known.
+    if (!canon_check(rp, col, wt, n, (int32_t)nnz, w.g[0].len, w.g[0].deg, &w.sc->noncanon,
+                     host_input ? nullptr : w.sc, w.vpart, s) ||
+        !S.readback())
         return MC_E_DEVICE;
+    if (c->hsc->err != 0)
+        return fail((mc_status)c->hsc->err, c->hsc->err == MC_E_OVERFLOW ? "total weight must be below 2^62"
+                                                                          : "malformed CSR (row_ptr, col or w)");
     if (c->hsc->noncanon == 0) {
         w.g[0].n = n;
         w.g[0].cap = nnz;
@@ -1128,7 +1136,6 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     }
     S.stats.input_normal = c->hsc->noncanon == 0;
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
-    if (!capforest_private_reset(w.pv, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected.
     // When the heuristic runs, its coarse graph has the same components and
     // decides it at a fraction of the cost (a vertex of degree 0 decides it

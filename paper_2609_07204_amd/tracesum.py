@@ -1,8 +1,8 @@
 """Summary of a rocprofv3 kernel trace of bench.py, per solve.
 
-A solve of a device-resident graph starts with the input check `k_validate`,
-so the trace is split into solves at each launch of that kernel (the
-batched form does not launch it). The summary gives every solve's GPU span
+Every solve starts with the normal-form check `k_canon` (which also checks a
+device input), so the trace is split into solves at each launch of that
+kernel (the batched form launches it once per batch). The summary gives every solve's GPU span
 (first kernel start to last kernel end before the next solve) and, over a
 chosen range of solves, every kernel's launches, total and average time,
 followed by rocprofv3's own statistics over the whole run.
@@ -17,7 +17,7 @@ import glob
 import os
 import sys
 
-MARKER = "k_validate"
+MARKER = "k_canon"
 
 
 def short(name):
