@@ -205,6 +205,44 @@ __global__ void k_chunk_start(const int32_t* __restrict__ gstart, int32_t n2, in
         cg[c] = first_key_ge(gstart, n2, c * CHUNK);
 }
 
+// One member row u of group g (chunk-local gl) into the chunk's LDS table,
+// by the SUB lanes of a lane group: four entries per lane at a time, so their
+// loads, then the labels of their targets, are in flight together.
+__device__ __forceinline__ void merge_row(const DGraph& src, const int32_t* __restrict__ L, int32_t u, int32_t g,
+                                          int gl, int sl, unsigned long long* hkey, long long* hval,
+                                          int64_t& nin) {
+    const int32_t o = src.off[u], l = src.len[u];
+    if (sl == 0) nin += l;
+    for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
+        int32_t x[4], t[4];
+        int64_t c[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int32_t j = j0 + q * SUB + sl;
+            x[q] = j < l ? src.col[o + j] : 0;
+            c[q] = j < l ? src.w[o + j] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) t[q] = c[q] > 0 ? (L ? L[x[q]] : x[q]) : g;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (t[q] == g) continue;   // a loop, zero weight or no entry
+            const unsigned long long key = ((unsigned long long)gl << 32) | (uint32_t)t[q];
+            uint32_t h = hash32((uint32_t)t[q] ^ ((uint32_t)gl * 0x9E3779B1u)) & (HSLOTS - 1);
+            for (;;) {
+                unsigned long long k = hkey[h];
+                if (k == key) break;
+                if (k == EMPTY_KEY) {
+                    unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
+                    if (old == EMPTY_KEY || old == key) break;
+                }
+                h = (h + 1) & (HSLOTS - 1);
+            }
+            atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c[q]);
+        }
+    }
+}
+
 // Algorithmic bytes (profiling): per input entry 12 B (col, w) plus 4 B for
 // the label of its target; per output entry 12 B; per group 12 B (len, deg).
 __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const int32_t* __restrict__ L,
@@ -219,6 +257,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     __shared__ int32_t gvs[CHUNK + 1];
     __shared__ int32_t gcur[CHUNK];
     __shared__ long long gdeg[CHUNK];
+    __shared__ int32_t mpre[NSUB + 1];   // few-group chunks: prefix of the small groups' member counts
 
     const int tid = threadIdx.x;
     const int32_t g_lo = cg[blockIdx.x];
@@ -235,43 +274,31 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     __syncthreads();
 
     const int sg = tid / SUB, sl = tid % SUB;
-    for (int gl = sg; gl < ng; gl += NSUB) {
-        if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
-        const int32_t g = g_lo + gl;
-        for (int32_t m = gvs[gl]; m < gvs[gl + 1]; m++) {
-            const int32_t u = perm ? perm[m] : m;
-            const int32_t o = src.off[u], l = src.len[u];
-            if (sl == 0) nin += l;
-            // four entries per lane at a time: their loads, then the labels
-            // of their targets, are in flight together
-            for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
-                int32_t x[4], t[4];
-                int64_t c[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int32_t j = j0 + q * SUB + sl;
-                    x[q] = j < l ? src.col[o + j] : 0;
-                    c[q] = j < l ? src.w[o + j] : 0;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; q++) t[q] = c[q] > 0 ? (L ? L[x[q]] : x[q]) : g;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    if (t[q] == g) continue;   // a loop, zero weight or no entry
-                    const unsigned long long key = ((unsigned long long)gl << 32) | (uint32_t)t[q];
-                    uint32_t h = hash32((uint32_t)t[q] ^ ((uint32_t)gl * 0x9E3779B1u)) & (HSLOTS - 1);
-                    for (;;) {
-                        unsigned long long k = hkey[h];
-                        if (k == key) break;
-                        if (k == EMPTY_KEY) {
-                            unsigned long long old = atomicCAS(&hkey[h], EMPTY_KEY, key);
-                            if (old == EMPTY_KEY || old == key) break;
-                        }
-                        h = (h + 1) & (HSLOTS - 1);
-                    }
-                    atomicAdd((unsigned long long*)&hval[h], (unsigned long long)c[q]);
-                }
+    if (ng >= NSUB) {
+        // many groups: one lane group per group, its members in turn
+        for (int gl = sg; gl < ng; gl += NSUB) {
+            if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
+            for (int32_t m = gvs[gl]; m < gvs[gl + 1]; m++)
+                merge_row(src, L, perm ? perm[m] : m, g_lo + gl, gl, sl, hkey, hval, nin);
+        }
+    } else {
+        // a few groups (large ones, each with many members): the members of
+        // the small groups NSUB at a time whatever their group, so every
+        // lane group stays busy
+        if (tid == 0) {
+            int32_t run = 0;
+            for (int gl = 0; gl < ng; gl++) {
+                mpre[gl] = run;
+                if (gst[gl + 1] - gst[gl] <= SMALL_MAX) run += gvs[gl + 1] - gvs[gl];
             }
+            mpre[ng] = run;
+        }
+        __syncthreads();
+        for (int32_t k = sg; k < mpre[ng]; k += NSUB) {
+            int gl = 0;   // the last group with mpre[gl] <= k (it has members)
+            while (gl + 1 < ng && mpre[gl + 1] <= k) gl++;
+            const int32_t m = gvs[gl] + (k - mpre[gl]);
+            merge_row(src, L, perm ? perm[m] : m, g_lo + gl, gl, sl, hkey, hval, nin);
         }
     }
     __syncthreads();
