@@ -136,9 +136,13 @@ constexpr int DENSE_MAX = 1024;
 // row is written in place. Larger groups take the tile path below.
 constexpr int MID_MAX = 2048;
 constexpr int MID_MEM = 1024;
-constexpr int MID_SLOTS = 4096;    // LDS table (load <= 1/2)
 constexpr int MID_T = 256;
-constexpr int MID_GRID = 512;
+// Groups of at most MID_HALF entries take a table of 2048 slots (32 KB of
+// LDS per workgroup, five workgroups per compute unit), larger ones 4096
+// slots (56 KB, two per compute unit): the merge of a group is a chain of
+// dependent loads, and more workgroups in flight hide more of it. Both keep
+// the table's load at most 1/2.
+constexpr int MID_HALF = 1024;
 
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
                            int32_t nd_max, int32_t* __restrict__ tsize, int32_t* __restrict__ bigm,
@@ -151,7 +155,10 @@ __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __
         dslot[g] = -1;
         const int32_t members = vstart ? vstart[g + 1] - vstart[g] : 1;
         if (s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM) {
-            mlist[atomicAdd(mcnt, 1)] = (int32_t)g;
+            // groups of at most MID_HALF entries from the front of the list,
+            // larger ones from the back
+            if (s <= MID_HALF) mlist[atomicAdd(&mcnt[0], 1)] = (int32_t)g;
+            else mlist[n2 - atomicAdd(&mcnt[1], 1)] = (int32_t)g;
             tsize[g] = 0;
             bigm[g] = 0;
         } else if (s > SMALL_MAX) {
@@ -324,13 +331,14 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     if (pb) prof_add(pb, nin * (L ? 16 : 12) + nout * 12 + ngrp * 12);
 }
 
+template <int MID_SLOTS>
 __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* __restrict__ L,
                                                     const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ vstart,
                                                     const int32_t* __restrict__ mstart,
                                                     const int32_t* __restrict__ gstart,
                                                     const int32_t* __restrict__ mlist,
-                                                    const int32_t* __restrict__ mcnt, DGraph dst,
+                                                    const int32_t* __restrict__ mcnt, int32_t n2, DGraph dst,
                                                     unsigned long long* pb) {
     __shared__ int32_t tk[MID_SLOTS];
     __shared__ long long tv[MID_SLOTS];
@@ -338,11 +346,12 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
     __shared__ int32_t wo[MID_MEM];       // row offset of each member
     __shared__ int32_t s_cnt;
     __shared__ long long s_deg;
-    const int32_t cnt = *mcnt;
+    const bool front = MID_SLOTS < 2 * MID_MAX;   // the list's front holds the groups of at most MID_HALF entries
+    const int32_t cnt = mcnt[front ? 0 : 1];
     const int tid = threadIdx.x;
     int64_t bytes = 0;
     for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int32_t g = mlist[i];
+        const int32_t g = mlist[front ? i : n2 - i];
         const int32_t m0 = vstart ? vstart[g] : g;
         const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
         const int32_t gs = gstart[g], s = gstart[g + 1] - gs;
@@ -867,7 +876,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     // extraction clears what it read)
     const int64_t ndm = ws.dense_elems / (n2 > 0 ? n2 : 1);
     const int32_t nd_max = (int32_t)(ndm < DENSE_MAX ? ndm : DENSE_MAX);
-    if (!fill_i32(ws.dinfo, 0, 1, s) || !fill_i32(ws.mcnt, 0, 1, s)) return false;
+    if (!fill_i32(ws.dinfo, 0, 1, s) || !fill_i32(ws.mcnt, 0, 2, s)) return false;
     k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, nd_max, ws.tsize, ws.bigm, ws.bcur, ws.dslot,
                                                  ws.dinfo, ws.mlist, ws.mcnt, dst);
     MC_LAUNCHED("k_classify");
@@ -882,8 +891,11 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     MC_LAUNCHED("k_merge_small");
     prof_end(PK_MERGE_SMALL, s);
     prof_begin(PK_MID_MERGE, s);
-    k_mid_merge<<<MID_GRID, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt, dst,
-                                           prof_dev_bytes(PK_MID_MERGE));
+    k_mid_merge<2 * MID_HALF><<<256 * 5, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt,
+                                                        n2, dst, prof_dev_bytes(PK_MID_MERGE));
+    MC_LAUNCHED("k_mid_merge");
+    k_mid_merge<2 * MID_MAX><<<256 * 2, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt,
+                                                       n2, dst, prof_dev_bytes(PK_MID_MERGE));
     MC_LAUNCHED("k_mid_merge");
     prof_end(PK_MID_MERGE, s);
     k_big_clear<<<2048, 256, 0, s>>>(ws.tsize + n2, ws.tkey, ws.tval);

@@ -64,8 +64,11 @@ def main(fetch_dir, write_dir, mib, workload="rhg", path=None):
     f_write = nbytes / max(write.get(ck, [0.0]) or [1.0])
     res = {"_calibration": {"copy_kernel": ck, "copy_bytes": nbytes, "fetch_factor": f_fetch,
                             "write_factor": f_write, "workload": workload}}
-    for k, src in kernel_sources().items():
-        if k not in fetch or k not in write:
+    srcs = kernel_sources()
+    for k in sorted(fetch):
+        # a template's dispatches are named with their arguments (k_x<2048>)
+        src = srcs.get(k.split("<")[0])
+        if src is None or k not in write:
             continue
         fb = sum(fetch[k]) / len(fetch[k]) * f_fetch
         wb = sum(write[k]) / len(write[k]) * f_write
