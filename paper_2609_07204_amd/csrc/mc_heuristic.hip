@@ -30,6 +30,7 @@ constexpr int LP_HSLOTS = 1024;
 constexpr int LP_T = 256;
 constexpr int LP_SUB = 16;
 constexpr int LP_NSUB = LP_T / LP_SUB;
+constexpr int LP_SEG = 2 * LP_SUB;   // entries of a piece of a row in chunks of fewer than LP_NSUB rows
 constexpr int LP_TASK = 1024;     // entries per task of a long row (multiple of 128)
 constexpr int LP_TSLOTS = 2 * LP_TASK;   // LDS slots of a task's pre-merge
 constexpr int LP_IT = LP_TASK / 4;       // threads of the pre-merge: four entries each
@@ -62,6 +63,43 @@ __global__ void k_lp_chunks(const int32_t* __restrict__ rstart, int32_t n, int64
 
 __device__ __forceinline__ uint32_t lp_hash(uint32_t gl, uint32_t lbl) { return hash32(lbl ^ (gl * 0x9E3779B1u)); }
 
+// Entries [j0, j1) of row v (chunk-local gl) into the chunk's LDS table by
+// the LP_SUB lanes of a lane group: four entries per lane at a time, so
+// their loads, then their labels' loads, are in flight together.
+__device__ __forceinline__ void lp_insert(const DGraph& g, const int32_t* __restrict__ lab_in, int32_t v, int gl,
+                                          int32_t o, int32_t j0, int32_t j1, int sl, unsigned long long* hkey,
+                                          unsigned long long* hval) {
+    for (int32_t jb = j0; jb < j1; jb += 4 * LP_SUB) {
+        int32_t x[4];
+        unsigned long long c[4];
+        uint32_t lb[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int32_t j = jb + u * LP_SUB + sl;
+            x[u] = j < j1 ? g.col[o + j] : v;
+            c[u] = j < j1 ? (unsigned long long)g.w[o + j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) lb[u] = x[u] != v ? (uint32_t)lab_in[x[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (x[u] == v) continue;   // a loop, or no entry
+            const unsigned long long key = ((unsigned long long)gl << 32) | lb[u];
+            uint32_t h = lp_hash((uint32_t)gl, lb[u]) & (LP_HSLOTS - 1);
+            for (;;) {
+                const unsigned long long k = hkey[h];
+                if (k == key) break;
+                if (k == LP_EMPTY) {
+                    const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, key);
+                    if (old == LP_EMPTY || old == key) break;
+                }
+                h = (h + 1) & (LP_HSLOTS - 1);
+            }
+            atomicAdd(&hval[h], c[u]);
+        }
+    }
+}
+
 __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __restrict__ lab_in,
                                                   int32_t* __restrict__ lab_out, const int32_t* __restrict__ rstart,
                                                   const int32_t* __restrict__ cg, int32_t* __restrict__ long_list,
@@ -75,6 +113,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
     __shared__ int32_t own[LP_CHUNK];
     __shared__ unsigned long long own_w[LP_CHUNK], best_w[LP_CHUNK];
     __shared__ int32_t best_l[LP_CHUNK];
+    __shared__ int32_t spre[LP_NSUB + 1];   // few-row chunks: prefix of the rows' piece counts
     const int tid = threadIdx.x;
     const int32_t g_lo = cg[blockIdx.x];
     const int32_t g_hi = cg[blockIdx.x + 1] < g.n ? cg[blockIdx.x + 1] : g.n;
@@ -102,40 +141,34 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
     }
     __syncthreads();
     const int sg = tid / LP_SUB, sl = tid % LP_SUB;
-    for (int gl = sg; gl < ng; gl += LP_NSUB) {
-        const int32_t v = g_lo + gl;
-        const int32_t o = g.off[v], l = g.len[v];
-        if (l > LP_SMALL) continue;
-        // four entries per lane at a time: their loads, then their labels'
-        // loads, are in flight together
-        for (int32_t j0 = 0; j0 < l; j0 += 4 * LP_SUB) {
-            int32_t x[4];
-            unsigned long long c[4];
-            uint32_t lb[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int32_t j = j0 + u * LP_SUB + sl;
-                x[u] = j < l ? g.col[o + j] : v;
-                c[u] = j < l ? (unsigned long long)g.w[o + j] : 0;
+    if (ng >= LP_NSUB) {
+        // many rows: one lane group per row, its entries from j = 0
+        for (int gl = sg; gl < ng; gl += LP_NSUB) {
+            const int32_t v = g_lo + gl;
+            const int32_t o = g.off[v], l = g.len[v];
+            if (l > LP_SMALL) continue;
+            lp_insert(g, lab_in, v, gl, o, 0, l, sl, hkey, hval);
+        }
+    } else {
+        // a few long rows: pieces of LP_SEG entries of any row, one per lane
+        // group, so that every lane group stays busy
+        if (tid == 0) {
+            int32_t run = 0;
+            for (int gl = 0; gl < ng; gl++) {
+                spre[gl] = run;
+                const int32_t l = g.len[g_lo + gl];
+                if (l <= LP_SMALL) run += (l + LP_SEG - 1) / LP_SEG;
             }
-#pragma unroll
-            for (int u = 0; u < 4; u++) lb[u] = x[u] != v ? (uint32_t)lab_in[x[u]] : 0;
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                if (x[u] == v) continue;   // a loop, or no entry
-                const unsigned long long key = ((unsigned long long)gl << 32) | lb[u];
-                uint32_t h = lp_hash((uint32_t)gl, lb[u]) & (LP_HSLOTS - 1);
-                for (;;) {
-                    const unsigned long long k = hkey[h];
-                    if (k == key) break;
-                    if (k == LP_EMPTY) {
-                        const unsigned long long old = atomicCAS(&hkey[h], LP_EMPTY, key);
-                        if (old == LP_EMPTY || old == key) break;
-                    }
-                    h = (h + 1) & (LP_HSLOTS - 1);
-                }
-                atomicAdd(&hval[h], c[u]);
-            }
+            spre[ng] = run;
+        }
+        __syncthreads();
+        for (int32_t k = sg; k < spre[ng]; k += LP_NSUB) {
+            int gl = 0;   // the last row with spre[gl] <= k (it has pieces)
+            while (gl + 1 < ng && spre[gl + 1] <= k) gl++;
+            const int32_t v = g_lo + gl;
+            const int32_t o = g.off[v], l = g.len[v];
+            const int32_t j0 = (k - spre[gl]) * LP_SEG;
+            lp_insert(g, lab_in, v, gl, o, j0, j0 + LP_SEG < l ? j0 + LP_SEG : l, sl, hkey, hval);
         }
     }
     __syncthreads();
