@@ -87,8 +87,8 @@ typedef struct {
                                  printed); MC_CF_AUTO (default): on the first
                                  round of each size regime (at least / below
                                  levels_min_n vertices) that runs CAPFOREST,
-                                 a short probe of shared passes (one per
-                                 compute unit, 128 pops each) runs first; if
+                                 a short probe of shared passes (four per
+                                 compute unit, 32 pops each) runs first; if
                                  it contracts fewer than one vertex in 1024
                                  private passes are kept, otherwise private
                                  passes of at most 4096 scans run in the same
@@ -156,7 +156,10 @@ mc_status mc_ctx_destroy(mc_ctx* ctx);
 mc_status mc_ctx_set_options(mc_ctx* ctx, const mc_options* opt);
 
 /* Device workspace bytes that mc_mincut needs for a graph with n vertices
- * and nnz entries. */
+ * and nnz entries. This includes room for one CAPFOREST pass per compute
+ * unit on small graphs (rounds that contract less than a tenth of their
+ * vertices raise the pass count to that); a smaller workspace that holds
+ * the first count (32 passes) is accepted too, and the solve then keeps 32. */
 mc_status mc_workspace_size(const mc_ctx* ctx, int32_t n, int32_t nnz, size_t* bytes);
 
 /* Solve one graph (Algorithm 2). `dev_workspace` is device memory of at
@@ -176,8 +179,8 @@ mc_status mc_mincut(mc_ctx* ctx, const mc_csr* g, void* dev_workspace, size_t ws
  * the process ends (its address is fetched when the first context on the
  * device is created); it calls no hipMalloc, hipFree or other allocating
  * routine, and kernel timing (mc_profile) is suspended for the call. Graphs
- * whose mc_workspace_size exceeds 64 MiB get MC_E_INVALID_ARG before any
- * device work. Every call on one GPU uses that GPU's one array, which keeps
+ * whose smallest workspace (32 passes on small rounds) exceeds 64 MiB get
+ * MC_E_INVALID_ARG before any device work. Every call on one GPU uses that GPU's one array, which keeps
  * the last call's contents (the solve initialises all it reads): calls that
  * overlap on one GPU, from any thread or context, race and must not be
  * made. */

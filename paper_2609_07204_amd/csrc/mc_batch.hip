@@ -1393,7 +1393,7 @@ extern "C" mc_status mc_server_create(mc_ctx* c, const mc_server_opts* opts, mc_
     const int32_t nslots = rn >= solo_min_n ? (opts->solo_slots > 0 ? opts->solo_slots : 1) : 0;
     size_t solo = 0;
     if (nslots > 0) {
-        if (mc_workspace_size(c, rn, (int32_t)std::min<int64_t>(re, INT32_MAX / 2), &solo) != MC_OK) return MC_E_INVALID_ARG;
+        solo = workspace_min_bytes(c, rn, (int32_t)std::min<int64_t>(re, INT32_MAX / 2));
         solo = (solo + 4095) & ~(size_t)4095;
     }
     if (solo * nslots + ((size_t)64 << 20) > opts->hbm_bytes)
@@ -1469,7 +1469,8 @@ extern "C" mc_status mc_server_submit(mc_server* S, const mc_csr* g, uint64_t* t
     const Caps& cp = S->E.cap;
     if (g->n >= S->solo_min_n) {
         size_t need = 0;
-        if (S->slots.empty() || mc_workspace_size(S->c, g->n, g->nnz, &need) != MC_OK || need > S->solo_bytes)
+        need = workspace_min_bytes(S->c, g->n, g->nnz);
+        if (S->slots.empty() || need > S->solo_bytes)
             return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");
     } else if (g->n > cp.nmax || g->n > cp.Ns || g->nnz > cp.Cs || g->n > cp.N || g->nnz > cp.C) {
         return mc_fail(MC_E_OOM, "mc_server_submit: graph larger than the server admits");

@@ -543,7 +543,7 @@ bool capforest_private(const PrivateArgs& a, hipStream_t s, int32_t max_pass_n) 
 }
 
 bool capforest_private_reset(const PrivateArgs& a, hipStream_t s) {
-    const int64_t count = (int64_t)a.passes * a.stride;
+    const int64_t count = a.region > 0 ? a.region : (int64_t)a.passes * a.stride;
     k_private_reset<<<4096, 256, 0, s>>>(a.st, a.r, count);
     MC_LAUNCHED("k_private_reset");
     return true;

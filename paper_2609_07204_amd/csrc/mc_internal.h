@@ -258,6 +258,8 @@ struct PrivateArgs {
     int32_t round;
     int32_t start;          // >= 0: every pass starts here
     int64_t stride;         // elements per pass in the per-pass arrays (>= n)
+    int64_t region;         // elements of each per-pass array (0: passes * stride); passes * stride <= region
+    int64_t region1;        // elements of l1 / dlist (0: passes * stride1)
     int32_t* st;            // [passes*stride] 0 new, 1 queued, 2 scanned, 3 in batch; all 0 between calls
     int64_t* r;             // [passes*stride] all 0 between calls
     int32_t* fifo;          // [passes*stride] capped vertices in crossing order
@@ -394,6 +396,10 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
 // pass checks the input into sc->err as an mc_status code: row bounds in
 // [0, nnz] and non-decreasing (a row that fails is not read), targets in
 // range, non-negative weights, total weight below 2^62 (part: 1024 partial
+// Smallest workspace mc_mincut accepts for a graph (small rounds keep their
+// first pass count); mc_workspace_size adds room for one pass per compute
+// unit.
+size_t workspace_min_bytes(const mc_ctx* c, int32_t n, int32_t nnz);
 // sums).
 bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
                  int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, hipStream_t s);

@@ -419,29 +419,38 @@ void carve_steps(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t len_c
     sa.max_singles = 0;
 }
 
-void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t*& psteps) {
-    pv.passes = passes;
+// Per-pass state of the private passes: `passes` passes over graphs of at
+// most n vertices, and (small > passes) up to `small` passes over graphs of
+// at most small_n vertices. A launch sets the stride to its current graph's
+// n, so the same region holds few passes over a large graph or many over a
+// small one.
+void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t*& psteps, int32_t small = 0,
+                   int32_t small_n = 0) {
+    const int32_t pmax = std::max(passes, small);
+    pv.passes = pmax;
     pv.stride = n;
-    const size_t cnt = (size_t)passes * (size_t)n;
+    pv.region = std::max((int64_t)passes * n, (int64_t)small * small_n);
+    pv.stride1 = (int64_t)n / 64 + 2;
+    pv.region1 = std::max((int64_t)passes * pv.stride1, (int64_t)small * ((int64_t)small_n / 64 + 2));
+    const size_t cnt = (size_t)pv.region;
     pv.st = a.take<int32_t>(cnt);
     pv.r = a.take<int64_t>(cnt);
     pv.fifo = a.take<int32_t>(cnt);
     pv.touched = a.take<int32_t>(cnt);
     pv.order = a.take<int32_t>(cnt);
-    pv.stride1 = (int64_t)n / 64 + 2;
-    pv.l1 = a.take<int64_t>((size_t)passes * (size_t)pv.stride1);
-    pv.dlist = a.take<int32_t>((size_t)passes * (size_t)pv.stride1);
-    pv.dbits = a.take<uint32_t>((size_t)passes * (size_t)(pv.stride1 / 32 + 1));
-    pv.nscan = a.take<int32_t>((size_t)passes);
-    pv.alpha = a.take<int64_t>((size_t)passes);
-    pv.alpha_len = a.take<int32_t>((size_t)passes);
-    pv.lam_out = a.take<int64_t>((size_t)passes);
-    psteps = a.take<int32_t>((size_t)passes);
-    pv.diag = a.take<int64_t>((size_t)passes * 8);
+    pv.l1 = a.take<int64_t>((size_t)pv.region1);
+    pv.dlist = a.take<int32_t>((size_t)pv.region1);
+    pv.dbits = a.take<uint32_t>((size_t)(pv.region1 / 32 + pmax + 1));
+    pv.nscan = a.take<int32_t>((size_t)pmax);
+    pv.alpha = a.take<int64_t>((size_t)pmax);
+    pv.alpha_len = a.take<int32_t>((size_t)pmax);
+    pv.lam_out = a.take<int64_t>((size_t)pmax);
+    psteps = a.take<int32_t>((size_t)pmax);
+    pv.diag = a.take<int64_t>((size_t)pmax * 8);
 }
 
 void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, int32_t len_cap, bool host_input,
-           int ngraphs, SolveWS& w) {
+           int ngraphs, SolveWS& w, int32_t small = 0, int32_t small_n = 0) {
     w.sc = a.take<DevScalars>(1);
     if (host_input) {
         w.in_rp = a.take<int32_t>((size_t)n + 1);
@@ -485,7 +494,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     lp_ws_carve(a, n, cap, w.lw);
     pr34_ws_carve(a, n, w.tw);
     w.lab2 = a.take<int32_t>((size_t)n + 1);
-    carve_private(a, n, ppasses, w.pv, w.psteps);
+    carve_private(a, n, ppasses, w.pv, w.psteps, small, small_n);
     carve_steps(a, n, cap, ppasses, len_cap, w.sa);
 }
 
@@ -503,20 +512,31 @@ int32_t pass_count(const mc_ctx* c) {
 // workgroup per pass, so several passes keep several compute units busy.
 int32_t levels_min_n(const mc_ctx* c) { return c->opt.levels_min_n > 0 ? c->opt.levels_min_n : (1 << 16); }
 
-// passes used on a current graph with n vertices
+// passes used on a current graph with n vertices (the first round of the
+// small-graph regime; see small_pass_max)
 int32_t private_pass_count(const mc_ctx* c, int32_t n) {
     if (c->opt.capforest_mode == MC_CF_SHARED || c->opt.deterministic) return 1;
     if (c->opt.capforest_passes > 0) return c->opt.capforest_passes;
     return n >= levels_min_n(c) ? 1 : 32;
 }
 
-// passes the workspace holds (the most any round of this solve uses)
-int32_t private_pass_alloc(const mc_ctx* c, int32_t n) {
-    int32_t p = private_pass_count(c, n);
-    if (c->opt.capforest_passes <= 0 && c->opt.capforest_mode != MC_CF_SHARED && !c->opt.deterministic)
-        p = std::max(p, private_pass_count(c, 2));
-    return p;
+// passes the workspace holds at the stride of the input (rounds on graphs
+// of at least levels_min_n vertices, and the complete fallback pass)
+int32_t large_pass_count(const mc_ctx* c) { return private_pass_count(c, levels_min_n(c)); }
+
+// Small-graph rounds start with 32 passes; a round that removes fewer than
+// one vertex in ten raises the count to one pass per compute unit for the
+// rest of the solve. On graphs that resist contraction each pass marks a
+// few edges and the passes run side by side on idle compute units, so more
+// passes mean proportionally fewer rounds (20,000-vertex 6-regular graphs
+// with three hubs: 152 rounds and 17.7 s with 32 passes, 37 rounds and
+// 3.5 s with 256).
+int32_t small_pass_max(const mc_ctx* c) {
+    if (c->opt.capforest_mode == MC_CF_SHARED || c->opt.deterministic || c->opt.capforest_passes > 0)
+        return private_pass_count(c, 2);
+    return std::max(32, c->cus);
 }
+int32_t small_pass_n(const mc_ctx* c, int32_t n) { return std::min(n, levels_min_n(c) - 1); }
 
 int32_t private_len_cap(const mc_ctx* c) {
     if (c->opt.pass_len_cap < 0) return 0;
@@ -540,6 +560,9 @@ struct Solver {
     bool conn_pending = false;    // connectivity not decided yet (the heuristic's coarse graph decides it)
     bool disconnected = false;    // lambda = 0; the side is set
     bool pv_clean = false;        // private pass state cleared (once per solve, before the first private pass)
+    int32_t small_max = 32;       // passes of small rounds the workspace holds
+    int32_t small_passes = 0;     // passes of small rounds now (0: the first round's count)
+    int64_t pv_stride = 0;        // stride of the last private launch (its pass orders)
     int64_t cur_m = 0;            // entries of the current graph
     int32_t last_cf_steps = 0;    // whole-GPU steps of the round's last CAPFOREST launch
     int64_t last_cf_scans = 0;    // and the vertices it scanned
@@ -567,6 +590,13 @@ struct Solver {
         if (t * 100 < (unsigned long long)n) tri_on = false;
     }
 
+    // passes of the private form on an n-vertex round
+    int32_t passes_for(int32_t n) const {
+        const int32_t base = private_pass_count(c, n);
+        if (n >= levels_min_n(c) || c->opt.capforest_passes > 0 || base == 1 || small_passes <= 0) return base;
+        return std::min(small_passes, small_max);
+    }
+
     bool readback() {
         MC_HIP(hipMemcpyAsync(c->hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
@@ -579,7 +609,7 @@ struct Solver {
         if (used == CF_RUN_NONE || h.best_pass < 0 || h.best_alpha >= lam) return true;
         const int32_t* pref = used == CF_RUN_SEQ      ? w.corder
                               : used == CF_RUN_SHARED ? w.order + (int64_t)h.best_pass * CF_HC
-                                                      : w.pv.order + (int64_t)h.best_pass * w.pv.stride;
+                                                      : w.pv.order + (int64_t)h.best_pass * pv_stride;
         if (!side_from_prefix(w.side, w.map0, n0, w.flag8, n, pref, &w.sc->best_len, s)) return false;
         return set_lam(h.best_alpha);
     }
@@ -593,13 +623,23 @@ struct Solver {
 
 }  // namespace
 
+// bytes of a solve's workspace with room for `small` passes of small rounds
+static size_t workspace_bytes(const mc_ctx* c, int32_t n, int32_t nnz, int32_t small) {
+    Arena a;
+    SolveWS w;
+    carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), true, 3, w, small,
+          small_pass_n(c, n));
+    return a.used + 256;
+}
+
+size_t workspace_min_bytes(const mc_ctx* c, int32_t n, int32_t nnz) {
+    return workspace_bytes(c, n, nnz, private_pass_count(c, 2));
+}
+
 extern "C" mc_status mc_workspace_size(const mc_ctx* c, int32_t n, int32_t nnz, size_t* bytes) {
     if (!c || !bytes) return fail(MC_E_INVALID_ARG, "mc_workspace_size: NULL argument");
     if (n < 2 || nnz < 0) return fail(MC_E_INVALID_ARG, "mc_workspace_size: need n >= 2 and nnz >= 0");
-    Arena a;
-    SolveWS w;
-    carve(a, n, nnz, pass_count(c), private_pass_alloc(c, n), private_len_cap(c), true, 3, w);
-    *bytes = a.used + 256;
+    *bytes = workspace_bytes(c, n, nnz, small_pass_max(c));
     return MC_OK;
 }
 
@@ -627,9 +667,13 @@ static void debug_round(Solver& S, const DGraph& g, int32_t round, int32_t passe
 
 // The shared-visited-array passes of Algorithm 1 as printed: many passes,
 // one wavefront each, that blacklist vertices another pass scanned. A probe
-// runs one pass per compute unit of at most 128 pops (scans or blacklistings)
-// each.
-constexpr int32_t kProbeScans = 128;
+// runs kProbePasses passes per compute unit of at most kProbeScans pops
+// (scans or blacklistings) each, 32 K pops on 256 compute units. The passes
+// run side by side while the pops of a pass are a chain, so four short
+// passes per unit take about a quarter of the time of one pass four times as
+// long (Chung-Lu 2^22: 256 passes of 128 pops took 0.69 ms).
+constexpr int32_t kProbeScans = 32;
+constexpr int32_t kProbePasses = 4;
 constexpr int32_t kProbePrivate = 4096;   // scans per private pass in a probe round
 static bool shared_passes(Solver& S, const DGraph& g, bool probe) {
     SolveWS& w = S.w;
@@ -640,7 +684,7 @@ static bool shared_passes(Solver& S, const DGraph& g, bool probe) {
     ca.claim = w.claim;
     ca.tag = ++S.c->tag;
     ca.shared = 1;
-    ca.passes = probe ? std::min(w.passes, S.c->cus) : w.passes;
+    ca.passes = probe ? std::min(w.passes, kProbePasses * S.c->cus) : w.passes;
     ca.len_cap = S.c->opt.pass_len_cap > 0 ? S.c->opt.pass_len_cap : 0;
     if (probe && (ca.len_cap <= 0 || ca.len_cap > kProbeScans)) ca.len_cap = kProbeScans;
     ca.pop_cap = probe ? kProbeScans : 0;
@@ -695,6 +739,14 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
     pa.g = g;
     pa.lam = &w.sc->lam;
     pa.parent = w.parent;
+    // the per-pass arrays at the current graph's stride, as many passes as
+    // the region holds
+    pa.stride = std::max<int64_t>(g.n, 1);
+    pa.stride1 = (int64_t)g.n / 64 + 2;
+    passes = (int32_t)std::min<int64_t>({(int64_t)passes, (int64_t)w.pv.passes, w.pv.region / pa.stride,
+                                         w.pv.region1 / pa.stride1});
+    if (passes < 1) return mc_hip_ok(hipErrorInvalidValue, "private passes: no room for one pass");
+    S.pv_stride = pa.stride;
     pa.passes = passes;
     pa.len_cap = len_cap;
     pa.seed = S.c->opt.seed;
@@ -818,8 +870,8 @@ static mc_status exact_rounds(Solver& S, int src) {
             // visited-array policy (Section 4, parallel session (1)): shared
             // or private visited state, fixed by the options or, in the
             // automatic mode, chosen on the first round of each size regime
-            // that runs CAPFOREST. A short probe of shared passes (one per
-            // compute unit, 128 pops each) runs first: if it contracts fewer
+            // that runs CAPFOREST. A short probe of shared passes (four per
+            // compute unit, 32 pops each) runs first: if it contracts fewer
             // than one vertex in 1024, private passes are kept; otherwise a
             // private run of at most kProbePrivate scans per pass follows in
             // the same round, and the form with more marks per millisecond
@@ -827,7 +879,7 @@ static mc_status exact_rounds(Solver& S, int src) {
             const int reg = n >= levels_min_n(S.c) ? 0 : 1;
             int form = S.c->opt.capforest_mode == MC_CF_SHARED ? CF_RUN_SHARED
                        : S.c->opt.capforest_mode == MC_CF_PRIVATE ? CF_RUN_PRIVATE : S.cf_choice[reg];
-            const int32_t npriv = std::min(w.pv.passes, private_pass_count(S.c, n));
+            const int32_t npriv = std::min(w.pv.passes, S.passes_for(n));
             bool private_done = false;
             if (form == CF_RUN_NONE) {
                 using clk = std::chrono::steady_clock;
@@ -868,7 +920,7 @@ static mc_status exact_rounds(Solver& S, int src) {
             }
         }
         if (!S.readback()) return MC_E_DEVICE;
-        if (S.debug) debug_round(S, *cur, round, used == CF_RUN_PRIVATE ? std::min(w.pv.passes, private_pass_count(S.c, n)) : 0);
+        if (S.debug) debug_round(S, *cur, round, used == CF_RUN_PRIVATE ? std::min(w.pv.passes, S.passes_for(n)) : 0);
         if (!S.apply_alpha(used, n)) return MC_E_DEVICE;
         if (!S.readback()) return MC_E_DEVICE;
         DevScalars h = *S.c->hsc;
@@ -927,6 +979,10 @@ static mc_status exact_rounds(Solver& S, int src) {
         if (!S.readback()) return MC_E_DEVICE;
         h = *S.c->hsc;
         S.cur_m = h.m2;
+        // a small round that removed fewer than one vertex in ten: more
+        // passes from now on (small_pass_max)
+        if (used == CF_RUN_PRIVATE && n < levels_min_n(S.c) && (int64_t)n2 * 10 > (int64_t)n * 9)
+            S.small_passes = S.small_max;
         if (n2 >= 2 && h.dmin < S.lam) {
             if (!side_from_vertex(w.side, w.map0, S.n0, &w.sc->dmin_arg, s)) return MC_E_DEVICE;
             if (!S.set_lam(h.dmin)) return MC_E_DEVICE;
@@ -1083,7 +1139,20 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     Arena a;
     a.base = (char*)dev_ws;
     a.size = ws_bytes;
-    carve(a, n, nnz, pass_count(c), private_pass_alloc(c, n), private_len_cap(c), host_input, 3, S.w);
+    // the most passes of small rounds that the workspace holds: one per
+    // compute unit, else the first round's count (the least a solve needs)
+    S.small_max = small_pass_max(c);
+    carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), host_input, 3, S.w, S.small_max,
+          small_pass_n(c, n));
+    if (a.used > ws_bytes) {
+        S.small_max = private_pass_count(c, 2);
+        a = Arena{};
+        a.base = (char*)dev_ws;
+        a.size = ws_bytes;
+        S.w = SolveWS{};
+        carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), host_input, 3, S.w,
+              S.small_max, small_pass_n(c, n));
+    }
     if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
     SolveWS& w = S.w;
     hipStream_t s = S.s;
@@ -1194,9 +1263,10 @@ extern "C" mc_status mc_mincut_static(mc_ctx* c, const mc_csr* g, int64_t* lambd
     if (!c || !g || !lambda) return fail(MC_E_INVALID_ARG, "mc_mincut_static: NULL argument");
     if (!c->scratch) return fail(MC_E_DEVICE, "mc_mincut_static: no static scratch on this device");
     if (g->n < 2 || g->nnz < 0) return fail(MC_E_INVALID_ARG, "mc_mincut_static: need n >= 2 and nnz >= 0");
-    size_t need = 0;
-    mc_status r = mc_workspace_size(c, g->n, g->nnz, &need);
-    if (r != MC_OK) return r;
+    // the least a solve needs (small rounds with their first pass count);
+    // mc_mincut takes more passes where the scratch holds them
+    const size_t need = workspace_min_bytes(c, g->n, g->nnz);
+    mc_status r = MC_OK;
     if (need > kStaticScratchBytes)
         return fail(MC_E_INVALID_ARG, "mc_mincut_static: the graph needs " + std::to_string(need) +
                                           " bytes of scratch, more than the static " +

@@ -38,7 +38,8 @@ def test_static_scratch_matches_workspace_solves():
     big = gen.mixed_graph(12000, 10, 2, 11, 1, 100)        # heuristic levels and exact rounds
     small = gen.planted(300, 420, 8, 3, 1, 9, 5)             # smaller than the first
     assert small.nnz < big.nnz and small.n < big.n and big.n >= 10000
-    assert ctx.workspace_bytes(big.n, big.nnz) <= 64 << 20
+    # the full workspace (one pass per compute unit on small rounds) may
+    # exceed the scratch; the solve then keeps the first pass count
     for rep in range(2):
         for g in (big, small):
             ref, ref_side = ctx.mincut(g)
