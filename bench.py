@@ -456,6 +456,8 @@ def main():
                     help="after the solves, one device-to-device copy of this many MiB (the known-size kernel "
                          "that scales hardware byte counters)")
     ap.add_argument("--lp-iters", type=int, default=0, help="label-propagation rounds per level (0: default)")
+    ap.add_argument("--contract-mode", type=int, default=0, choices=[0, 1],
+                    help="edge merge of the contractions: 0 hash (default), 1 radix sort")
     ap.add_argument("--tri-cap", type=int, default=-1, help="row-length cap of reduction tests 3 and 4 (-1: default)")
     ap.add_argument("--heuristic-min-n", type=int, default=10000,
                     help="run the label-propagation bound on graphs with at least this many vertices (0: off)")
@@ -495,6 +497,8 @@ def main():
     extra = {}
     if args.lp_iters > 0:
         extra["lp_iters"] = args.lp_iters
+    if args.contract_mode:
+        extra["contract_mode"] = args.contract_mode
     if args.tri_cap >= 0:
         extra["pr_tri_deg_cap"] = args.tri_cap
     ctx = mc.Context(0, capforest_passes=args.passes, pass_len_cap=args.len_cap,

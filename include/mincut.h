@@ -118,6 +118,15 @@ typedef struct {
                                  below 2048, else a binary heap; 1 = buckets;
                                  2 = heap (the largest key, then the
                                  smallest id, as the sequential pass) */
+    int32_t contract_mode;    /* edge merge of the contractions (Section 2:
+                                 parallel edges summed, loops dropped) in
+                                 mc_mincut and the step calls: 0 = hashing by
+                                 contracted vertex (default); 1 = a radix
+                                 sort of the contracted entries and a
+                                 segmented reduction (rows sorted by target;
+                                 the workspace grows by about 40 bytes per
+                                 entry). The batched and served forms always
+                                 hash. */
 } mc_options;
 
 typedef struct {

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("pass_len_cap", ctypes.c_int32), ("capforest_mode", ctypes.c_int32),
                 ("levels_min_n", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("batch_pass_threads", ctypes.c_int32), ("batch_lp", ctypes.c_int32),
-                ("finish_max_n", ctypes.c_int32), ("queue", ctypes.c_int32)]
+                ("finish_max_n", ctypes.c_int32), ("queue", ctypes.c_int32), ("contract_mode", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

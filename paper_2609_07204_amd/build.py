@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libmincut.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mc_host.cpp", "mc_scan.hip", "mc_finish.hip", "mc_contract.hip", "mc_graph_ops.hip", "mc_capforest.hip",
+SOURCES = ["mc_host.cpp", "mc_scan.hip", "mc_finish.hip", "mc_contract.hip", "mc_sort.hip", "mc_graph_ops.hip", "mc_capforest.hip",
            "mc_capforest_private.hip", "mc_capforest_steps.hip", "mc_heuristic.hip", "mc_batch.hip", "mc_solver.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

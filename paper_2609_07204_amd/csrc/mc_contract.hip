@@ -795,7 +795,9 @@ inline int grid_for(int64_t count, int threads, int cap = 8192) {
 
 }  // namespace
 
-void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws) {
+void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool sort) {
+    ws.sorted = sort;
+    if (sort) sort_ws_carve(a, n, cap, ws.sw);
     ws.gcnt = a.take<int32_t>((size_t)n + 2);
     ws.vstart = ws.gcnt;
     ws.gcur = a.take<int32_t>((size_t)n + 1);
@@ -841,6 +843,7 @@ bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) 
 
 bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws, DevScalars* sc,
               hipStream_t s) {
+    if (ws.sorted) return contract_sorted(src, L, n2, dst, ws, sc, s);
     const int32_t n = src.n;
     dst.n = n2;
     const int32_t* perm = nullptr;

@@ -57,6 +57,8 @@ mc_status mc_options_check(const mc_options* o) {
     if (o->validate != 0 && o->validate != 1) return mc_fail(MC_E_INVALID_ARG, "options: validate must be 0 or 1");
     if (o->finish_max_n > 1024) return mc_fail(MC_E_INVALID_ARG, "options: finish_max_n must be at most 1024");
     if (o->queue < 0 || o->queue > 2) return mc_fail(MC_E_INVALID_ARG, "options: queue must be 0, 1 or 2");
+    if (o->contract_mode < 0 || o->contract_mode > 1)
+        return mc_fail(MC_E_INVALID_ARG, "options: contract_mode must be 0 (hash) or 1 (sort)");
     return MC_OK;
 }
 

@@ -68,6 +68,20 @@ bool iota_i32(int32_t* p, int64_t count, hipStream_t s);
 // ------------------------------------------------------- contraction
 // Scratch of the contraction (sized for at most n input vertices and cap
 // entries).
+// Workspace of the sort-based edge merge (mc_sort.hip)
+struct SortWS {
+    int64_t cap = 0;
+    uint64_t* key[2] = {};   // [cap+1] keys, ping-pong
+    int64_t* val[2] = {};    // [cap+1] weights, ping-pong
+    int32_t* flag = nullptr; // [cap+2] run heads
+    int32_t* uidx = nullptr; // [cap+2] their exclusive prefix
+    int32_t* hist = nullptr; // [256 * tiles + 2] per-tile digit counts -> offsets
+    int32_t* scan_tmp = nullptr;
+    int32_t* wcnt = nullptr; // per-wavefront entry counts -> offsets
+    int32_t* rend = nullptr; // [n+1] end of each row's entries
+};
+void sort_ws_carve(Arena& a, int32_t n, int64_t cap, SortWS& w);
+
 struct ContractWS {
     int32_t* gcnt;    // [n+1]  members per group -> vstart
     int32_t* vstart;  // [n+1]
@@ -93,8 +107,11 @@ struct ContractWS {
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
     int32_t* mlist;   // [n+1] groups merged by one workgroup each in LDS
     int32_t* mcnt;    // [4] their count
+    bool sorted = false;   // merge by sorting (mc_sort.hip) instead of hashing
+    SortWS sw;
 };
-void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws);
+// sort: also carve the sort merge's workspace and use it in contract()
+void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool sort = false);
 // Zero the dense accumulators (once after carving; every contraction leaves
 // them zero again).
 bool contract_ws_reset(const ContractWS& ws, hipStream_t s);
@@ -107,6 +124,11 @@ bool contract_ws_reset(const ContractWS& ws, hipStream_t s);
 // the minimum degree (and its vertex) into sc->dmin / sc->dmin_arg.
 bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws,
               DevScalars* sc, hipStream_t s);
+
+// contract() by a radix sort of the contracted entries and a segmented
+// reduction (rows sorted by target); needs ws.sw.
+bool contract_sorted(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws, DevScalars* sc,
+                     hipStream_t s);
 
 // Minimum degree of g (ties: smallest vertex) into sc->dmin / dmin_arg.
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s);

@@ -450,7 +450,7 @@ void carve_private(Arena& a, int32_t n, int32_t passes, PrivateArgs& pv, int32_t
 }
 
 void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, int32_t len_cap, bool host_input,
-           int ngraphs, SolveWS& w, int32_t small = 0, int32_t small_n = 0) {
+           int ngraphs, SolveWS& w, int32_t small = 0, int32_t small_n = 0, bool sort = false) {
     w.sc = a.take<DevScalars>(1);
     if (host_input) {
         w.in_rp = a.take<int32_t>((size_t)n + 1);
@@ -465,7 +465,7 @@ void carve(Arena& a, int32_t n, int64_t cap, int32_t passes, int32_t ppasses, in
     w.claim = a.take<int32_t>((size_t)n + 1);
     w.map0 = a.take<int32_t>((size_t)n + 1);
     w.side = a.take<uint8_t>((size_t)n + 1);
-    contract_ws_carve(a, n, cap, w.cw);
+    contract_ws_carve(a, n, cap, w.cw, sort);
     pr12_ws_carve(a, n, cap, w.prw);
     w.passes = passes;
     w.order = a.take<int32_t>((size_t)passes * CF_HC);
@@ -628,7 +628,7 @@ static size_t workspace_bytes(const mc_ctx* c, int32_t n, int32_t nnz, int32_t s
     Arena a;
     SolveWS w;
     carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), true, 3, w, small,
-          small_pass_n(c, n));
+          small_pass_n(c, n), c->opt.contract_mode == 1);
     return a.used + 256;
 }
 
@@ -1143,7 +1143,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     // compute unit, else the first round's count (the least a solve needs)
     S.small_max = small_pass_max(c);
     carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), host_input, 3, S.w, S.small_max,
-          small_pass_n(c, n));
+          small_pass_n(c, n), c->opt.contract_mode == 1);
     if (a.used > ws_bytes) {
         S.small_max = private_pass_count(c, 2);
         a = Arena{};
@@ -1151,7 +1151,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         a.size = ws_bytes;
         S.w = SolveWS{};
         carve(a, n, nnz, pass_count(c), large_pass_count(c), private_len_cap(c), host_input, 3, S.w,
-              S.small_max, small_pass_n(c, n));
+              S.small_max, small_pass_n(c, n), c->opt.contract_mode == 1);
     }
     if (a.used > ws_bytes) return fail(MC_E_INVALID_ARG, "mc_mincut: workspace too small");
     SolveWS& w = S.w;
@@ -1337,6 +1337,8 @@ void carve_step(Arena& a, int32_t n, int64_t cap, int32_t passes, StepWS& w) {
     w.cl1 = a.take<int64_t>((size_t)n / 64 + 2);
     carve_private(a, n, passes, w.pv, w.psteps);
     carve_steps(a, n, cap, passes, 0, w.sa);
+    // the sort merge's workspace too, so that contract_mode can pick either
+    sort_ws_carve(a, n, cap, w.cw.sw);
 }
 
 mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws, size_t bytes, StepWS& w) {
@@ -1347,6 +1349,7 @@ mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws
     a.size = bytes;
     carve_step(a, n, cap, passes, w);
     if (a.used > bytes) return fail(MC_E_INVALID_ARG, "step: workspace too small");
+    w.cw.sorted = c->opt.contract_mode == 1;
     if (!contract_ws_reset(w.cw, c->stream)) return fail(MC_E_DEVICE, "step: workspace reset failed");
     return MC_OK;
 }

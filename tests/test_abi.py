@@ -102,7 +102,7 @@ def test_option_values_rejected_before_device_work():
     h = ctypes.c_void_p()
     for field, value in [("pr_tri_deg_cap", 65), ("pr_tri_deg_cap", -1), ("batch_pass_threads", 100),
                          ("batch_lp", 3), ("capforest_mode", 3), ("deterministic", 2), ("lp_iters", -1),
-                         ("finish_max_n", 1025), ("queue", 3)]:
+                         ("finish_max_n", 1025), ("queue", 3), ("contract_mode", 2), ("contract_mode", -1)]:
         o = mc.default_options(**{field: value})
         assert mc.lib().mc_ctx_create(0, None, ctypes.byref(o), ctypes.byref(h)) == -1, field
         assert field in mc.lib().mc_last_error().decode()

@@ -34,6 +34,21 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_sort():
+    """A context whose contractions merge by radix sort (contract_mode 1)."""
+    import paper_2609_07204_amd as mc
+    c = mc.Context(0, contract_mode=1)
+    yield c
+    c.close()
+
+
+@pytest.fixture(params=[0, 1], ids=["hash", "sort"])
+def cctx(request, ctx, ctx_sort):
+    """The context of each edge-merge mode."""
+    return ctx if request.param == 0 else ctx_sort
+
+
 def canon_dev(ctx, g):
     """Device padded graph of g with degrees filled (identity contraction)."""
     src = ctx.dgraph(g)
@@ -61,17 +76,18 @@ def raw_graph(n, m, seed, wmax=7):
 
 
 @pytest.mark.parametrize("n,m,seed", [(2, 1, 1), (5, 30, 2), (40, 300, 3), (700, 9000, 4), (3000, 60000, 5)])
-def test_normalise_matches_oracle(ctx, n, m, seed):
+def test_normalise_matches_oracle(cctx, n, m, seed):
     say("normalise", n, m, seed)
     g = raw_graph(n, m, seed)
-    dst, dmin, darg = canon_dev(ctx, g)
+    dst, dmin, darg = canon_dev(cctx, g)
     rp, col, w = oracle.contract(g, np.arange(n, dtype=np.int32), n)
     assert_same_csr(dst, rp, col, w)
     deg = oracle.degrees(g)
     assert dmin == deg.min() and darg == int(np.argmin(deg))
 
 
-def test_normalise_hub_rows(ctx):
+def test_normalise_hub_rows(cctx):
+    ctx = cctx
     # rows far longer than the chunk limit take the global-table path
     say("normalise hubs")
     r = gen.SplitMix64(9)
@@ -88,7 +104,8 @@ def test_normalise_hub_rows(ctx):
 
 
 @pytest.mark.parametrize("seed,n2frac", [(1, 0.5), (2, 0.05), (3, 0.9), (4, 0.002), (5, 1.0)])
-def test_contract_random_labels(ctx, seed, n2frac):
+def test_contract_random_labels(cctx, seed, n2frac):
+    ctx = cctx
     say("contract labels", seed, n2frac)
     g = gen.erdos_renyi(4000, 12 / 3999, seed, 1, 50, lcc=False)
     r = gen.SplitMix64(100 + seed)
@@ -105,7 +122,8 @@ def test_contract_random_labels(ctx, seed, n2frac):
     assert dmin == odeg.min() and darg == int(np.argmin(odeg))
 
 
-def test_contract_mixed_group_sizes(ctx):
+def test_contract_mixed_group_sizes(cctx):
+    ctx = cctx
     # one giant group, many tiny ones, and medium groups straddling the
     # small/large threshold
     say("contract mixed groups")
@@ -123,7 +141,8 @@ def test_contract_mixed_group_sizes(ctx):
     assert_same_csr(dst, rp, col, w)
 
 
-def test_contract_groups_around_workgroup_limits(ctx):
+def test_contract_groups_around_workgroup_limits(cctx):
+    ctx = cctx
     # groups of 150..1300 members at about three entries each: below, inside
     # and above the range merged by one workgroup per group (by entries, and
     # by members on both sides of 1024)
@@ -145,6 +164,39 @@ def test_contract_groups_around_workgroup_limits(ctx):
     assert_same_csr(dst, rp, col, w)
     odeg = np.array([w[rp[x]:rp[x + 1]].sum() for x in range(n2)])
     assert dmin == odeg.min() and darg == int(np.argmin(odeg))
+
+
+@pytest.mark.parametrize("n2,seed", [(3, 1), (50000, 2), (150000, 3)])
+def test_sort_merge_large_contractions(ctx_sort, n2, seed):
+    # many tiles, an even (4) and an odd (5) number of radix passes, runs of
+    # thousands of parallel entries (n2 = 3), labels in random order
+    say("sort merge", n2, seed)
+    g = gen.chung_lu(200000, 2.5, 10.0, seed, 1, 30, kcore=0, lcc=False)
+    rng = np.random.default_rng(seed)
+    lab = rng.integers(0, n2, g.n).astype(np.int32)
+    lab[:n2] = rng.permutation(n2).astype(np.int32)
+    import torch
+    src, _, _ = canon_dev(ctx_sort, g)
+    dst, dmin, darg = ctx_sort.step_contract(src, torch.as_tensor(lab).cuda(), n2)
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert_same_csr(dst, rp, col, w)
+    odeg = np.array([w[rp[x]:rp[x + 1]].sum() for x in range(n2)])
+    assert dmin == odeg.min() and darg == int(np.argmin(odeg))
+
+
+def test_solves_with_sort_merge(ctx_sort):
+    # whole solves whose every contraction merges by sorting
+    cases = [(gen.config_planted_2x1000(), 5), (gen.wheel(300), 598), (gen.two_cliques(40, 50, 3), 3),
+             (gen.disjoint_union(gen.complete(6), gen.cycle([2, 3, 4])), 0)]
+    for g, lam in cases:
+        say("sort-merge solve", g.name)
+        solve_check(ctx_sort, g, lam)
+        solve_check(ctx_sort, g, lam, device_input=True)
+    for g in (gen.chung_lu(30000, 2.5, 12.0, 17, 1, 50, kcore=3, lcc=True),
+              gen.rhg(20000, 16, 3.0, 5, 1, 100, kcore=0, lcc=True),
+              gen.mixed_graph(5000, 16, 1, 6, 1, 1000)):
+        say("sort-merge solve", g.name, g.n)
+        solve_check(ctx_sort, g, oracle.noi(g)[0])
 
 
 # ---------------------------------------------------------- union-find
