@@ -212,8 +212,10 @@ def batch_run(ctx, gs, tune_gs, steps, warmup, plain=True, cpu_seconds=15.0, fix
         t = time.time()
         tuning = ctx.batch_autotune(devs=tdevs, workspace=ws, sample=len(tdevs))
         tuning["seconds"] = time.time() - t
-        log("autotune on a separate batch (%d graphs, %.1fs): pass threads %d, admission bound %s" % (
-            tuning["sample"], tuning["seconds"], tuning["pass_threads"], "on" if tuning["lp"] == 1 else "off"))
+        log("autotune on a separate batch (%d graphs, %.1fs): pass threads %d, admission bound %s, "
+            "finisher limit %d, queue %d" % (tuning["sample"], tuning["seconds"], tuning["pass_threads"],
+                                             "on" if tuning["lp"] == 1 else "off", tuning["finish_max_n"],
+                                             tuning["queue"]))
         del tdevs, ws
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=ctx.device)
     torch.cuda.synchronize()

@@ -226,13 +226,15 @@ mc_status mc_mincut_batch(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* de
 /* Autotuner of the batched form. Solves a sample of the batch (`sample`
  * graphs: the sample/8 largest by entries, since a batch takes as long as
  * its largest graphs' passes, and the rest spread evenly over the k given;
- * all of them when sample <= 0 or >= k) twice per candidate setting - every
- * pass workgroup size of batch_pass_threads, with and without the admission
- * bound of batch_lp - after one untimed run, times each (wall clock around
- * the synchronised call, the faster of the two), and stores the fastest
- * setting in the context's options (the
- * other options are left as they are). The results of the sample solves
- * are discarded; a setting changes only the speed, never a result.
+ * all of them when sample <= 0 or >= k) twice per candidate setting, after
+ * one untimed run, times each (wall clock around the synchronised call,
+ * the faster of the two), and stores the fastest setting in the context's
+ * options (the other options are left as they are). Two stages: every pass
+ * workgroup size of batch_pass_threads, with and without the admission
+ * bound of batch_lp; then, with the best of those, the finisher's size
+ * limit (finish_max_n 1024, 512, 256, or no finisher) and its queue (queue
+ * 0, 1, 2 at the best limit). The results of the sample solves are
+ * discarded; a setting changes only the speed, never a result.
  * dev_workspace must hold mc_batch_workspace_size of the whole batch (the
  * sample needs less). On error the options are left unchanged. */
 #define MC_TUNE_MAX 16
@@ -244,6 +246,10 @@ typedef struct {
     int32_t cand_threads[MC_TUNE_MAX];
     int32_t cand_lp[MC_TUNE_MAX];
     double cand_ms[MC_TUNE_MAX];  /* wall time of each setting on the sample */
+    int32_t finish_max_n;      /* chosen finish_max_n (-1: no finisher) */
+    int32_t queue;             /* chosen queue */
+    int32_t cand_finish[MC_TUNE_MAX];
+    int32_t cand_queue[MC_TUNE_MAX];
 } mc_tuning;
 mc_status mc_batch_autotune(mc_ctx* ctx, int32_t k, const mc_csr* graphs, void* dev_workspace, size_t ws_bytes,
                             int32_t sample, mc_tuning* out);

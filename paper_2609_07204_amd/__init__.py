@@ -60,7 +60,9 @@ MC_TUNE_MAX = 16
 class Tuning(ctypes.Structure):
     _fields_ = [("pass_threads", ctypes.c_int32), ("lp", ctypes.c_int32), ("sample", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("cand_threads", ctypes.c_int32 * MC_TUNE_MAX),
-                ("cand_lp", ctypes.c_int32 * MC_TUNE_MAX), ("cand_ms", ctypes.c_double * MC_TUNE_MAX)]
+                ("cand_lp", ctypes.c_int32 * MC_TUNE_MAX), ("cand_ms", ctypes.c_double * MC_TUNE_MAX),
+                ("finish_max_n", ctypes.c_int32), ("queue", ctypes.c_int32),
+                ("cand_finish", ctypes.c_int32 * MC_TUNE_MAX), ("cand_queue", ctypes.c_int32 * MC_TUNE_MAX)]
 
 
 class RoundTime(ctypes.Structure):
@@ -303,8 +305,9 @@ class Context:
 
     def batch_autotune(self, graphs=None, devs=None, workspace=None, sample=0):
         """Time the batched form on a spread sample of the batch under every
-        pass workgroup size, with and without the admission bound, and keep
-        the fastest in this context (mc_batch_autotune). Returns the timings."""
+        pass workgroup size, with and without the admission bound, then the
+        finisher's size limit and queue, and keep the fastest in this context
+        (mc_batch_autotune). Returns the timings."""
         torch = _torch()
         arr, keep = self._csr_array(graphs, devs)
         k = len(arr)
@@ -318,8 +321,12 @@ class Context:
         del keep
         self.options.batch_pass_threads = t.pass_threads
         self.options.batch_lp = t.lp
-        return {"pass_threads": t.pass_threads, "lp": t.lp, "sample": t.sample,
-                "candidates": [{"pass_threads": t.cand_threads[i], "lp": t.cand_lp[i], "ms": t.cand_ms[i]}
+        self.options.finish_max_n = t.finish_max_n
+        self.options.queue = t.queue
+        return {"pass_threads": t.pass_threads, "lp": t.lp, "finish_max_n": t.finish_max_n, "queue": t.queue,
+                "sample": t.sample,
+                "candidates": [{"pass_threads": t.cand_threads[i], "lp": t.cand_lp[i],
+                                "finish_max_n": t.cand_finish[i], "queue": t.cand_queue[i], "ms": t.cand_ms[i]}
                                for i in range(t.candidates)]}
 
     # ------------------------------------------------------------ timing

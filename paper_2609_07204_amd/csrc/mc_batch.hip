@@ -408,7 +408,7 @@ struct EngineWS {
     PrivateArgs pv;
     unsigned long long* pmarks;
     unsigned long long* vpart;
-    int32_t *flist, *fdrop, *frounds, *ferr;   // finisher: graphs, lowered bound, rounds, error
+    int32_t *flist, *fdrop, *frounds, *ferr;   // finisher: graphs, lowered bound, rounds, error and work-queue ticket
     uint8_t* fside;           // [N] the finisher's side over the current vertices
 };
 
@@ -841,7 +841,7 @@ struct Engine {
         const int32_t nf = (int32_t)flist.size();
         if (nf > 0) {
             EG_HIP(hipMemcpyAsync(w.flist, flist.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, s));
-            EG_OK(fill_i32(w.ferr, 0, 1, s));
+            EG_OK(fill_i32(w.ferr, 0, 2, s));
             FinishArgs fa{};
             fa.g = G;
             fa.gvoff = w.voff;
@@ -858,8 +858,9 @@ struct Engine {
             fa.seed = c->opt.seed ^ ((uint64_t)(uint32_t)round << 20);
             fa.rounds = w.frounds;
             fa.err = w.ferr;
+            fa.qnext = w.ferr + 1;
             fa.qmode = c->opt.queue;
-            EG_OK(finish_graphs(fa, nf, s));
+            EG_OK(finish_graphs(fa, nf, c->cus, s));
             k_bg_fin_snap<<<grid_for(nf, 256), 256, 0, s>>>(w.flist, nf, w.fdrop, w.snap);
             EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_fin_snap"));
         }
@@ -1173,30 +1174,71 @@ extern "C" mc_status mc_batch_autotune(mc_ctx* c, int32_t k, const mc_csr* gs, v
     mc_status r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
     if (r != MC_OK) { c->opt = saved; return r; }
     double best = 0;
+    // the faster of two synchronised runs of the sample with the current options
+    auto timed = [&](double* ms) -> mc_status {
+        *ms = 0;
+        for (int rep = 0; rep < 2; rep++) {
+            if (hipStreamSynchronize(c->stream) != hipSuccess) return mc_fail(MC_E_DEVICE, "mc_batch_autotune: sync");
+            const auto t0 = std::chrono::steady_clock::now();
+            const mc_status rr = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
+            if (rr != MC_OK) return rr;
+            const double t1 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            *ms = rep == 0 || t1 < *ms ? t1 : *ms;
+        }
+        return MC_OK;
+    };
+    auto record = [&](double ms) {
+        const int32_t j = t.candidates++;
+        t.cand_threads[j] = c->opt.batch_pass_threads;
+        t.cand_lp[j] = c->opt.batch_lp;
+        t.cand_finish[j] = c->opt.finish_max_n;
+        t.cand_queue[j] = c->opt.queue;
+        t.cand_ms[j] = ms;
+        if (j == 0 || ms < best) {
+            best = ms;
+            t.pass_threads = c->opt.batch_pass_threads;
+            t.lp = c->opt.batch_lp;
+            t.finish_max_n = c->opt.finish_max_n;
+            t.queue = c->opt.queue;
+        }
+    };
+    // stage 1: pass workgroup size and admission bound
     for (int32_t lp = 1; lp <= 2; lp++) {
         for (int32_t th : threads) {
             c->opt.batch_pass_threads = th;
             c->opt.batch_lp = lp;
-            double ms = 0;
-            for (int rep = 0; rep < 2; rep++) {
-                if (hipStreamSynchronize(c->stream) != hipSuccess) { c->opt = saved; return mc_fail(MC_E_DEVICE, "sync"); }
-                const auto t0 = std::chrono::steady_clock::now();
-                r = mc_mincut_batch(c, m, sub.data(), dev_ws, ws_bytes, lam.data(), nullptr, nullptr);
-                if (r != MC_OK) { c->opt = saved; return r; }
-                const double t1 =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                ms = rep == 0 || t1 < ms ? t1 : ms;
-            }
-            const int32_t j = t.candidates++;
-            t.cand_threads[j] = th;
-            t.cand_lp[j] = lp;
-            t.cand_ms[j] = ms;
-            if (j == 0 || ms < best) { best = ms; t.pass_threads = th; t.lp = lp; }
+            double ms;
+            if ((r = timed(&ms)) != MC_OK) { c->opt = saved; return r; }
+            record(ms);
+        }
+    }
+    // stage 2: the finisher's size limit, then its queue
+    c->opt.batch_pass_threads = t.pass_threads;
+    c->opt.batch_lp = t.lp;
+    static const int32_t limits[] = {512, 256, -1};
+    for (int32_t f : limits) {
+        c->opt.finish_max_n = f;
+        c->opt.queue = t.queue;
+        double ms;
+        if ((r = timed(&ms)) != MC_OK) { c->opt = saved; return r; }
+        record(ms);
+    }
+    if (t.finish_max_n >= 0) {
+        const int32_t q0 = t.queue;
+        for (int32_t q = 0; q <= 2; q++) {
+            if (q == q0) continue;
+            c->opt.finish_max_n = t.finish_max_n;
+            c->opt.queue = q;
+            double ms;
+            if ((r = timed(&ms)) != MC_OK) { c->opt = saved; return r; }
+            record(ms);
         }
     }
     c->opt = saved;
     c->opt.batch_pass_threads = t.pass_threads;
     c->opt.batch_lp = t.lp;
+    c->opt.finish_max_n = t.finish_max_n;
+    c->opt.queue = t.queue;
     *out = t;
     return MC_OK;
 }

@@ -373,12 +373,9 @@ __device__ void block_scan_lds(const int32_t* a, int32_t* out, int32_t n, FinLds
 
 }  // namespace
 
-__global__ __launch_bounds__(FT) void k_finish(FinishArgs a) {
-    __shared__ FinLds S;
-    __shared__ int32_t scal[8];
-    __shared__ int64_t sc64[4];
+// All remaining rounds of graph k by one workgroup (see the file comment).
+static __device__ __forceinline__ void finish_one(const FinishArgs& a, int32_t k, FinLds& S, int32_t* scal, int64_t* sc64) {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid / MC_WAVE;
-    const int32_t k = a.glist ? a.glist[blockIdx.x] : (int32_t)blockIdx.x;
     const int32_t vb = a.gvoff ? a.gvoff[k] : 0;
     const int32_t n0 = a.gvoff ? a.gvoff[k + 1] - vb : a.g.n;
     int64_t lam = a.lam_in[k];
@@ -573,6 +570,26 @@ __global__ __launch_bounds__(FT) void k_finish(FinishArgs a) {
         for (int32_t u = tid; u < n0; u += FT) a.fside[vb + u] = S.bestf[u];
 }
 
+// One persistent launch over a work queue: each workgroup takes the next
+// graph of the list (an atomic ticket) until the list is used up, so a
+// launch of as many workgroups as fit the device serves any number of
+// graphs, and a workgroup that drew small graphs takes more of them.
+__global__ __launch_bounds__(FT) void k_finish(FinishArgs a, int32_t count) {
+    __shared__ FinLds S;
+    __shared__ int32_t scal[8];
+    __shared__ int64_t sc64[4];
+    __shared__ int32_t ticket;
+    for (;;) {
+        if (threadIdx.x == 0) ticket = atomicAdd(a.qnext, 1);
+        __syncthreads();
+        const int32_t i = ticket;
+        __syncthreads();
+        if (i >= count) break;
+        finish_one(a, a.glist ? a.glist[i] : i, S, scal, sc64);
+        __syncthreads();
+    }
+}
+
 // One pass of the finisher's CAPFOREST on its own (parity and measurement):
 // graph g (n <= FIN_N, rows at off/len, local targets), from `start` at
 // bound lam, with the queue of qmode (1 buckets, 2 heap). Writes the marks
@@ -611,9 +628,11 @@ __global__ __launch_bounds__(FT) void k_fin_pass(DGraph g, int32_t start, int32_
     }
 }
 
-bool finish_graphs(const FinishArgs& a, int32_t count, hipStream_t s) {
+bool finish_graphs(const FinishArgs& a, int32_t count, int32_t cus, hipStream_t s) {
     if (count <= 0) return true;
-    k_finish<<<count, FT, 0, s>>>(a);
+    // one workgroup per compute unit at most (the LDS holds one)
+    const int32_t grid = count < cus ? count : cus;
+    k_finish<<<grid, FT, 0, s>>>(a, count);
     MC_LAUNCHED("k_finish");
     return true;
 }

@@ -389,8 +389,11 @@ struct FinishArgs {
     int32_t* rounds;          // [K] rounds taken (may be nullptr)
     int32_t* err;             // [1] 0, or why a graph could not finish
     int32_t qmode;            // 0 buckets while lam < 2048 else heap, 1 buckets, 2 heap
+    int32_t* qnext;           // [1] work-queue ticket, 0 at the launch
 };
-bool finish_graphs(const FinishArgs& a, int32_t count, hipStream_t s);
+// count graphs of a.glist, by at most `cus` persistent workgroups that draw
+// the graphs from a work queue (a.qnext must be 0)
+bool finish_graphs(const FinishArgs& a, int32_t count, int32_t cus, hipStream_t s);
 // one pass of the finisher's CAPFOREST (step ABI): see k_fin_pass
 bool finish_pass(const DGraph& g, int32_t start, int32_t qmode, int64_t* lam_io, int64_t* best_alpha,
                  int32_t* parent, int32_t* order, int32_t* nscan, int32_t* best_len, hipStream_t s);

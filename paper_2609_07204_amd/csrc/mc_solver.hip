@@ -380,7 +380,7 @@ struct SolveWS {
     unsigned long long* vpart = nullptr;
     int32_t* vpart_i32() { return reinterpret_cast<int32_t*>(vpart); }
     int64_t* fin64 = nullptr;     // [2] finisher: bound in, bound out
-    int32_t* fin32 = nullptr;     // [4] finisher: dropped, rounds, error
+    int32_t* fin32 = nullptr;     // [4] finisher: dropped, rounds, error, work-queue ticket
     int32_t* fx_col[2] = {nullptr, nullptr};   // finisher scratch graphs
     int64_t* fx_w[2] = {nullptr, nullptr};
 };
@@ -808,6 +808,7 @@ static mc_status finish(Solver& S, DGraph* cur, int32_t round) {
     fa.dropped = w.fin32;
     fa.rounds = w.fin32 + 1;
     fa.err = w.fin32 + 2;
+    fa.qnext = w.fin32 + 3;
     fa.fside = w.flag8;
     for (int q = 0; q < 2; q++) {
         fa.xcol[q] = w.fx_col[q];
@@ -816,7 +817,7 @@ static mc_status finish(Solver& S, DGraph* cur, int32_t round) {
     fa.xwindow = 0;
     fa.seed = S.c->opt.seed ^ ((uint64_t)(uint32_t)round << 20);
     fa.qmode = S.c->opt.deterministic ? 2 : S.c->opt.queue;
-    if (!fill_i32(w.fin32, 0, 4, s) || !finish_graphs(fa, 1, s)) return MC_E_DEVICE;
+    if (!fill_i32(w.fin32, 0, 4, s) || !finish_graphs(fa, 1, S.c->cus, s)) return MC_E_DEVICE;
     int64_t lam_out = 0;
     int32_t r32[4] = {0, 0, 0, 0};
     if (hipMemcpyAsync(&lam_out, w.fin64, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||

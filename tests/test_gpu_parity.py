@@ -835,7 +835,7 @@ def test_batch_pass_sizes_match_oracle(ctx, threads, lp):
     try:
         lams, sides = ctx.mincut_batch(gs)
     finally:
-        ctx.set_options(batch_pass_threads=0, batch_lp=0)
+        ctx.set_options(batch_pass_threads=0, batch_lp=0, finish_max_n=0, queue=0)
     bad = [(i, gs[i].name) for i, g in enumerate(gs)
            if lams[i] != oracle_lambda(g) or oracle.cut_value(g, sides[i]) != lams[i] or sides[i][0] != 0]
     assert not bad, bad[:5]
@@ -845,19 +845,24 @@ def test_batch_autotune_picks_a_setting_and_keeps_results(ctx):
     import paper_2609_07204_amd as mc
     gs = batch_mix(31, 200)
     t = ctx.batch_autotune(gs, sample=80)
-    say("autotune", t["pass_threads"], t["lp"], [round(c["ms"], 2) for c in t["candidates"]])
-    assert t["sample"] == 80 and len(t["candidates"]) == 10
+    say("autotune", t["pass_threads"], t["lp"], t["finish_max_n"], t["queue"],
+        [round(c["ms"], 2) for c in t["candidates"]])
+    # 10 pass settings, 3 finisher limits, and the 2 other queues unless the
+    # finisher lost
+    assert t["sample"] == 80 and len(t["candidates"]) in (13, 15)
     assert t["pass_threads"] in (64, 128, 256, 512, 1024) and t["lp"] in (1, 2)
+    assert t["finish_max_n"] in (0, 512, 256, -1) and t["queue"] in (0, 1, 2)
     assert all(c["ms"] > 0 for c in t["candidates"])
     best = min(t["candidates"], key=lambda c: c["ms"])
-    assert (best["pass_threads"], best["lp"]) == (t["pass_threads"], t["lp"])
+    assert (best["pass_threads"], best["lp"], best["finish_max_n"], best["queue"]) == \
+        (t["pass_threads"], t["lp"], t["finish_max_n"], t["queue"])
     try:
         lams, sides = ctx.mincut_batch(gs)
         assert all(lams[i] == oracle_lambda(g) and oracle.cut_value(g, sides[i]) == lams[i] for i, g in enumerate(gs))
         with pytest.raises(mc.MincutError):
             ctx.set_options(batch_pass_threads=100)
     finally:
-        ctx.set_options(batch_pass_threads=0, batch_lp=0)
+        ctx.set_options(batch_pass_threads=0, batch_lp=0, finish_max_n=0, queue=0)
 
 
 def test_batch_device_input_same_as_host(ctx):
