@@ -579,7 +579,28 @@ __global__ __launch_bounds__(T) void k_cfs_end(StepArgs a) {
 
 }  // namespace
 
-bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
+// the kernels of one whole-GPU step
+static bool launch_step(const StepArgs& a, int hub_blocks, int tile_blocks, bool timed, hipStream_t s) {
+    k_cfs_popscan<<<POP_BLOCKS, POP_T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_popscan");
+    k_cfs_plan<<<a.pv.passes, T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_plan");
+    k_cfs_tiles<<<1, T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_tiles");
+    k_cfs_tileinfo<<<tile_blocks, 256, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_tileinfo");
+    if (timed) prof_begin(PK_CFS_EDGES, s);
+    k_cfs_edges<<<4096, ET, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_edges");
+    if (timed) prof_end(PK_CFS_EDGES, s);
+    k_cfs_hubfix<<<hub_blocks, 256, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_hubfix");
+    k_cfs_finish<<<a.pv.passes, T, 0, s>>>(a);
+    MC_LAUNCHED("k_cfs_finish");
+    return true;
+}
+
+bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s, hipStream_t cap) {
     const int32_t P = a.pv.passes;
     if (P <= 0) return true;
     if (a.pv.g.n > a.pv.stride) {
@@ -596,32 +617,45 @@ bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s) {
     const int tile_blocks = std::max(1, std::min<int>((int)((a.max_tiles + 255) / 256), 1024));
     k_cfs_init<<<P, T, 0, s>>>(a);
     MC_LAUNCHED("k_cfs_init");
+    // Steps run in groups of `poll` between two reads of the running flag
+    // (a finished pass leaves later steps with nothing to do). A group's
+    // launches take the same arguments every time (the state is on the
+    // device), so with kernel timing off it is captured once as a HIP graph
+    // and replayed: one graph launch instead of 7 * poll kernel launches.
     const int poll = 4;
-    a.steps_run = 0;
-    for (int32_t step = 0;; step++) {
-        a.steps_run = step + 1;
-        k_cfs_popscan<<<POP_BLOCKS, POP_T, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_popscan");
-        k_cfs_plan<<<P, T, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_plan");
-        k_cfs_tiles<<<1, T, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_tiles");
-        k_cfs_tileinfo<<<tile_blocks, 256, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_tileinfo");
-        prof_begin(PK_CFS_EDGES, s);
-        k_cfs_edges<<<4096, ET, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_edges");
-        prof_end(PK_CFS_EDGES, s);
-        k_cfs_hubfix<<<hub_blocks, 256, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_hubfix");
-        k_cfs_finish<<<P, T, 0, s>>>(a);
-        MC_LAUNCHED("k_cfs_finish");
-        if (step % poll == poll - 1) {
-            MC_HIP(hipMemcpyAsync(running_host, a.running, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            MC_HIP(hipStreamSynchronize(s));
-            if (*running_host == 0) break;
+    const bool timed = a.prof != nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (cap && !timed) {
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int k = 0; ok && k < poll; k++) ok = launch_step(a, hub_blocks, tile_blocks, false, cap);
+        ok = hipStreamEndCapture(cap, &graph) == hipSuccess && ok;
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            // no graph: the eager launches below (clear the capture's error)
+            exec = nullptr;
+            (void)hipGetLastError();
         }
-        if (step > 4 * (int64_t)a.pv.g.n + 64) {
+    }
+    a.steps_run = 0;
+    for (int32_t step = 0;; step += poll) {
+        a.steps_run = step + poll;
+        if (exec) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return mc_hip_ok(hipErrorUnknown, "capforest_steps: graph launch failed");
+            }
+        } else {
+            for (int k = 0; k < poll; k++)
+                if (!launch_step(a, hub_blocks, tile_blocks, timed, s)) return false;
+        }
+        bool fail = hipMemcpyAsync(running_host, a.running, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess;
+        if (fail || *running_host == 0 || step > 4 * (int64_t)a.pv.g.n + 64) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (fail) return mc_hip_ok(hipErrorUnknown, "capforest_steps: poll failed");
+            if (*running_host == 0) break;
             mc_hip_ok(hipErrorUnknown, "capforest_steps: no progress");
             return false;
         }

@@ -363,7 +363,10 @@ struct StepArgs {
 constexpr int HUB_LEN = 512;
 constexpr int HUB_SLOTS = 16;
 
-bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s);
+// With cap (a non-default stream of the caller's device) and kernel timing
+// off, each group of steps between two polls is captured once as a HIP
+// graph on cap and replayed on s.
+bool capforest_steps(StepArgs& a, int32_t* running_host, hipStream_t s, hipStream_t cap = nullptr);
 
 // ------------------------------------------------------------ finisher
 // Device-resident exact rounds for graphs of at most FIN_N vertices: one
@@ -440,4 +443,6 @@ struct mc_ctx {
     int32_t tag = 0;             // round tag for visited arrays (never reset)
     void* prof = nullptr;        // kernel timing (mc_profile), owned by the solver file
     void* scratch = nullptr;     // device address of this GPU's static scratch (mc_mincut_static)
+    hipStream_t cap_stream = nullptr;   // private stream the step graphs are captured on (made at first use)
+    bool graphs_off = false;     // no graph capture (set while mc_mincut_static runs)
 };

@@ -254,6 +254,7 @@ extern "C" mc_status mc_ctx_create(int device, void* hip_stream, const mc_option
 
 extern "C" mc_status mc_ctx_destroy(mc_ctx* c) {
     if (!c) return MC_OK;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->hsc) (void)hipHostFree(c->hsc);
     delete static_cast<Prof*>(c->prof);
     delete c;
@@ -726,6 +727,18 @@ static bool sequential_pass(Solver& S, const DGraph& g, int32_t round) {
 }
 
 // `passes` private batched passes over g (len_cap 0: complete), results in sc.
+// the context's private stream for graph capture (null: capture off, or the
+// stream could not be made)
+static hipStream_t capture_stream(mc_ctx* c) {
+    if (c->graphs_off) return nullptr;
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        c->graphs_off = true;
+        (void)hipGetLastError();
+    }
+    return c->cap_stream;
+}
+
 static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t passes, int32_t len_cap) {
     SolveWS& w = S.w;
     // every pass leaves its state cleared, so one clear per solve suffices,
@@ -775,7 +788,7 @@ static bool private_passes(Solver& S, const DGraph& g, int32_t round, int32_t pa
         // per whole-GPU step; bound such runs (the complete fallback pass is
         // never bounded)
         sa.max_singles = len_cap > 0 ? 256 : 0;
-        if (!capforest_steps(sa, &running, S.s)) return false;
+        if (!capforest_steps(sa, &running, S.s, capture_stream(S.c))) return false;
         S.last_cf_steps = sa.steps_run;
         S.last_cf_scans = sa.scans_run;
     } else if (!capforest_private(pa, S.s)) {
@@ -1272,11 +1285,15 @@ extern "C" mc_status mc_mincut_static(mc_ctx* c, const mc_csr* g, int64_t* lambd
         return fail(MC_E_INVALID_ARG, "mc_mincut_static: the graph needs " + std::to_string(need) +
                                           " bytes of scratch, more than the static " +
                                           std::to_string(kStaticScratchBytes) + " (use mc_mincut with a workspace)");
-    // kernel timing is suspended for the call: its event pool could allocate
+    // kernel timing and graph capture are suspended for the call: the event
+    // pool and graph instantiation could allocate
     void* prof = c->prof;
+    const bool graphs_off = c->graphs_off;
     c->prof = nullptr;
+    c->graphs_off = true;
     r = mc_mincut(c, g, c->scratch, kStaticScratchBytes, lambda, side_out, st);
     c->prof = prof;
+    c->graphs_off = graphs_off;
     return r;
 }
 

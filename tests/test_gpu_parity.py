@@ -579,6 +579,27 @@ def test_solver_levels_with_hubs(ctx, seed, wmax):
     c.close()
 
 
+def test_capforest_step_graphs_match_eager_steps():
+    # whole-GPU CAPFOREST steps replayed from captured HIP graphs (timing
+    # off) and launched one by one (timing on): several solves in a row,
+    # each with several replays per round, all equal to the oracle
+    import paper_2609_07204_amd as mc
+    c = mc.Context(0, levels_min_n=1000)
+    graphs = [gen.chung_lu(1 << 14, 2.5, 12.0, 21, 1, 20, kcore=3, lcc=True),
+              gen.mixed_graph(6000, 12, 1, 8, 1, 100), hub_graph(4000, 3, 1500, 6, 7, 1, 50)]
+    for rep in range(2):
+        for g in graphs:
+            ref = oracle.noi(g)[0]
+            c.profile(True)
+            lam_e, side_e, st_e = c.mincut(g, return_stats=True)
+            c.profile(False)
+            lam_g, side_g, st_g = c.mincut(g, return_stats=True)
+            say("step graphs", g.name, rep, lam_g, st_e["rounds"], st_g["rounds"])
+            assert lam_e == lam_g == ref
+            assert oracle.cut_value(g, side_e) == ref and oracle.cut_value(g, side_g) == ref
+    c.close()
+
+
 @pytest.mark.parametrize("log2n,seed", [(16, 3), (17, 5)])
 def test_solver_levels_chung_lu_hubs(ctx, log2n, seed):
     # power-law graphs whose hubs (rows of 512 entries or more) take the
