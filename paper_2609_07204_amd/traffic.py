@@ -48,6 +48,8 @@ def per_kernel(d, counter):
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].strip()
+            if name.startswith("void "):   # template instances are named with their return type
+                name = name[5:]
             out.setdefault(name, []).append(float(r["Counter_Value"]))
     return out
 
