@@ -341,11 +341,14 @@ enum {
     MC_K_GROUP_SCATTER = 4,    /* k_group_scatter: members grouped by label */
     MC_K_PR12 = 5,             /* k_pr12: reduction tests 1 and 2 */
     MC_K_CONNECT_LINK = 6,     /* k_uf_link_rest: connectivity unions */
-    MC_K_LP_SMALL = 7,         /* k_lp_small: label-propagation round, rows of <= 512 entries */
+    MC_K_LP_SMALL = 7,         /* k_lp_small: label-propagation round, rows of <= 256 entries */
     MC_K_LP_FIRST = 8,         /* k_lp_first: first label-propagation round (from singletons) */
-    MC_K_MID_MERGE = 9,        /* k_mid_merge: contraction of groups of 513..2048 entries */
-    MC_K_PR1_FIRST = 10,       /* k_pr1_first: unions of every row's first two test-1 entries */
-    MC_K_PR1_REST = 11,        /* k_pr1_rest: unions of the remaining test-1 entries */
+    MC_K_MID_MERGE = 9,        /* k_mid_merge<2048>, k_mid_merge<4096>: contraction of groups of
+                                  513..2048 entries */
+    MC_K_PR1_FIRST = 10,       /* k_pr1_first: link rounds of every row's first and second test-1
+                                  entries */
+    MC_K_PR1_REST = 11,        /* k_pr1_trees (at most 255 trees) or k_pr1_rest: linking of the
+                                  trees those rounds leave */
     MC_K_COUNT = 12
 };
 typedef struct {
