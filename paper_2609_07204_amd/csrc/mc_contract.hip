@@ -745,45 +745,58 @@ __global__ void k_big_finalize(const int32_t* __restrict__ bebase, int32_t n2, c
         if (bebase[g + 1] > bebase[g]) dst.len[g] = bcur[g];
 }
 
-// minimum degree, ties to the smallest vertex, and the entry count:
-// per-block partials, then one block folds them
+// minimum degree, ties to the smallest vertex, the entry count and the
+// maximum degree: per-block partials, then one block folds them
 __global__ __launch_bounds__(256) void k_min_deg_blocks(const int64_t* __restrict__ deg,
                                                        const int32_t* __restrict__ len, int32_t n,
                                                        int64_t* __restrict__ rv, int32_t* __restrict__ ri,
-                                                       int64_t* __restrict__ rm) {
-    __shared__ int64_t sv[4], sm[4];
+                                                       int64_t* __restrict__ rm, int64_t* __restrict__ rd) {
+    __shared__ int64_t sv[4], sm[4], sd[4];
     __shared__ int32_t si[4];
-    int64_t best = 0, m = 0;
+    int64_t best = 0, m = 0, dmax = 0;
     int32_t bid = -1;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = deg[v];
         m += len[v];
+        dmax = d > dmax ? d : dmax;
         if (bid < 0 || d < best) { best = d; bid = (int32_t)v; }
     }
     wave_argmin(best, bid);
     m = wave_sum_i64(m);
-    if (lane_id() == 0) { sv[threadIdx.x / MC_WAVE] = best; si[threadIdx.x / MC_WAVE] = bid; sm[threadIdx.x / MC_WAVE] = m; }
+    dmax = wave_max_i64(dmax);
+    if (lane_id() == 0) {
+        const int wv = threadIdx.x / MC_WAVE;
+        sv[wv] = best; si[wv] = bid; sm[wv] = m; sd[wv] = dmax;
+    }
     __syncthreads();
     if (threadIdx.x < MC_WAVE) {
         int64_t b = threadIdx.x < 4 ? sv[threadIdx.x] : 0;
         int32_t i = threadIdx.x < 4 ? si[threadIdx.x] : -1;
         wave_argmin(b, i);
-        if (threadIdx.x == 0) { rv[blockIdx.x] = b; ri[blockIdx.x] = i; rm[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3]; }
+        if (threadIdx.x == 0) {
+            rv[blockIdx.x] = b; ri[blockIdx.x] = i;
+            rm[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+            const int64_t a = sd[0] > sd[1] ? sd[0] : sd[1], b = sd[2] > sd[3] ? sd[2] : sd[3];
+            rd[blockIdx.x] = a > b ? a : b;
+        }
     }
 }
 
 __global__ __launch_bounds__(64) void k_min_deg_final(const int64_t* __restrict__ rv, const int32_t* __restrict__ ri,
-                                                     const int64_t* __restrict__ rm, int nblocks, DevScalars* sc) {
-    int64_t best = 0, m = 0;
+                                                     const int64_t* __restrict__ rm, const int64_t* __restrict__ rd,
+                                                     int nblocks, DevScalars* sc) {
+    int64_t best = 0, m = 0, dmax = 0;
     int32_t bid = -1;
     for (int i = threadIdx.x; i < nblocks; i += MC_WAVE) {
         int32_t id = ri[i];
         m += rm[i];
+        dmax = rd[i] > dmax ? rd[i] : dmax;
         if (id >= 0 && (bid < 0 || rv[i] < best || (rv[i] == best && id < bid))) { best = rv[i]; bid = id; }
     }
     wave_argmin(best, bid);
     m = wave_sum_i64(m);
-    if (threadIdx.x == 0) { sc->dmin = best; sc->dmin_arg = bid; sc->m2 = m; }
+    dmax = wave_max_i64(dmax);
+    if (threadIdx.x == 0) { sc->dmin = best; sc->dmin_arg = bid; sc->m2 = m; sc->dmax = dmax; }
 }
 
 inline int grid_for(int64_t count, int threads, int cap = 8192) {
@@ -823,6 +836,7 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool so
     ws.red_val = a.take<int64_t>(1024);
     ws.red_id = a.take<int32_t>(1024);
     ws.red_m = a.take<int64_t>(1024);
+    ws.red_d = a.take<int64_t>(1024);
     ws.cg = a.take<int32_t>((size_t)((cap + n) / CHUNK) + 4);
     ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
     ws.xg = a.take<int32_t>(slots / TILE_SLOTS + 8);
@@ -834,9 +848,9 @@ bool contract_ws_reset(const ContractWS& ws, hipStream_t s) { return fill_i64(ws
 
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) {
     int nb = grid_for(g.n, 256, 1024);
-    k_min_deg_blocks<<<nb, 256, 0, s>>>(g.deg, g.len, g.n, ws.red_val, ws.red_id, ws.red_m);
+    k_min_deg_blocks<<<nb, 256, 0, s>>>(g.deg, g.len, g.n, ws.red_val, ws.red_id, ws.red_m, ws.red_d);
     MC_LAUNCHED("k_min_deg_blocks");
-    k_min_deg_final<<<1, 64, 0, s>>>(ws.red_val, ws.red_id, ws.red_m, nb, sc);
+    k_min_deg_final<<<1, 64, 0, s>>>(ws.red_val, ws.red_id, ws.red_m, ws.red_d, nb, sc);
     MC_LAUNCHED("k_min_deg_final");
     return true;
 }

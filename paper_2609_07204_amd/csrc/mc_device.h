@@ -37,7 +37,7 @@ struct DevScalars {
     int32_t n2;             // vertex count after relabelling
     int32_t err;            // validation error code (0 = fine)
     int32_t noncanon;       // 1: the input CSR needs the merging normalisation
-    int32_t pad[2];
+    int64_t dmax;           // maximum degree of the graph the last min_degree read
 };
 
 // ------------------------------------------------------------- atomics
@@ -108,6 +108,13 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // ------------------------------------------------- wave reductions
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
     return v;
 }
 __device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {

@@ -70,19 +70,21 @@ __device__ __forceinline__ uint32_t lp_hash(uint32_t gl, uint32_t lbl) { return 
 
 // Entries [j0, j1) of row v (chunk-local gl) into the chunk's LDS table by
 // the LP_SUB lanes of a lane group: four entries per lane at a time, so
-// their loads, then their labels' loads, are in flight together.
+// their loads, then their labels' loads, are in flight together. V holds a
+// table sum: 32 bits when every row's degree is below 2^32.
+template <typename V>
 __device__ __forceinline__ void lp_insert(const DGraph& g, const int32_t* __restrict__ lab_in, int32_t v, int gl,
                                           int32_t o, int32_t j0, int32_t j1, int sl, unsigned long long* hkey,
-                                          unsigned long long* hval) {
+                                          V* hval) {
     for (int32_t jb = j0; jb < j1; jb += 4 * LP_SUB) {
         int32_t x[4];
-        unsigned long long c[4];
+        V c[4];
         uint32_t lb[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int32_t j = jb + u * LP_SUB + sl;
             x[u] = j < j1 ? g.col[o + j] : v;
-            c[u] = j < j1 ? (unsigned long long)g.w[o + j] : 0;
+            c[u] = j < j1 ? (V)g.w[o + j] : 0;
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) lb[u] = x[u] != v ? (uint32_t)lab_in[x[u]] : 0;
@@ -105,6 +107,21 @@ __device__ __forceinline__ void lp_insert(const DGraph& g, const int32_t* __rest
     }
 }
 
+// Per-row choice state of a chunk. Wide (64-bit sums): the heaviest other
+// weight, then the smallest other label of that weight, in two sweeps.
+// Narrow (32-bit sums): both in one 64-bit word, weight high and the
+// label's complement low, so one atomic max per slot finds the heaviest
+// weight and, among its labels, the smallest.
+template <typename V> struct LpBest;
+template <> struct LpBest<unsigned long long> {
+    unsigned long long w[LP_CHUNK];
+    int32_t l[LP_CHUNK];
+};
+template <> struct LpBest<uint32_t> {
+    unsigned long long wl[LP_CHUNK];
+};
+
+template <typename V>
 __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __restrict__ lab_in,
                                                   int32_t* __restrict__ lab_out, const int32_t* __restrict__ rstart,
                                                   const int32_t* __restrict__ cg, int32_t* __restrict__ long_list,
@@ -113,11 +130,13 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
                                                   unsigned long long* __restrict__ long_own,
                                                   int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
                                                   int32_t* __restrict__ task_idx, unsigned long long* pb) {
+    constexpr bool NARROW = sizeof(V) == 4;
     __shared__ unsigned long long hkey[LP_HSLOTS];
-    __shared__ unsigned long long hval[LP_HSLOTS];
+    __shared__ V hval[LP_HSLOTS];
     __shared__ int32_t own[LP_CHUNK];
-    __shared__ unsigned long long own_w[LP_CHUNK], best_w[LP_CHUNK];
-    __shared__ int32_t best_l[LP_CHUNK];
+    __shared__ V own_w[LP_CHUNK];
+    __shared__ LpBest<V> best;
+    __shared__ int32_t roff[LP_CHUNK], rlen[LP_CHUNK];
     __shared__ int32_t spre[LP_NSUB + 1];   // few-row chunks: prefix of the rows' piece counts
     const int tid = threadIdx.x;
     const int32_t g_lo = cg[blockIdx.x];
@@ -125,13 +144,21 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
     if (g_lo >= g.n || g_lo >= g_hi) return;
     const int32_t ng = g_hi - g_lo;
     for (int i = tid; i < LP_HSLOTS; i += LP_T) { hkey[i] = LP_EMPTY; hval[i] = 0; }
+    int32_t my_pieces = 0;   // few-row chunks: pieces of row tid
     for (int i = tid; i < ng; i += LP_T) {
         const int32_t v = g_lo + i;
         own[i] = lab_in[v];
         own_w[i] = 0;
-        best_w[i] = 0;
-        best_l[i] = INT32_MAX;
+        if constexpr (NARROW) {
+            best.wl[i] = 0;
+        } else {
+            best.w[i] = 0;
+            best.l[i] = INT32_MAX;
+        }
         const int32_t l = g.len[v];
+        roff[i] = g.off[v];
+        rlen[i] = l;
+        if (l <= LP_SMALL) my_pieces = (l + LP_SEG - 1) / LP_SEG;
         if (l > LP_SMALL) {
             const int32_t k = atomicAdd(&counters[0], 1);
             const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
@@ -144,64 +171,77 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
             for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
         }
     }
+    if (ng < LP_NSUB && tid < MC_WAVE) {
+        // few rows (thread i holds row i): inclusive scan of the piece
+        // counts over the first lanes of wave 0
+        int32_t x = my_pieces;
+        for (int d = 1; d < LP_NSUB; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, MC_WAVE);
+            if (tid >= d) x += y;
+        }
+        if (tid == 0) spre[0] = 0;
+        if (tid < ng) spre[tid + 1] = x;
+    }
     __syncthreads();
     const int sg = tid / LP_SUB, sl = tid % LP_SUB;
     if (ng >= LP_NSUB) {
         // many rows: one lane group per row, its entries from j = 0
         for (int gl = sg; gl < ng; gl += LP_NSUB) {
-            const int32_t v = g_lo + gl;
-            const int32_t o = g.off[v], l = g.len[v];
+            const int32_t o = roff[gl], l = rlen[gl];
             if (l > LP_SMALL) continue;
-            lp_insert(g, lab_in, v, gl, o, 0, l, sl, hkey, hval);
+            lp_insert<V>(g, lab_in, g_lo + gl, gl, o, 0, l, sl, hkey, hval);
         }
     } else {
         // a few long rows: pieces of LP_SEG entries of any row, one per lane
         // group, so that every lane group stays busy
-        if (tid == 0) {
-            int32_t run = 0;
-            for (int gl = 0; gl < ng; gl++) {
-                spre[gl] = run;
-                const int32_t l = g.len[g_lo + gl];
-                if (l <= LP_SMALL) run += (l + LP_SEG - 1) / LP_SEG;
-            }
-            spre[ng] = run;
-        }
-        __syncthreads();
         for (int32_t k = sg; k < spre[ng]; k += LP_NSUB) {
             int gl = 0;   // the last row with spre[gl] <= k (it has pieces)
             while (gl + 1 < ng && spre[gl + 1] <= k) gl++;
             const int32_t v = g_lo + gl;
-            const int32_t o = g.off[v], l = g.len[v];
+            const int32_t o = roff[gl], l = rlen[gl];
             const int32_t j0 = (k - spre[gl]) * LP_SEG;
-            lp_insert(g, lab_in, v, gl, o, j0, j0 + LP_SEG < l ? j0 + LP_SEG : l, sl, hkey, hval);
+            lp_insert<V>(g, lab_in, v, gl, o, j0, j0 + LP_SEG < l ? j0 + LP_SEG : l, sl, hkey, hval);
         }
     }
     __syncthreads();
-    // sweep 1: own weight, heaviest other weight
+    // sweep 1: own weight, heaviest other weight (narrow: and its label)
     for (int i = tid; i < LP_HSLOTS; i += LP_T) {
         const unsigned long long k = hkey[i];
         if (k == LP_EMPTY) continue;
         const int gl = (int)(k >> 32);
-        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
-        if (lbl == own[gl]) own_w[gl] = hval[i];
-        else atomicMax(&best_w[gl], hval[i]);
+        const uint32_t lbl = (uint32_t)(k & 0xFFFFFFFFu);
+        if ((int32_t)lbl == own[gl]) {
+            own_w[gl] = hval[i];
+        } else if constexpr (NARROW) {
+            atomicMax(&best.wl[gl], ((unsigned long long)hval[i] << 32) | (unsigned long long)(~lbl));
+        } else {
+            atomicMax(&best.w[gl], hval[i]);
+        }
     }
     __syncthreads();
-    // sweep 2: smallest other label of that weight
-    for (int i = tid; i < LP_HSLOTS; i += LP_T) {
-        const unsigned long long k = hkey[i];
-        if (k == LP_EMPTY) continue;
-        const int gl = (int)(k >> 32);
-        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
-        if (lbl != own[gl] && hval[i] == best_w[gl]) atomicMin(&best_l[gl], lbl);
+    if constexpr (!NARROW) {
+        // sweep 2: smallest other label of that weight
+        for (int i = tid; i < LP_HSLOTS; i += LP_T) {
+            const unsigned long long k = hkey[i];
+            if (k == LP_EMPTY) continue;
+            const int gl = (int)(k >> 32);
+            const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
+            if (lbl != own[gl] && hval[i] == best.w[gl]) atomicMin(&best.l[gl], lbl);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     int64_t bytes = 0;
     for (int i = tid; i < ng; i += LP_T) {
         const int32_t v = g_lo + i;
-        const int32_t l = g.len[v];
+        const int32_t l = rlen[i];
         if (l > LP_SMALL) continue;
-        lab_out[v] = best_l[i] != INT32_MAX && best_w[i] > own_w[i] ? best_l[i] : own[i];
+        if constexpr (NARROW) {
+            // table sums are at least 1, so a word of 0 means no other label
+            const unsigned long long b = best.wl[i];
+            lab_out[v] = b != 0 && (uint32_t)(b >> 32) > own_w[i] ? (int32_t)(~(uint32_t)b) : own[i];
+        } else {
+            lab_out[v] = best.l[i] != INT32_MAX && best.w[i] > own_w[i] ? best.l[i] : own[i];
+        }
         bytes += 16 + 16 * (int64_t)l;   // off, len, own label, new label; col, w, label of each target
     }
     if (pb) prof_add(pb, bytes);
@@ -528,6 +568,16 @@ __global__ __launch_bounds__(MC_WAVE) void k_lp_first_fold(DGraph g, int32_t* __
 }
 
 // flag[l] = 1 for every label in use (flag zeroed before)
+// flag[0] = 1 when some row's weight sum reaches 2^32 (one thread per row)
+__global__ void k_lp_wide_rows(DGraph g, int32_t* __restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = g.off[v], l = g.len[v];
+        unsigned long long d = 0;
+        for (int32_t j = 0; j < l && d < (1ULL << 32); j++) d += (unsigned long long)g.w[o + j];
+        if (d >= (1ULL << 32)) flag[0] = 1;
+    }
+}
+
 __global__ void k_label_used(const int32_t* __restrict__ lab, int32_t n, int32_t* __restrict__ flag) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         flag[lab[v]] = 1;
@@ -557,7 +607,8 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w) {
     w.cg = a.take<int32_t>((size_t)((cap + n) / LP_CHUNK) + 4);
 }
 
-bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s) {
+bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s,
+              bool narrow) {
     const int32_t n = g.n;
     // row prefix (entries) of the current rows -> chunk starts
     k_row_len<<<grid_for(n, 256), 256, 0, s>>>(g.len, n, cw.mstart);
@@ -569,9 +620,14 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     MC_LAUNCHED("k_lp_chunks");
     if (!fill_i32(w.counters, 0, 4, s)) return false;
     prof_begin(PK_LP_SMALL, s);
-    k_lp_small<<<(unsigned)nchunks, LP_T, 0, s>>>(g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base,
-                                                  w.counters, w.long_best, w.long_own, w.long_lab, w.task_row,
-                                                  w.task_idx, prof_dev_bytes(PK_LP_SMALL));
+    if (narrow)
+        k_lp_small<uint32_t><<<(unsigned)nchunks, LP_T, 0, s>>>(
+            g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base, w.counters, w.long_best, w.long_own,
+            w.long_lab, w.task_row, w.task_idx, prof_dev_bytes(PK_LP_SMALL));
+    else
+        k_lp_small<unsigned long long><<<(unsigned)nchunks, LP_T, 0, s>>>(
+            g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base, w.counters, w.long_best, w.long_own,
+            w.long_lab, w.task_row, w.task_idx, prof_dev_bytes(PK_LP_SMALL));
     MC_LAUNCHED("k_lp_small");
     prof_end(PK_LP_SMALL, s);
     const int tb = 2048;
@@ -590,6 +646,18 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     k_lp_long_final<<<64, 256, 0, s>>>(lab_in, lab_out, w.long_list, w.counters, w.long_best, w.long_own,
                                        w.long_lab);
     MC_LAUNCHED("k_lp_long_final");
+    return true;
+}
+
+bool lp_narrow(const DGraph& g, int32_t* flag_tmp, bool* narrow, hipStream_t s) {
+    int32_t h = 0;
+    if (!fill_i32(flag_tmp, 0, 1, s)) return false;
+    k_lp_wide_rows<<<grid_for(g.n, 256), 256, 0, s>>>(g, flag_tmp);
+    MC_LAUNCHED("k_lp_wide_rows");
+    if (hipMemcpyAsync(&h, flag_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return false;
+    *narrow = h == 0;
     return true;
 }
 

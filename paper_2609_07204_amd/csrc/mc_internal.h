@@ -102,6 +102,7 @@ struct ContractWS {
     int64_t* red_val; // [1024] per-block minima
     int32_t* red_id;  // [1024]
     int64_t* red_m;   // [1024] per-block entry counts
+    int64_t* red_d;   // [1024] per-block maximum degrees
     int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
     int32_t* tinfo;   // [2*(cap/4096+2)] group and first member of every large-group tile
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
@@ -130,7 +131,8 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
 bool contract_sorted(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws, DevScalars* sc,
                      hipStream_t s);
 
-// Minimum degree of g (ties: smallest vertex) into sc->dmin / dmin_arg.
+// Minimum degree of g (ties: smallest vertex) into sc->dmin / dmin_arg, its
+// entry count into sc->m2 and its maximum degree into sc->dmax.
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s);
 
 // --------------------------------------------------------- union-find
@@ -211,8 +213,13 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w);
 // One synchronous label-propagation round over g (Section 2.1 heuristic):
 // lab_out[v] = heaviest neighbour label, keeping lab_in[v] unless another
 // label is strictly heavier, smallest label on ties. Uses cw.mstart,
-// cw.scan_tmp, cw.tkey and cw.tval as scratch.
-bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s);
+// cw.scan_tmp, cw.tkey and cw.tval as scratch. narrow: every row's degree is
+// below 2^32, so the per-label sums of short rows are kept in 32 bits.
+bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s,
+              bool narrow = false);
+// *narrow = every row of g has a weight sum below 2^32 (reads every weight;
+// synchronises s). flag_tmp: one int of device scratch.
+bool lp_narrow(const DGraph& g, int32_t* flag_tmp, bool* narrow, hipStream_t s);
 // The same round from singleton labels (lab_in[v] = v) on a normal graph:
 // lab_out[v] = v's heaviest neighbour, the smallest on ties, v if isolated.
 bool lp_first(const DGraph& g, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s);

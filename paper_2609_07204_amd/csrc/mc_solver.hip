@@ -1073,11 +1073,13 @@ static mc_status heuristic(Solver& S) {
         prof_round_begin(1, n, S.cur_m, s);
         int32_t* a = w.parent;   // labels ping-pong between parent[] and lab2[]
         int32_t* b = w.lab2;
-        // the first round starts from singleton labels on a normal graph
+        // the first round starts from singleton labels on a normal graph;
+        // the last readback holds cur's maximum degree (its last min_degree)
+        const bool narrow = S.c->hsc->dmax < ((int64_t)1 << 32);
         if (!lp_first(*cur, b, w.lw, w.cw, s)) return MC_E_DEVICE;
         std::swap(a, b);
         for (int it = 1; it < iters; it++) {
-            if (!lp_round(*cur, a, b, w.lw, w.cw, s)) return MC_E_DEVICE;
+            if (!lp_round(*cur, a, b, w.lw, w.cw, s, narrow)) return MC_E_DEVICE;
             std::swap(a, b);
         }
         if (!lp_relabel(a, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback()) return MC_E_DEVICE;
@@ -1462,7 +1464,9 @@ extern "C" mc_status mc_step_lp(mc_ctx* c, const mc_dgraph* g, const int32_t* la
     StepWS w;
     mc_status r = step_begin(c, g->n, g->cap, 1, ws, bytes, w);
     if (r != MC_OK) return r;
-    const bool ok = lab_in ? lp_round(to_dgraph(g), lab_in, lab_out, w.lw, w.cw, c->stream)
+    bool narrow = false;
+    if (lab_in && !lp_narrow(to_dgraph(g), w.lw.counters + 3, &narrow, c->stream)) return MC_E_DEVICE;
+    const bool ok = lab_in ? lp_round(to_dgraph(g), lab_in, lab_out, w.lw, w.cw, c->stream, narrow)
                            : lp_first(to_dgraph(g), lab_out, w.lw, w.cw, c->stream);
     if (!ok) return MC_E_DEVICE;
     return sync_read(c, w);

@@ -693,6 +693,29 @@ def test_lp_round_all_row_classes_match_oracle(ctx, seed, nlab):
     assert np.array_equal(ctx.step_lp(dev, want), oracle.lp_round(g, want))
 
 
+@pytest.mark.parametrize("seed,wlo,whi,hubs", [(21, 1 << 29, (1 << 29) + 2, 0), (22, 1 << 30, 1 << 33, 5),
+                                               (23, (1 << 32) - 3, (1 << 32) - 1, 0)])
+def test_lp_round_label_sums_near_32_bits(ctx, seed, wlo, whi, hubs):
+    # short rows keep their per-label sums in 32 bits when every row's
+    # weight sum is below 2^32 and in 64 bits otherwise: row sums just
+    # below 2^32 (sums past 2^31, three weights so that sums tie), row sums
+    # far above it with hub rows, and single weights just below 2^32
+    if hubs:
+        g = hub_graph(3000, hubs, 1800, 6, seed, wlo, whi)
+    else:
+        g = gen.regular(3000, 6 if wlo < (1 << 30) else 1, seed, wlo, whi)
+    rs = np.add.reduceat(g.w.astype(object), g.row_ptr[:-1]) if len(g.w) else []
+    narrow = max(rs) < (1 << 32)
+    say("lp sums", seed, "max row sum", max(rs), "narrow" if narrow else "wide")
+    assert narrow == (hubs == 0)
+    r = np.random.default_rng(seed)
+    dev = ctx.dgraph(g)
+    for lab in (np.arange(g.n, dtype=np.int32), r.integers(0, 7, g.n).astype(np.int32),
+                r.integers(0, 400, g.n).astype(np.int32)):
+        want = oracle.lp_round(g, lab)
+        assert np.array_equal(ctx.step_lp(dev, lab), want)
+
+
 def test_lp_round_ties_and_own_label(ctx):
     # star-like rows with equal weights: ties go to the smallest label, and a
     # vertex keeps its label unless another is strictly heavier
