@@ -341,7 +341,9 @@ enum {
     MC_K_GROUP_SCATTER = 4,    /* k_group_scatter: members grouped by label */
     MC_K_PR12 = 5,             /* k_pr12: reduction tests 1 and 2 */
     MC_K_CONNECT_LINK = 6,     /* k_uf_link_rest: connectivity unions */
-    MC_K_LP_SMALL = 7,         /* k_lp_small: label-propagation round, rows of <= 256 entries */
+    MC_K_LP_SMALL = 7,         /* k_lp_flat: label-propagation round, rows of <= 256 entries
+                                  (k_lp_small instead when the graph has 2^27 - 1 vertices or
+                                  more, or a degree of 2^32 or more) */
     MC_K_LP_FIRST = 8,         /* k_lp_first: first label-propagation round (from singletons) */
     MC_K_MID_MERGE = 9,        /* k_mid_merge<2048>, k_mid_merge<4096>: contraction of groups of
                                   513..2048 entries */

@@ -147,13 +147,15 @@ constexpr int MID_HALF = 1024;
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
                            int32_t nd_max, int32_t* __restrict__ tsize, int32_t* __restrict__ bigm,
                            int32_t* __restrict__ bcur, int32_t* __restrict__ dslot, int32_t* __restrict__ dinfo,
-                           int32_t* __restrict__ mlist, int32_t* __restrict__ mcnt, DGraph dst) {
+                           int32_t* __restrict__ mlist, int32_t* __restrict__ mcnt, int32_t* __restrict__ ssize,
+                           DGraph dst) {
     const int64_t dense_min = n2 / 4;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n2; g += (int64_t)gridDim.x * blockDim.x) {
         int32_t s = gstart[g + 1] - gstart[g];
         dst.off[g] = gstart[g];
         dslot[g] = -1;
         const int32_t members = vstart ? vstart[g + 1] - vstart[g] : 1;
+        ssize[g] = s <= SMALL_MAX ? s : 0;
         if (s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM) {
             // groups of at most MID_HALF entries from the front of the list,
             // larger ones from the back
@@ -190,12 +192,12 @@ __device__ __forceinline__ int32_t last_le(const int32_t* __restrict__ a, int32_
     return lo;
 }
 
-// first g in [0, n2] with gstart[g] + g >= key
-__device__ __forceinline__ int32_t first_key_ge(const int32_t* __restrict__ gstart, int32_t n2, int64_t key) {
+// first g in [0, n2] with sstart[g] + g >= key
+__device__ __forceinline__ int32_t first_key_ge(const int32_t* __restrict__ sstart, int32_t n2, int64_t key) {
     int32_t lo = 0, hi = n2 + 1;
     while (lo < hi) {
         int32_t mid = lo + (hi - lo) / 2;
-        if ((int64_t)gstart[mid] + mid >= key) hi = mid; else lo = mid + 1;
+        if ((int64_t)sstart[mid] + mid >= key) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
@@ -204,12 +206,14 @@ constexpr int MERGE_THREADS = 256;
 constexpr int SUB = 16;                              // lanes per group
 constexpr int NSUB = MERGE_THREADS / SUB;
 
-// first group of every chunk: cg[c] = first g with gstart[g] + g >= c CHUNK
-// (one independent search per thread, so their latencies overlap)
-__global__ void k_chunk_start(const int32_t* __restrict__ gstart, int32_t n2, int64_t nchunks,
+// first group of every chunk: cg[c] = first g with sstart[g] + g >= c CHUNK,
+// sstart the prefix of the small groups' entry counts (larger groups count
+// as empty, so no chunk is spent on their entries); one independent search
+// per thread, so their latencies overlap
+__global__ void k_chunk_start(const int32_t* __restrict__ sstart, int32_t n2, int64_t nchunks,
                               int32_t* __restrict__ cg) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += (int64_t)gridDim.x * blockDim.x)
-        cg[c] = first_key_ge(gstart, n2, c * CHUNK);
+        cg[c] = first_key_ge(sstart, n2, c * CHUNK);
 }
 
 // One member row u of group g (chunk-local gl) into the chunk's LDS table,
@@ -331,6 +335,28 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     if (pb) prof_add(pb, nin * (L ? 16 : 12) + nout * 12 + ngrp * 12);
 }
 
+// A mid group's place in the list and sizes.
+struct MidMeta {
+    int32_t g, m0, mc, gs, s;
+};
+__device__ __forceinline__ MidMeta mid_meta(int32_t g, const int32_t* __restrict__ vstart,
+                                            const int32_t* __restrict__ gstart) {
+    MidMeta m{g, 0, 0, 0, 0};
+    if (g < 0) return m;
+    m.m0 = vstart ? vstart[g] : g;
+    m.mc = vstart ? vstart[g + 1] - m.m0 : 1;
+    m.gs = gstart[g];
+    m.s = gstart[g + 1] - m.gs;
+    return m;
+}
+
+// One workgroup per mid group, looping over the list. The merge of a group
+// is a chain of dependent loads (list entry, group bounds, member rows,
+// entries, target labels), so the loop is software-pipelined: while group A
+// merges its entries, the member offsets of the next group B are loaded
+// into registers, the bounds of the group C after it and the list entry of
+// the one after that, so each group waits for two dependent loads (entries,
+// then labels) instead of six.
 template <int MID_SLOTS>
 __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* __restrict__ L,
                                                     const int32_t* __restrict__ perm,
@@ -340,6 +366,7 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
                                                     const int32_t* __restrict__ mlist,
                                                     const int32_t* __restrict__ mcnt, int32_t n2, DGraph dst,
                                                     unsigned long long* pb) {
+    constexpr int PER = MID_MEM / MID_T;   // members staged per thread
     __shared__ int32_t tk[MID_SLOTS];
     __shared__ long long tv[MID_SLOTS];
     __shared__ int32_t wm[MID_MEM + 1];   // group-relative entry offset of each member
@@ -349,21 +376,47 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
     const bool front = MID_SLOTS < 2 * MID_MAX;   // the list's front holds the groups of at most MID_HALF entries
     const int32_t cnt = mcnt[front ? 0 : 1];
     const int tid = threadIdx.x;
-    int64_t bytes = 0;
-    for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int32_t g = mlist[front ? i : n2 - i];
-        const int32_t m0 = vstart ? vstart[g] : g;
-        const int32_t mc = vstart ? vstart[g + 1] - m0 : 1;
-        const int32_t gs = gstart[g], s = gstart[g + 1] - gs;
-        __syncthreads();
-        for (int k = tid; k < MID_SLOTS; k += MID_T) { tk[k] = -1; tv[k] = 0; }
-        for (int k = tid; k < mc; k += MID_T) {
-            wm[k] = mstart[m0 + k] - gs;
-            wo[k] = src.off[perm ? perm[m0 + k] : m0 + k];
+    const int32_t G = (int32_t)gridDim.x;
+    auto list_at = [&](int32_t i) -> int32_t { return i < cnt ? mlist[front ? i : n2 - i] : -1; };
+    // the members of group m into registers: entry offset and row offset
+    auto stage = [&](const MidMeta& m, int32_t* rw, int32_t* ro) {
+        int32_t p[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int32_t k = q * MID_T + tid;
+            rw[q] = k < m.mc ? mstart[m.m0 + k] - m.gs : 0;
+            p[q] = k < m.mc ? (perm ? perm[m.m0 + k] : m.m0 + k) : 0;
         }
-        if (tid == 0) { wm[mc] = s; s_cnt = 0; s_deg = 0; }
+#pragma unroll
+        for (int q = 0; q < PER; q++) ro[q] = q * MID_T + tid < m.mc ? src.off[p[q]] : 0;
+    };
+    int64_t bytes = 0;
+    int32_t i = blockIdx.x;
+    if (i >= cnt) return;
+    for (int k = tid; k < MID_SLOTS; k += MID_T) { tk[k] = -1; tv[k] = 0; }
+    MidMeta A = mid_meta(list_at(i), vstart, gstart);
+    int32_t aw[PER], ao[PER];
+    stage(A, aw, ao);
+    MidMeta B = mid_meta(list_at(i + G), vstart, gstart);
+    int32_t c_g = list_at(i + 2 * G);
+    for (;;) {
+        // A's members into LDS (the previous group's readers passed the
+        // barrier that ended its sweep)
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int32_t k = q * MID_T + tid;
+            if (k < A.mc) { wm[k] = aw[q]; wo[k] = ao[q]; }
+        }
+        if (tid == 0) { wm[A.mc] = A.s; s_cnt = 0; s_deg = 0; }
         __syncthreads();
-        for (int32_t e0 = 0; e0 < s; e0 += 4 * MID_T) {
+        // loads of the groups to come, issued before A's entries so that
+        // their latencies overlap
+        const MidMeta C = mid_meta(c_g, vstart, gstart);
+        const int32_t d_g = list_at(i + 3 * G);
+        int32_t bw[PER], bo[PER];
+        stage(B, bw, bo);
+        const int32_t g = A.g;
+        for (int32_t e0 = 0; e0 < A.s; e0 += 4 * MID_T) {
             int32_t x[4], t[4];
             int64_t c[4];
 #pragma unroll
@@ -371,8 +424,8 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
                 const int32_t e = e0 + q * MID_T + tid;
                 x[q] = 0;
                 c[q] = 0;
-                if (e >= s) continue;
-                int32_t lo = 0, hi = mc;   // the member holding entry e
+                if (e >= A.s) continue;
+                int32_t lo = 0, hi = A.mc;   // the member holding entry e
                 while (hi - lo > 1) { const int32_t mid = (lo + hi) >> 1; if (wm[mid] <= e) lo = mid; else hi = mid; }
                 x[q] = src.col[wo[lo] + (e - wm[lo])];
                 c[q] = src.w[wo[lo] + (e - wm[lo])];
@@ -396,20 +449,32 @@ __global__ __launch_bounds__(MID_T) void k_mid_merge(DGraph src, const int32_t* 
             }
         }
         __syncthreads();
+        // sweep: the merged row out, the table cleared for the next group
         for (int k = tid; k < MID_SLOTS; k += MID_T) {
-            if (tk[k] < 0) continue;
+            const int32_t key = tk[k];
+            if (key < 0) continue;
+            const long long val = tv[k];
+            tk[k] = -1;
+            tv[k] = 0;
             const int32_t pos = atomicAdd(&s_cnt, 1);
-            dst.col[gs + pos] = tk[k];
-            dst.w[gs + pos] = tv[k];
-            atomicAdd((unsigned long long*)&s_deg, (unsigned long long)tv[k]);
+            dst.col[A.gs + pos] = key;
+            dst.w[A.gs + pos] = val;
+            atomicAdd((unsigned long long*)&s_deg, (unsigned long long)val);
         }
         __syncthreads();
         if (tid == 0) {
             dst.len[g] = s_cnt;
             dst.deg[g] = s_deg;
             // col, w (and the label of each target) in; col, w out; off, len, deg
-            bytes += (int64_t)s * (L ? 16 : 12) + (int64_t)s_cnt * 12 + 12 * mc;
+            bytes += (int64_t)A.s * (L ? 16 : 12) + (int64_t)s_cnt * 12 + 12 * A.mc;
         }
+        i += G;
+        if (i >= cnt) break;
+        A = B;
+#pragma unroll
+        for (int q = 0; q < PER; q++) { aw[q] = bw[q]; ao[q] = bo[q]; }
+        B = C;
+        c_g = d_g;
     }
     if (pb) prof_add(pb, bytes);
 }
@@ -841,6 +906,7 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool so
     ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
     ws.xg = a.take<int32_t>(slots / TILE_SLOTS + 8);
     ws.mlist = a.take<int32_t>((size_t)n + 1);
+    ws.sstart = a.take<int32_t>((size_t)n + 2);
     ws.mcnt = a.take<int32_t>(4);
 }
 
@@ -895,12 +961,15 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     const int32_t nd_max = (int32_t)(ndm < DENSE_MAX ? ndm : DENSE_MAX);
     if (!fill_i32(ws.dinfo, 0, 1, s) || !fill_i32(ws.mcnt, 0, 2, s)) return false;
     k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, nd_max, ws.tsize, ws.bigm, ws.bcur, ws.dslot,
-                                                 ws.dinfo, ws.mlist, ws.mcnt, dst);
+                                                 ws.dinfo, ws.mlist, ws.mcnt, ws.sstart, dst);
     MC_LAUNCHED("k_classify");
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
     if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
+    if (!scan_i32(ws.sstart, ws.sstart, n2, ws.scan_tmp, s)) return false;  // small-group entry prefix
+    // at most this many chunks hold small groups; the rest of the grid finds
+    // no group and returns
     const int64_t chunks = (src.cap + n2) / CHUNK + 2;
-    k_chunk_start<<<grid_for(chunks + 1, 256), 256, 0, s>>>(gstart, n2, chunks, ws.cg);
+    k_chunk_start<<<grid_for(chunks + 1, 256), 256, 0, s>>>(ws.sstart, n2, chunks, ws.cg);
     MC_LAUNCHED("k_chunk_start");
     prof_begin(PK_MERGE_SMALL, s);
     k_merge_small<<<(unsigned)chunks, MERGE_THREADS, 0, s>>>(src, L, perm, vstart, gstart, n2, ws.cg, dst,

@@ -70,21 +70,19 @@ __device__ __forceinline__ uint32_t lp_hash(uint32_t gl, uint32_t lbl) { return 
 
 // Entries [j0, j1) of row v (chunk-local gl) into the chunk's LDS table by
 // the LP_SUB lanes of a lane group: four entries per lane at a time, so
-// their loads, then their labels' loads, are in flight together. V holds a
-// table sum: 32 bits when every row's degree is below 2^32.
-template <typename V>
+// their loads, then their labels' loads, are in flight together.
 __device__ __forceinline__ void lp_insert(const DGraph& g, const int32_t* __restrict__ lab_in, int32_t v, int gl,
                                           int32_t o, int32_t j0, int32_t j1, int sl, unsigned long long* hkey,
-                                          V* hval) {
+                                          unsigned long long* hval) {
     for (int32_t jb = j0; jb < j1; jb += 4 * LP_SUB) {
         int32_t x[4];
-        V c[4];
+        unsigned long long c[4];
         uint32_t lb[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int32_t j = jb + u * LP_SUB + sl;
             x[u] = j < j1 ? g.col[o + j] : v;
-            c[u] = j < j1 ? (V)g.w[o + j] : 0;
+            c[u] = j < j1 ? (unsigned long long)g.w[o + j] : 0;
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) lb[u] = x[u] != v ? (uint32_t)lab_in[x[u]] : 0;
@@ -107,21 +105,9 @@ __device__ __forceinline__ void lp_insert(const DGraph& g, const int32_t* __rest
     }
 }
 
-// Per-row choice state of a chunk. Wide (64-bit sums): the heaviest other
-// weight, then the smallest other label of that weight, in two sweeps.
-// Narrow (32-bit sums): both in one 64-bit word, weight high and the
-// label's complement low, so one atomic max per slot finds the heaviest
-// weight and, among its labels, the smallest.
-template <typename V> struct LpBest;
-template <> struct LpBest<unsigned long long> {
-    unsigned long long w[LP_CHUNK];
-    int32_t l[LP_CHUNK];
-};
-template <> struct LpBest<uint32_t> {
-    unsigned long long wl[LP_CHUNK];
-};
-
-template <typename V>
+// General form (any degree, any vertex count): a table of 64-bit keys (row,
+// label) and 64-bit sums; the heaviest other weight, then the smallest other
+// label of that weight, in two sweeps.
 __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __restrict__ lab_in,
                                                   int32_t* __restrict__ lab_out, const int32_t* __restrict__ rstart,
                                                   const int32_t* __restrict__ cg, int32_t* __restrict__ long_list,
@@ -130,12 +116,11 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
                                                   unsigned long long* __restrict__ long_own,
                                                   int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
                                                   int32_t* __restrict__ task_idx, unsigned long long* pb) {
-    constexpr bool NARROW = sizeof(V) == 4;
     __shared__ unsigned long long hkey[LP_HSLOTS];
-    __shared__ V hval[LP_HSLOTS];
+    __shared__ unsigned long long hval[LP_HSLOTS];
     __shared__ int32_t own[LP_CHUNK];
-    __shared__ V own_w[LP_CHUNK];
-    __shared__ LpBest<V> best;
+    __shared__ unsigned long long own_w[LP_CHUNK], best_w[LP_CHUNK];
+    __shared__ int32_t best_l[LP_CHUNK];
     __shared__ int32_t roff[LP_CHUNK], rlen[LP_CHUNK];
     __shared__ int32_t spre[LP_NSUB + 1];   // few-row chunks: prefix of the rows' piece counts
     const int tid = threadIdx.x;
@@ -149,12 +134,8 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
         const int32_t v = g_lo + i;
         own[i] = lab_in[v];
         own_w[i] = 0;
-        if constexpr (NARROW) {
-            best.wl[i] = 0;
-        } else {
-            best.w[i] = 0;
-            best.l[i] = INT32_MAX;
-        }
+        best_w[i] = 0;
+        best_l[i] = INT32_MAX;
         const int32_t l = g.len[v];
         roff[i] = g.off[v];
         rlen[i] = l;
@@ -189,7 +170,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
         for (int gl = sg; gl < ng; gl += LP_NSUB) {
             const int32_t o = roff[gl], l = rlen[gl];
             if (l > LP_SMALL) continue;
-            lp_insert<V>(g, lab_in, g_lo + gl, gl, o, 0, l, sl, hkey, hval);
+            lp_insert(g, lab_in, g_lo + gl, gl, o, 0, l, sl, hkey, hval);
         }
     } else {
         // a few long rows: pieces of LP_SEG entries of any row, one per lane
@@ -200,51 +181,186 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
             const int32_t v = g_lo + gl;
             const int32_t o = roff[gl], l = rlen[gl];
             const int32_t j0 = (k - spre[gl]) * LP_SEG;
-            lp_insert<V>(g, lab_in, v, gl, o, j0, j0 + LP_SEG < l ? j0 + LP_SEG : l, sl, hkey, hval);
+            lp_insert(g, lab_in, v, gl, o, j0, j0 + LP_SEG < l ? j0 + LP_SEG : l, sl, hkey, hval);
         }
     }
     __syncthreads();
-    // sweep 1: own weight, heaviest other weight (narrow: and its label)
+    // sweep 1: own weight, heaviest other weight
     for (int i = tid; i < LP_HSLOTS; i += LP_T) {
         const unsigned long long k = hkey[i];
         if (k == LP_EMPTY) continue;
         const int gl = (int)(k >> 32);
-        const uint32_t lbl = (uint32_t)(k & 0xFFFFFFFFu);
-        if ((int32_t)lbl == own[gl]) {
-            own_w[gl] = hval[i];
-        } else if constexpr (NARROW) {
-            atomicMax(&best.wl[gl], ((unsigned long long)hval[i] << 32) | (unsigned long long)(~lbl));
-        } else {
-            atomicMax(&best.w[gl], hval[i]);
-        }
+        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
+        if (lbl == own[gl]) own_w[gl] = hval[i];
+        else atomicMax(&best_w[gl], hval[i]);
     }
     __syncthreads();
-    if constexpr (!NARROW) {
-        // sweep 2: smallest other label of that weight
-        for (int i = tid; i < LP_HSLOTS; i += LP_T) {
-            const unsigned long long k = hkey[i];
-            if (k == LP_EMPTY) continue;
-            const int gl = (int)(k >> 32);
-            const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
-            if (lbl != own[gl] && hval[i] == best.w[gl]) atomicMin(&best.l[gl], lbl);
-        }
-        __syncthreads();
+    // sweep 2: smallest other label of that weight
+    for (int i = tid; i < LP_HSLOTS; i += LP_T) {
+        const unsigned long long k = hkey[i];
+        if (k == LP_EMPTY) continue;
+        const int gl = (int)(k >> 32);
+        const int32_t lbl = (int32_t)(k & 0xFFFFFFFFu);
+        if (lbl != own[gl] && hval[i] == best_w[gl]) atomicMin(&best_l[gl], lbl);
     }
+    __syncthreads();
     int64_t bytes = 0;
     for (int i = tid; i < ng; i += LP_T) {
         const int32_t v = g_lo + i;
         const int32_t l = rlen[i];
         if (l > LP_SMALL) continue;
-        if constexpr (NARROW) {
-            // table sums are at least 1, so a word of 0 means no other label
-            const unsigned long long b = best.wl[i];
-            lab_out[v] = b != 0 && (uint32_t)(b >> 32) > own_w[i] ? (int32_t)(~(uint32_t)b) : own[i];
-        } else {
-            lab_out[v] = best.l[i] != INT32_MAX && best.w[i] > own_w[i] ? best.l[i] : own[i];
-        }
+        lab_out[v] = best_l[i] != INT32_MAX && best_w[i] > own_w[i] ? best_l[i] : own[i];
         bytes += 16 + 16 * (int64_t)l;   // off, len, own label, new label; col, w, label of each target
     }
     if (pb) prof_add(pb, bytes);
+}
+
+// Flat form of k_lp_small for graphs below 2^27 vertices whose maximum
+// degree is below 2^32. A chunk spans LPF_CHUNK key units, a row counting its
+// entries plus LPF_ROWW, so it starts at most LPF_ROWS rows and holds fewer
+// than LPF_CHUNK + LP_SMALL entries of short rows. Its threads take those
+// entries in order, each up to LPF_PER of them at once (the row of an entry
+// by a search of the chunk's row prefix in LDS), so every lane has work and
+// the loads of consecutive entries coalesce. A table slot is one 64-bit word:
+// the key (chunk-local row, 5 bits; label, 27 bits) high and the label's
+// weight sum low, which a 64-bit add updates without carrying into the key.
+constexpr int LPF_CHUNK = 512;
+constexpr int LPF_ROWW = 16;
+constexpr int LPF_ROWS = LPF_CHUNK / LPF_ROWW;   // 32
+constexpr int LPF_T = 128;
+constexpr int LPF_PER = (LPF_CHUNK + LP_SMALL + LPF_T - 1) / LPF_T;   // 6
+constexpr int LPF_SLOTS = 1024;                  // > 767 entries: load below 3/4
+constexpr int LPF_LBITS = 27;
+constexpr uint32_t LPF_EMPTY = 0xFFFFFFFFu;      // no row 31 holds label 2^27 - 1 (n < 2^27 - 1)
+static_assert(LPF_ROWS <= (1 << (32 - LPF_LBITS)), "row index must fit the key");
+static_assert(LPF_PER * LPF_T >= LPF_CHUNK + LP_SMALL - 1, "one pass must cover a chunk");
+
+// cg[c] = first row v with rstart[v] + LPF_ROWW v >= c LPF_CHUNK
+__global__ void k_lpf_chunks(const int32_t* __restrict__ rstart, int32_t n, int64_t nchunks, int32_t* __restrict__ cg) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nchunks; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t key = c * LPF_CHUNK;
+        int32_t lo = 0, hi = n + 1;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if ((int64_t)rstart[mid] + (int64_t)LPF_ROWW * mid >= key) hi = mid; else lo = mid + 1;
+        }
+        cg[c] = lo;
+    }
+}
+
+__global__ __launch_bounds__(LPF_T) void k_lp_flat(DGraph g, const int32_t* __restrict__ lab_in,
+                                                  int32_t* __restrict__ lab_out, const int32_t* __restrict__ cg,
+                                                  int32_t* __restrict__ long_list, int32_t* __restrict__ long_base,
+                                                  int32_t* __restrict__ counters,
+                                                  unsigned long long* __restrict__ long_best,
+                                                  unsigned long long* __restrict__ long_own,
+                                                  int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
+                                                  int32_t* __restrict__ task_idx, unsigned long long* pb) {
+    __shared__ unsigned long long tab[LPF_SLOTS];
+    __shared__ unsigned long long best[LPF_ROWS];   // weight high, complemented label low
+    __shared__ int32_t rpre[LPF_ROWS + 1];          // prefix of the short rows' lengths
+    __shared__ int32_t roff[LPF_ROWS], rlen[LPF_ROWS], own[LPF_ROWS];
+    __shared__ uint32_t own_w[LPF_ROWS];
+    const int tid = threadIdx.x;
+    const int32_t g_lo = cg[blockIdx.x];
+    const int32_t g_hi = cg[blockIdx.x + 1] < g.n ? cg[blockIdx.x + 1] : g.n;
+    if (g_lo >= g.n || g_lo >= g_hi) return;
+    const int32_t ng = g_hi - g_lo;   // at most LPF_ROWS
+    for (int i = tid; i < LPF_SLOTS; i += LPF_T) tab[i] = (unsigned long long)LPF_EMPTY << 32;
+    int32_t my_short = 0;
+    if (tid < ng) {
+        const int32_t v = g_lo + tid;
+        const int32_t l = g.len[v];
+        own[tid] = lab_in[v];
+        roff[tid] = g.off[v];
+        rlen[tid] = l;
+        own_w[tid] = 0;
+        best[tid] = 0;
+        if (l <= LP_SMALL) {
+            my_short = l;
+        } else {
+            const int32_t k = atomicAdd(&counters[0], 1);
+            const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
+            const int32_t t0 = atomicAdd(&counters[2], nt);
+            long_list[k] = v;
+            long_base[k] = atomicAdd(&counters[1], (2 * l + 255) / 256 * 256);
+            long_best[k] = 0;
+            long_own[k] = 0;
+            long_lab[k] = INT32_MAX;
+            for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
+        }
+    }
+    if (tid < MC_WAVE) {
+        // inclusive scan of the short rows' lengths over the lanes of wave 0
+        int32_t x = my_short;
+        for (int d = 1; d < LPF_ROWS; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, MC_WAVE);
+            if (tid >= d) x += y;
+        }
+        if (tid == 0) rpre[0] = 0;
+        if (tid < ng) rpre[tid + 1] = x;
+    }
+    __syncthreads();
+    const int32_t E = rpre[ng];
+    int32_t r[LPF_PER], x[LPF_PER];
+    uint32_t c[LPF_PER], lb[LPF_PER];
+#pragma unroll
+    for (int q = 0; q < LPF_PER; q++) {
+        const int32_t e = q * LPF_T + tid;
+        r[q] = -1;
+        x[q] = 0;
+        c[q] = 0;
+        if (e >= E) continue;
+        int32_t lo = 0;   // the last row with rpre[lo] <= e (a row with entries, as e < E)
+#pragma unroll
+        for (int b = LPF_ROWS / 2; b > 0; b >>= 1)
+            if (lo + b < ng && rpre[lo + b] <= e) lo += b;
+        const int32_t j = roff[lo] + (e - rpre[lo]);
+        r[q] = lo;
+        x[q] = g.col[j];
+        c[q] = (uint32_t)g.w[j];
+    }
+#pragma unroll
+    for (int q = 0; q < LPF_PER; q++) lb[q] = r[q] >= 0 && x[q] != g_lo + r[q] ? (uint32_t)lab_in[x[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < LPF_PER; q++) {
+        if (r[q] < 0 || x[q] == g_lo + r[q]) continue;   // no entry, or a loop
+        const uint32_t key = ((uint32_t)r[q] << LPF_LBITS) | lb[q];
+        const unsigned long long kw = (unsigned long long)key << 32;
+        uint32_t h = hash32(key) & (LPF_SLOTS - 1);
+        for (;;) {
+            const uint32_t k = (uint32_t)(tab[h] >> 32);
+            if (k == key) break;
+            if (k == LPF_EMPTY) {
+                const unsigned long long old = atomicCAS(&tab[h], (unsigned long long)LPF_EMPTY << 32, kw);
+                if ((uint32_t)(old >> 32) == LPF_EMPTY || (uint32_t)(old >> 32) == key) break;
+            }
+            h = (h + 1) & (LPF_SLOTS - 1);
+        }
+        atomicAdd(&tab[h], (unsigned long long)c[q]);
+    }
+    __syncthreads();
+    for (int i = tid; i < LPF_SLOTS; i += LPF_T) {
+        const unsigned long long t = tab[i];
+        const uint32_t key = (uint32_t)(t >> 32);
+        if (key == LPF_EMPTY) continue;
+        const int row = (int)(key >> LPF_LBITS);
+        const uint32_t lbl = key & ((1u << LPF_LBITS) - 1);
+        const uint32_t sum = (uint32_t)t;
+        if ((int32_t)lbl == own[row]) own_w[row] = sum;
+        else atomicMax(&best[row], ((unsigned long long)sum << 32) | (unsigned long long)(~lbl));
+    }
+    __syncthreads();
+    if (tid < ng && rlen[tid] <= LP_SMALL) {
+        // sums are at least 1, so a word of 0 means no other label
+        const unsigned long long b = best[tid];
+        lab_out[g_lo + tid] = b != 0 && (uint32_t)(b >> 32) > own_w[tid] ? (int32_t)(~(uint32_t)b) : own[tid];
+    }
+    if (pb) {
+        int64_t bytes = 0;
+        if (tid < ng && rlen[tid] <= LP_SMALL) bytes = 16 + 16 * (int64_t)rlen[tid];
+        prof_add(pb, bytes);
+    }
 }
 
 // Long rows are cut into tasks of LP_TASK entries; task t of row k owns the
@@ -604,7 +720,8 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w) {
     w.task_row = a.take<int32_t>(ntask);
     w.task_idx = a.take<int32_t>(ntask);
     w.counters = a.take<int32_t>(4);
-    w.cg = a.take<int32_t>((size_t)((cap + n) / LP_CHUNK) + 4);
+    // chunk starts of either chunking (LPF_ROWW n / LPF_CHUNK >= n / LP_CHUNK)
+    w.cg = a.take<int32_t>((size_t)((cap + (int64_t)LPF_ROWW * n) / LPF_CHUNK) + (size_t)((cap + n) / LP_CHUNK) + 4);
 }
 
 bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s,
@@ -614,21 +731,28 @@ bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w,
     k_row_len<<<grid_for(n, 256), 256, 0, s>>>(g.len, n, cw.mstart);
     MC_LAUNCHED("k_row_len");
     if (!scan_i32(cw.mstart, cw.mstart, n, cw.scan_tmp, s)) return false;
+    if (!fill_i32(w.counters, 0, 4, s)) return false;
+    if (narrow && n < (1 << LPF_LBITS) - 1) {
+        // chunk keys run up to entries + LPF_ROWW rows <= cap + LPF_ROWW n
+        const int64_t nchunks = (g.cap + (int64_t)LPF_ROWW * n) / LPF_CHUNK + 2;
+        k_lpf_chunks<<<grid_for(nchunks + 1, 256), 256, 0, s>>>(cw.mstart, n, nchunks, w.cg);
+        MC_LAUNCHED("k_lpf_chunks");
+        prof_begin(PK_LP_SMALL, s);
+        k_lp_flat<<<(unsigned)nchunks, LPF_T, 0, s>>>(g, lab_in, lab_out, w.cg, w.long_list, w.long_base, w.counters,
+                                                      w.long_best, w.long_own, w.long_lab, w.task_row, w.task_idx,
+                                                      prof_dev_bytes(PK_LP_SMALL));
+        MC_LAUNCHED("k_lp_flat");
+    } else {
     // chunk keys run up to (entries + rows) <= cap + n
     const int64_t nchunks = (g.cap + n) / LP_CHUNK + 2;
     k_lp_chunks<<<grid_for(nchunks + 1, 256), 256, 0, s>>>(cw.mstart, n, nchunks, w.cg);
     MC_LAUNCHED("k_lp_chunks");
-    if (!fill_i32(w.counters, 0, 4, s)) return false;
     prof_begin(PK_LP_SMALL, s);
-    if (narrow)
-        k_lp_small<uint32_t><<<(unsigned)nchunks, LP_T, 0, s>>>(
-            g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base, w.counters, w.long_best, w.long_own,
-            w.long_lab, w.task_row, w.task_idx, prof_dev_bytes(PK_LP_SMALL));
-    else
-        k_lp_small<unsigned long long><<<(unsigned)nchunks, LP_T, 0, s>>>(
-            g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base, w.counters, w.long_best, w.long_own,
-            w.long_lab, w.task_row, w.task_idx, prof_dev_bytes(PK_LP_SMALL));
+    k_lp_small<<<(unsigned)nchunks, LP_T, 0, s>>>(g, lab_in, lab_out, cw.mstart, w.cg, w.long_list, w.long_base,
+                                                  w.counters, w.long_best, w.long_own, w.long_lab, w.task_row,
+                                                  w.task_idx, prof_dev_bytes(PK_LP_SMALL));
     MC_LAUNCHED("k_lp_small");
+    }
     prof_end(PK_LP_SMALL, s);
     const int tb = 2048;
     k_lp_long_clear<<<tb, LP_T, 0, s>>>(g, w.long_list, w.long_base, w.counters, w.task_row, w.task_idx, cw.tkey,

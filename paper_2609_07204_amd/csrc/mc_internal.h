@@ -108,6 +108,7 @@ struct ContractWS {
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
     int32_t* mlist;   // [n+1] groups merged by one workgroup each in LDS
     int32_t* mcnt;    // [4] their count
+    int32_t* sstart;  // [n+2] entry counts of the small groups (others 0) -> their prefix
     bool sorted = false;   // merge by sorting (mc_sort.hip) instead of hashing
     SortWS sw;
 };
@@ -214,7 +215,8 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w);
 // lab_out[v] = heaviest neighbour label, keeping lab_in[v] unless another
 // label is strictly heavier, smallest label on ties. Uses cw.mstart,
 // cw.scan_tmp, cw.tkey and cw.tval as scratch. narrow: every row's degree is
-// below 2^32, so the per-label sums of short rows are kept in 32 bits.
+// below 2^32, so (below 2^27 vertices) the per-label sums of short rows are
+// kept in 32 bits, beside a 32-bit key, in one word of the chunk's table.
 bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s,
               bool narrow = false);
 // *narrow = every row of g has a weight sum below 2^32 (reads every weight;

@@ -119,7 +119,7 @@ thread_local Prof* g_prof = nullptr;   // the profiler of the solve running on t
 constexpr size_t kProfCounterBytes = sizeof(unsigned long long) * PK_COUNT * PROF_LANES * PROF_STRIDE;
 
 const char* const kProfNames[PK_COUNT] = {"k_cfs_edges",    "k_merge_small", "k_big_insert", "k_group_count",
-                                          "k_group_scatter", "k_pr12",       "k_uf_link_rest", "k_lp_small",
+                                          "k_group_scatter", "k_pr12",       "k_uf_link_rest", "k_lp_flat",
                                           "k_lp_first",     "k_mid_merge",   "k_pr1_first",  "k_pr1_rest"};
 
 // sets g_prof for the duration of one call and resolves its events at the end
