@@ -136,11 +136,11 @@ constexpr int DENSE_MAX = 1024;
 // row is written in place. Larger groups take the tile path below.
 constexpr int MID_MAX = 2048;
 constexpr int MID_MEM = 1024;
-constexpr int MID_T = 256;
+constexpr int MID_T = 512;
 // Groups of at most MID_HALF entries take a table of 2048 slots (32 KB of
-// LDS per workgroup, five workgroups per compute unit), larger ones 4096
-// slots (56 KB, two per compute unit): the merge of a group is a chain of
-// dependent loads, and more workgroups in flight hide more of it. Both keep
+// LDS per workgroup of eight waves, four workgroups per compute unit),
+// larger ones 4096 slots (56 KB, two per compute unit): the merge of a group
+// waits on its loads, and more waves in flight hide more of that. Both keep
 // the table's load at most 1/2.
 constexpr int MID_HALF = 1024;
 
@@ -977,7 +977,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     MC_LAUNCHED("k_merge_small");
     prof_end(PK_MERGE_SMALL, s);
     prof_begin(PK_MID_MERGE, s);
-    k_mid_merge<2 * MID_HALF><<<256 * 5, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt,
+    k_mid_merge<2 * MID_HALF><<<256 * 4, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt,
                                                         n2, dst, prof_dev_bytes(PK_MID_MERGE));
     MC_LAUNCHED("k_mid_merge");
     k_mid_merge<2 * MID_MAX><<<256 * 2, MID_T, 0, s>>>(src, L, perm, vstart, ws.mstart, gstart, ws.mlist, ws.mcnt,
