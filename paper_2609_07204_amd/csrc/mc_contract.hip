@@ -27,7 +27,9 @@
 
 namespace {
 
-constexpr int CHUNK = 512;          // chunk span in (entry offset + group index)
+constexpr int CHUNK = 512;          // chunk span in (entry offset + GROUP_W group index)
+constexpr int GROUP_W = 4;          // key units of a group: a chunk starts at most CHUNK / GROUP_W groups
+constexpr int CHUNK_GROUPS = CHUNK / GROUP_W;
 constexpr int SMALL_MAX = 512;      // larger groups take the global-table path
 constexpr int HSLOTS = 1024;        // LDS hash slots per chunk (> the most entries a chunk holds)
 constexpr int TILE_SLOTS = 256;     // global-table allocation and extraction unit
@@ -192,12 +194,12 @@ __device__ __forceinline__ int32_t last_le(const int32_t* __restrict__ a, int32_
     return lo;
 }
 
-// first g in [0, n2] with sstart[g] + g >= key
+// first g in [0, n2] with sstart[g] + GROUP_W g >= key
 __device__ __forceinline__ int32_t first_key_ge(const int32_t* __restrict__ sstart, int32_t n2, int64_t key) {
     int32_t lo = 0, hi = n2 + 1;
     while (lo < hi) {
         int32_t mid = lo + (hi - lo) / 2;
-        if ((int64_t)sstart[mid] + mid >= key) hi = mid; else lo = mid + 1;
+        if ((int64_t)sstart[mid] + (int64_t)GROUP_W * mid >= key) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
@@ -206,7 +208,7 @@ constexpr int MERGE_THREADS = 256;
 constexpr int SUB = 16;                              // lanes per group
 constexpr int NSUB = MERGE_THREADS / SUB;
 
-// first group of every chunk: cg[c] = first g with sstart[g] + g >= c CHUNK,
+// first group of every chunk: cg[c] = first g with sstart[g] + GROUP_W g >= c CHUNK,
 // sstart the prefix of the small groups' entry counts (larger groups count
 // as empty, so no chunk is spent on their entries); one independent search
 // per thread, so their latencies overlap
@@ -264,10 +266,10 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
                                                               unsigned long long* pb) {
     __shared__ unsigned long long hkey[HSLOTS];
     __shared__ long long hval[HSLOTS];
-    __shared__ int32_t gst[CHUNK + 1];
-    __shared__ int32_t gvs[CHUNK + 1];
-    __shared__ int32_t gcur[CHUNK];
-    __shared__ long long gdeg[CHUNK];
+    __shared__ int32_t gst[CHUNK_GROUPS + 1];
+    __shared__ int32_t gvs[CHUNK_GROUPS + 1];
+    __shared__ int32_t gcur[CHUNK_GROUPS];
+    __shared__ long long gdeg[CHUNK_GROUPS];
     __shared__ int32_t mpre[NSUB + 1];   // few-group chunks: prefix of the small groups' member counts
 
     const int tid = threadIdx.x;
@@ -902,7 +904,7 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool so
     ws.red_id = a.take<int32_t>(1024);
     ws.red_m = a.take<int64_t>(1024);
     ws.red_d = a.take<int64_t>(1024);
-    ws.cg = a.take<int32_t>((size_t)((cap + n) / CHUNK) + 4);
+    ws.cg = a.take<int32_t>((size_t)((cap + (int64_t)GROUP_W * n) / CHUNK) + 4);
     ws.tinfo = a.take<int32_t>(2 * ((size_t)(cap / BIG_TILE) + 2));
     ws.xg = a.take<int32_t>(slots / TILE_SLOTS + 8);
     ws.mlist = a.take<int32_t>((size_t)n + 1);
@@ -968,7 +970,7 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
     if (!scan_i32(ws.sstart, ws.sstart, n2, ws.scan_tmp, s)) return false;  // small-group entry prefix
     // at most this many chunks hold small groups; the rest of the grid finds
     // no group and returns
-    const int64_t chunks = (src.cap + n2) / CHUNK + 2;
+    const int64_t chunks = (src.cap + (int64_t)GROUP_W * n2) / CHUNK + 2;
     k_chunk_start<<<grid_for(chunks + 1, 256), 256, 0, s>>>(ws.sstart, n2, chunks, ws.cg);
     MC_LAUNCHED("k_chunk_start");
     prof_begin(PK_MERGE_SMALL, s);

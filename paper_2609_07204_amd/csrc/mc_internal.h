@@ -103,7 +103,7 @@ struct ContractWS {
     int32_t* red_id;  // [1024]
     int64_t* red_m;   // [1024] per-block entry counts
     int64_t* red_d;   // [1024] per-block maximum degrees
-    int32_t* cg;      // [(cap+n)/512+4] first group of every merge chunk
+    int32_t* cg;      // [(cap+4n)/512+4] first group of every merge chunk
     int32_t* tinfo;   // [2*(cap/4096+2)] group and first member of every large-group tile
     int32_t* xg;      // [(5 cap/2)/256+8] group of every 256-slot table tile
     int32_t* mlist;   // [n+1] groups merged by one workgroup each in LDS
