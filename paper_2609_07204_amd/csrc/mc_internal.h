@@ -122,8 +122,20 @@ bool contract_ws_reset(const ContractWS& ws, hipStream_t s);
 // loops, parallel and zero-weight entries) into `dst` with n2 vertices.
 // A vertex with label -1 is dropped (with its row; no kept row may point at
 // it).
-// dst.cap must be >= the sum of src.len. Writes dst.off/len/col/w/deg and
-// the minimum degree (and its vertex) into sc->dmin / sc->dmin_arg.
+// dst.cap must be >= the sum of src.len. Of src.cap only one use is made:
+// it bounds the sum of src.len and sizes the launch grids, so a caller that
+// knows that sum may pass it there (entries_view). Writes
+// dst.off/len/col/w/deg and the minimum degree (and its vertex) into
+// sc->dmin / sc->dmin_arg.
+// g with cap lowered to m, the sum of its row lengths when the caller knows
+// it (m < 0: unknown), for contract and lp_round: their grids then follow
+// the graph's entries rather than its arrays' capacity. Entry positions
+// (off + j) may exceed m, so the view serves those two calls alone.
+inline DGraph entries_view(const DGraph& g, int64_t m) {
+    DGraph v = g;
+    if (m >= 0 && m < v.cap) v.cap = m;
+    return v;
+}
 bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, ContractWS& ws,
               DevScalars* sc, hipStream_t s);
 
@@ -214,7 +226,8 @@ void lp_ws_carve(Arena& a, int32_t n, int64_t cap, LpWS& w);
 // One synchronous label-propagation round over g (Section 2.1 heuristic):
 // lab_out[v] = heaviest neighbour label, keeping lab_in[v] unless another
 // label is strictly heavier, smallest label on ties. Uses cw.mstart,
-// cw.scan_tmp, cw.tkey and cw.tval as scratch. narrow: every row's degree is
+// cw.scan_tmp, cw.tkey and cw.tval as scratch. g.cap bounds the sum of
+// g.len (it sizes the launch grids, as in contract). narrow: every row's degree is
 // below 2^32, so (below 2^27 vertices) the per-label sums of short rows are
 // kept in 32 bits, beside a 32-bit key, in one word of the chunk's table.
 bool lp_round(const DGraph& g, const int32_t* lab_in, int32_t* lab_out, LpWS& w, ContractWS& cw, hipStream_t s,

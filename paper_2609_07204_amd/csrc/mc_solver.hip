@@ -988,7 +988,7 @@ static mc_status exact_rounds(Solver& S, int src) {
             cur->n = 1;
             break;
         }
-        if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s)) return MC_E_DEVICE;
+        if (!contract(entries_view(*cur, S.cur_m), w.L, n2, *nxt, w.cw, w.sc, s)) return MC_E_DEVICE;
         if (!map_update(w.map0, w.L, S.n0, s)) return MC_E_DEVICE;
         if (!S.readback()) return MC_E_DEVICE;
         h = *S.c->hsc;
@@ -1039,7 +1039,8 @@ static DGraph* contract_and_bound(Solver& S, DGraph* cur, int32_t n2, int* nxt_i
     hipStream_t s = S.s;
     DGraph* nxt = &w.g[*nxt_idx];
     *err = MC_E_DEVICE;
-    if (!contract(*cur, w.L, n2, *nxt, w.cw, w.sc, s) || !map_update(w.map0, w.L, S.n0, s) || !S.readback())
+    if (!contract(entries_view(*cur, S.cur_m), w.L, n2, *nxt, w.cw, w.sc, s) || !map_update(w.map0, w.L, S.n0, s) ||
+        !S.readback())
         return nullptr;
     const DevScalars h = *S.c->hsc;
     S.cur_m = h.m2;
@@ -1079,7 +1080,7 @@ static mc_status heuristic(Solver& S) {
         if (!lp_first(*cur, b, w.lw, w.cw, s)) return MC_E_DEVICE;
         std::swap(a, b);
         for (int it = 1; it < iters; it++) {
-            if (!lp_round(*cur, a, b, w.lw, w.cw, s, narrow)) return MC_E_DEVICE;
+            if (!lp_round(entries_view(*cur, S.cur_m), a, b, w.lw, w.cw, s, narrow)) return MC_E_DEVICE;
             std::swap(a, b);
         }
         if (!lp_relabel(a, n, w.L, w.flag, w.cw.scan_tmp, w.sc, s) || !S.readback()) return MC_E_DEVICE;
