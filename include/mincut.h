@@ -72,7 +72,8 @@ typedef struct {
                                  (default 2) */
     int32_t pr_tri_deg_cap;   /* reduction tests 3 and 4 on edges whose two
                                  rows have at most this many entries (<= 64;
-                                 default 16; 0 = off); they stop for the rest
+                                 default 16; 0 = off) in solves that do not
+                                 run the heuristic; they stop for the rest
                                  of a solve once a round gains fewer than one
                                  contraction per 100 vertices */
     int32_t capforest_passes; /* concurrent CAPFOREST passes per round
