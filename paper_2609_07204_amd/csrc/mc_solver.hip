@@ -1197,21 +1197,23 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     // the identity folds loops, parallel entries and zero weights; the
     // padded view of the input reuses g[1]'s arrays. A device input is
     // checked in the same pass (host inputs were checked on the host), and
-    // nothing else reads it before the check's result is known.
+    // nothing else reads it before the check's result is known. The minimum
+    // degree of a normal input is taken before that readback: it reads only
+    // the lengths and degrees the pass wrote, so one readback serves both.
+    w.g[0].n = n;
     if (!canon_check(rp, col, wt, n, (int32_t)nnz, w.g[0].len, w.g[0].deg, &w.sc->noncanon,
                      host_input ? nullptr : w.sc, w.vpart, s) ||
-        !S.readback())
+        !min_degree(w.g[0], w.cw, w.sc, s) || !S.readback())
         return MC_E_DEVICE;
     if (c->hsc->err != 0)
         return fail((mc_status)c->hsc->err, c->hsc->err == MC_E_OVERFLOW ? "total weight must be below 2^62"
                                                                           : "malformed CSR (row_ptr, col or w)");
-    if (c->hsc->noncanon == 0) {
-        w.g[0].n = n;
+    const bool input_normal = c->hsc->noncanon == 0;
+    if (input_normal) {
         w.g[0].cap = nnz;
         w.g[0].off = const_cast<int32_t*>(rp);
         w.g[0].col = const_cast<int32_t*>(col);
         w.g[0].w = const_cast<int64_t*>(wt);
-        if (!min_degree(w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
     } else {
         DGraph user = w.g[1];
         user.n = n;
@@ -1221,7 +1223,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         if (!csr_to_padded(rp, n, user.off, user.len, s)) return MC_E_DEVICE;
         if (!contract(user, nullptr, n, w.g[0], w.cw, w.sc, s)) return MC_E_DEVICE;
     }
-    S.stats.input_normal = c->hsc->noncanon == 0;
+    S.stats.input_normal = input_normal;
     if (!iota_i32(w.map0, n, s) || !fill_i32(w.claim, 0, n, s)) return MC_E_DEVICE;
     // connectivity: lambda = 0 iff the positive-weight graph is disconnected.
     // When the heuristic runs, its coarse graph has the same components and
@@ -1233,7 +1235,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     // after it (hyperbolic 2^23: 7.12 ms per solve with them, 6.83 without;
     // Chung-Lu 2^22: 14.54 and 14.42 ms).
     if (run_heuristic) S.tri_on = false;
-    if (!S.readback()) return MC_E_DEVICE;
+    if (!input_normal && !S.readback()) return MC_E_DEVICE;   // the normalisation's minimum degree
     if (run_heuristic && c->hsc->dmin > 0) {
         S.conn_pending = true;
     } else if (!check_connected(S, w.g[0])) {

@@ -716,6 +716,24 @@ def test_lp_round_label_sums_near_32_bits(ctx, seed, wlo, whi, hubs):
         assert np.array_equal(ctx.step_lp(dev, lab), want)
 
 
+@pytest.mark.parametrize("seed,nlab", [(31, 3), (32, 60), (33, 0)])
+def test_lp_round_general_kernel_all_row_classes(ctx, seed, nlab):
+    # weights so large that row sums pass 2^32: the general LP kernel (64-bit
+    # keys and sums) takes every row, with rows of every length class (chunks
+    # of many short rows, chunks of a few rows cut into pieces, long rows);
+    # few distinct weights, so that label sums tie; bit-exact
+    g = gen.chung_lu(20000, 2.1, 24, seed, 1 << 30, (1 << 30) + 2, kcore=0, lcc=False)
+    d = np.diff(g.row_ptr)
+    rs = np.add.reduceat(g.w.astype(object), g.row_ptr[:-1])
+    assert max(rs) >= (1 << 32) and d.max() > 256 and ((d > 32) & (d <= 256)).sum() > 0
+    r = np.random.default_rng(seed)
+    lab = np.arange(g.n, dtype=np.int32) if nlab == 0 else r.integers(0, nlab, g.n).astype(np.int32)
+    dev = ctx.dgraph(g)
+    want = oracle.lp_round(g, lab)
+    assert np.array_equal(ctx.step_lp(dev, lab), want)
+    assert np.array_equal(ctx.step_lp(dev, want), oracle.lp_round(g, want))
+
+
 def test_lp_round_ties_and_own_label(ctx):
     # star-like rows with equal weights: ties go to the smallest label, and a
     # vertex keeps its label unless another is strictly heavier
