@@ -141,6 +141,34 @@ def test_contract_mixed_group_sizes(cctx):
     assert_same_csr(dst, rp, col, w)
 
 
+@pytest.mark.parametrize("n2,seed,giants", [(50000, 4, 8), (150000, 5, 3), (9000, 6, 20)])
+def test_contract_many_giant_groups(cctx, n2, seed, giants):
+    # giant groups (at least n2 / 4 entries: dense accumulators) beside many
+    # small groups, their targets spread over all of n2; half of a giant
+    # group's entries point into the other giant groups (a few hot targets)
+    ctx = cctx
+    say("contract giant groups", n2, seed, giants)
+    g = gen.chung_lu(200000, 2.5, 10.0, seed, 1, 30, kcore=0, lcc=False)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(g.n)
+    lab = rng.integers(giants, n2, g.n).astype(np.int32)
+    lab[order[: n2 - giants]] = np.arange(giants, n2, dtype=np.int32)   # every small group has a member
+    per = min((g.n - (n2 - giants)) // giants, g.n // (2 * giants))   # members of each giant group
+    for k in range(giants):
+        lab[order[n2 - giants + k * per: n2 - giants + (k + 1) * per]] = k
+    deg = np.diff(g.row_ptr)
+    sizes = np.bincount(lab, weights=deg, minlength=n2)
+    say("giant entries", sorted(sizes[:giants].astype(int))[:3], "n2/4", n2 // 4)
+    assert (sizes[:giants] >= n2 // 4).all() and (sizes[:giants] > 2048).all()
+    import torch
+    src, _, _ = canon_dev(ctx, g)
+    dst, dmin, darg = ctx.step_contract(src, torch.as_tensor(lab).cuda(), n2)
+    rp, col, w = oracle.contract(g, lab, n2)
+    assert_same_csr(dst, rp, col, w)
+    odeg = np.array([w[rp[x]:rp[x + 1]].sum() for x in range(n2)])
+    assert dmin == odeg.min() and darg == int(np.argmin(odeg))
+
+
 def test_contract_groups_around_workgroup_limits(cctx):
     ctx = cctx
     # groups of 150..1300 members at about three entries each: below, inside
