@@ -633,7 +633,7 @@ struct Engine {
         DGraph S = w.stage;
         S.n = NS;
         S.cap = CS;
-        EG_OK(canon_check(w.in_rp, w.in_col, w.in_w, NS, 0, w.stage.len, w.stage.deg, &w.sc->noncanon, nullptr, nullptr, s));
+        EG_OK(canon_check(w.in_rp, w.in_col, w.in_w, NS, 0, w.stage.len, w.stage.deg, &w.sc->noncanon, nullptr, nullptr, nullptr, s));
         if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
         if (c->hsc->noncanon == 0) {
             S.off = w.in_rp;

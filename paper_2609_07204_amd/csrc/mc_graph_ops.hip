@@ -832,11 +832,16 @@ __global__ __launch_bounds__(256) void k_validate_sum(const unsigned long long* 
 // same pass checks the input: row bounds within
 // [0, nnz] and non-decreasing (a row that fails is not read), targets in
 // range, weights non-negative, and the weights' sum, saturated at WCAP, into
-// part[blockIdx.x] for k_validate_sum.
+// part[blockIdx.x] for k_validate_sum. With lp1, the same pass writes the
+// first label-propagation round from singleton labels (Section 2.1
+// heuristic): every row's heaviest neighbour, the smallest on ties, or the
+// row itself when it has none; it is that round's result when the input is
+// in normal form (the caller drops it otherwise).
 __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                               const int64_t* __restrict__ w, int32_t n, int32_t nnz,
                                               int32_t* __restrict__ len, int64_t* __restrict__ deg,
-                                              int32_t* noncanon, DevScalars* sc, unsigned long long* part) {
+                                              int32_t* noncanon, DevScalars* sc, unsigned long long* part,
+                                              int32_t* __restrict__ lp1) {
     // 16 lanes take 16 consecutive rows: their offsets come in one load,
     // and each lane then loads up to four entries of a row at once
     const int64_t nsub = (int64_t)gridDim.x * (blockDim.x / SUB);
@@ -852,11 +857,14 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, c
             my_e = my_o = 0;
         }
         int64_t my_d = 0;
+        int32_t my_lp = INT32_MAX;
         const int32_t rows = n - v0 < SUB ? (int32_t)(n - v0) : SUB;
         for (int32_t r = 0; r < rows; r++) {
             const int32_t v = (int32_t)v0 + r;
             const int32_t o = __shfl(my_o, r, SUB), e = __shfl(my_e, r, SUB), l = e - o;
             int64_t d = 0;
+            int64_t bw = 0;
+            int32_t bx = INT32_MAX;
             bool bad = false;
             for (int32_t j0 = 0; j0 < l; j0 += 4 * SUB) {
                 int32_t x[4], xp[4];
@@ -873,6 +881,10 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, c
                     if (j0 + u * SUB + sl < l) {
                         d += c[u];
                         bad |= x[u] == v || c[u] <= 0 || xp[u] >= x[u];
+                        if (x[u] != v && c[u] > 0 && (c[u] > bw || (c[u] == bw && x[u] < bx))) {
+                            bw = c[u];
+                            bx = x[u];
+                        }
                         if (sc) {
                             if (x[u] < 0 || x[u] >= n || c[u] < 0) set_err(sc, MC_E_BAD_GRAPH);
                             if (c[u] > 0) {
@@ -884,12 +896,20 @@ __global__ __launch_bounds__(256) void k_canon(const int32_t* __restrict__ rp, c
                 }
             }
             for (int k = SUB / 2; k > 0; k >>= 1) d += __shfl_xor(d, k, SUB);
-            if (sl == r) my_d = d;
+            if (lp1) {
+                for (int k = SUB / 2; k > 0; k >>= 1) {
+                    const int64_t w2 = __shfl_xor(bw, k, SUB);
+                    const int32_t x2 = __shfl_xor(bx, k, SUB);
+                    if (w2 > bw || (w2 == bw && x2 < bx)) { bw = w2; bx = x2; }
+                }
+            }
+            if (sl == r) { my_d = d; my_lp = bx; }
             bad_any |= bad;
         }
         if (v0 + sl < n) {
             len[v0 + sl] = my_e - my_o;
             deg[v0 + sl] = my_d;
+            if (lp1) lp1[v0 + sl] = my_lp != INT32_MAX ? my_lp : (int32_t)(v0 + sl);
         }
     }
     if (__ballot(bad_any) && lane_id() == 0 && ld_acq(noncanon) == 0) st_rel(noncanon, 1);
@@ -1098,11 +1118,12 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
 }
 
 bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
-                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, hipStream_t s) {
+                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, int32_t* lp1,
+                 hipStream_t s) {
     if (!fill_i32(noncanon, 0, 1, s)) return false;
     // with checks, at most 1024 blocks (the partial sums of the weights)
     const int nb = grid_for(((int64_t)n + SUB - 1) / SUB * SUB, 256, sc ? 1024 : 8192);
-    k_canon<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, len, deg, noncanon, sc, part);
+    k_canon<<<nb, 256, 0, s>>>(row_ptr, col, w, n, nnz, len, deg, noncanon, sc, part, lp1);
     MC_LAUNCHED("k_canon");
     if (sc) {
         k_validate_sum<<<1, 256, 0, s>>>(part, nb, sc);

@@ -446,13 +446,17 @@ bool csr_to_padded(const int32_t* row_ptr, int32_t n, int32_t* off, int32_t* len
 // pass checks the input into sc->err as an mc_status code: row bounds in
 // [0, nnz] and non-decreasing (a row that fails is not read), targets in
 // range, non-negative weights, total weight below 2^62 (part: 1024 partial
+// sums). With lp1 (n entries) it also writes every row's heaviest
+// neighbour (smallest on ties; the row itself when it has none): the first
+// label-propagation round from singleton labels when the input is normal.
+bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
+                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, int32_t* lp1,
+                 hipStream_t s);
+
 // Smallest workspace mc_mincut accepts for a graph (small rounds keep their
 // first pass count); mc_workspace_size adds room for one pass per compute
 // unit.
 size_t workspace_min_bytes(const mc_ctx* c, int32_t n, int32_t nnz);
-// sums).
-bool canon_check(const int32_t* row_ptr, const int32_t* col, const int64_t* w, int32_t n, int32_t nnz, int32_t* len,
-                 int64_t* deg, int32_t* noncanon, DevScalars* sc, unsigned long long* part, hipStream_t s);
 
 
 // The library context (opaque to callers).

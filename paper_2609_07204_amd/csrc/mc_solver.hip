@@ -559,6 +559,7 @@ struct Solver {
     bool tri_on = false;          // reduction tests 3 and 4 still pay off
     bool in_heuristic = false;    // exact rounds on the heuristic's coarse graph
     bool conn_pending = false;    // connectivity not decided yet (the heuristic's coarse graph decides it)
+    bool lp1_ready = false;       // the input pass left the first LP round of the input in lab2
     bool disconnected = false;    // lambda = 0; the side is set
     bool pv_clean = false;        // private pass state cleared (once per solve, before the first private pass)
     int32_t small_max = 32;       // passes of small rounds the workspace holds
@@ -1074,10 +1075,12 @@ static mc_status heuristic(Solver& S) {
         prof_round_begin(1, n, S.cur_m, s);
         int32_t* a = w.parent;   // labels ping-pong between parent[] and lab2[]
         int32_t* b = w.lab2;
-        // the first round starts from singleton labels on a normal graph;
-        // the last readback holds cur's maximum degree (its last min_degree)
+        // the first round starts from singleton labels on a normal graph
+        // (on the input, the input pass took it already); the last readback
+        // holds cur's maximum degree (its last min_degree)
         const bool narrow = S.c->hsc->dmax < ((int64_t)1 << 32);
-        if (!lp_first(*cur, b, w.lw, w.cw, s)) return MC_E_DEVICE;
+        if (S.lp1_ready && cur == &w.g[0]) S.lp1_ready = false;
+        else if (!lp_first(*cur, b, w.lw, w.cw, s)) return MC_E_DEVICE;
         std::swap(a, b);
         for (int it = 1; it < iters; it++) {
             if (!lp_round(entries_view(*cur, S.cur_m), a, b, w.lw, w.cw, s, narrow)) return MC_E_DEVICE;
@@ -1201,8 +1204,11 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     // degree of a normal input is taken before that readback: it reads only
     // the lengths and degrees the pass wrote, so one readback serves both.
     w.g[0].n = n;
+    // a solve that runs the heuristic takes its first label-propagation
+    // round from this pass when the input is normal
+    const bool run_heuristic = c->opt.heuristic_min_n > 0 && n >= c->opt.heuristic_min_n;
     if (!canon_check(rp, col, wt, n, (int32_t)nnz, w.g[0].len, w.g[0].deg, &w.sc->noncanon,
-                     host_input ? nullptr : w.sc, w.vpart, s) ||
+                     host_input ? nullptr : w.sc, w.vpart, run_heuristic ? w.lab2 : nullptr, s) ||
         !min_degree(w.g[0], w.cw, w.sc, s) || !S.readback())
         return MC_E_DEVICE;
     if (c->hsc->err != 0)
@@ -1229,7 +1235,7 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
     // When the heuristic runs, its coarse graph has the same components and
     // decides it at a fraction of the cost (a vertex of degree 0 decides it
     // here).
-    const bool run_heuristic = c->opt.heuristic_min_n > 0 && n >= c->opt.heuristic_min_n;
+    S.lp1_ready = run_heuristic && input_normal;
     // Tests 3 and 4 run only in solves without the heuristic. With it they
     // cost more than they save, on the clusters and in the exact rounds
     // after it (hyperbolic 2^23: 7.12 ms per solve with them, 6.83 without;
