@@ -158,11 +158,23 @@ __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __
         dslot[g] = -1;
         const int32_t members = vstart ? vstart[g + 1] - vstart[g] : 1;
         ssize[g] = s <= SMALL_MAX ? s : 0;
-        if (s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM) {
-            // groups of at most MID_HALF entries from the front of the list,
-            // larger ones from the back
-            if (s <= MID_HALF) mlist[atomicAdd(&mcnt[0], 1)] = (int32_t)g;
-            else mlist[n2 - atomicAdd(&mcnt[1], 1)] = (int32_t)g;
+        const bool mid = s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM;
+        // groups of at most MID_HALF entries from the front of the list,
+        // larger ones from the back; a wavefront reserves its places with one
+        // atomic per list (two counters shared by every group serialise)
+        const bool front = mid && s <= MID_HALF, back = mid && s > MID_HALF;
+        const unsigned long long mfr = __ballot(front), mbk = __ballot(back);
+        const unsigned long long below = (1ULL << lane_id()) - 1;
+        const int lead_f = mfr ? __ffsll((long long)mfr) - 1 : 0;
+        const int lead_b = mbk ? __ffsll((long long)mbk) - 1 : 0;
+        int32_t base_f = 0, base_b = 0;
+        if (mfr && lane_id() == lead_f) base_f = atomicAdd(&mcnt[0], __popcll(mfr));
+        if (mbk && lane_id() == lead_b) base_b = atomicAdd(&mcnt[1], __popcll(mbk));
+        base_f = __shfl(base_f, lead_f, MC_WAVE);
+        base_b = __shfl(base_b, lead_b, MC_WAVE);
+        if (mid) {
+            if (front) mlist[base_f + __popcll(mfr & below)] = (int32_t)g;
+            else mlist[n2 - (base_b + __popcll(mbk & below))] = (int32_t)g;
             tsize[g] = 0;
             bigm[g] = 0;
         } else if (s > SMALL_MAX) {
