@@ -543,7 +543,6 @@ struct Engine {
         one.passes = 1;
         EG_OK(capforest_private_reset(one, s));
         EG_OK(fill_i32((int32_t*)w.sc, 0, sizeof(DevScalars) / 4, s));
-        EG_OK(contract_ws_reset(w.cw, s));
         // prefix marks are set and cleared per round; they start all zero
         EG_OK(fill_u8(w.inpref, 0, (int64_t)cp.N + 1, s));
         tri_on = c->opt.pr_tri_deg_cap > 0;

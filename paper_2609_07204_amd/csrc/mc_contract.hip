@@ -782,11 +782,21 @@ __global__ __launch_bounds__(EX_T) void k_big_extract(const int32_t* __restrict_
     }
 }
 
-// dense accumulators of the giant groups: stream over n2 targets, emit the
-// non-zero ones, and leave the array zero for the next contraction
+// the dense accumulators the giant groups of this contraction use, zeroed
+// once their count is known (no earlier reset needed)
+__global__ void k_dense_clear(const int32_t* __restrict__ dinfo, int32_t nd_max, int32_t n2,
+                              int64_t* __restrict__ dense) {
+    const int32_t nd = dinfo[0] < nd_max ? dinfo[0] : nd_max;
+    const int64_t total = (int64_t)nd * n2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        dense[i] = 0;
+}
+
+// dense accumulators of the giant groups: stream over n2 targets and emit
+// the non-zero ones
 __global__ __launch_bounds__(EX_T) void k_dense_extract(const int32_t* __restrict__ dinfo, int32_t nd_max,
                                                         const int32_t* __restrict__ gstart, int32_t n2,
-                                                        int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
+                                                        const int64_t* __restrict__ dense, int32_t* __restrict__ bcur,
                                                         DGraph dst) {
     constexpr int PERL = 16;                       // a unit is 1024 targets
     constexpr int UNIT = PERL * MC_WAVE;
@@ -800,7 +810,7 @@ __global__ __launch_bounds__(EX_T) void k_dense_extract(const int32_t* __restric
         const int32_t d = (int32_t)(u % nd);
         const int32_t t0 = (int32_t)(u / nd) * UNIT + lane_id();
         const int32_t g = dinfo[1 + d];
-        int64_t* acc = dense + (int64_t)d * n2;
+        const int64_t* acc = dense + (int64_t)d * n2;
         bool take[PERL];
         int32_t key[PERL];
         int64_t val[PERL];
@@ -810,10 +820,7 @@ __global__ __launch_bounds__(EX_T) void k_dense_extract(const int32_t* __restric
             val[q] = key[q] < n2 ? acc[key[q]] : 0;
         }
 #pragma unroll
-        for (int q = 0; q < PERL; q++) {
-            take[q] = val[q] != 0;
-            if (take[q]) acc[key[q]] = 0;
-        }
+        for (int q = 0; q < PERL; q++) take[q] = val[q] != 0;
         wave_emit<PERL>(g, take, key, val, gstart[g], bcur, dst);
     }
 }
@@ -924,7 +931,6 @@ void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool so
     ws.mcnt = a.take<int32_t>(4);
 }
 
-bool contract_ws_reset(const ContractWS& ws, hipStream_t s) { return fill_i64(ws.dense, 0, ws.dense_elems, s); }
 
 bool min_degree(const DGraph& g, ContractWS& ws, DevScalars* sc, hipStream_t s) {
     int nb = grid_for(g.n, 256, 1024);
@@ -969,14 +975,16 @@ bool contract(const DGraph& src, const int32_t* L, int32_t n2, DGraph& dst, Cont
         MC_LAUNCHED("k_group_start");
         gstart = ws.gstart;
     }
-    // the dense accumulators are zero here (reset after carving, and every
-    // extraction clears what it read)
     const int64_t ndm = ws.dense_elems / (n2 > 0 ? n2 : 1);
     const int32_t nd_max = (int32_t)(ndm < DENSE_MAX ? ndm : DENSE_MAX);
     if (!fill_i32(ws.dinfo, 0, 1, s) || !fill_i32(ws.mcnt, 0, 2, s)) return false;
     k_classify<<<grid_for(n2, 256), 256, 0, s>>>(gstart, vstart, n2, nd_max, ws.tsize, ws.bigm, ws.bcur, ws.dslot,
                                                  ws.dinfo, ws.mlist, ws.mcnt, ws.sstart, dst);
     MC_LAUNCHED("k_classify");
+    if (nd_max > 0) {
+        k_dense_clear<<<grid_for((int64_t)nd_max * n2, 256, 4096), 256, 0, s>>>(ws.dinfo, nd_max, n2, ws.dense);
+        MC_LAUNCHED("k_dense_clear");
+    }
     if (!scan_i32(ws.tsize, ws.tsize, n2, ws.scan_tmp, s)) return false;  // -> tbase
     if (!scan_i32(ws.bigm, ws.bigm, n2, ws.scan_tmp, s)) return false;    // -> bebase
     if (!scan_i32(ws.sstart, ws.sstart, n2, ws.scan_tmp, s)) return false;  // small-group entry prefix

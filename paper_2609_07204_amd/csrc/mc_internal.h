@@ -96,7 +96,7 @@ struct ContractWS {
     int64_t* tval;    // [4*cap+1024]
     int32_t* dslot;   // [n+1]  dense accumulator of a giant group, or -1
     int32_t* dinfo;   // [1+DENSE_MAX] count, then the group of each slot
-    int64_t* dense;   // [dense_elems] accumulators, n2 each; all zero between contractions
+    int64_t* dense;   // [dense_elems] accumulators, n2 each; zeroed by each contraction for its giant groups
     int64_t dense_elems;
     int32_t* scan_tmp;
     int64_t* red_val; // [1024] per-block minima
@@ -114,9 +114,6 @@ struct ContractWS {
 };
 // sort: also carve the sort merge's workspace and use it in contract()
 void contract_ws_carve(Arena& a, int32_t n, int64_t cap, ContractWS& ws, bool sort = false);
-// Zero the dense accumulators (once after carving; every contraction leaves
-// them zero again).
-bool contract_ws_reset(const ContractWS& ws, hipStream_t s);
 
 // Contract `src` by labels L (L == nullptr: identity, which only folds
 // loops, parallel and zero-weight entries) into `dst` with n2 vertices.

@@ -1193,7 +1193,6 @@ extern "C" mc_status mc_mincut(mc_ctx* c, const mc_csr* g, void* dev_ws, size_t 
         wt = w.in_w;
     }
     k_reset_round<<<1, 1, 0, s>>>(w.sc);
-    if (!contract_ws_reset(w.cw, s)) return MC_E_DEVICE;
     // normalise. An input already in normal form (rows strictly increasing,
     // no loops, positive weights) is used in place as the first graph: no
     // kernel writes the current graph's off/col/w. Otherwise contraction by
@@ -1385,7 +1384,6 @@ mc_status step_begin(mc_ctx* c, int32_t n, int64_t cap, int32_t passes, void* ws
     carve_step(a, n, cap, passes, w);
     if (a.used > bytes) return fail(MC_E_INVALID_ARG, "step: workspace too small");
     w.cw.sorted = c->opt.contract_mode == 1;
-    if (!contract_ws_reset(w.cw, c->stream)) return fail(MC_E_DEVICE, "step: workspace reset failed");
     return MC_OK;
 }
 
