@@ -133,9 +133,10 @@ __global__ void k_group_start(const int32_t* __restrict__ vstart, const int32_t*
 // number of dense groups is at most budget / n2 (and DENSE_MAX).
 constexpr int DENSE_MAX = 1024;
 
-// Groups of (SMALL_MAX, MID_MAX] entries and at most MID_MEM members are
-// merged by one workgroup each, entirely in LDS: no global atomics, and the
-// row is written in place. Larger groups take the tile path below.
+// Groups of (SMALL_MAX, MID_MAX] entries and at most MID_MEM members (and
+// the small groups of many members, below) are merged by one workgroup each,
+// entirely in LDS: no global atomics, and the row is written in place.
+// Larger groups take the tile path below.
 constexpr int MID_MAX = 2048;
 constexpr int MID_MEM = 1024;
 constexpr int MID_T = 512;
@@ -145,6 +146,11 @@ constexpr int MID_T = 512;
 // waits on its loads, and more waves in flight hide more of that. Both keep
 // the table's load at most 1/2.
 constexpr int MID_HALF = 1024;
+// Small groups of more than MERGE_MANY members (and at most MID_MEM) are
+// merged by the mid-group workgroups too: the chunk merge walks a group's
+// members one after the other (a chain of dependent loads each), where a
+// mid-group workgroup stages all of them at once and takes the entries flat.
+constexpr int MERGE_MANY = 32;
 
 __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __restrict__ vstart, int32_t n2,
                            int32_t nd_max, int32_t* __restrict__ tsize, int32_t* __restrict__ bigm,
@@ -157,8 +163,8 @@ __global__ void k_classify(const int32_t* __restrict__ gstart, const int32_t* __
         dst.off[g] = gstart[g];
         dslot[g] = -1;
         const int32_t members = vstart ? vstart[g + 1] - vstart[g] : 1;
-        ssize[g] = s <= SMALL_MAX ? s : 0;
-        const bool mid = s > SMALL_MAX && s <= MID_MAX && members <= MID_MEM;
+        const bool mid = members <= MID_MEM && (s > SMALL_MAX ? s <= MID_MAX : members > MERGE_MANY);
+        ssize[g] = s <= SMALL_MAX && !mid ? s : 0;
         // groups of at most MID_HALF entries from the front of the list,
         // larger ones from the back; a wavefront reserves its places with one
         // atomic per list (two counters shared by every group serialise)
@@ -298,11 +304,17 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     for (int i = tid; i < ng; i += MERGE_THREADS) { gcur[i] = 0; gdeg[i] = 0; }
     __syncthreads();
 
+    // the groups merged here: at most SMALL_MAX entries, and not the many-
+    // member ones the mid-group workgroups take (as k_classify splits them)
+    auto here = [&](int gl) {
+        const int32_t mc = gvs[gl + 1] - gvs[gl];
+        return gst[gl + 1] - gst[gl] <= SMALL_MAX && !(mc > MERGE_MANY && mc <= MID_MEM);
+    };
     const int sg = tid / SUB, sl = tid % SUB;
     if (ng >= NSUB) {
         // many groups: one lane group per group, its members in turn
         for (int gl = sg; gl < ng; gl += NSUB) {
-            if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
+            if (!here(gl)) continue;
             for (int32_t m = gvs[gl]; m < gvs[gl + 1]; m++)
                 merge_row(src, L, perm ? perm[m] : m, g_lo + gl, gl, sl, hkey, hval, nin);
         }
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
             int32_t run = 0;
             for (int gl = 0; gl < ng; gl++) {
                 mpre[gl] = run;
-                if (gst[gl + 1] - gst[gl] <= SMALL_MAX) run += gvs[gl + 1] - gvs[gl];
+                if (here(gl)) run += gvs[gl + 1] - gvs[gl];
             }
             mpre[ng] = run;
         }
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge_small(DGraph src, const
     }
     __syncthreads();
     for (int gl = tid; gl < ng; gl += MERGE_THREADS) {
-        if (gst[gl + 1] - gst[gl] > SMALL_MAX) continue;
+        if (!here(gl)) continue;
         dst.len[g_lo + gl] = gcur[gl];
         dst.deg[g_lo + gl] = gdeg[gl];
         ngrp++;
