@@ -165,6 +165,24 @@ __global__ __launch_bounds__(256) void k_bg_segmin(const int64_t* deg, const int
     }
 }
 
+// the largest total degree of one graph (its vertex range voff[i] ..
+// voff[i+1]) into sc->gmax: every degree of any contraction of the batch is
+// below it, since a cluster lies inside one graph
+__global__ __launch_bounds__(256) void k_bg_wmax(const int64_t* deg, const int32_t* voff, int32_t k,
+                                                DevScalars* sc) {
+    __shared__ int64_t ss[4];
+    for (int32_t i = blockIdx.x; i < k; i += gridDim.x) {
+        int64_t t = 0;
+        for (int32_t v = voff[i] + threadIdx.x; v < voff[i + 1]; v += 256) t += deg[v];
+        t = wave_sum_i64(t);
+        __syncthreads();
+        if (lane_id() == 0) ss[threadIdx.x / MC_WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax((unsigned long long*)&sc->gmax, (unsigned long long)(ss[0] + ss[1] + ss[2] + ss[3]));
+    }
+}
+
 // voff2[i] = number of component roots before voff[i] (scan of root flags)
 __global__ void k_bg_offsets(const int32_t* scan, const int32_t* voff, int32_t k, int32_t* voff2) {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= k; i += gridDim.x * blockDim.x)
@@ -633,7 +651,14 @@ struct Engine {
         S.n = NS;
         S.cap = CS;
         EG_OK(canon_check(w.in_rp, w.in_col, w.in_w, NS, 0, w.stage.len, w.stage.deg, &w.sc->noncanon, nullptr, nullptr, nullptr, s));
+        // the largest graph's total degree (of the input rows, loops and
+        // parallel entries counted: an upper bound) decides whether the
+        // label-propagation rounds may keep 32-bit sums
+        EG_OK(fill_i64(&w.sc->gmax, 0, 1, s));
+        k_bg_wmax<<<std::min(k, 8192), 256, 0, s>>>(w.stage.deg, w.s_voff, k, w.sc);
+        EG_OK(mc_hip_ok(hipGetLastError(), "k_bg_wmax"));
         if (!readback()) return mc_fail(MC_E_DEVICE, "readback failed");
+        const bool narrow = c->hsc->gmax < ((int64_t)1 << 32);
         if (c->hsc->noncanon == 0) {
             S.off = w.in_rp;
             S.col = w.in_col;
@@ -650,7 +675,7 @@ struct Engine {
         // the label-propagation heuristic on the staged graphs (every graph
         // at once); its best bounds are applied after the minimum degrees
         const bool lp = c->opt.batch_lp == 1 || (c->opt.batch_lp == 0 && c->opt.heuristic_min_n > 0);
-        if (lp) EG_OK(heuristic_levels(S, k, NS, sv));
+        if (lp) EG_OK(heuristic_levels(S, k, NS, sv, narrow));
         DGraph& G = w.g[cur];
         k_eg_append<<<grid_for((int64_t)CS + NS, 256), 256, 0, s>>>(S, CS, G, n, used);
         EG_OK(mc_hip_ok(hipGetLastError(), "k_eg_append"));
@@ -699,7 +724,7 @@ struct Engine {
     // vertices, ranges sv): w.best receives each graph's best collapsed
     // degree and w.h_side the matching side. The coarse graphs live in the
     // two union-graph buffers that are not current.
-    bool heuristic_levels(const DGraph& S, int32_t k, int32_t NS, const std::vector<int32_t>& sv) {
+    bool heuristic_levels(const DGraph& S, int32_t k, int32_t NS, const std::vector<int32_t>& sv, bool narrow) {
         const int iters = c->opt.lp_iters > 0 ? c->opt.lp_iters : 2;
         if (!fill_i64(w.best, INT64_MAX, k, s) || !fill_u8(w.h_side, 0, NS, s) || !iota_i32(w.h_map, NS, s))
             return false;
@@ -718,7 +743,7 @@ struct Engine {
             if (!lp_first(Gc, lb, w.lw, w.cw, s)) return false;
             std::swap(la, lb);
             for (int it = 1; it < iters; it++) {
-                if (!lp_round(Gc, la, lb, w.lw, w.cw, s)) return false;
+                if (!lp_round(Gc, la, lb, w.lw, w.cw, s, narrow)) return false;
                 std::swap(la, lb);
             }
             if (!lp_relabel(la, nc, w.h_lab, w.flag, w.cw.scan_tmp, w.sc, s)) return false;

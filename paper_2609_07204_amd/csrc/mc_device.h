@@ -38,6 +38,7 @@ struct DevScalars {
     int32_t err;            // validation error code (0 = fine)
     int32_t noncanon;       // 1: the input CSR needs the merging normalisation
     int64_t dmax;           // maximum degree of the graph the last min_degree read
+    int64_t gmax;           // batched form: the largest total degree of one graph of the batch
 };
 
 // ------------------------------------------------------------- atomics
