@@ -345,7 +345,9 @@ enum {
     MC_K_LP_SMALL = 7,         /* k_lp_flat: label-propagation round, rows of <= 256 entries
                                   (k_lp_small instead when the graph has 2^27 - 1 vertices or
                                   more, or a degree of 2^32 or more) */
-    MC_K_LP_FIRST = 8,         /* k_lp_first: first label-propagation round (from singletons) */
+    MC_K_LP_FIRST = 8,         /* k_lp_first: first label-propagation round (from singletons) of
+                                  the coarse levels; a normal input's own first round is taken in
+                                  the input check's pass (k_canon), untimed */
     MC_K_MID_MERGE = 9,        /* k_mid_merge<2048>, k_mid_merge<4096>: contraction of groups of
                                   513..2048 entries */
     MC_K_PR1_FIRST = 10,       /* k_pr1_first: link rounds of every row's first and second test-1
