@@ -68,6 +68,26 @@ __global__ void k_lp_chunks(const int32_t* __restrict__ rstart, int32_t n, int64
 
 __device__ __forceinline__ uint32_t lp_hash(uint32_t gl, uint32_t lbl) { return hash32(lbl ^ (gl * 0x9E3779B1u)); }
 
+// Row v of l > LP_SMALL entries to the long-row list: its slot k, its
+// global table of round_up(2 l, 256) slots, and its tasks of LP_TASK
+// entries (the long-row kernels merge it).
+__device__ __forceinline__ void lp_list_long(int32_t v, int32_t l, int32_t* __restrict__ long_list,
+                                             int32_t* __restrict__ long_base, int32_t* __restrict__ counters,
+                                             unsigned long long* __restrict__ long_best,
+                                             unsigned long long* __restrict__ long_own,
+                                             int32_t* __restrict__ long_lab, int32_t* __restrict__ task_row,
+                                             int32_t* __restrict__ task_idx) {
+    const int32_t k = atomicAdd(&counters[0], 1);
+    const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
+    const int32_t t0 = atomicAdd(&counters[2], nt);
+    long_list[k] = v;
+    long_base[k] = atomicAdd(&counters[1], (2 * l + 255) / 256 * 256);
+    long_best[k] = 0;
+    long_own[k] = 0;
+    long_lab[k] = INT32_MAX;
+    for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
+}
+
 // Entries [j0, j1) of row v (chunk-local gl) into the chunk's LDS table by
 // the LP_SUB lanes of a lane group: four entries per lane at a time, so
 // their loads, then their labels' loads, are in flight together.
@@ -141,15 +161,7 @@ __global__ __launch_bounds__(LP_T) void k_lp_small(DGraph g, const int32_t* __re
         rlen[i] = l;
         if (l <= LP_SMALL) my_pieces = (l + LP_SEG - 1) / LP_SEG;
         if (l > LP_SMALL) {
-            const int32_t k = atomicAdd(&counters[0], 1);
-            const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
-            const int32_t t0 = atomicAdd(&counters[2], nt);
-            long_list[k] = v;
-            long_base[k] = atomicAdd(&counters[1], (2 * l + 255) / 256 * 256);
-            long_best[k] = 0;
-            long_own[k] = 0;
-            long_lab[k] = INT32_MAX;
-            for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
+            lp_list_long(v, l, long_list, long_base, counters, long_best, long_own, long_lab, task_row, task_idx);
         }
     }
     if (ng < LP_NSUB && tid < MC_WAVE) {
@@ -279,15 +291,7 @@ __global__ __launch_bounds__(LPF_T) void k_lp_flat(DGraph g, const int32_t* __re
         if (l <= LP_SMALL) {
             my_short = l;
         } else {
-            const int32_t k = atomicAdd(&counters[0], 1);
-            const int32_t nt = (l + LP_TASK - 1) / LP_TASK;
-            const int32_t t0 = atomicAdd(&counters[2], nt);
-            long_list[k] = v;
-            long_base[k] = atomicAdd(&counters[1], (2 * l + 255) / 256 * 256);
-            long_best[k] = 0;
-            long_own[k] = 0;
-            long_lab[k] = INT32_MAX;
-            for (int32_t t = 0; t < nt; t++) task_row[t0 + t] = k, task_idx[t0 + t] = t;
+            lp_list_long(v, l, long_list, long_base, counters, long_best, long_own, long_lab, task_row, task_idx);
         }
     }
     if (tid < MC_WAVE) {
