@@ -80,6 +80,30 @@ def test_bench_reports_traffic_only_for_its_workload_and_source():
         assert bench.traffic_for("k_no_such_kernel", measured) is None
 
 
+def test_traffic_kernels_name_their_defining_sources():
+    # every kernel of the committed summary is keyed to the file that
+    # defines it (template instances by their base name)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        pytest.skip("no committed traffic summary")
+    srcs = traffic.kernel_sources()
+    for w, tab in json.load(open(path)).items():
+        for kernel, rec in tab.items():
+            if kernel.startswith("_"):
+                continue
+            assert srcs.get(kernel.split("<")[0]) == rec["source"], (w, kernel)
+
+
+def test_headline_roofline_kernel_has_current_traffic():
+    # the hyperbolic solve's dominant kernel (the roofline's) has a counter
+    # figure measured on its current source
+    import bench
+    if not os.path.exists(os.path.join(ROOT, "profiles", "traffic.json")):
+        pytest.skip("no committed traffic summary")
+    got = bench.traffic_for("k_lp_flat", "rhg")
+    assert got is not None and got > 0
+
+
 def test_bench_refuses_more_than_one_gpu():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
                        stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)
